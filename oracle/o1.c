@@ -1,0 +1,343 @@
+/*
+ * oracle/o1.c -- CPU ORACLE. TEST INFRASTRUCTURE ONLY.
+ *
+ * This file is not part of the product. Only the tests, the smoke check and
+ * the CPU-baseline leg of the benchmark may build, load or call it. It shares
+ * no code, header, table or constant with the HIP library: it is a plain,
+ * slow, literal reading of the paper, kept deliberately simple so a reader can
+ * check it against the paper by eye.
+ *
+ * What it computes (Section 2.1, objective statement): given a combinational
+ * netlist of basic gates, per-pin delays and the 0/1/X/Z waveforms of the
+ * source nets, the waveform of every gate output.
+ *
+ *  - 4-value logic with Z evaluated as X (Section 2.2) and the AND / OR / XOR
+ *    truth tables of Table 1, typed in below. NOT, BUF, NAND, NOR, XNOR and
+ *    the 3/4-input AND and OR are built from them. MUX2 is not in the paper:
+ *    s=0 selects d0, s=1 selects d1, an unknown select gives the data value
+ *    if both data inputs agree and X otherwise (Verilog's ?: merge rule) --
+ *    parity unpinned by the paper for MUX2.
+ *  - Per gate: Algorithm 2 (output waveform of an unlocked cell): a time merge
+ *    of the input waveforms; at each earliest time every input that has a
+ *    transition there is updated; the gate is evaluated; if the output value
+ *    changed, the delay is the minimum over the inputs that changed at that
+ *    time (Section 2.3 and Fig. 2; Section 3.2), and the new transition is
+ *    added to the output with the "glitch eaten" rule of Eq. 1 (every earlier
+ *    determined transition whose appearance time is not before the new one is
+ *    denied) and the redundant-transition drop of Fig. 3 (a transition to the
+ *    value the output already has is not stored).
+ *  - Delay model: the paper's delay matrix is indexed by triggering pin, input
+ *    edge and output value (Section 2.3). The netlists here give one rise and
+ *    one fall delay per pin; the delay of a new output value 1 is the pin's
+ *    rise delay, of 0 its fall delay, of X the smaller of the two (the
+ *    Verilog rule for transitions to x -- parity unpinned by the paper for the
+ *    X case). A pin with no transition at the merge time has no edge, which
+ *    the paper's matrix expresses as an infinite delay.
+ *  - Readings where the paper is silent: every input starts at X and the
+ *    previous evaluated output starts at X; an empty input waveform stays X;
+ *    outputs are not clipped to a window; an equal appearance time denies the
+ *    older transition (Eq. 1 uses <=).
+ *  - The whole circuit: gates are evaluated in a topological order that this
+ *    file computes itself (Kahn's algorithm), so each gate's inputs are
+ *    complete when it is evaluated (the dependency rule of Section 4.1).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define O1_X 2
+#define O1_Z 3
+#define O1_INF INT64_MAX
+
+/* ---- Table 1: 4-value AND, OR and XOR. Row = first operand, column =
+ * second operand, both in the order 0, 1, X, Z. ---------------------------- */
+static const uint8_t TABLE1_AND[4][4] = {
+    {0, 0, 0, 0},
+    {0, 1, 2, 2},
+    {0, 2, 2, 2},
+    {0, 2, 2, 2},
+};
+static const uint8_t TABLE1_OR[4][4] = {
+    {0, 1, 2, 2},
+    {1, 1, 1, 1},
+    {2, 1, 2, 2},
+    {2, 1, 2, 2},
+};
+static const uint8_t TABLE1_XOR[4][4] = {
+    {0, 1, 2, 2},
+    {1, 0, 2, 2},
+    {2, 2, 2, 2},
+    {2, 2, 2, 2},
+};
+
+enum { T_BUF, T_NOT, T_AND2, T_OR2, T_NAND2, T_NOR2, T_XOR2, T_XNOR2, T_AND3, T_MUX2,
+       T_AND4, T_OR4, T_COUNT };
+
+static int arity_of(int type) {
+    switch (type) {
+    case T_BUF: case T_NOT: return 1;
+    case T_AND3: case T_MUX2: return 3;
+    case T_AND4: case T_OR4: return 4;
+    default: return 2;
+    }
+}
+
+/* Z is read as X (Section 2.2). */
+static uint8_t z_as_x(uint8_t a) { return a == O1_Z ? O1_X : a; }
+
+static uint8_t logic_not(uint8_t a) {
+    a = z_as_x(a);
+    return a == 0 ? 1 : a == 1 ? 0 : O1_X;
+}
+
+/* The module function of one basic gate over its current input values. */
+uint8_t o1_calculate_signal(int type, const uint8_t *in) {
+    switch (type) {
+    case T_BUF: return z_as_x(in[0]);
+    case T_NOT: return logic_not(in[0]);
+    case T_AND2: return TABLE1_AND[in[0]][in[1]];
+    case T_OR2: return TABLE1_OR[in[0]][in[1]];
+    case T_NAND2: return logic_not(TABLE1_AND[in[0]][in[1]]);
+    case T_NOR2: return logic_not(TABLE1_OR[in[0]][in[1]]);
+    case T_XOR2: return TABLE1_XOR[in[0]][in[1]];
+    case T_XNOR2: return logic_not(TABLE1_XOR[in[0]][in[1]]);
+    case T_AND3: return TABLE1_AND[TABLE1_AND[in[0]][in[1]]][in[2]];
+    case T_AND4: return TABLE1_AND[TABLE1_AND[TABLE1_AND[in[0]][in[1]]][in[2]]][in[3]];
+    case T_OR4: return TABLE1_OR[TABLE1_OR[TABLE1_OR[in[0]][in[1]]][in[2]]][in[3]];
+    case T_MUX2: {
+        uint8_t d0 = z_as_x(in[0]), d1 = z_as_x(in[1]), s = z_as_x(in[2]);
+        if (s == 0) return d0;
+        if (s == 1) return d1;
+        return d0 == d1 ? d0 : O1_X;
+    }
+    }
+    return O1_X;
+}
+
+/* ---- A growable waveform: parallel arrays of times and values. ---------- */
+typedef struct {
+    int64_t *t;
+    uint8_t *v;
+    int64_t n, cap;
+} o1_wave;
+
+static int wave_push(o1_wave *w, uint8_t v, int64_t t) {
+    if (w->n == w->cap) {
+        int64_t cap = w->cap ? 2 * w->cap : 16;
+        int64_t *nt = (int64_t *)realloc(w->t, (size_t)cap * sizeof(int64_t));
+        if (!nt) return -1;
+        w->t = nt;
+        uint8_t *nv = (uint8_t *)realloc(w->v, (size_t)cap);
+        if (!nv) return -1;
+        w->v = nv;
+        w->cap = cap;
+    }
+    w->t[w->n] = t;
+    w->v[w->n] = v;
+    w->n++;
+    return 0;
+}
+
+/* Delay of one pin for a new output value (reduced delay model, see header). */
+static int64_t pin_delay(int32_t rise, int32_t fall, uint8_t out_value) {
+    if (out_value == 1) return rise;
+    if (out_value == 0) return fall;
+    return rise < fall ? rise : fall;
+}
+
+/* addSignalChange: Eq. 1 "glitch eaten", then the redundant drop of Fig. 3.
+ * Every entry already in `out` was determined at an earlier merge time, and
+ * the entries are in increasing appearance time, so the denied ones are the
+ * tail whose appearance time is >= t_r. */
+static int add_signal_change(o1_wave *out, uint8_t v, int64_t t_r) {
+    while (out->n > 0 && out->t[out->n - 1] >= t_r) out->n--;
+    uint8_t current = out->n > 0 ? out->v[out->n - 1] : O1_X;
+    if (v == current) return 0;
+    return wave_push(out, v, t_r);
+}
+
+/* Algorithm 2 for one single-output gate. `in_t[i]`, `in_v[i]`, `in_n[i]`
+ * are the waveform of input pin i. */
+int o1_process_cell(int type, const int64_t *const *in_t, const uint8_t *const *in_v,
+                    const int64_t *in_n, const int32_t *rise, const int32_t *fall,
+                    o1_wave *out) {
+    int k = arity_of(type);
+    uint8_t current_signals[4];
+    int64_t earliest_index[4];
+    int64_t earliest_timestamp[4];
+    int changed[4];
+    for (int i = 0; i < k; i++) {
+        current_signals[i] = O1_X;
+        earliest_index[i] = 0;
+        earliest_timestamp[i] = in_n[i] > 0 ? in_t[i][0] : O1_INF;
+    }
+    uint8_t previous_output = O1_X;
+    for (;;) {
+        int64_t t_earliest = O1_INF;
+        for (int i = 0; i < k; i++)
+            if (earliest_timestamp[i] < t_earliest) t_earliest = earliest_timestamp[i];
+        if (t_earliest == O1_INF) break;
+        for (int i = 0; i < k; i++) {
+            changed[i] = 0;
+            int64_t j = earliest_index[i];
+            if (earliest_timestamp[i] == t_earliest) {
+                current_signals[i] = in_v[i][j];
+                changed[i] = 1;
+                if (j + 1 == in_n[i]) {
+                    earliest_timestamp[i] = O1_INF;
+                } else {
+                    earliest_index[i] = j + 1;
+                    earliest_timestamp[i] = in_t[i][j + 1];
+                }
+            }
+        }
+        uint8_t new_output = o1_calculate_signal(type, current_signals);
+        if (new_output != previous_output) {
+            int64_t del = O1_INF;
+            for (int i = 0; i < k; i++) {
+                if (!changed[i]) continue; /* no edge on this pin: infinite delay */
+                int64_t d = pin_delay(rise[i], fall[i], new_output);
+                if (d < del) del = d;
+            }
+            if (add_signal_change(out, new_output, t_earliest + del)) return -1;
+        }
+        previous_output = new_output;
+    }
+    return 0;
+}
+
+/* ---- Whole circuit. ------------------------------------------------------ */
+typedef struct {
+    int64_t S, G;
+    o1_wave *gate_out; /* [G] */
+} o1_result;
+
+/* Kahn's algorithm over the gate graph; returns 0 and fills `order` with all
+ * gates, or -2 if the gates do not form a DAG. */
+static int topological_order(int64_t S, int64_t G, const int64_t *pin_off,
+                             const int64_t *pin_net, int64_t *order) {
+    int64_t *indeg = (int64_t *)calloc((size_t)(G ? G : 1), sizeof(int64_t));
+    int64_t *fo_cnt = (int64_t *)calloc((size_t)(G + 1), sizeof(int64_t));
+    if (!indeg || !fo_cnt) { free(indeg); free(fo_cnt); return -1; }
+    int64_t P = pin_off[G];
+    for (int64_t g = 0; g < G; g++)
+        for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++)
+            if (pin_net[p] >= S) { indeg[g]++; fo_cnt[pin_net[p] - S + 1]++; }
+    for (int64_t g = 0; g < G; g++) fo_cnt[g + 1] += fo_cnt[g];
+    int64_t *fo = (int64_t *)malloc((size_t)(P ? P : 1) * sizeof(int64_t));
+    int64_t *fill = (int64_t *)calloc((size_t)(G ? G : 1), sizeof(int64_t));
+    if (!fo || !fill) { free(indeg); free(fo_cnt); free(fo); free(fill); return -1; }
+    for (int64_t g = 0; g < G; g++)
+        for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++)
+            if (pin_net[p] >= S) {
+                int64_t d = pin_net[p] - S;
+                fo[fo_cnt[d] + fill[d]++] = g;
+            }
+    int64_t head = 0, tail = 0;
+    for (int64_t g = 0; g < G; g++)
+        if (indeg[g] == 0) order[tail++] = g;
+    while (head < tail) {
+        int64_t d = order[head++];
+        for (int64_t e = fo_cnt[d]; e < fo_cnt[d + 1]; e++)
+            if (--indeg[fo[e]] == 0) order[tail++] = fo[e];
+    }
+    free(indeg); free(fo_cnt); free(fo); free(fill);
+    return tail == G ? 0 : -2;
+}
+
+void o1_free(o1_result *r) {
+    if (!r) return;
+    for (int64_t g = 0; g < r->G; g++) { free(r->gate_out[g].t); free(r->gate_out[g].v); }
+    free(r->gate_out);
+    free(r);
+}
+
+/* Simulate the whole netlist. Returns NULL on a malformed netlist (cycle,
+ * bad arity, bad net id) or out of memory; *status receives the reason:
+ * -1 memory, -2 cycle, -3 malformed. */
+o1_result *o1_simulate(int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
+                       const int64_t *pin_net, const int32_t *rise, const int32_t *fall,
+                       const int64_t *src_off, const int64_t *src_t, const uint8_t *src_v,
+                       int *status) {
+    *status = 0;
+    for (int64_t g = 0; g < G; g++) {
+        if (type[g] >= T_COUNT || pin_off[g + 1] - pin_off[g] != arity_of(type[g])) {
+            *status = -3;
+            return NULL;
+        }
+        for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++)
+            if (pin_net[p] < 0 || pin_net[p] >= S + G || pin_net[p] == S + g) {
+                *status = -3;
+                return NULL;
+            }
+    }
+    o1_result *r = (o1_result *)calloc(1, sizeof(o1_result));
+    int64_t *order = (int64_t *)malloc((size_t)(G ? G : 1) * sizeof(int64_t));
+    if (!r || !order) { free(r); free(order); *status = -1; return NULL; }
+    r->S = S;
+    r->G = G;
+    r->gate_out = (o1_wave *)calloc((size_t)(G ? G : 1), sizeof(o1_wave));
+    if (!r->gate_out) { free(order); free(r); *status = -1; return NULL; }
+    int rc = topological_order(S, G, pin_off, pin_net, order);
+    if (rc) { free(order); o1_free(r); *status = rc; return NULL; }
+    for (int64_t idx = 0; idx < G; idx++) {
+        int64_t g = order[idx];
+        const int64_t *in_t[4];
+        const uint8_t *in_v[4];
+        int64_t in_n[4];
+        int k = arity_of(type[g]);
+        for (int i = 0; i < k; i++) {
+            int64_t net = pin_net[pin_off[g] + i];
+            if (net < S) {
+                in_t[i] = src_t + src_off[net];
+                in_v[i] = src_v + src_off[net];
+                in_n[i] = src_off[net + 1] - src_off[net];
+            } else {
+                o1_wave *w = &r->gate_out[net - S];
+                in_t[i] = w->t;
+                in_v[i] = w->v;
+                in_n[i] = w->n;
+            }
+        }
+        if (o1_process_cell(type[g], in_t, in_v, in_n, rise + pin_off[g], fall + pin_off[g],
+                            &r->gate_out[g])) {
+            free(order); o1_free(r); *status = -1; return NULL;
+        }
+    }
+    free(order);
+    return r;
+}
+
+/* Per-gate output lengths. */
+void o1_lengths(const o1_result *r, int64_t *len) {
+    for (int64_t g = 0; g < r->G; g++) len[g] = r->gate_out[g].n;
+}
+
+/* Copy all gate outputs into CSR arrays: off[G+1], t[off[G]], v[off[G]]. */
+void o1_copy(const o1_result *r, int64_t *off, int64_t *t, uint8_t *v) {
+    int64_t pos = 0;
+    for (int64_t g = 0; g < r->G; g++) {
+        off[g] = pos;
+        memcpy(t + pos, r->gate_out[g].t, (size_t)r->gate_out[g].n * sizeof(int64_t));
+        memcpy(v + pos, r->gate_out[g].v, (size_t)r->gate_out[g].n);
+        pos += r->gate_out[g].n;
+    }
+    off[r->G] = pos;
+}
+
+/* Single-gate entry point for unit tests of Algorithm 2. Writes at most `cap`
+ * entries; returns the output length, or -1 on error. */
+int64_t o1_gate(int type, const int64_t *const *in_t, const uint8_t *const *in_v,
+                const int64_t *in_n, const int32_t *rise, const int32_t *fall,
+                int64_t *out_t, uint8_t *out_v, int64_t cap) {
+    o1_wave w = {0, 0, 0, 0};
+    if (o1_process_cell(type, in_t, in_v, in_n, rise, fall, &w)) { free(w.t); free(w.v); return -1; }
+    int64_t n = w.n;
+    if (n <= cap) {
+        memcpy(out_t, w.t, (size_t)n * sizeof(int64_t));
+        memcpy(out_v, w.v, (size_t)n);
+    }
+    free(w.t);
+    free(w.v);
+    return n;
+}

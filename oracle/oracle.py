@@ -1,0 +1,347 @@
+"""CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module. It shares no code with the HIP library
+(``paper_2304_13398_amd``) and never imports it; the only thing both sides see
+is the arrays drawn by ``paper_2304_13398_amd.workloads``.
+
+Three independent formulations of the same result (all in plain code):
+
+* **O1** (``o1.c``, called through ctypes): Algorithm 2 per gate with the
+  Eq. 1 "glitch eaten" rule and the redundant-transition drop of Fig. 3, gates
+  in a topological order. This is the parity authority for the GPU.
+* **O2** (``o2_simulate``, pure Python): a global discrete-event simulator. A
+  time-ordered agenda; at each time the gates are visited in level order, each
+  gate is evaluated if one of its inputs changed at that time (scheduling its
+  new transition with the Eq. 1 denial and the Fig. 3 drop against its pending
+  list), then its pending transition due at that time, if any, is applied to
+  its output net.
+* **O3** (``o3_simulate``, pure Python, tiny inputs only): the dense-time
+  definition. Every net has a value y(T) at every integer T (X before its first
+  transition). A gate's candidate transitions are the times where its
+  evaluated value changes, each with appearance time T + the minimum delay
+  over the pins whose value changed at T; the output at T is the value of the
+  last-determined candidate whose appearance time is <= T. (Eq. 1 denies
+  exactly the candidates that a later-determined one overtakes, and the Fig. 3
+  drop does not change the value function, so this is the same waveform.)
+
+The gate functions in this file use the possibility reading of Section 2.2
+(X may be 0 or 1, Z is read as X): a gate's result is 0 or 1 when every
+combination of possible input values gives that result, X otherwise. It is a
+different formulation from the table look-ups of ``o1.c``; both are pinned to
+Table 1 by the tests.
+
+Parity unpinned by the paper: MUX2 (not in the paper), the delay of a
+transition to X (min of rise and fall), and 3/4-input types beyond what
+associativity of Table 1 fixes. See the module docstring of ``o1.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import heapq
+import itertools
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libo1.so")
+SRC = os.path.join(HERE, "o1.c")
+
+X, Z = 2, 3
+BUF, NOT, AND2, OR2, NAND2, NOR2, XOR2, XNOR2, AND3, MUX2, AND4, OR4 = range(12)
+ARITY = (1, 1, 2, 2, 2, 2, 2, 2, 3, 3, 4, 4)
+
+
+# ---------------------------------------------------------------------------
+# Build and load O1.
+
+def build(force: bool = True, src: str = SRC, out: str = LIB, extra=()) -> str:
+    """Compile ``o1.c`` with gcc into a shared library (plain -O2)."""
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", *extra, "-o", tmp, src])
+        os.replace(tmp, out)
+    return out
+
+
+class _O1:
+    def __init__(self, path):
+        lib = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        lib.o1_simulate.restype = P
+        lib.o1_simulate.argtypes = [i64, i64, P, P, P, P, P, P, P, P, ctypes.POINTER(ctypes.c_int)]
+        lib.o1_lengths.argtypes = [P, P]
+        lib.o1_copy.argtypes = [P, P, P, P]
+        lib.o1_free.argtypes = [P]
+        lib.o1_gate.restype = i64
+        lib.o1_gate.argtypes = [ctypes.c_int, P, P, P, P, P, P, P, i64]
+        lib.o1_calculate_signal.restype = ctypes.c_uint8
+        lib.o1_calculate_signal.argtypes = [ctypes.c_int, P]
+        self.lib = lib
+
+
+_o1_cache = {}
+
+
+def o1_lib(path: str | None = None) -> _O1:
+    path = path or LIB
+    if path not in _o1_cache:
+        if path == LIB and not os.path.exists(LIB):
+            build(force=False)
+        _o1_cache[path] = _O1(path)
+    return _o1_cache[path]
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def o1_simulate(nl, st, lib: str | None = None):
+    """O1 on a whole netlist. Returns (off[G+1], t, v): gate g's waveform is
+    t[off[g]:off[g+1]], v[off[g]:off[g+1]]."""
+    L = o1_lib(lib).lib
+    type_ = np.ascontiguousarray(nl.type, dtype=np.uint8)
+    pin_off = np.ascontiguousarray(nl.pin_off, dtype=np.int64)
+    pin_net = np.ascontiguousarray(nl.pin_net, dtype=np.int64)
+    rise = np.ascontiguousarray(nl.rise, dtype=np.int32)
+    fall = np.ascontiguousarray(nl.fall, dtype=np.int32)
+    soff = np.ascontiguousarray(st.off, dtype=np.int64)
+    st_t = np.ascontiguousarray(st.t, dtype=np.int64)
+    st_v = np.ascontiguousarray(st.v, dtype=np.uint8)
+    status = ctypes.c_int(0)
+    h = L.o1_simulate(nl.S, nl.G, _ptr(type_), _ptr(pin_off), _ptr(pin_net), _ptr(rise),
+                      _ptr(fall), _ptr(soff), _ptr(st_t), _ptr(st_v), ctypes.byref(status))
+    if not h:
+        raise OracleError({-1: "out of memory", -2: "cycle", -3: "malformed netlist"}
+                          .get(status.value, str(status.value)))
+    try:
+        ln = np.empty(nl.G, dtype=np.int64)
+        L.o1_lengths(h, _ptr(ln))
+        n = int(ln.sum())
+        off = np.empty(nl.G + 1, dtype=np.int64)
+        t = np.empty(n, dtype=np.int64)
+        v = np.empty(n, dtype=np.uint8)
+        L.o1_copy(h, _ptr(off), _ptr(t), _ptr(v))
+    finally:
+        L.o1_free(h)
+    return off, t, v
+
+
+def o1_gate(gtype, waves, rise, fall, lib: str | None = None):
+    """O1 on one gate. ``waves`` = list of (times, values) per pin."""
+    L = o1_lib(lib).lib
+    k = ARITY[gtype]
+    assert len(waves) == k
+    ts = [np.ascontiguousarray(w[0], dtype=np.int64) for w in waves]
+    vs = [np.ascontiguousarray(w[1], dtype=np.uint8) for w in waves]
+    pt = (ctypes.c_void_p * 4)(*[t.ctypes.data for t in ts], *([0] * (4 - k)))
+    pv = (ctypes.c_void_p * 4)(*[v.ctypes.data for v in vs], *([0] * (4 - k)))
+    n = np.array([len(t) for t in ts] + [0] * (4 - k), dtype=np.int64)
+    r = np.ascontiguousarray(rise, dtype=np.int32)
+    f = np.ascontiguousarray(fall, dtype=np.int32)
+    cap = int(n.sum()) + 1
+    ot = np.empty(cap, dtype=np.int64)
+    ov = np.empty(cap, dtype=np.uint8)
+    m = L.o1_gate(gtype, ctypes.cast(pt, ctypes.c_void_p), ctypes.cast(pv, ctypes.c_void_p),
+                  _ptr(n), _ptr(r), _ptr(f), _ptr(ot), _ptr(ov), cap)
+    if m < 0:
+        raise OracleError("o1_gate failed")
+    return list(zip(ot[:m].tolist(), ov[:m].tolist()))
+
+
+def o1_eval(gtype, vals, lib: str | None = None) -> int:
+    """O1's gate function on one input combination."""
+    a = np.zeros(4, dtype=np.uint8)
+    a[:len(vals)] = vals
+    return int(o1_lib(lib).lib.o1_calculate_signal(gtype, _ptr(a)))
+
+
+# ---------------------------------------------------------------------------
+# Gate functions, possibility reading (Section 2.2).
+
+def _possible(v):
+    return (0,) if v == 0 else (1,) if v == 1 else (0, 1)   # X and Z: either level
+
+
+def _collapse(results):
+    s = set(results)
+    return s.pop() if len(s) == 1 else X
+
+
+_BOOL = {
+    BUF: lambda a: a[0],
+    NOT: lambda a: 1 - a[0],
+    AND2: lambda a: a[0] & a[1],
+    OR2: lambda a: a[0] | a[1],
+    NAND2: lambda a: 1 - (a[0] & a[1]),
+    NOR2: lambda a: 1 - (a[0] | a[1]),
+    XOR2: lambda a: a[0] ^ a[1],
+    XNOR2: lambda a: 1 - (a[0] ^ a[1]),
+    AND3: lambda a: a[0] & a[1] & a[2],
+    MUX2: lambda a: a[1] if a[2] else a[0],
+    AND4: lambda a: a[0] & a[1] & a[2] & a[3],
+    OR4: lambda a: a[0] | a[1] | a[2] | a[3],
+}
+
+
+def gate_eval(gtype, vals) -> int:
+    """Value of a gate: 0 or 1 if every combination of possible input levels
+    agrees, else X."""
+    f = _BOOL[gtype]
+    return _collapse(f(c) for c in itertools.product(*(_possible(v) for v in vals)))
+
+
+def pin_delay(rise, fall, value):
+    return rise if value == 1 else fall if value == 0 else min(rise, fall)
+
+
+# ---------------------------------------------------------------------------
+# Shared helpers of O2/O3 (structure only).
+
+def _levels(nl):
+    """Longest-path level of every gate (sources are level 0), by repeated
+    relaxation over the pins; raises on a cycle."""
+    S, G = nl.S, nl.G
+    lvl = np.zeros(S + G, dtype=np.int64)
+    for _ in range(G + 1):
+        changed = False
+        for g in range(G):
+            pins = nl.pin_net[nl.pin_off[g]:nl.pin_off[g + 1]]
+            want = 1 + max(int(lvl[p]) for p in pins)
+            if lvl[S + g] != want:
+                lvl[S + g] = want
+                changed = True
+        if not changed:
+            return lvl
+    raise OracleError("cycle")
+
+
+def _pins(nl, g):
+    a, b = int(nl.pin_off[g]), int(nl.pin_off[g + 1])
+    return ([int(x) for x in nl.pin_net[a:b]], [int(x) for x in nl.rise[a:b]],
+            [int(x) for x in nl.fall[a:b]])
+
+
+def _source_waves(st, S):
+    return [list(zip(st.t[st.off[s]:st.off[s + 1]].tolist(),
+                     st.v[st.off[s]:st.off[s + 1]].tolist())) for s in range(S)]
+
+
+# ---------------------------------------------------------------------------
+# O2: global discrete-event simulation.
+
+def o2_simulate(nl, st):
+    """Returns a list of G waveforms, each a list of (time, value)."""
+    S, G = nl.S, nl.G
+    lvl = _levels(nl)
+    order = sorted(range(G), key=lambda g: (lvl[S + g], g))
+    fanout = [[] for _ in range(S + G)]
+    pins = [_pins(nl, g) for g in range(G)]
+    for g in range(G):
+        for p in pins[g][0]:
+            fanout[p].append(g)
+    value = [X] * (S + G)           # committed value of every net
+    last_eval = [X] * G             # previous evaluated output of every gate
+    pending = [[] for _ in range(G)]  # scheduled (time, value), increasing time
+    out = [[] for _ in range(G)]
+    agenda = []                     # heap of times at which something may happen
+    src_events = {}
+    for s, w in enumerate(_source_waves(st, S)):
+        for t, v in w:
+            src_events.setdefault(t, []).append((s, v))
+            heapq.heappush(agenda, t)
+    seen = set()
+    while agenda:
+        T = heapq.heappop(agenda)
+        if T in seen:
+            continue
+        seen.add(T)
+        changed_nets = set()
+        for s, v in src_events.get(T, ()):
+            value[s] = v
+            changed_nets.add(s)
+        for g in order:
+            nets, rise, fall = pins[g]
+            hit = [i for i, n in enumerate(nets) if n in changed_nets]
+            if hit:
+                e = gate_eval(nl.type[g], [value[n] for n in nets])
+                if e != last_eval[g]:
+                    d = min(pin_delay(rise[i], fall[i], e) for i in hit)
+                    tr = T + d
+                    pend = pending[g]
+                    while pend and pend[-1][0] >= tr:      # Eq. 1
+                        pend.pop()
+                    proj = pend[-1][1] if pend else value[S + g]
+                    if e != proj:                           # Fig. 3 drop
+                        pend.append((tr, e))
+                        heapq.heappush(agenda, tr)
+                last_eval[g] = e
+            pend = pending[g]
+            if pend and pend[0][0] == T:
+                _, v = pend.pop(0)
+                value[S + g] = v
+                out[g].append((T, v))
+                changed_nets.add(S + g)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# O3: dense-time definition (tiny inputs only).
+
+def o3_simulate(nl, st, t_max=None):
+    S, G = nl.S, nl.G
+    lvl = _levels(nl)
+    srcw = _source_waves(st, S)
+    if t_max is None:
+        last = max([w[-1][0] for w in srcw if w] + [0])
+        dm = int(max(nl.rise.max(initial=0), nl.fall.max(initial=0)))
+        t_max = last + (int(lvl.max(initial=0)) + 1) * (dm + 1) + 1
+    n_t = t_max + 2                       # index 0 is time -1, index i is time i-1
+    y = np.full((S + G, n_t), X, dtype=np.int64)
+    for s, w in enumerate(srcw):
+        for t, v in w:
+            y[s, t + 1:] = v
+    order = sorted(range(G), key=lambda g: (lvl[S + g], g))
+    for g in order:
+        nets, rise, fall = _pins(nl, g)
+        gt = int(nl.type[g])
+        e = [X] + [gate_eval(gt, [int(y[n, i]) for n in nets]) for i in range(1, n_t)]
+        cands = []                         # (appearance time, value), in determination order
+        for i in range(1, n_t):
+            if e[i] != e[i - 1]:
+                ch = [k for k, n in enumerate(nets) if y[n, i] != y[n, i - 1]]
+                d = min(pin_delay(rise[k], fall[k], e[i]) for k in ch)
+                cands.append((i - 1 + d, e[i]))
+        for i in range(1, n_t):
+            T = i - 1
+            j = [c for c in cands if c[0] <= T]
+            y[S + g, i] = j[-1][1] if j else X
+    out = []
+    for g in range(G):
+        row = y[S + g]
+        out.append([(i - 1, int(row[i])) for i in range(1, n_t) if row[i] != row[i - 1]])
+    return out
+
+
+def combinational(nl, src_values):
+    """Textbook zero-delay evaluation: the value of every gate for one vector of
+    source values, gates in level order."""
+    S, G = nl.S, nl.G
+    lvl = _levels(nl)
+    val = list(src_values) + [X] * G
+    for g in sorted(range(G), key=lambda g: (lvl[S + g], g)):
+        nets, _, _ = _pins(nl, g)
+        val[S + g] = gate_eval(int(nl.type[g]), [val[n] for n in nets])
+    return val[S:]
+
+
+def csr_to_lists(off, t, v):
+    return [list(zip(t[off[g]:off[g + 1]].tolist(), v[off[g]:off[g + 1]].tolist()))
+            for g in range(len(off) - 1)]
