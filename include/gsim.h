@@ -1,0 +1,205 @@
+/*
+ * gsim.h -- C ABI of the MI355X timing-aware 4-value gate-level re-simulator.
+ *
+ * The library computes, for a combinational netlist of basic gates with
+ * per-pin rise/fall delays and the 0/1/X/Z waveforms of its source nets, the
+ * waveform of every gate output (the re-simulation objective of Section 2.1 of
+ * "Acceleration for Timing-Aware Gate-Level Logic Simulation with One-Pass GPU
+ * Parallelism"). Per gate it merges the input waveforms in time, evaluates the
+ * 4-value gate function (Section 2.2, Table 1; Z is read as X), takes the
+ * minimum delay over the pins that changed (Section 2.3, Fig. 2; Section 3.2),
+ * applies the "glitch eaten" denial of Eq. 1 and drops redundant transitions
+ * (Fig. 3) -- the output-waveform procedure of Algorithm 2. All levels of a
+ * job run on the GPU after one host-to-device transfer of the stimuli, and
+ * results stay in device memory until fetched (Section 3, one-pass
+ * parallelism).
+ *
+ * Conventions
+ *  - Values are uint8 codes: 0, 1, X = 2, Z = 3. Gate outputs are never Z.
+ *  - Times are int64 picoseconds in [0, 2^62); delays are int32 picoseconds
+ *    >= 0. Times are not clipped to a window.
+ *  - Nets [0, S) are sources (primary and pseudo-primary inputs); gate g
+ *    (0 <= g < G, in the caller's order) drives net S + g.
+ *  - A waveform is a list of (time, value) transitions with strictly
+ *    increasing times, no two equal consecutive values, and a first value
+ *    other than X: every net is X before its first transition.
+ *  - Delay model: a transition of the output to 1 uses the triggering pin's
+ *    rise delay, to 0 its fall delay, to X the smaller of the two; with
+ *    several pins changing at the same time the minimum over those pins wins.
+ *
+ * Errors: every call returns a gsim_status and never throws. On error no
+ * partial result is visible and sim_last_error() describes the failure.
+ * Ownership: every caller array is read (or copied) during the call and stays
+ * the caller's; device netlists belong to the context until unloaded; a job's
+ * results belong to the context until sim_release_job().
+ * Thread safety: one context may be used from one host thread at a time.
+ */
+#ifndef GSIM_H
+#define GSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gsim_ctx_s *gsim_ctx;
+typedef int64_t gsim_netlist; /* handle, > 0 */
+typedef int64_t gsim_job;     /* handle, > 0 */
+
+typedef enum {
+    GSIM_OK = 0,
+    GSIM_E_ARG = -1,       /* bad argument: null pointer, bad size, bad id, bad arity */
+    GSIM_E_CYCLE = -2,     /* the gates do not form a DAG */
+    GSIM_E_WAVEFORM = -3,  /* a source waveform breaks the waveform conventions */
+    GSIM_E_OOM = -4,       /* device memory budget exhausted (no partial result) */
+    GSIM_E_DEVICE = -5,    /* HIP runtime error or no usable device */
+    GSIM_E_HANDLE = -6,    /* unknown or already released handle */
+    GSIM_E_OVERFLOW = -7   /* a time plus the longest path delay would leave [0, 2^62) */
+} gsim_status;
+
+/* Gate types. Pin order in brackets. Table 1 gives AND, OR and XOR; NOT, BUF,
+ * NAND, NOR, XNOR and the 3/4-input AND/OR follow from it; MUX2 (not in the
+ * paper) selects d0 for s=0, d1 for s=1, and for an unknown select gives the
+ * data value if d0 and d1 agree, X otherwise. */
+enum gsim_gate_type {
+    GSIM_BUF = 0,   /* [a] */
+    GSIM_NOT = 1,   /* [a] */
+    GSIM_AND2 = 2,  /* [a b] */
+    GSIM_OR2 = 3,
+    GSIM_NAND2 = 4,
+    GSIM_NOR2 = 5,
+    GSIM_XOR2 = 6,
+    GSIM_XNOR2 = 7,
+    GSIM_AND3 = 8,  /* [a b c] */
+    GSIM_MUX2 = 9,  /* [d0 d1 s] */
+    GSIM_AND4 = 10, /* [a b c d] */
+    GSIM_OR4 = 11,
+    GSIM_NUM_TYPES = 12
+};
+
+/* Tunables, set with sim_set_option() on a context; they apply to later runs. */
+enum gsim_option {
+    /* Output storage per job, in transitions; 0 = automatic (see sim_run).
+     * A run that needs more ends with GSIM_E_OOM from sim_wait. */
+    GSIM_OPT_ARENA_TRANSITIONS = 1,
+    /* Evaluate-kernel choice: 0 = automatic (wavefront per gate; gates whose
+     * largest pin delay exceeds the wavefront kernel's window go to the lane
+     * kernel), 1 = lane-per-gate kernel for every gate. */
+    GSIM_OPT_KERNEL = 2,
+    /* Level loop: 0 = one stream-ordered launch chain per run, 1 = the chain
+     * captured once in a HIP graph and replayed. */
+    GSIM_OPT_LEVEL_LOOP = 3
+};
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Open a context on HIP device `device`. `hbm_budget_bytes` caps the device
+ * memory the context allocates (0 = 90% of the device's free memory). */
+gsim_status sim_create(int device, uint64_t hbm_budget_bytes, gsim_ctx *out);
+/* Release every netlist, job and buffer of the context. */
+gsim_status sim_destroy(gsim_ctx ctx);
+/* Message of the last failed call on `ctx` (or of the last failed
+ * context-free call when ctx is NULL); owned by the library, valid until the
+ * next call on the same context. Never NULL. */
+const char *sim_last_error(gsim_ctx ctx);
+gsim_status sim_set_option(gsim_ctx ctx, int option, int64_t value);
+
+/* ---- netlists ------------------------------------------------------------ */
+
+/* Validate, levelize and upload a netlist (host levelizer and CSR builder).
+ *   S, G     number of source nets and gates (S >= 1, G >= 0)
+ *   type     [G] gate types (enum gsim_gate_type)
+ *   pin_off  [G+1] gate g's pins are pin_off[g] .. pin_off[g+1]-1; pin_off[0]=0,
+ *            and each gate has exactly the arity of its type
+ *   pin_net  [P] net read by each pin, in [0, S+G) and never the gate's own net;
+ *            repeated nets on one gate are allowed
+ *   rise_ps, fall_ps [P] per-pin delays, >= 0
+ * Errors: GSIM_E_ARG (malformed), GSIM_E_CYCLE, GSIM_E_OOM, GSIM_E_DEVICE. */
+gsim_status sim_load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type,
+                             const int64_t *pin_off, const int64_t *pin_net,
+                             const int32_t *rise_ps, const int32_t *fall_ps,
+                             gsim_netlist *out);
+gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl);
+
+typedef struct {
+    int64_t S, G, P;
+    int32_t levels;          /* longest path length in gates (0 if G = 0) */
+    int32_t max_delay_ps;    /* largest pin delay */
+    int64_t max_path_delay;  /* largest sum of per-gate largest delays along a path */
+    int64_t lane_gates;      /* gates routed to the lane-per-gate kernel */
+} gsim_netlist_info;
+gsim_status sim_netlist_info(gsim_ctx ctx, gsim_netlist nl, gsim_netlist_info *out);
+
+/* ---- runs ----------------------------------------------------------------- */
+
+/* Start one re-simulation of `nl` over host-resident source waveforms:
+ *   src_off [S+1] source s's transitions are t/v[src_off[s] .. src_off[s+1]-1]
+ *   t [N_in], v [N_in] with N_in = src_off[S]
+ * The stimuli are validated and copied to the device (one transfer), then every
+ * level runs on `hip_stream` (a hipStream_t; NULL = the context's stream)
+ * without host synchronisation. Returns after enqueueing. Output storage is
+ * GSIM_OPT_ARENA_TRANSITIONS, or by default an estimate of twice the pin-read
+ * volume of an input-length-preserving circuit, capped by the budget.
+ * Errors: GSIM_E_ARG, GSIM_E_WAVEFORM, GSIM_E_OVERFLOW, GSIM_E_OOM, GSIM_E_HANDLE. */
+gsim_status sim_run(gsim_ctx ctx, gsim_netlist nl, const int64_t *src_off, const int64_t *t,
+                    const uint8_t *v, void *hip_stream, gsim_job *out);
+
+/* As sim_run, but the three arrays are device pointers (e.g. owned by PyTorch)
+ * holding N_in = src_off[S] transitions; the caller keeps them alive and
+ * unmodified until the job completes. They are validated on the host only if
+ * `validate` is non-zero (one device-to-host copy); otherwise the caller
+ * guarantees the waveform conventions. */
+gsim_status sim_run_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_off,
+                           const int64_t *d_t, const uint8_t *d_v, int64_t n_in,
+                           int validate, void *hip_stream, gsim_job *out);
+
+/* Block until the job's device work is done. GSIM_E_OOM if its output storage
+ * overflowed (the job then holds no results). */
+gsim_status sim_wait(gsim_ctx ctx, gsim_job job);
+
+typedef struct {
+    int64_t n_in;            /* source transitions */
+    int64_t n_out;           /* output transitions over all gates */
+    int64_t pin_reads;       /* sum over gates and pins of the read waveform's length */
+    int64_t arena_used;      /* transitions of output storage reserved */
+    int64_t arena_capacity;
+    double device_ms;        /* device time of the level chain (HIP events) */
+} gsim_job_stats;
+/* Statistics of a finished job (waits for it). */
+gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out);
+
+/* Copy waveforms of a finished job to host memory.
+ *   nets  [n] net ids to fetch (sources included); NULL = all S+G nets in id order
+ *   out_off [n+1] receives offsets into out_t/out_v (out_off[0] = 0)
+ *   out_t, out_v: capacity `cap` transitions; if out_t is NULL only out_off is
+ *   filled (size query). GSIM_E_ARG if cap < out_off[n]. */
+gsim_status sim_fetch_waveforms(gsim_ctx ctx, gsim_job job, const int64_t *nets, int64_t n,
+                                int64_t *out_off, int64_t *out_t, uint8_t *out_v, int64_t cap);
+
+/* Free a job's device storage. */
+gsim_status sim_release_job(gsim_ctx ctx, gsim_job job);
+
+/* ---- host-only helpers (no device needed) ----------------------------------- */
+
+/* The levelizer of sim_load_netlist: level[g] = 1 + max level of its input
+ * nets (sources are level 0). Same validation and errors as sim_load_netlist
+ * (ctx-free: read the message with sim_last_error(NULL)). */
+gsim_status sim_levelize(int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
+                         const int64_t *pin_net, const int32_t *rise_ps, const int32_t *fall_ps,
+                         int32_t *level_out, int32_t *n_levels_out);
+
+/* Check source waveforms against the conventions above and the time range
+ * needed by a netlist whose longest path delay is `max_path_delay`.
+ * GSIM_E_WAVEFORM or GSIM_E_OVERFLOW with the first offending source named in
+ * sim_last_error(NULL). */
+gsim_status sim_validate_stimulus(int64_t S, const int64_t *src_off, const int64_t *t,
+                                  const uint8_t *v, int64_t max_path_delay);
+
+/* Library version string. */
+const char *sim_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSIM_H */

@@ -1,0 +1,908 @@
+// Host runtime of libgsim: validation, levelizer, netlist upload, device
+// memory pool, the per-job level chain, and waveform fetch. Exposes the C ABI
+// declared in include/gsim.h.
+#include "gsim.h"
+#include "gsim_internal.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+using namespace gsim;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Errors.
+
+std::mutex g_err_mu;
+std::string g_err;  // last error of a context-free call
+
+struct Failure {
+    gsim_status st;
+    std::string msg;
+};
+
+Failure fail(gsim_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return Failure{st, buf};
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess)                                                               \
+            return fail(GSIM_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e));      \
+    } while (0)
+
+const Failure kOk{GSIM_OK, ""};
+
+// ---------------------------------------------------------------------------
+// Gate functions for the device look-up table.
+//
+// A 4-value signal is held as the pair (can be 0, can be 1): 0 = (1,0),
+// 1 = (0,1), X and Z = (1,1) -- X may be either level and Z is read as X
+// (Section 2.2). AND can be 1 only if every input can be 1 and can be 0 if any
+// can; OR is the dual; XOR is unknown if any input is, else the parity;
+// NOT swaps the pair; MUX2 can take a level if a select level that is possible
+// leads to a data input that can take it.
+struct Pair {
+    bool c0, c1;
+};
+Pair pair_of(int v) { return v == 0 ? Pair{true, false} : v == 1 ? Pair{false, true} : Pair{true, true}; }
+uint8_t value_of(Pair p) { return (p.c0 && p.c1) ? kX : (p.c1 ? 1 : 0); }
+
+const int kArity[GSIM_NUM_TYPES] = {1, 1, 2, 2, 2, 2, 2, 2, 3, 3, 4, 4};
+
+uint8_t gate_value(int type, const int *in) {
+    Pair a[kMaxPins];
+    for (int i = 0; i < kArity[type]; i++) a[i] = pair_of(in[i]);
+    auto all1 = [&](int k) { bool r = true; for (int i = 0; i < k; i++) r = r && a[i].c1; return r; };
+    auto any1 = [&](int k) { bool r = false; for (int i = 0; i < k; i++) r = r || a[i].c1; return r; };
+    auto all0 = [&](int k) { bool r = true; for (int i = 0; i < k; i++) r = r && a[i].c0; return r; };
+    auto any0 = [&](int k) { bool r = false; for (int i = 0; i < k; i++) r = r || a[i].c0; return r; };
+    auto neg = [](Pair p) { return Pair{p.c1, p.c0}; };
+    auto parity = [&](int k) {
+        bool unknown = false;
+        int ones = 0;
+        for (int i = 0; i < k; i++) {
+            unknown = unknown || (a[i].c0 && a[i].c1);
+            ones += a[i].c1 ? 1 : 0;
+        }
+        if (unknown) return Pair{true, true};
+        return (ones & 1) ? Pair{false, true} : Pair{true, false};
+    };
+    Pair r{true, true};
+    switch (type) {
+    case GSIM_BUF: r = a[0]; break;
+    case GSIM_NOT: r = neg(a[0]); break;
+    case GSIM_AND2: r = Pair{any0(2), all1(2)}; break;
+    case GSIM_OR2: r = Pair{all0(2), any1(2)}; break;
+    case GSIM_NAND2: r = neg(Pair{any0(2), all1(2)}); break;
+    case GSIM_NOR2: r = neg(Pair{all0(2), any1(2)}); break;
+    case GSIM_XOR2: r = parity(2); break;
+    case GSIM_XNOR2: r = neg(parity(2)); break;
+    case GSIM_AND3: r = Pair{any0(3), all1(3)}; break;
+    case GSIM_AND4: r = Pair{any0(4), all1(4)}; break;
+    case GSIM_OR4: r = Pair{all0(4), any1(4)}; break;
+    case GSIM_MUX2: {
+        const Pair d0 = a[0], d1 = a[1], s = a[2];
+        r = Pair{(s.c0 && d0.c0) || (s.c1 && d1.c0), (s.c0 && d0.c1) || (s.c1 && d1.c1)};
+        break;
+    }
+    }
+    return value_of(r);
+}
+
+// [type][packed] with pin i's value in bits 2i..2i+1; bits of absent pins are ignored.
+std::vector<uint8_t> build_lut() {
+    std::vector<uint8_t> lut(GSIM_NUM_TYPES * 256);
+    for (int t = 0; t < GSIM_NUM_TYPES; t++)
+        for (int packed = 0; packed < 256; packed++) {
+            int in[kMaxPins];
+            for (int i = 0; i < kMaxPins; i++) in[i] = (packed >> (2 * i)) & 3;
+            lut[t * 256 + packed] = gate_value(t, in);
+        }
+    return lut;
+}
+
+// ---------------------------------------------------------------------------
+// Netlist validation and levelization (host).
+
+struct Levelized {
+    std::vector<int32_t> level;  // [G], >= 1
+    int32_t n_levels = 0;
+    int32_t max_delay = 0;
+    int64_t max_path_delay = 0;
+};
+
+Failure levelize(int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
+                 const int64_t *pin_net, const int32_t *rise, const int32_t *fall, Levelized *out) {
+    if (S < 0 || G < 0) return fail(GSIM_E_ARG, "S and G must be >= 0 (S=%lld G=%lld)", (long long)S, (long long)G);
+    if (S + G > INT32_MAX) return fail(GSIM_E_ARG, "S + G exceeds 2^31-1 nets");
+    if (G > 0 && (!type || !pin_off || !pin_net || !rise || !fall))
+        return fail(GSIM_E_ARG, "null netlist array");
+    if (G > 0 && pin_off[0] != 0) return fail(GSIM_E_ARG, "pin_off[0] must be 0");
+    for (int64_t g = 0; g < G; g++) {
+        if (type[g] >= GSIM_NUM_TYPES) return fail(GSIM_E_ARG, "gate %lld: unknown type %d", (long long)g, type[g]);
+        const int64_t k = pin_off[g + 1] - pin_off[g];
+        if (k != kArity[type[g]])
+            return fail(GSIM_E_ARG, "gate %lld: %lld pins, type %d needs %d", (long long)g, (long long)k,
+                        type[g], kArity[type[g]]);
+    }
+    const int64_t P = G > 0 ? pin_off[G] : 0;
+    int32_t max_delay = 0;
+    for (int64_t g = 0; g < G; g++)
+        for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++) {
+            const int64_t n = pin_net[p];
+            if (n < 0 || n >= S + G) return fail(GSIM_E_ARG, "pin %lld: net %lld out of range", (long long)p, (long long)n);
+            if (n == S + g) return fail(GSIM_E_CYCLE, "gate %lld reads its own output", (long long)g);
+            if (rise[p] < 0 || fall[p] < 0) return fail(GSIM_E_ARG, "pin %lld: negative delay", (long long)p);
+            max_delay = std::max(max_delay, std::max(rise[p], fall[p]));
+        }
+    // Kahn's algorithm over gate-to-gate edges.
+    std::vector<int64_t> indeg(G, 0), fo_start(G + 1, 0);
+    for (int64_t p = 0; p < P; p++)
+        if (pin_net[p] >= S) fo_start[pin_net[p] - S + 1]++;
+    for (int64_t g = 0; g < G; g++) fo_start[g + 1] += fo_start[g];
+    std::vector<int64_t> fo(fo_start[G]);
+    {
+        std::vector<int64_t> fill(fo_start.begin(), fo_start.end() - 1);
+        for (int64_t g = 0; g < G; g++)
+            for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++)
+                if (pin_net[p] >= S) {
+                    indeg[g]++;
+                    fo[fill[pin_net[p] - S]++] = g;
+                }
+    }
+    out->level.assign(G, 1);
+    std::vector<int64_t> path(G, 0);  // longest sum of per-gate max delays ending at g
+    std::vector<int64_t> queue;
+    queue.reserve(G);
+    for (int64_t g = 0; g < G; g++)
+        if (indeg[g] == 0) queue.push_back(g);
+    int32_t nl = 0;
+    int64_t mpd = 0;
+    for (size_t h = 0; h < queue.size(); h++) {
+        const int64_t g = queue[h];
+        int32_t dm = 0;
+        for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++) dm = std::max(dm, std::max(rise[p], fall[p]));
+        path[g] += dm;
+        nl = std::max(nl, out->level[g]);
+        mpd = std::max(mpd, path[g]);
+        for (int64_t e = fo_start[g]; e < fo_start[g + 1]; e++) {
+            const int64_t c = fo[e];
+            out->level[c] = std::max(out->level[c], out->level[g] + 1);
+            path[c] = std::max(path[c], path[g]);
+            if (--indeg[c] == 0) queue.push_back(c);
+        }
+    }
+    if ((int64_t)queue.size() != G)
+        return fail(GSIM_E_CYCLE, "netlist has a cycle (%lld of %lld gates ordered)", (long long)queue.size(), (long long)G);
+    out->n_levels = nl;
+    out->max_delay = max_delay;
+    out->max_path_delay = mpd;
+    return kOk;
+}
+
+Failure validate_stimulus(int64_t S, const int64_t *src_off, const int64_t *t, const uint8_t *v,
+                          int64_t max_path_delay) {
+    if (!src_off) return fail(GSIM_E_ARG, "null src_off");
+    if (src_off[0] != 0) return fail(GSIM_E_WAVEFORM, "src_off[0] must be 0");
+    const int64_t limit = kTimeLimit - max_path_delay;
+    for (int64_t s = 0; s < S; s++) {
+        const int64_t a = src_off[s], b = src_off[s + 1];
+        if (b < a) return fail(GSIM_E_WAVEFORM, "source %lld: negative length", (long long)s);
+        if (b > a && (!t || !v)) return fail(GSIM_E_ARG, "null t or v");
+        uint8_t prev = kX;
+        for (int64_t i = a; i < b; i++) {
+            if (v[i] > 3) return fail(GSIM_E_WAVEFORM, "source %lld: value %d at index %lld", (long long)s, v[i], (long long)i);
+            if (v[i] == prev)
+                return fail(GSIM_E_WAVEFORM, "source %lld: value %d repeats the previous one (or a leading X) at index %lld",
+                            (long long)s, v[i], (long long)i);
+            if (t[i] < 0) return fail(GSIM_E_WAVEFORM, "source %lld: negative time", (long long)s);
+            if (i > a && t[i] <= t[i - 1])
+                return fail(GSIM_E_WAVEFORM, "source %lld: times not strictly increasing at index %lld", (long long)s, (long long)i);
+            if (t[i] >= limit)
+                return fail(GSIM_E_OVERFLOW, "source %lld: time %lld plus the longest path delay %lld leaves [0, 2^62)",
+                            (long long)s, (long long)t[i], (long long)max_path_delay);
+            prev = v[i];
+        }
+    }
+    return kOk;
+}
+
+// ---------------------------------------------------------------------------
+// Device memory: a budgeted caching pool. Released blocks are kept for reuse
+// and only returned to HIP when the budget needs room.
+
+class Pool {
+  public:
+    explicit Pool(uint64_t budget) : budget_(budget) {}
+    ~Pool() { trim(); }
+
+    void *get(size_t bytes) {
+        bytes = round(bytes);
+        auto it = cache_.lower_bound(bytes);
+        if (it != cache_.end() && it->first <= bytes + bytes / 4 + (64u << 20)) {
+            void *p = it->second;
+            cached_ -= it->first;
+            live_ += it->first;
+            sizes_[p] = it->first;
+            cache_.erase(it);
+            return p;
+        }
+        if (live_ + cached_ + bytes > budget_) trim();
+        if (live_ + bytes > budget_) return nullptr;
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            trim();
+            if (hipMalloc(&p, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+        }
+        live_ += bytes;
+        sizes_[p] = bytes;
+        return p;
+    }
+    void put(void *p) {
+        if (!p) return;
+        auto it = sizes_.find(p);
+        if (it == sizes_.end()) return;
+        live_ -= it->second;
+        cached_ += it->second;
+        cache_.emplace(it->second, p);
+        sizes_.erase(it);
+    }
+    void trim() {
+        for (auto &kv : cache_) (void)hipFree(kv.second);
+        cache_.clear();
+        cached_ = 0;
+    }
+    uint64_t budget() const { return budget_; }
+    uint64_t live() const { return live_; }
+
+  private:
+    static size_t round(size_t b) { return (b + (2u << 20) - 1) & ~size_t((2u << 20) - 1); }
+    uint64_t budget_, live_ = 0, cached_ = 0;
+    std::multimap<size_t, void *> cache_;
+    std::unordered_map<void *, size_t> sizes_;
+};
+
+// ---------------------------------------------------------------------------
+
+struct LevelRange {
+    int64_t begin, n_wave, n_lane;  // gates [begin, begin+n_wave) wave kernel, then n_lane lane kernel
+};
+
+struct Netlist {
+    int64_t S = 0, G = 0, P = 0;
+    int32_t n_levels = 0, max_delay = 0;
+    int64_t max_path_delay = 0;
+    int64_t lane_gates = 0;
+    std::vector<LevelRange> levels;
+    std::vector<int64_t> internal_of_user;  // [G]
+    std::vector<int64_t> arity_sum_level;   // unused reserve
+    GateRec *d_rec = nullptr;
+    int64_t max_level_blocks = 0;
+    int kernel_mode = 0;
+};
+
+struct Job {
+    int64_t nl_id = 0;
+    Netlist *nl = nullptr;
+    hipStream_t stream = nullptr;
+    int64_t n_in = 0, capacity = 0;
+    int64_t *d_off = nullptr, *d_len = nullptr, *d_blocksum = nullptr, *d_partial = nullptr;
+    int64_t *d_src_off = nullptr;
+    int64_t *d_T = nullptr;
+    uint8_t *d_V = nullptr;
+    DevState *d_state = nullptr;
+    DevState *h_state = nullptr;  // pinned
+    hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_done = nullptr;
+    bool waited = false, failed = false;
+    int64_t n_partial = 0;
+};
+
+}  // namespace
+
+struct gsim_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::unique_ptr<Pool> pool;
+    uint8_t *d_lut = nullptr;
+    std::string err;
+    int64_t next_id = 1;
+    std::map<int64_t, std::unique_ptr<Netlist>> netlists;
+    std::map<int64_t, std::unique_ptr<Job>> jobs;
+    int64_t opt_arena = 0;
+    int opt_kernel = 0;
+    int opt_level_loop = 0;
+};
+
+namespace {
+
+gsim_status record(gsim_ctx ctx, const Failure &f) {
+    if (f.st != GSIM_OK) {
+        if (ctx) {
+            ctx->err = f.msg;
+        } else {
+            std::lock_guard<std::mutex> lk(g_err_mu);
+            g_err = f.msg;
+        }
+    }
+    return f.st;
+}
+
+Failure set_device(gsim_ctx ctx) {
+    HIP_TRY(hipSetDevice(ctx->device));
+    return kOk;
+}
+
+void free_job_buffers(gsim_ctx ctx, Job *j) {
+    Pool &pool = *ctx->pool;
+    pool.put(j->d_off);
+    pool.put(j->d_len);
+    pool.put(j->d_blocksum);
+    pool.put(j->d_partial);
+    pool.put(j->d_src_off);
+    pool.put(j->d_T);
+    pool.put(j->d_V);
+    pool.put(j->d_state);
+    j->d_off = j->d_len = j->d_blocksum = j->d_partial = j->d_src_off = nullptr;
+    j->d_T = nullptr;
+    j->d_V = nullptr;
+    j->d_state = nullptr;
+}
+
+void destroy_job(gsim_ctx ctx, Job *j) {
+    if (j->ev_done) (void)hipEventSynchronize(j->ev_done);
+    free_job_buffers(ctx, j);
+    if (j->h_state) (void)hipHostFree(j->h_state);
+    if (j->ev_start) (void)hipEventDestroy(j->ev_start);
+    if (j->ev_end) (void)hipEventDestroy(j->ev_end);
+    if (j->ev_done) (void)hipEventDestroy(j->ev_done);
+    j->h_state = nullptr;
+    j->ev_start = j->ev_end = j->ev_done = nullptr;
+}
+
+Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
+                     const int64_t *pin_net, const int32_t *rise, const int32_t *fall, gsim_netlist *out) {
+    if (!out) return fail(GSIM_E_ARG, "null output handle");
+    Levelized lv;
+    Failure f = levelize(S, G, type, pin_off, pin_net, rise, fall, &lv);
+    if (f.st != GSIM_OK) return f;
+    auto nl = std::make_unique<Netlist>();
+    nl->S = S;
+    nl->G = G;
+    nl->P = G > 0 ? pin_off[G] : 0;
+    nl->n_levels = lv.n_levels;
+    nl->max_delay = lv.max_delay;
+    nl->max_path_delay = lv.max_path_delay;
+    nl->kernel_mode = ctx->opt_kernel;
+
+    // Gate order: by level; inside a level, wavefront-kernel gates first, then
+    // lane-kernel gates (largest pin delay beyond the wavefront window, or all
+    // gates when the lane kernel is forced), each in the caller's order.
+    auto gate_dmax = [&](int64_t g) {
+        int32_t d = 0;
+        for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++) d = std::max(d, std::max(rise[p], fall[p]));
+        return d;
+    };
+    auto is_lane = [&](int64_t g) { return ctx->opt_kernel == 1 || gate_dmax(g) > kCarryCap; };
+    const int32_t L = lv.n_levels;
+    std::vector<int64_t> cnt(2 * (size_t)L + 2, 0);
+    for (int64_t g = 0; g < G; g++) cnt[2 * (size_t)lv.level[g] + (is_lane(g) ? 1 : 0)]++;
+    std::vector<int64_t> start(cnt.size() + 1, 0);
+    for (size_t i = 0; i < cnt.size(); i++) start[i + 1] = start[i] + cnt[i];
+    nl->levels.resize(L);
+    for (int32_t l = 1; l <= L; l++) {
+        LevelRange &r = nl->levels[l - 1];
+        r.begin = start[2 * (size_t)l];
+        r.n_wave = cnt[2 * (size_t)l];
+        r.n_lane = cnt[2 * (size_t)l + 1];
+        nl->lane_gates += r.n_lane;
+        nl->max_level_blocks = std::max(nl->max_level_blocks, (r.n_wave + r.n_lane + kSizeBlock - 1) / kSizeBlock);
+    }
+    nl->internal_of_user.resize(G);
+    {
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t g = 0; g < G; g++)
+            nl->internal_of_user[g] = fill[2 * (size_t)lv.level[g] + (is_lane(g) ? 1 : 0)]++;
+    }
+    std::vector<GateRec> recs(G);
+    for (int64_t g = 0; g < G; g++) {
+        GateRec r;
+        std::memset(&r, 0, sizeof r);
+        r.type = type[g];
+        r.k = (uint8_t)(pin_off[g + 1] - pin_off[g]);
+        for (int i = 0; i < r.k; i++) {
+            const int64_t p = pin_off[g] + i;
+            const int64_t n = pin_net[p];
+            r.net[i] = (int32_t)(n < S ? n : S + nl->internal_of_user[n - S]);
+            r.rise[i] = rise[p];
+            r.fall[i] = fall[p];
+        }
+        r.dmax = gate_dmax(g);
+        r.user_gate = (int32_t)g;
+        recs[nl->internal_of_user[g]] = r;
+    }
+    f = set_device(ctx);
+    if (f.st != GSIM_OK) return f;
+    if (G > 0) {
+        nl->d_rec = (GateRec *)ctx->pool->get(sizeof(GateRec) * (size_t)G);
+        if (!nl->d_rec) return fail(GSIM_E_OOM, "no device memory for %lld gate records", (long long)G);
+        hipError_t e = hipMemcpy(nl->d_rec, recs.data(), sizeof(GateRec) * (size_t)G, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            ctx->pool->put(nl->d_rec);
+            return fail(GSIM_E_DEVICE, "netlist upload: %s", hipGetErrorString(e));
+        }
+    }
+    const int64_t id = ctx->next_id++;
+    ctx->netlists[id] = std::move(nl);
+    *out = id;
+    return kOk;
+}
+
+template <class T>
+T *pool_get(Pool &pool, int64_t n) {
+    return (T *)pool.get(sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+}
+
+// Enqueue the level chain of a job whose sources are already in the arena.
+Failure enqueue_levels(gsim_ctx ctx, Job *j) {
+    Netlist &nl = *j->nl;
+    hipStream_t s = j->stream;
+    HIP_TRY(launch_init_sources(j->d_src_off, nl.S, j->d_off, j->d_len, j->d_state, j->n_in, j->capacity, s));
+    HIP_TRY(hipEventRecord(j->ev_start, s));
+    EvalArgs a;
+    a.rec = nl.d_rec;
+    a.S = nl.S;
+    a.blockbase = j->d_blocksum;
+    a.off = j->d_off;
+    a.len = j->d_len;
+    a.T = j->d_T;
+    a.V = j->d_V;
+    a.state = j->d_state;
+    a.lut = ctx->d_lut;
+    for (const LevelRange &r : nl.levels) {
+        const int64_t n = r.n_wave + r.n_lane;
+        HIP_TRY(launch_size(nl.d_rec, r.begin, n, nl.S, j->d_len, j->d_off, j->d_blocksum, s));
+        HIP_TRY(launch_level_scan(j->d_blocksum, (n + kSizeBlock - 1) / kSizeBlock, j->d_state, s));
+        a.lvl_begin = r.begin;
+        a.g_begin = r.begin;
+        a.n = r.n_wave;
+        HIP_TRY(launch_eval_wave(a, s));
+        a.g_begin = r.begin + r.n_wave;
+        a.n = r.n_lane;
+        HIP_TRY(launch_eval_lane(a, s));
+    }
+    HIP_TRY(hipEventRecord(j->ev_end, s));
+    HIP_TRY(launch_count_out(j->d_len, nl.S, nl.G, j->d_partial, j->n_partial, j->d_state, s));
+    HIP_TRY(hipMemcpyAsync(j->h_state, j->d_state, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(j->ev_done, s));
+    return kOk;
+}
+
+int64_t default_capacity(const Netlist &nl, int64_t n_in) {
+    // Twice the pin-read volume of a circuit whose every net is as long as
+    // the mean source waveform, plus the sources.
+    const double mean = nl.S > 0 ? (double)n_in / (double)nl.S : 0.0;
+    const double est = (double)n_in + 2.0 * (double)nl.P * mean + 1024.0;
+    return (int64_t)std::min(est, 9.0e18);
+}
+
+Failure start_job(gsim_ctx ctx, gsim_netlist nlh, int64_t n_in, hipStream_t stream,
+                  std::unique_ptr<Job> &out) {
+    auto it = ctx->netlists.find(nlh);
+    if (it == ctx->netlists.end()) return fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nlh);
+    Netlist &nl = *it->second;
+    Failure f = set_device(ctx);
+    if (f.st != GSIM_OK) return f;
+    auto j = std::make_unique<Job>();
+    j->nl_id = nlh;
+    j->nl = &nl;
+    j->stream = stream ? stream : ctx->stream;
+    j->n_in = n_in;
+    Pool &pool = *ctx->pool;
+    const int64_t N = nl.S + nl.G;
+    j->n_partial = std::max<int64_t>(1, std::min<int64_t>(1024, (nl.G + 255) / 256));
+    j->d_off = pool_get<int64_t>(pool, N);
+    j->d_len = pool_get<int64_t>(pool, N);
+    j->d_blocksum = pool_get<int64_t>(pool, std::max<int64_t>(nl.max_level_blocks, 1));
+    j->d_partial = pool_get<int64_t>(pool, j->n_partial);
+    j->d_src_off = pool_get<int64_t>(pool, nl.S + 1);
+    j->d_state = pool_get<DevState>(pool, 1);
+    if (!j->d_off || !j->d_len || !j->d_blocksum || !j->d_partial || !j->d_src_off || !j->d_state) {
+        free_job_buffers(ctx, j.get());
+        return fail(GSIM_E_OOM, "no device memory for the job's per-net tables");
+    }
+    int64_t cap = ctx->opt_arena > 0 ? ctx->opt_arena : default_capacity(nl, n_in);
+    cap = std::max(cap, n_in);
+    if (ctx->opt_arena <= 0) {
+        // fit the automatic estimate into what the budget leaves
+        const uint64_t room = pool.budget() > pool.live() ? pool.budget() - pool.live() : 0;
+        const int64_t fit = (int64_t)(room / 9 * 95 / 100);
+        if (cap > fit) cap = std::max(n_in, fit - (4 << 20));
+    }
+    j->capacity = cap;
+    j->d_T = pool_get<int64_t>(pool, cap);
+    j->d_V = j->d_T ? pool_get<uint8_t>(pool, cap) : nullptr;
+    if (!j->d_T || !j->d_V) {
+        free_job_buffers(ctx, j.get());
+        return fail(GSIM_E_OOM, "no device memory for an output arena of %lld transitions", (long long)cap);
+    }
+    if (hipHostMalloc((void **)&j->h_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&j->ev_start) != hipSuccess || hipEventCreate(&j->ev_end) != hipSuccess ||
+        hipEventCreateWithFlags(&j->ev_done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        destroy_job(ctx, j.get());
+        return fail(GSIM_E_DEVICE, "event or pinned-memory creation failed");
+    }
+    out = std::move(j);
+    return kOk;
+}
+
+Failure run_host(gsim_ctx ctx, gsim_netlist nlh, const int64_t *src_off, const int64_t *t,
+                 const uint8_t *v, void *stream, gsim_job *out) {
+    if (!out || !src_off) return fail(GSIM_E_ARG, "null argument");
+    auto it = ctx->netlists.find(nlh);
+    if (it == ctx->netlists.end()) return fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nlh);
+    Netlist &nl = *it->second;
+    Failure f = validate_stimulus(nl.S, src_off, t, v, nl.max_path_delay);
+    if (f.st != GSIM_OK) return f;
+    const int64_t n_in = src_off[nl.S];
+    std::unique_ptr<Job> j;
+    f = start_job(ctx, nlh, n_in, (hipStream_t)stream, j);
+    if (f.st != GSIM_OK) return f;
+    hipStream_t s = j->stream;
+    auto cleanup = [&](Failure e) { destroy_job(ctx, j.get()); return e; };
+    if (hipMemcpyAsync(j->d_src_off, src_off, sizeof(int64_t) * (size_t)(nl.S + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+        (n_in > 0 && hipMemcpyAsync(j->d_T, t, sizeof(int64_t) * (size_t)n_in, hipMemcpyHostToDevice, s) != hipSuccess) ||
+        (n_in > 0 && hipMemcpyAsync(j->d_V, v, (size_t)n_in, hipMemcpyHostToDevice, s) != hipSuccess))
+        return cleanup(fail(GSIM_E_DEVICE, "stimulus upload: %s", hipGetErrorString(hipGetLastError())));
+    f = enqueue_levels(ctx, j.get());
+    if (f.st != GSIM_OK) return cleanup(f);
+    const int64_t id = ctx->next_id++;
+    ctx->jobs[id] = std::move(j);
+    *out = id;
+    return kOk;
+}
+
+Failure run_device(gsim_ctx ctx, gsim_netlist nlh, const int64_t *d_src_off, const int64_t *d_t,
+                   const uint8_t *d_v, int64_t n_in, int validate, void *stream, gsim_job *out) {
+    if (!out || !d_src_off || n_in < 0 || (n_in > 0 && (!d_t || !d_v))) return fail(GSIM_E_ARG, "bad argument");
+    auto it = ctx->netlists.find(nlh);
+    if (it == ctx->netlists.end()) return fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nlh);
+    Netlist &nl = *it->second;
+    Failure f = set_device(ctx);
+    if (f.st != GSIM_OK) return f;
+    if (validate) {
+        std::vector<int64_t> so(nl.S + 1), tt(n_in);
+        std::vector<uint8_t> vv(n_in);
+        HIP_TRY(hipStreamSynchronize(stream ? (hipStream_t)stream : ctx->stream));
+        HIP_TRY(hipMemcpy(so.data(), d_src_off, sizeof(int64_t) * (size_t)(nl.S + 1), hipMemcpyDeviceToHost));
+        if (so[nl.S] != n_in) return fail(GSIM_E_ARG, "src_off[S] = %lld but n_in = %lld", (long long)so[nl.S], (long long)n_in);
+        if (n_in > 0) {
+            HIP_TRY(hipMemcpy(tt.data(), d_t, sizeof(int64_t) * (size_t)n_in, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(vv.data(), d_v, (size_t)n_in, hipMemcpyDeviceToHost));
+        }
+        f = validate_stimulus(nl.S, so.data(), tt.data(), vv.data(), nl.max_path_delay);
+        if (f.st != GSIM_OK) return f;
+    }
+    std::unique_ptr<Job> j;
+    f = start_job(ctx, nlh, n_in, (hipStream_t)stream, j);
+    if (f.st != GSIM_OK) return f;
+    hipStream_t s = j->stream;
+    auto cleanup = [&](Failure e) { destroy_job(ctx, j.get()); return e; };
+    if (hipMemcpyAsync(j->d_src_off, d_src_off, sizeof(int64_t) * (size_t)(nl.S + 1), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        (n_in > 0 && hipMemcpyAsync(j->d_T, d_t, sizeof(int64_t) * (size_t)n_in, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
+        (n_in > 0 && hipMemcpyAsync(j->d_V, d_v, (size_t)n_in, hipMemcpyDeviceToDevice, s) != hipSuccess))
+        return cleanup(fail(GSIM_E_DEVICE, "stimulus copy: %s", hipGetErrorString(hipGetLastError())));
+    f = enqueue_levels(ctx, j.get());
+    if (f.st != GSIM_OK) return cleanup(f);
+    const int64_t id = ctx->next_id++;
+    ctx->jobs[id] = std::move(j);
+    *out = id;
+    return kOk;
+}
+
+Failure find_job(gsim_ctx ctx, gsim_job id, Job **out) {
+    auto it = ctx->jobs.find(id);
+    if (it == ctx->jobs.end()) return fail(GSIM_E_HANDLE, "unknown job handle %lld", (long long)id);
+    *out = it->second.get();
+    return kOk;
+}
+
+Failure wait_job(gsim_ctx ctx, Job *j) {
+    if (!j->waited) {
+        Failure f = set_device(ctx);
+        if (f.st != GSIM_OK) return f;
+        HIP_TRY(hipEventSynchronize(j->ev_done));
+        j->waited = true;
+        if (j->h_state->overflow) {
+            j->failed = true;
+            free_job_buffers(ctx, j);
+        }
+    }
+    if (j->failed)
+        return fail(GSIM_E_OOM, "output arena of %lld transitions overflowed; set GSIM_OPT_ARENA_TRANSITIONS larger",
+                    (long long)j->capacity);
+    if (j->h_state->carry_error)
+        return fail(GSIM_E_DEVICE, "internal consistency check failed (code %d)", j->h_state->carry_error);
+    return kOk;
+}
+
+Failure fetch(gsim_ctx ctx, Job *j, const int64_t *nets, int64_t n, int64_t *out_off, int64_t *out_t,
+              uint8_t *out_v, int64_t cap) {
+    Failure f = wait_job(ctx, j);
+    if (f.st != GSIM_OK) return f;
+    Netlist &nl = *j->nl;
+    const int64_t N = nl.S + nl.G;
+    if (!nets) n = N;
+    if (n < 0 || !out_off) return fail(GSIM_E_ARG, "bad net list");
+    std::vector<int64_t> internal(n);
+    for (int64_t i = 0; i < n; i++) {
+        const int64_t u = nets ? nets[i] : i;
+        if (u < 0 || u >= N) return fail(GSIM_E_ARG, "net %lld out of range", (long long)u);
+        internal[i] = u < nl.S ? u : nl.S + nl.internal_of_user[u - nl.S];
+    }
+    std::vector<int64_t> off(N), len(N);
+    HIP_TRY(hipMemcpy(off.data(), j->d_off, sizeof(int64_t) * (size_t)N, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(len.data(), j->d_len, sizeof(int64_t) * (size_t)N, hipMemcpyDeviceToHost));
+    out_off[0] = 0;
+    for (int64_t i = 0; i < n; i++) out_off[i + 1] = out_off[i] + len[internal[i]];
+    if (!out_t) return kOk;
+    if (!out_v) return fail(GSIM_E_ARG, "null out_v");
+    if (cap < out_off[n]) return fail(GSIM_E_ARG, "capacity %lld < %lld transitions", (long long)cap, (long long)out_off[n]);
+    // Gather in batches through a device staging buffer.
+    const int64_t total = out_off[n];
+    const int64_t stage = std::max<int64_t>(1, std::min<int64_t>(total, int64_t(64) << 20));
+    Pool &pool = *ctx->pool;
+    int64_t *d_st = pool_get<int64_t>(pool, stage);
+    uint8_t *d_sv = pool_get<uint8_t>(pool, stage);
+    const int64_t max_batch = 1 << 16;
+    int64_t *d_meta = pool_get<int64_t>(pool, 3 * max_batch);
+    auto release = [&]() { pool.put(d_st); pool.put(d_sv); pool.put(d_meta); };
+    if (!d_st || !d_sv || !d_meta) { release(); return fail(GSIM_E_OOM, "no device memory for the fetch staging buffer"); }
+    hipStream_t s = ctx->stream;
+    std::vector<int64_t> meta(3 * max_batch);
+    int64_t i = 0;
+    while (i < n) {
+        // nets [i, e) whose total fits the staging buffer (a single larger net is copied directly)
+        const int64_t li = len[internal[i]];
+        if (li > stage) {
+            const int64_t a = off[internal[i]];
+            hipError_t e1 = hipMemcpy(out_t + out_off[i], j->d_T + a, sizeof(int64_t) * (size_t)li, hipMemcpyDeviceToHost);
+            hipError_t e2 = hipMemcpy(out_v + out_off[i], j->d_V + a, (size_t)li, hipMemcpyDeviceToHost);
+            if (e1 != hipSuccess || e2 != hipSuccess) { release(); return fail(GSIM_E_DEVICE, "fetch copy failed"); }
+            i++;
+            continue;
+        }
+        int64_t e = i, acc = 0;
+        while (e < n && e - i < max_batch && acc + len[internal[e]] <= stage) {
+            meta[e - i] = off[internal[e]];
+            meta[max_batch + (e - i)] = len[internal[e]];
+            meta[2 * max_batch + (e - i)] = acc;
+            acc += len[internal[e]];
+            e++;
+        }
+        const int64_t nb = e - i;
+        hipError_t err = hipMemcpyAsync(d_meta, meta.data(), sizeof(int64_t) * 3 * (size_t)max_batch, hipMemcpyHostToDevice, s);
+        if (err == hipSuccess)
+            err = launch_gather(d_meta, d_meta + max_batch, d_meta + 2 * max_batch, nb, j->d_T, j->d_V, d_st, d_sv, s);
+        if (err == hipSuccess && acc > 0)
+            err = hipMemcpyAsync(out_t + out_off[i], d_st, sizeof(int64_t) * (size_t)acc, hipMemcpyDeviceToHost, s);
+        if (err == hipSuccess && acc > 0)
+            err = hipMemcpyAsync(out_v + out_off[i], d_sv, (size_t)acc, hipMemcpyDeviceToHost, s);
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        if (err != hipSuccess) { release(); return fail(GSIM_E_DEVICE, "fetch: %s", hipGetErrorString(err)); }
+        i = e;
+    }
+    release();
+    return kOk;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI.
+
+extern "C" {
+
+const char *sim_version(void) { return "gsim 0.1 (gfx950)"; }
+
+const char *sim_last_error(gsim_ctx ctx) {
+    if (ctx) return ctx->err.c_str();
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    static thread_local std::string copy;
+    copy = g_err;
+    return copy.c_str();
+}
+
+gsim_status sim_create(int device, uint64_t hbm_budget_bytes, gsim_ctx *out) {
+    if (!out) return record(nullptr, fail(GSIM_E_ARG, "null output"));
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return record(nullptr, fail(GSIM_E_DEVICE, "no HIP device"));
+    }
+    if (device < 0 || device >= n) return record(nullptr, fail(GSIM_E_ARG, "device %d of %d", device, n));
+    auto ctx = std::make_unique<gsim_ctx_s>();
+    ctx->device = device;
+    if (hipSetDevice(device) != hipSuccess) return record(nullptr, fail(GSIM_E_DEVICE, "hipSetDevice failed"));
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return record(nullptr, fail(GSIM_E_DEVICE, "hipMemGetInfo failed"));
+    const uint64_t budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(free_b / 10 * 9);
+    ctx->pool = std::make_unique<Pool>(budget);
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess)
+        return record(nullptr, fail(GSIM_E_DEVICE, "stream creation failed"));
+    std::vector<uint8_t> lut = build_lut();
+    ctx->d_lut = (uint8_t *)ctx->pool->get(lut.size());
+    if (!ctx->d_lut || hipMemcpy(ctx->d_lut, lut.data(), lut.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipStreamDestroy(ctx->stream);
+        return record(nullptr, fail(GSIM_E_DEVICE, "gate table upload failed"));
+    }
+    *out = ctx.release();
+    return GSIM_OK;
+}
+
+gsim_status sim_destroy(gsim_ctx ctx) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    (void)hipSetDevice(ctx->device);
+    for (auto &kv : ctx->jobs) destroy_job(ctx, kv.second.get());
+    ctx->jobs.clear();
+    for (auto &kv : ctx->netlists) ctx->pool->put(kv.second->d_rec);
+    ctx->netlists.clear();
+    ctx->pool->put(ctx->d_lut);
+    ctx->pool.reset();
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return GSIM_OK;
+}
+
+gsim_status sim_set_option(gsim_ctx ctx, int option, int64_t value) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    switch (option) {
+    case GSIM_OPT_ARENA_TRANSITIONS:
+        if (value < 0) return record(ctx, fail(GSIM_E_ARG, "arena size must be >= 0"));
+        ctx->opt_arena = value;
+        return GSIM_OK;
+    case GSIM_OPT_KERNEL:
+        if (value < 0 || value > 1) return record(ctx, fail(GSIM_E_ARG, "kernel option must be 0 or 1"));
+        ctx->opt_kernel = (int)value;
+        return GSIM_OK;
+    case GSIM_OPT_LEVEL_LOOP:
+        if (value < 0 || value > 1) return record(ctx, fail(GSIM_E_ARG, "level loop option must be 0 or 1"));
+        ctx->opt_level_loop = (int)value;
+        return GSIM_OK;
+    }
+    return record(ctx, fail(GSIM_E_ARG, "unknown option %d", option));
+}
+
+gsim_status sim_load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type,
+                             const int64_t *pin_off, const int64_t *pin_net,
+                             const int32_t *rise_ps, const int32_t *fall_ps, gsim_netlist *out) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    return record(ctx, load_netlist(ctx, S, G, type, pin_off, pin_net, rise_ps, fall_ps, out));
+}
+
+gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    auto it = ctx->netlists.find(nl);
+    if (it == ctx->netlists.end()) return record(ctx, fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nl));
+    for (auto &kv : ctx->jobs)
+        if (kv.second->nl_id == nl)
+            return record(ctx, fail(GSIM_E_ARG, "netlist %lld still has job %lld", (long long)nl, (long long)kv.first));
+    ctx->pool->put(it->second->d_rec);
+    ctx->netlists.erase(it);
+    return GSIM_OK;
+}
+
+gsim_status sim_netlist_info(gsim_ctx ctx, gsim_netlist nl, gsim_netlist_info *out) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    auto it = ctx->netlists.find(nl);
+    if (it == ctx->netlists.end()) return record(ctx, fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nl));
+    if (!out) return record(ctx, fail(GSIM_E_ARG, "null output"));
+    const Netlist &n = *it->second;
+    out->S = n.S;
+    out->G = n.G;
+    out->P = n.P;
+    out->levels = n.n_levels;
+    out->max_delay_ps = n.max_delay;
+    out->max_path_delay = n.max_path_delay;
+    out->lane_gates = n.lane_gates;
+    return GSIM_OK;
+}
+
+gsim_status sim_run(gsim_ctx ctx, gsim_netlist nl, const int64_t *src_off, const int64_t *t,
+                    const uint8_t *v, void *hip_stream, gsim_job *out) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    return record(ctx, run_host(ctx, nl, src_off, t, v, hip_stream, out));
+}
+
+gsim_status sim_run_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_off,
+                           const int64_t *d_t, const uint8_t *d_v, int64_t n_in, int validate,
+                           void *hip_stream, gsim_job *out) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    return record(ctx, run_device(ctx, nl, d_src_off, d_t, d_v, n_in, validate, hip_stream, out));
+}
+
+gsim_status sim_wait(gsim_ctx ctx, gsim_job job) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    Job *j = nullptr;
+    Failure f = find_job(ctx, job, &j);
+    if (f.st == GSIM_OK) f = wait_job(ctx, j);
+    return record(ctx, f);
+}
+
+gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    if (!out) return record(ctx, fail(GSIM_E_ARG, "null output"));
+    Job *j = nullptr;
+    Failure f = find_job(ctx, job, &j);
+    if (f.st == GSIM_OK) f = wait_job(ctx, j);
+    if (f.st != GSIM_OK) return record(ctx, f);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, j->ev_start, j->ev_end) != hipSuccess)
+        return record(ctx, fail(GSIM_E_DEVICE, "event timing failed"));
+    out->n_in = j->n_in;
+    out->n_out = j->h_state->n_out;
+    out->pin_reads = j->h_state->pin_reads;
+    out->arena_used = j->h_state->arena_top;
+    out->arena_capacity = j->capacity;
+    out->device_ms = ms;
+    return GSIM_OK;
+}
+
+gsim_status sim_fetch_waveforms(gsim_ctx ctx, gsim_job job, const int64_t *nets, int64_t n,
+                                int64_t *out_off, int64_t *out_t, uint8_t *out_v, int64_t cap) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    Job *j = nullptr;
+    Failure f = find_job(ctx, job, &j);
+    if (f.st == GSIM_OK) f = set_device(ctx);
+    if (f.st == GSIM_OK) f = fetch(ctx, j, nets, n, out_off, out_t, out_v, cap);
+    return record(ctx, f);
+}
+
+gsim_status sim_release_job(gsim_ctx ctx, gsim_job job) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    auto it = ctx->jobs.find(job);
+    if (it == ctx->jobs.end()) return record(ctx, fail(GSIM_E_HANDLE, "unknown job handle %lld", (long long)job));
+    (void)hipSetDevice(ctx->device);
+    destroy_job(ctx, it->second.get());
+    ctx->jobs.erase(it);
+    return GSIM_OK;
+}
+
+gsim_status sim_levelize(int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
+                         const int64_t *pin_net, const int32_t *rise_ps, const int32_t *fall_ps,
+                         int32_t *level_out, int32_t *n_levels_out) {
+    Levelized lv;
+    Failure f = levelize(S, G, type, pin_off, pin_net, rise_ps, fall_ps, &lv);
+    if (f.st != GSIM_OK) return record(nullptr, f);
+    if (level_out) std::copy(lv.level.begin(), lv.level.end(), level_out);
+    if (n_levels_out) *n_levels_out = lv.n_levels;
+    return GSIM_OK;
+}
+
+gsim_status sim_validate_stimulus(int64_t S, const int64_t *src_off, const int64_t *t,
+                                  const uint8_t *v, int64_t max_path_delay) {
+    if (S < 0 || max_path_delay < 0) return record(nullptr, fail(GSIM_E_ARG, "negative S or path delay"));
+    return record(nullptr, validate_stimulus(S, src_off, t, v, max_path_delay));
+}
+
+}  // extern "C"

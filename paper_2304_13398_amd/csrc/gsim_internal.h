@@ -1,0 +1,79 @@
+// Internal layout shared by the host runtime and the HIP kernels of libgsim.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsim {
+
+constexpr int kMaxPins = 4;
+constexpr uint8_t kX = 2;
+constexpr int64_t kInf = INT64_MAX;
+constexpr int64_t kTimeLimit = int64_t(1) << 62;  // times live in [0, 2^62)
+
+// Transitions per pin loaded per round of the wavefront kernel (one per lane).
+constexpr int kTile = 64;
+// Tentative (not yet final) output transitions the wavefront kernel can hold
+// between rounds. A tentative transition appears after the round's horizon H
+// and at most the gate's largest pin delay after it, and tentative appearance
+// times are distinct integers, so a gate whose largest pin delay is at most
+// kCarryCap never needs more.
+constexpr int kCarryCap = 256;
+// Gates handled per sizing block.
+constexpr int kSizeBlock = 256;
+
+// One gate, 64 bytes, in level order. Nets are internal ids: sources keep
+// their id, the gate at internal position i drives net S + i.
+struct alignas(64) GateRec {
+    int32_t net[kMaxPins];   // unused pins: 0
+    int32_t rise[kMaxPins];
+    int32_t fall[kMaxPins];
+    uint8_t type;
+    uint8_t k;               // pin count
+    uint8_t pad0[2];
+    int32_t dmax;            // largest rise/fall delay over the pins
+    int32_t user_gate;       // the caller's gate index
+    int32_t pad1;
+};
+static_assert(sizeof(GateRec) == 64, "GateRec must be 64 bytes");
+
+// Per-job device state.
+struct DevState {
+    int64_t arena_top;       // first free transition slot
+    int64_t capacity;        // arena size in transitions
+    int64_t pin_reads;       // sum of reserved bounds = sum over pins of read lengths
+    int64_t n_out;           // output transitions (filled by the final reduction)
+    int32_t overflow;        // arena exhausted: later levels are skipped
+    int32_t carry_error;     // wavefront kernel exceeded its tentative window (never expected)
+};
+
+struct EvalArgs {
+    const GateRec *rec;      // all gates, level order
+    int64_t g_begin;         // first gate of this launch (internal index)
+    int64_t n;               // gates in this launch
+    int64_t lvl_begin;       // first gate of the level (sizing blocks are relative to it)
+    int64_t S;
+    const int64_t *blockbase;  // per sizing block: absolute arena base
+    int64_t *off;            // [S+G] arena offset of each net
+    int64_t *len;            // [S+G] transitions of each net
+    int64_t *T;              // arena times
+    uint8_t *V;              // arena values
+    DevState *state;
+    const uint8_t *lut;      // [kNumTypes][256] gate value by packed pin values
+};
+
+// Kernel launchers (kernels.hip). All are asynchronous on `s`.
+hipError_t launch_init_sources(const int64_t *d_src_off, int64_t S, int64_t *off, int64_t *len,
+                               DevState *state, int64_t n_in, int64_t capacity, hipStream_t s);
+hipError_t launch_size(const GateRec *rec, int64_t lvl_begin, int64_t n, int64_t S,
+                       const int64_t *len, int64_t *off, int64_t *blocksum, hipStream_t s);
+hipError_t launch_level_scan(int64_t *blocksum, int64_t nb, DevState *state, hipStream_t s);
+hipError_t launch_eval_wave(const EvalArgs &a, hipStream_t s);
+hipError_t launch_eval_lane(const EvalArgs &a, hipStream_t s);
+hipError_t launch_count_out(const int64_t *len, int64_t S, int64_t G, int64_t *partial,
+                            int64_t n_partial, DevState *state, hipStream_t s);
+hipError_t launch_gather(const int64_t *src_off, const int64_t *n_items, const int64_t *dst_off,
+                         int64_t n_nets, const int64_t *T, const uint8_t *V, int64_t *out_t,
+                         uint8_t *out_v, hipStream_t s);
+
+}  // namespace gsim

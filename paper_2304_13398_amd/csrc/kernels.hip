@@ -1,0 +1,621 @@
+// HIP kernels of libgsim for gfx950 (CDNA4, wave64).
+//
+// One job = one pass over the levels of the netlist, all enqueued on one
+// stream with no host synchronisation (the one-round-trip idea of Section 3).
+// Per level:
+//   size   : w_g = sum of the lengths of gate g's input waveforms. A gate's
+//            output has at most as many transitions as it has distinct input
+//            times (each merged time yields at most one candidate), which is
+//            at most w_g -- Eq. 2 applied to one gate -- so w_g slots are
+//            reserved for it. Block-local exclusive scan.
+//   scan   : one block turns the block totals into absolute arena bases and
+//            advances the arena top (a device bump allocator).
+//   eval   : the output waveform of every gate of the level (Algorithm 2 with
+//            the Eq. 1 denial and the Fig. 3 drop), written at its base.
+#include "gsim_internal.h"
+
+namespace gsim {
+
+namespace {
+
+__device__ __forceinline__ int64_t readlane64(int64_t x, int lane) {
+    int lo = __builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+    int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), lane);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ int64_t shfl_down64(int64_t x, int d) {
+    int lo = __shfl_down((int)(uint32_t)x, d, 64);
+    int hi = __shfl_down((int)(uint32_t)((uint64_t)x >> 32), d, 64);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+}
+
+// Delay of one pin for a new output value: 1 -> rise, 0 -> fall, X -> the
+// smaller of the two.
+__device__ __forceinline__ int64_t pin_delay(int32_t rise, int32_t fall, uint8_t v) {
+    return v == 1 ? rise : v == 0 ? fall : (rise < fall ? rise : fall);
+}
+
+// Wave-wide inclusive prefix sum of an int.
+__device__ __forceinline__ int wave_incl_sum(int x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        int o = __shfl_up(x, s, 64);
+        if (lane >= s) x += o;
+    }
+    return x;
+}
+
+// Wave-wide inclusive suffix minimum (over lanes >= this lane).
+__device__ __forceinline__ int64_t wave_suffix_min(int64_t x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        int64_t o = shfl_down64(x, s);
+        if (lane + s < 64) x = min64(x, o);
+    }
+    return x;
+}
+
+// -------------------------------------------------------------------------
+// Sources: copied into the arena at [0, n_in) by the host; here their
+// offsets and lengths, and the job state.
+__global__ void init_sources_kernel(const int64_t *__restrict__ src_off, int64_t S,
+                                    int64_t *__restrict__ off, int64_t *__restrict__ len,
+                                    DevState *state, int64_t n_in, int64_t capacity) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < S) {
+        int64_t a = src_off[i];
+        off[i] = a;
+        len[i] = src_off[i + 1] - a;
+    }
+    if (i == 0) {
+        state->arena_top = n_in;
+        state->capacity = capacity;
+        state->pin_reads = 0;
+        state->n_out = 0;
+        state->overflow = 0;
+        state->carry_error = 0;
+    }
+}
+
+// -------------------------------------------------------------------------
+// Per-level sizing: w_g and its block-local exclusive scan.
+__global__ __launch_bounds__(kSizeBlock) void size_kernel(const GateRec *__restrict__ rec,
+                                                          int64_t lvl_begin, int64_t n,
+                                                          int64_t S,
+                                                          const int64_t *__restrict__ len,
+                                                          int64_t *__restrict__ off,
+                                                          int64_t *__restrict__ blocksum) {
+    __shared__ int64_t wsum[kSizeBlock / 64];
+    const int64_t i = (int64_t)blockIdx.x * kSizeBlock + threadIdx.x;
+    int64_t w = 0;
+    if (i < n) {
+        const GateRec &r = rec[lvl_begin + i];
+        const int k = r.k;
+#pragma unroll
+        for (int p = 0; p < kMaxPins; p++)
+            if (p < k) w += len[r.net[p]];
+    }
+    // inclusive scan within the wave (64-bit)
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    int64_t x = w;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        int lo = __shfl_up((int)(uint32_t)x, s, 64);
+        int hi = __shfl_up((int)(uint32_t)((uint64_t)x >> 32), s, 64);
+        int64_t o = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+        if (lane >= s) x += o;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int64_t before = 0, total = 0;
+#pragma unroll
+    for (int j = 0; j < kSizeBlock / 64; j++) {
+        if (j < wv) before += wsum[j];
+        total += wsum[j];
+    }
+    if (i < n) off[S + lvl_begin + i] = before + x - w;
+    if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
+}
+
+// One block: block totals -> absolute bases; bump the arena top.
+__global__ __launch_bounds__(1024) void level_scan_kernel(int64_t *__restrict__ blocksum,
+                                                          int64_t nb, DevState *state) {
+    __shared__ int64_t wsum[16];
+    __shared__ int64_t carry_s;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry_s = state->arena_top;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
+        const int64_t i = c0 + threadIdx.x;
+        const int64_t w = i < nb ? blocksum[i] : 0;
+        int64_t x = w;
+#pragma unroll
+        for (int s = 1; s < 64; s <<= 1) {
+            int lo = __shfl_up((int)(uint32_t)x, s, 64);
+            int hi = __shfl_up((int)(uint32_t)((uint64_t)x >> 32), s, 64);
+            int64_t o = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+            if (lane >= s) x += o;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int64_t before = 0, total = 0;
+        for (int j = 0; j < 16; j++) {
+            if (j < wv) before += wsum[j];
+            total += wsum[j];
+        }
+        const int64_t base = carry_s;
+        if (i < nb) blocksum[i] = base + before + x - w;
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = base + total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t top = carry_s;
+        const int64_t used = top - state->arena_top;
+        if (top > state->capacity || state->overflow) {
+            state->overflow = 1;
+        } else {
+            state->pin_reads += used;
+            state->arena_top = top;
+        }
+    }
+}
+
+// -------------------------------------------------------------------------
+// Wavefront-per-gate evaluation.
+//
+// The per-gate procedure (Algorithm 2 with Eq. 1 and the Fig. 3 drop) is
+// computed in the following equivalent data-parallel form. Let the distinct
+// merged input times be t_1 < t_2 < ... and e_i the gate value once every
+// input transition at or before t_i is applied (e_0 = X). A candidate is an
+// i with e_i != e_{i-1}; it appears at r_i = t_i + the minimum delay over the
+// pins with a transition at t_i. Appending candidates in order while denying
+// every earlier one with an appearance time >= r_i (Eq. 1) keeps exactly the
+// candidates j with r_j < r_k for every later candidate k (survivors); and
+// dropping a transition equal to the output's current value (Fig. 3) is the
+// same as keeping, among the survivors, those whose value differs from the
+// previous survivor's (X before the first).
+//
+// The wave walks the inputs in rounds of up to 64 transitions per pin. The
+// round's horizon H is the smallest last-loaded time over pins that have more
+// transitions beyond the tile; every input transition at or before H is in
+// the round. Each lane takes one transition per pin: it finds, by binary
+// search in the other pins' tiles, how many of their transitions are before
+// or at its time, which gives its rank in the merged order, whether it is the
+// first transition at that time, the pin values just before and just after
+// that time, hence e before/after and the candidate. Candidates are scattered
+// by merged rank, and survivors come from a reverse suffix minimum over the
+// wave. A survivor with r <= H is final (later candidates appear after H); the
+// others stay tentative in LDS and are re-tested against the next rounds. At
+// most (largest pin delay) of them exist (distinct integer appearance times in
+// (H, H + dmax]), so gates with dmax <= kCarryCap are handled exactly.
+struct WaveLds {
+    int64_t tt[kMaxPins][kTile];        // tile times (kInf beyond the pin's end)
+    int64_t sr[kMaxPins * kTile];       // candidate appearance time by merged rank (kInf: none)
+    int64_t qr[kCarryCap + kMaxPins * kTile];  // tentative survivors, then this round's
+    uint8_t tv[kMaxPins][kTile];
+    uint8_t sv[kMaxPins * kTile];
+    uint8_t qv[kCarryCap + kMaxPins * kTile];
+    uint8_t lut[256];
+};
+
+// Number of entries of the sorted 64-entry tile `a` that are < t.
+__device__ __forceinline__ int count_less(const int64_t *a, int64_t t) {
+    int lo = 0;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1)
+        if (a[lo + s - 1] < t) lo += s;
+    lo += a[lo] < t ? 1 : 0;  // lo <= 63 here
+    return lo;
+}
+
+__global__ __launch_bounds__(64) void eval_wave_kernel(EvalArgs A) {
+    __shared__ WaveLds L;
+    const int lane = lane_id();
+    const int64_t gi = blockIdx.x;
+    if (gi >= A.n) return;
+    const int64_t gate = A.g_begin + gi;
+    const GateRec R = A.rec[gate];
+    const int k = R.k;
+    const int64_t S = A.S;
+    int64_t *len = A.len;
+    int64_t *off = A.off;
+
+    if (A.state->overflow) {
+        if (lane == 0) { len[S + gate] = 0; off[S + gate] = 0; }
+        return;
+    }
+    const int64_t ob = A.blockbase[(gate - A.lvl_begin) / kSizeBlock] + off[S + gate];
+
+    int64_t pb[kMaxPins], pl[kMaxPins], cur[kMaxPins];
+    uint8_t cval[kMaxPins];
+    int64_t reserved = 0;  // slots sized for this gate: the sum of its input lengths
+#pragma unroll
+    for (int p = 0; p < kMaxPins; p++) {
+        pb[p] = 0; pl[p] = 0; cur[p] = 0; cval[p] = kX;
+        if (p < k) { pb[p] = off[R.net[p]]; pl[p] = len[R.net[p]]; reserved += pl[p]; }
+    }
+    reinterpret_cast<uint32_t *>(L.lut)[lane] =
+        reinterpret_cast<const uint32_t *>(A.lut + (int)R.type * 256)[lane];
+
+    const int64_t *__restrict__ T = A.T;
+    const uint8_t *__restrict__ V = A.V;
+    uint8_t last_val = kX;   // value of the last final survivor
+    int nq = 0;              // tentative survivors held in L.qr/L.qv[0, nq)
+    int64_t out_n = 0;
+
+    for (;;) {
+        bool more = false;
+#pragma unroll
+        for (int p = 0; p < kMaxPins; p++) more |= cur[p] < pl[p];
+        if (!more) break;
+
+        // ---- load one tile per pin, find the horizon H
+        int64_t my_t[kMaxPins];
+        int64_t rem[kMaxPins];
+        int64_t H = kInf;
+#pragma unroll
+        for (int p = 0; p < kMaxPins; p++) {
+            rem[p] = pl[p] - cur[p];
+            int64_t x = kInf;
+            uint8_t y = 0;
+            if (lane < rem[p]) {
+                x = T[pb[p] + cur[p] + lane];
+                y = V[pb[p] + cur[p] + lane];
+            }
+            L.tt[p][lane] = x;
+            L.tv[p][lane] = y;
+            my_t[p] = x;
+            if (rem[p] > kTile) H = min64(H, readlane64(x, kTile - 1));
+        }
+        int m[kMaxPins];
+        int M = 0;
+#pragma unroll
+        for (int p = 0; p < kMaxPins; p++) {
+            m[p] = __popcll(__ballot(lane < rem[p] && my_t[p] <= H));
+            M += m[p];
+        }
+        __syncthreads();
+
+        // ---- candidates, scattered by merged rank
+#pragma unroll
+        for (int p = 0; p < kMaxPins; p++) {
+            if (p >= k || lane >= m[p]) continue;
+            const int64_t t = my_t[p];
+            int lb[kMaxPins];
+            bool eq[kMaxPins];
+            bool leader = true;
+            int rank = lane;
+#pragma unroll
+            for (int q = 0; q < kMaxPins; q++) {
+                if (q >= k) { lb[q] = 0; eq[q] = false; continue; }
+                if (q == p) { lb[q] = lane; eq[q] = true; continue; }
+                lb[q] = count_less(L.tt[q], t);
+                eq[q] = lb[q] < kTile && L.tt[q][lb[q] < kTile ? lb[q] : 0] == t;
+                if (q < p) {
+                    leader = leader && !eq[q];
+                    rank += lb[q] + (eq[q] ? 1 : 0);
+                } else {
+                    rank += lb[q];
+                }
+            }
+            int64_t r = kInf;
+            uint8_t sv = 0xFF;
+            if (leader) {
+                int pack_after = 0, pack_before = 0;
+#pragma unroll
+                for (int q = 0; q < kMaxPins; q++) {
+                    if (q >= k) continue;
+                    const int ub = lb[q] + (eq[q] ? 1 : 0);
+                    const uint8_t va = ub > 0 ? L.tv[q][ub - 1] : cval[q];
+                    const uint8_t vb = lb[q] > 0 ? L.tv[q][lb[q] - 1] : cval[q];
+                    pack_after |= (int)va << (2 * q);
+                    pack_before |= (int)vb << (2 * q);
+                }
+                const uint8_t ea = L.lut[pack_after];
+                const uint8_t eb = L.lut[pack_before];
+                if (ea != eb) {
+                    int64_t d = kInf;
+#pragma unroll
+                    for (int q = 0; q < kMaxPins; q++)
+                        if (q < k && eq[q]) d = min64(d, pin_delay(R.rise[q], R.fall[q], ea));
+                    r = t + d;
+                    sv = ea;
+                }
+            }
+            L.sr[rank] = r;
+            L.sv[rank] = sv;
+        }
+        __syncthreads();
+
+        // ---- survivors among this round's candidates (reverse suffix minimum)
+        int64_t r4[4];
+        uint8_t v4[4];
+        int64_t lmin = kInf;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int s = lane * 4 + j;
+            r4[j] = s < M ? L.sr[s] : kInf;
+            v4[j] = s < M ? L.sv[s] : 0xFF;
+            lmin = min64(lmin, r4[j]);
+        }
+        const int64_t suf = wave_suffix_min(lmin);
+        const int64_t round_min = readlane64(suf, 0);
+        int64_t later = shfl_down64(suf, 1);
+        if (lane == 63) later = kInf;
+        bool keep4[4];
+        int nkeep = 0;
+#pragma unroll
+        for (int j = 3; j >= 0; j--) {
+            keep4[j] = v4[j] != 0xFF && r4[j] < later;
+            later = min64(later, r4[j]);
+            nkeep += keep4[j] ? 1 : 0;
+        }
+        // tentative survivors of earlier rounds outlive this round iff they
+        // appear before every candidate of this round (they are increasing)
+        int ncs = 0;
+        for (int c0 = 0; c0 < nq; c0 += 64) {
+            const int c = c0 + lane;
+            ncs += __popcll(__ballot(c < nq && L.qr[c] < round_min));
+        }
+        const int incl = wave_incl_sum(nkeep);
+        const int nsurv = __builtin_amdgcn_readlane(incl, 63);
+        {
+            int pos = ncs + incl - nkeep;
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                if (keep4[j]) { L.qr[pos] = r4[j]; L.qv[pos] = v4[j]; pos++; }
+        }
+        const int nseq = ncs + nsurv;
+        __syncthreads();
+
+        // ---- final survivors (r <= H): drop repeats, append to the output
+        int nf = 0;
+        for (int c0 = 0; c0 < nseq; c0 += 64) {
+            const int c = c0 + lane;
+            nf += __popcll(__ballot(c < nseq && L.qr[c] <= H));
+        }
+        for (int c0 = 0; c0 < nf; c0 += 64) {
+            const int j = c0 + lane;
+            const bool in = j < nf;
+            const uint8_t v = in ? L.qv[j] : 0;
+            const uint8_t vp = j == 0 ? last_val : (in ? L.qv[j - 1] : 0);
+            const bool keep = in && v != vp;
+            const uint64_t mask = __ballot(keep);
+            const int64_t at = out_n + lanes_below(mask);
+            if (keep && at < reserved) {
+                A.T[ob + at] = L.qr[j];
+                A.V[ob + at] = v;
+            }
+            out_n += __popcll(mask);
+        }
+        if (nf > 0) last_val = L.qv[nf - 1];
+
+        // ---- keep the tentative ones at the front for the next round
+        int ntent = nseq - nf;
+        if (ntent > kCarryCap) {  // cannot happen for dmax <= kCarryCap
+            if (lane == 0) A.state->carry_error = 1;
+            ntent = kCarryCap;
+        }
+        if (nf > 0 && ntent > 0) {
+            int64_t rr[kCarryCap / 64];
+            uint8_t vv[kCarryCap / 64];
+#pragma unroll
+            for (int c = 0; c < kCarryCap / 64; c++) {
+                const int j = c * 64 + lane;
+                if (j < ntent) { rr[c] = L.qr[nf + j]; vv[c] = L.qv[nf + j]; }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < kCarryCap / 64; c++) {
+                const int j = c * 64 + lane;
+                if (j < ntent) { L.qr[j] = rr[c]; L.qv[j] = vv[c]; }
+            }
+        }
+        nq = ntent;
+
+#pragma unroll
+        for (int p = 0; p < kMaxPins; p++) {
+            if (m[p] > 0) {
+                cval[p] = L.tv[p][m[p] - 1];
+                cur[p] += m[p];
+            }
+        }
+        __syncthreads();
+    }
+    if (out_n > reserved) {  // cannot happen: at most one output per distinct input time
+        if (lane == 0) A.state->carry_error = 2;
+        out_n = reserved;
+    }
+    if (lane == 0) {
+        len[S + gate] = out_n;
+        off[S + gate] = ob;
+    }
+}
+
+// -------------------------------------------------------------------------
+// Lane-per-gate evaluation: the sequential procedure on one lane, with the
+// gate's reserved output region used directly as the list of scheduled
+// transitions (denials pop its tail). Exact for any delay.
+__global__ __launch_bounds__(64) void eval_lane_kernel(EvalArgs A) {
+    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= A.n) return;
+    const int64_t gate = A.g_begin + gi;
+    const int64_t S = A.S;
+    if (A.state->overflow) {
+        A.len[S + gate] = 0;
+        A.off[S + gate] = 0;
+        return;
+    }
+    const GateRec R = A.rec[gate];
+    const int k = R.k;
+    const int64_t ob = A.blockbase[(gate - A.lvl_begin) / kSizeBlock] + A.off[S + gate];
+    int64_t pb[kMaxPins], pl[kMaxPins], idx[kMaxPins];
+    uint8_t cv[kMaxPins];
+    int64_t reserved = 0;
+    for (int p = 0; p < kMaxPins; p++) {
+        pb[p] = 0; pl[p] = 0; idx[p] = 0; cv[p] = kX;
+        if (p < k) { pb[p] = A.off[R.net[p]]; pl[p] = A.len[R.net[p]]; reserved += pl[p]; }
+    }
+    const uint8_t *lut = A.lut + (int)R.type * 256;
+    int64_t *T = A.T;
+    uint8_t *V = A.V;
+    uint8_t prev = kX;
+    int64_t n = 0;
+    for (;;) {
+        int64_t te = kInf;
+        for (int p = 0; p < k; p++)
+            if (idx[p] < pl[p]) te = min64(te, T[pb[p] + idx[p]]);
+        if (te == kInf) break;
+        int changed = 0;
+        int pack = 0;
+        for (int p = 0; p < k; p++) {
+            if (idx[p] < pl[p] && T[pb[p] + idx[p]] == te) {
+                cv[p] = V[pb[p] + idx[p]];
+                idx[p]++;
+                changed |= 1 << p;
+            }
+            pack |= (int)cv[p] << (2 * p);
+        }
+        const uint8_t e = lut[pack];
+        if (e != prev) {
+            int64_t d = kInf;
+            for (int p = 0; p < k; p++)
+                if (changed & (1 << p)) d = min64(d, pin_delay(R.rise[p], R.fall[p], e));
+            const int64_t tr = te + d;
+            while (n > 0 && T[ob + n - 1] >= tr) n--;
+            const uint8_t cur = n > 0 ? V[ob + n - 1] : kX;
+            if (e != cur) {
+                if (n >= reserved) {  // cannot happen: at most one output per distinct input time
+                    A.state->carry_error = 2;
+                    break;
+                }
+                T[ob + n] = tr;
+                V[ob + n] = e;
+                n++;
+            }
+        }
+        prev = e;
+    }
+    A.len[S + gate] = n;
+    A.off[S + gate] = ob;
+}
+
+// -------------------------------------------------------------------------
+// Sum of the gate output lengths (two stages: partial sums, then one block).
+__global__ __launch_bounds__(256) void count_partial_kernel(const int64_t *__restrict__ len,
+                                                            int64_t S, int64_t G,
+                                                            int64_t *__restrict__ partial) {
+    __shared__ int64_t ws[4];
+    int64_t acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < G; i += (int64_t)gridDim.x * 256)
+        acc += len[S + i];
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) acc += shfl_down64(acc, s);
+    if (lane_id() == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ __launch_bounds__(64) void count_final_kernel(const int64_t *__restrict__ partial,
+                                                         int64_t n, DevState *state) {
+    int64_t acc = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 64) acc += partial[i];
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) acc += shfl_down64(acc, s);
+    if (threadIdx.x == 0) state->n_out = acc;
+}
+
+// -------------------------------------------------------------------------
+// Gather: net i's n_items[i] transitions from the arena at src_off[i] to the
+// staging buffers at dst_off[i]. One block per net.
+__global__ __launch_bounds__(256) void gather_kernel(const int64_t *__restrict__ src_off,
+                                                     const int64_t *__restrict__ n_items,
+                                                     const int64_t *__restrict__ dst_off,
+                                                     int64_t n_nets,
+                                                     const int64_t *__restrict__ T,
+                                                     const uint8_t *__restrict__ V,
+                                                     int64_t *__restrict__ out_t,
+                                                     uint8_t *__restrict__ out_v) {
+    for (int64_t i = blockIdx.x; i < n_nets; i += gridDim.x) {
+        const int64_t a = src_off[i], n = n_items[i], d = dst_off[i];
+        for (int64_t j = threadIdx.x; j < n; j += 256) {
+            out_t[d + j] = T[a + j];
+            out_v[d + j] = V[a + j];
+        }
+    }
+}
+
+}  // namespace
+
+// -------------------------------------------------------------------------
+// Launchers.
+
+hipError_t launch_init_sources(const int64_t *d_src_off, int64_t S, int64_t *off, int64_t *len,
+                               DevState *state, int64_t n_in, int64_t capacity, hipStream_t s) {
+    const int64_t nb = (S + 255) / 256 > 0 ? (S + 255) / 256 : 1;
+    init_sources_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(d_src_off, S, off, len, state,
+                                                                n_in, capacity);
+    return hipGetLastError();
+}
+
+hipError_t launch_size(const GateRec *rec, int64_t lvl_begin, int64_t n, int64_t S,
+                       const int64_t *len, int64_t *off, int64_t *blocksum, hipStream_t s) {
+    const int64_t nb = (n + kSizeBlock - 1) / kSizeBlock;
+    if (nb == 0) return hipSuccess;
+    size_kernel<<<dim3((unsigned)nb), dim3(kSizeBlock), 0, s>>>(rec, lvl_begin, n, S, len, off,
+                                                                blocksum);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_scan(int64_t *blocksum, int64_t nb, DevState *state, hipStream_t s) {
+    level_scan_kernel<<<dim3(1), dim3(1024), 0, s>>>(blocksum, nb, state);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_wave(const EvalArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    eval_wave_kernel<<<dim3((unsigned)a.n), dim3(64), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_lane(const EvalArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    const int64_t nb = (a.n + 63) / 64;
+    eval_lane_kernel<<<dim3((unsigned)nb), dim3(64), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_out(const int64_t *len, int64_t S, int64_t G, int64_t *partial,
+                            int64_t n_partial, DevState *state, hipStream_t s) {
+    count_partial_kernel<<<dim3((unsigned)n_partial), dim3(256), 0, s>>>(len, S, G, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    count_final_kernel<<<dim3(1), dim3(64), 0, s>>>(partial, n_partial, state);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const int64_t *src_off, const int64_t *n_items, const int64_t *dst_off,
+                         int64_t n_nets, const int64_t *T, const uint8_t *V, int64_t *out_t,
+                         uint8_t *out_v, hipStream_t s) {
+    if (n_nets == 0) return hipSuccess;
+    const int64_t nb = n_nets < 65536 ? n_nets : 65536;
+    gather_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(src_off, n_items, dst_off, n_nets, T, V,
+                                                          out_t, out_v);
+    return hipGetLastError();
+}
+
+}  // namespace gsim

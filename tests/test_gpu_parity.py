@@ -1,0 +1,279 @@
+"""HIP path vs the CPU oracle O1, element by element, through the C ABI.
+
+Every comparison is exact (integer times and 2-bit values: tolerance 0).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2304_13398_amd import gsim as G
+from paper_2304_13398_amd import workloads as W
+from tests import oracle_pins as P
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sim():
+    s = G.Sim(0)
+    yield s
+    s.close()
+
+
+def gpu(sim, nl, st, kernel=0):
+    sim.set_option(G.OPT_KERNEL, kernel)
+    try:
+        return sim.simulate(nl, st)
+    finally:
+        sim.set_option(G.OPT_KERNEL, 0)
+
+
+def assert_same(got, want, nl=None):
+    goff, gt, gv = got
+    woff, wt, wv = want
+    if np.array_equal(goff, woff) and np.array_equal(gt, wt) and np.array_equal(gv, wv):
+        return
+    glen, wlen = np.diff(goff), np.diff(woff)
+    for g in range(len(wlen)):
+        a = list(zip(gt[goff[g]:goff[g + 1]].tolist(), gv[goff[g]:goff[g + 1]].tolist()))
+        b = list(zip(wt[woff[g]:woff[g + 1]].tolist(), wv[woff[g]:woff[g + 1]].tolist()))
+        if a != b:
+            info = ""
+            if nl is not None:
+                info = (f" type={int(nl.type[g])} pins={nl.pin_net[nl.pin_off[g]:nl.pin_off[g + 1]].tolist()}"
+                        f" rise={nl.rise[nl.pin_off[g]:nl.pin_off[g + 1]].tolist()}"
+                        f" fall={nl.fall[nl.pin_off[g]:nl.pin_off[g + 1]].tolist()}")
+            n_bad = int(np.sum(glen != wlen))
+            pytest.fail(f"gate {g} differs ({n_bad} gates with other lengths){info}\n"
+                        f" gpu   ({len(a)}): {a[:12]}\n oracle({len(b)}): {b[:12]}")
+    pytest.fail("arrays differ")
+
+
+def check(sim, nl, st, kernel=0):
+    say(f"case {nl.name or 'netlist'} G={nl.G} S={nl.S} N_in={st.n} kernel={kernel}")
+    want = O.o1_simulate(nl, st)
+    got = gpu(sim, nl, st, kernel)
+    assert_same(got, want, nl)
+    return got
+
+
+def test_config1_tiny(sim):
+    check(sim, *W.config1(seed=1))
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_config1_other_seeds(sim, seed):
+    check(sim, *W.config1(seed=seed))
+
+
+def test_config1_lane_kernel(sim):
+    check(sim, *W.config1(seed=1), kernel=1)
+
+
+def test_config2_generator_20k(sim):
+    """The mid-size generator (power-law fanout, fan-in 1-4) at 20k gates and
+    full depth, 1,000 transitions per PI: many 64-transition tiles per pin and
+    ragged tails."""
+    check(sim, *W.config2(G=20_000, S=64))
+
+
+def test_config3_generator_30k(sim):
+    """Industrial-shaped generator (delays up to 200 ps, 150 levels) at 30k gates."""
+    check(sim, *W.config3(G=30_000, S=300))
+
+
+def test_worked_examples_on_gpu(sim):
+    # Fig. 2: simultaneous falls, minimum delay
+    nl = P.netlist_of(2, [(W.AND2, [0, 1])], [3, 7], [5, 10])
+    st = P.stimulus_of([[(0, 1), (100, 0)], [(0, 1), (100, 0)]])
+    off, t, v = gpu(sim, nl, st)
+    assert list(zip(t.tolist(), v.tolist())) == [(3, 1), (105, 0)]
+    # Fig. 3: glitch eaten, redundant fall dropped
+    nl = P.netlist_of(2, [(W.AND2, [0, 1])], [15, 1], [4, 5])
+    st = P.stimulus_of([[(0, 0), (5, 1)], [(0, 1), (10, 0)]])
+    off, t, v = gpu(sim, nl, st)
+    assert list(zip(t.tolist(), v.tolist())) == [(4, 0)]
+    # several denials by one candidate (4-value logic)
+    nl = P.netlist_of(2, [(W.XOR2, [0, 1])], [100, 1], [100, 1])
+    st = P.stimulus_of([[(10, 1), (11, 2), (12, 0)], [(0, 0), (13, 1)]])
+    off, t, v = gpu(sim, nl, st)
+    assert list(zip(t.tolist(), v.tolist())) == [(14, 1)]
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_zero_delays(sim, kernel):
+    nl = W.make_netlist(G=3000, S=24, L=12, types=W.TYPES_ALL, dmin=0, dmax=0, seed=7,
+                        name="zero-delay")
+    st = W.make_stimulus(S=24, n_per_src=150, window=2000, seed=7)
+    check(sim, nl, st, kernel)
+
+
+def test_delays_at_tentative_window_edge(sim):
+    """Largest pin delay = 256 = the wavefront kernel's tentative window."""
+    nl = W.make_netlist(G=2000, S=16, L=10, types=W.TYPES_ALL, dmin=200, dmax=256, seed=8,
+                        name="dmax256")
+    st = W.make_stimulus(S=16, n_per_src=300, window=3000, seed=8)
+    h = sim.load_netlist(nl)
+    assert sim.netlist_info(h).lane_gates == 0
+    sim.unload_netlist(h)
+    check(sim, nl, st)
+
+
+def test_large_delays_use_lane_kernel(sim):
+    nl = W.make_netlist(G=2000, S=16, L=10, types=W.TYPES_ALL, dmin=0, dmax=900, seed=9,
+                        name="dmax900")
+    st = W.make_stimulus(S=16, n_per_src=300, window=3000, seed=9)
+    h = sim.load_netlist(nl)
+    info = sim.netlist_info(h)
+    assert 0 < info.lane_gates < nl.G
+    sim.unload_netlist(h)
+    check(sim, nl, st)
+
+
+def test_dense_short_pulses(sim):
+    """Transitions 1 ps apart against delays up to 40 ps: long chains of
+    tentative transitions and denials across tile boundaries."""
+    nl = W.make_netlist(G=1500, S=8, L=15, types=W.TYPES_ALL, dmin=0, dmax=40, seed=10,
+                        name="dense")
+    st = W.make_stimulus(S=8, n_per_src=700, window=800, seed=10)
+    check(sim, nl, st)
+
+
+def test_empty_and_single_transition_sources(sim):
+    nl = W.make_netlist(G=800, S=10, L=8, types=W.TYPES_ALL, dmin=1, dmax=30, seed=11,
+                        name="ragged-sources")
+    waves = []
+    rng = np.random.default_rng(11)
+    for s in range(10):
+        n = [0, 1, 0, 2, 63, 64, 65, 127, 128, 129][s]
+        waves.append(P._random_wave(rng, n, 400))
+    check(sim, nl, P.stimulus_of(waves))
+
+
+def test_duplicate_pins_and_z_sources(sim):
+    gates = [(W.XOR2, [0, 0]), (W.AND2, [1, 1]), (W.MUX2, [0, 1, 1]), (W.OR4, [2, 2, 3, 3]),
+             (W.AND4, [4, 5, 4, 6]), (W.NOT, [7]), (W.BUF, [2])]
+    k = sum(len(g[1]) for g in gates)
+    rng = np.random.default_rng(12)
+    nl = P.netlist_of(3, gates, rng.integers(0, 9, k).tolist(), rng.integers(0, 9, k).tolist())
+    waves = [[(0, 3), (5, 1), (9, 3), (12, 2), (20, 0)], [(1, 1), (2, 3), (3, 0)], [(4, 3)]]
+    check(sim, nl, P.stimulus_of(waves))
+
+
+def test_no_gates(sim):
+    nl = P.netlist_of(2, [], [], [])
+    st = P.stimulus_of([[(0, 1)], []])
+    h = sim.load_netlist(nl)
+    j = sim.run(h, st)
+    sim.wait(j)
+    off, t, v = sim.fetch(j)
+    assert off.tolist() == [0, 1, 1] and t.tolist() == [0] and v.tolist() == [1]
+    sim.release(j)
+    sim.unload_netlist(h)
+
+
+def test_shuffled_gate_order(sim):
+    nl, st = W.config1(seed=5)
+    rng = np.random.default_rng(1)
+    perm = rng.permutation(nl.G)
+    inv = np.argsort(perm)
+    remap = np.concatenate([np.arange(nl.S), nl.S + inv])
+    gates = [(int(nl.type[g]), [int(remap[x]) for x in nl.pin_net[nl.pin_off[g]:nl.pin_off[g + 1]]])
+             for g in perm]
+    rise = np.concatenate([nl.rise[nl.pin_off[g]:nl.pin_off[g + 1]] for g in perm])
+    fall = np.concatenate([nl.fall[nl.pin_off[g]:nl.pin_off[g + 1]] for g in perm])
+    check(sim, P.netlist_of(nl.S, gates, rise, fall), st)
+
+
+def test_fetch_subset_sources_and_stats(sim):
+    nl, st = W.config1(seed=6)
+    want = O.o1_simulate(nl, st)
+    h = sim.load_netlist(nl)
+    j = sim.run(h, st)
+    sim.wait(j)
+    nets = np.array([nl.S + 5, 3, nl.S + nl.G - 1, 0, nl.S + 5])
+    off, t, v = sim.fetch(j, nets)
+    for i, n in enumerate(nets.tolist()):
+        a, b = off[i], off[i + 1]
+        if n < nl.S:
+            wt, wv = st.t[st.off[n]:st.off[n + 1]], st.v[st.off[n]:st.off[n + 1]]
+        else:
+            g = n - nl.S
+            wt, wv = want[1][want[0][g]:want[0][g + 1]], want[2][want[0][g]:want[0][g + 1]]
+        assert np.array_equal(t[a:b], wt) and np.array_equal(v[a:b], wv)
+    s = sim.stats(j)
+    assert s.n_in == st.n and s.n_out == int(want[0][-1])
+    assert s.pin_reads >= s.n_out and s.device_ms > 0
+    with pytest.raises(G.GsimError) as e:
+        sim.fetch(j, np.array([nl.S + nl.G]))
+    assert e.value.status == G.E_ARG
+    sim.release(j)
+    with pytest.raises(G.GsimError) as e:
+        sim.wait(j)
+    assert e.value.status == G.E_HANDLE
+    sim.unload_netlist(h)
+
+
+def test_two_runs_identical(sim):
+    nl, st = W.config2(G=5000, S=32, L=30, n_per_src=400)
+    a = gpu(sim, nl, st)
+    b = gpu(sim, nl, st)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_arena_overflow_reports_oom(sim):
+    nl, st = W.config1(seed=1)
+    h = sim.load_netlist(nl)
+    sim.set_option(G.OPT_ARENA_TRANSITIONS, st.n + 1000)
+    try:
+        j = sim.run(h, st)
+        with pytest.raises(G.GsimError) as e:
+            sim.wait(j)
+        assert e.value.status == G.E_OOM
+        sim.release(j)
+    finally:
+        sim.set_option(G.OPT_ARENA_TRANSITIONS, 0)
+    j = sim.run(h, st)          # the context still works afterwards
+    sim.wait(j)
+    off, t, v = sim.fetch(j, np.arange(nl.S, nl.S + nl.G))
+    assert_same((off, t, v), O.o1_simulate(nl, st), nl)
+    sim.release(j)
+    sim.unload_netlist(h)
+
+
+def test_invalid_stimulus_rejected(sim):
+    nl, st = W.config1(seed=1)
+    h = sim.load_netlist(nl)
+    bad_v = st.v.copy()
+    bad_v[5] = bad_v[4]
+    with pytest.raises(G.GsimError) as e:
+        sim.run(h, W.Stimulus(st.off, st.t, bad_v))
+    assert e.value.status == G.E_WAVEFORM
+    sim.unload_netlist(h)
+
+
+def test_run_device_from_torch(sim):
+    import torch
+    nl, st = W.config1(seed=2)
+    want = O.o1_simulate(nl, st)
+    dev = torch.device("cuda:0")
+    d_off = torch.from_numpy(st.off).to(dev)
+    d_t = torch.from_numpy(st.t).to(dev)
+    d_v = torch.from_numpy(st.v).to(dev)
+    stream = torch.cuda.current_stream()
+    h = sim.load_netlist(nl)
+    j = sim.run_device(h, d_off.data_ptr(), d_t.data_ptr(), d_v.data_ptr(), st.n,
+                       stream=stream.cuda_stream, validate=True)
+    sim.wait(j)
+    got = sim.fetch(j, np.arange(nl.S, nl.S + nl.G))
+    assert_same(got, want, nl)
+    sim.release(j)
+    sim.unload_netlist(h)
