@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Throughput of the re-simulation hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--seed S] [--no-cpu-baseline]
+
+A step is one whole job: every level of the 1M-gate mid-size workload (1M
+gates, 2,048 PIs, 60 levels, fan-in 1-4, power-law fanout, 1-50 ps delays,
+1,000 transitions per PI over 1 us) simulated from stimuli already resident
+in HBM, through the C ABI (sim_run_device), on one stream, with jobs
+enqueued two deep so host enqueue overlaps device work. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--gates", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-levels", type=int, default=10,
+                    help="levels of the workload the oracle runs for the CPU baseline")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="instead of the workload, time a plain device-to-device copy of BYTES "
+                         "(the practical HBM ceiling, and the reference for the profiler's "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
+    return ap.parse_args()
+
+
+def copy_probe(nbytes, reps=5):
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    gbps = 2 * nbytes / (ms / 1000.0) / 1e9
+    print(json.dumps({"copy_probe_bytes": nbytes, "ms_per_copy": ms,
+                      "read_plus_write_gbps": gbps}), flush=True)
+    return 0
+
+
+def algorithmic_bytes(nl, lengths):
+    """Bytes the evaluate launches must move, per level: every input waveform a
+    level reads once (8 B per transition: the device packs time << 2 | value
+    into one word), every output written once, the 64-byte gate record, the
+    per-net offset and length (16 B) of every pin read and of every output
+    written."""
+    S = nl.S
+    per_level = []
+    pin_gate = np.repeat(np.arange(nl.G), np.diff(nl.pin_off))
+    for lv in range(1, int(nl.level.max()) + 1):
+        gates = np.nonzero(nl.level == lv)[0]
+        pins = np.isin(pin_gate, gates)
+        nets = np.unique(nl.pin_net[pins])
+        b = 8 * int(lengths[nets].sum()) + 8 * int(lengths[S + gates].sum())
+        b += 64 * len(gates) + 16 * int(pins.sum()) + 16 * len(gates)
+        per_level.append(b)
+    return per_level
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path.", file=sys.stderr, flush=True)
+        return 2
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
+    import torch
+    from paper_2304_13398_amd import gsim as G
+    from paper_2304_13398_amd import workloads as W
+
+    t_gen = time.perf_counter()
+    S = max(32, int(round(2048 * args.gates / 1_000_000)))
+    nl, st = W.config2(seed=args.seed, G=args.gates, S=S)
+    t_gen = time.perf_counter() - t_gen
+    print(f"[bench] workload generated in {t_gen:.1f}s: G={nl.G} S={nl.S} P={nl.P} N_in={st.n}",
+          file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    d_off = torch.from_numpy(st.off).to(dev)
+    d_t = torch.from_numpy(st.t).to(dev)
+    d_v = torch.from_numpy(st.v).to(dev)
+    stream = torch.cuda.current_stream()
+    sim = G.Sim(0)
+    sim.set_option(G.OPT_KERNEL_TIMING, 1)
+    h = sim.load_netlist(nl)
+    info = sim.netlist_info(h)
+
+    def launch():
+        return sim.run_device(h, d_off.data_ptr(), d_t.data_ptr(), d_v.data_ptr(), st.n,
+                              stream=stream.cuda_stream)
+
+    stats = []
+
+    def finish(j, keep):
+        sim.wait(j)
+        if keep:
+            stats.append(sim.stats(j))
+        sim.release(j)
+
+    # warmup (also validates the stimuli once on the device copy)
+    j = sim.run_device(h, d_off.data_ptr(), d_t.data_ptr(), d_v.data_ptr(), st.n,
+                       stream=stream.cuda_stream, validate=True)
+    finish(j, False)
+    for _ in range(max(0, args.warmup - 1)):
+        finish(launch(), False)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prev = None
+    for _ in range(args.steps):
+        j = launch()
+        if prev is not None:
+            finish(prev, True)
+        prev = j
+    if prev is not None:
+        finish(prev, True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    print(f"[bench] timed {args.steps} steps in {wall:.3f}s", file=sys.stderr, flush=True)
+
+    n_out = stats[-1].n_out
+    assert all(s.n_out == n_out for s in stats), "steps disagree on the output size"
+    ms_per_step = wall / args.steps * 1000.0
+    value = n_out / (ms_per_step / 1000.0)
+    dev_ms = statistics.median(s.device_ms for s in stats)
+    eval_ms = statistics.median(s.eval_ms for s in stats)
+    launches = stats[-1].eval_launches
+
+    # algorithmic bytes of the evaluate launches, from this run's lengths
+    j = launch()
+    sim.wait(j)
+    off = np.zeros(nl.S + nl.G + 1, dtype=np.int64)
+    sim.lib.sim_fetch_waveforms(sim.ctx, j, None, nl.S + nl.G,
+                                off.ctypes.data_as(G.ctypes.c_void_p), None, None, 0)
+    sim.release(j)
+    lengths = np.diff(off)
+    per_level = algorithmic_bytes(nl, lengths)
+    b_eval = float(sum(per_level))
+    achieved = b_eval / (eval_ms / 1000.0) / 1e9
+    b_pin = 8.0 * stats[-1].pin_reads + 8.0 * n_out
+
+    out = {
+        "metric": "output transitions/sec",
+        "value": value,
+        "unit": "transitions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {
+            "workload": "mid-size re-simulation: 1M-gate levelled random DAG, 2,048 PIs, "
+                        "60 levels, fan-in 1-4, power-law fanout (alpha 2.2, cap 1,000), "
+                        "rise/fall 1-50 ps, 1,000 transitions per PI over [0, 1e6] ps, "
+                        "values 0/1/X/Z p=.45/.45/.05/.05",
+            "seed": args.seed, "gates": nl.G, "sources": nl.S, "pins": nl.P,
+            "levels": info.levels, "n_in": st.n, "n_out": int(n_out),
+            "parallelism": "single GPU",
+        },
+        "device_ms_per_step": dev_ms,
+        "hbm_gbps_step": (b_eval / (dev_ms / 1000.0) / 1e9),
+        "roofline": {
+            "kernel": "eval_wave_kernel (+ eval_lane_kernel, none here)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": None,
+            "algorithmic_bytes_per_launch": b_eval / launches,
+            "avg_launch_ms": eval_ms / launches,
+            "launches_per_step": launches,
+            "per_pin_bytes_gbps": b_pin / (eval_ms / 1000.0) / 1e9,
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        lv = min(args.cpu_levels, info.levels)
+        n_gates = int(np.searchsorted(nl.level, lv, side="right"))
+        sub = nl.prefix(n_gates)
+        t1 = time.perf_counter()
+        o_off, _, _ = O.o1_simulate(sub, st)
+        cpu_s = time.perf_counter() - t1
+        out["cpu_baseline"] = {
+            "value": float(o_off[-1]) / cpu_s,
+            "unit": "transitions/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"oracle O1 (single thread, plain C) on levels 1-{lv} of the same workload "
+                      f"({n_gates} gates, {int(o_off[-1])} output transitions, {cpu_s:.1f}s)",
+        }
+    print(json.dumps(out), flush=True)
+    sim.unload_netlist(h)
+    sim.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

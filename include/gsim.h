@@ -89,7 +89,10 @@ enum gsim_option {
     GSIM_OPT_KERNEL = 2,
     /* Level loop: 0 = one stream-ordered launch chain per run, 1 = the chain
      * captured once in a HIP graph and replayed. */
-    GSIM_OPT_LEVEL_LOOP = 3
+    GSIM_OPT_LEVEL_LOOP = 3,
+    /* 1 = bracket every level's evaluate launches with HIP events on the job's
+     * stream; sim_job_stats then reports their summed device time. */
+    GSIM_OPT_KERNEL_TIMING = 4
 };
 
 /* ---- context ------------------------------------------------------------ */
@@ -165,6 +168,9 @@ typedef struct {
     int64_t arena_used;      /* transitions of output storage reserved */
     int64_t arena_capacity;
     double device_ms;        /* device time of the level chain (HIP events) */
+    double eval_ms;          /* with GSIM_OPT_KERNEL_TIMING: summed device time of the
+                                evaluate launches, else 0 */
+    int64_t eval_launches;   /* levels timed for eval_ms */
 } gsim_job_stats;
 /* Statistics of a finished job (waits for it). */
 gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out);

@@ -284,9 +284,15 @@ class Pool {
 
 // ---------------------------------------------------------------------------
 
+// Gates of one level, in three consecutive groups: wavefront kernel with the
+// small tentative window, wavefront kernel with the large window, lane kernel.
 struct LevelRange {
-    int64_t begin, n_wave, n_lane;  // gates [begin, begin+n_wave) wave kernel, then n_lane lane kernel
+    int64_t begin, n_small, n_large, n_lane;
+    int64_t size() const { return n_small + n_large + n_lane; }
 };
+
+// Evaluate-kernel class of a gate by its largest pin delay.
+enum GateClass { kClassSmall = 0, kClassLarge = 1, kClassLane = 2 };
 
 struct Netlist {
     int64_t S = 0, G = 0, P = 0;
@@ -308,11 +314,13 @@ struct Job {
     int64_t n_in = 0, capacity = 0;
     int64_t *d_off = nullptr, *d_len = nullptr, *d_blocksum = nullptr, *d_partial = nullptr;
     int64_t *d_src_off = nullptr;
-    int64_t *d_T = nullptr;
-    uint8_t *d_V = nullptr;
+    int64_t *d_src_t = nullptr;   // host stimuli staged on the device (sim_run only)
+    uint8_t *d_src_v = nullptr;
+    uint64_t *d_K = nullptr;      // arena of packed transitions
     DevState *d_state = nullptr;
     DevState *h_state = nullptr;  // pinned
     hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_done = nullptr;
+    std::vector<hipEvent_t> ev_levels;  // with kernel timing: before/after each level's evaluate
     bool waited = false, failed = false;
     int64_t n_partial = 0;
 };
@@ -331,6 +339,7 @@ struct gsim_ctx_s {
     int64_t opt_arena = 0;
     int opt_kernel = 0;
     int opt_level_loop = 0;
+    int opt_timing = 0;
 };
 
 namespace {
@@ -359,12 +368,13 @@ void free_job_buffers(gsim_ctx ctx, Job *j) {
     pool.put(j->d_blocksum);
     pool.put(j->d_partial);
     pool.put(j->d_src_off);
-    pool.put(j->d_T);
-    pool.put(j->d_V);
+    pool.put(j->d_src_t);
+    pool.put(j->d_src_v);
+    pool.put(j->d_K);
     pool.put(j->d_state);
-    j->d_off = j->d_len = j->d_blocksum = j->d_partial = j->d_src_off = nullptr;
-    j->d_T = nullptr;
-    j->d_V = nullptr;
+    j->d_off = j->d_len = j->d_blocksum = j->d_partial = j->d_src_off = j->d_src_t = nullptr;
+    j->d_src_v = nullptr;
+    j->d_K = nullptr;
     j->d_state = nullptr;
 }
 
@@ -375,6 +385,8 @@ void destroy_job(gsim_ctx ctx, Job *j) {
     if (j->ev_start) (void)hipEventDestroy(j->ev_start);
     if (j->ev_end) (void)hipEventDestroy(j->ev_end);
     if (j->ev_done) (void)hipEventDestroy(j->ev_done);
+    for (hipEvent_t e : j->ev_levels) (void)hipEventDestroy(e);
+    j->ev_levels.clear();
     j->h_state = nullptr;
     j->ev_start = j->ev_end = j->ev_done = nullptr;
 }
@@ -402,26 +414,34 @@ Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, co
         for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++) d = std::max(d, std::max(rise[p], fall[p]));
         return d;
     };
-    auto is_lane = [&](int64_t g) { return ctx->opt_kernel == 1 || gate_dmax(g) > kCarryCap; };
+    auto gate_class = [&](int64_t g) {
+        if (ctx->opt_kernel == 1) return (int)kClassLane;
+        const int32_t d = gate_dmax(g);
+        return d <= kWindowSmall ? (int)kClassSmall : d <= kWindowLarge ? (int)kClassLarge : (int)kClassLane;
+    };
     const int32_t L = lv.n_levels;
-    std::vector<int64_t> cnt(2 * (size_t)L + 2, 0);
-    for (int64_t g = 0; g < G; g++) cnt[2 * (size_t)lv.level[g] + (is_lane(g) ? 1 : 0)]++;
+    std::vector<int64_t> cnt(3 * ((size_t)L + 1), 0);
+    std::vector<int> cls(G);
+    for (int64_t g = 0; g < G; g++) {
+        cls[g] = gate_class(g);
+        cnt[3 * (size_t)lv.level[g] + cls[g]]++;
+    }
     std::vector<int64_t> start(cnt.size() + 1, 0);
     for (size_t i = 0; i < cnt.size(); i++) start[i + 1] = start[i] + cnt[i];
     nl->levels.resize(L);
     for (int32_t l = 1; l <= L; l++) {
         LevelRange &r = nl->levels[l - 1];
-        r.begin = start[2 * (size_t)l];
-        r.n_wave = cnt[2 * (size_t)l];
-        r.n_lane = cnt[2 * (size_t)l + 1];
+        r.begin = start[3 * (size_t)l];
+        r.n_small = cnt[3 * (size_t)l + kClassSmall];
+        r.n_large = cnt[3 * (size_t)l + kClassLarge];
+        r.n_lane = cnt[3 * (size_t)l + kClassLane];
         nl->lane_gates += r.n_lane;
-        nl->max_level_blocks = std::max(nl->max_level_blocks, (r.n_wave + r.n_lane + kSizeBlock - 1) / kSizeBlock);
+        nl->max_level_blocks = std::max(nl->max_level_blocks, (r.size() + kSizeBlock - 1) / kSizeBlock);
     }
     nl->internal_of_user.resize(G);
     {
         std::vector<int64_t> fill(start.begin(), start.end() - 1);
-        for (int64_t g = 0; g < G; g++)
-            nl->internal_of_user[g] = fill[2 * (size_t)lv.level[g] + (is_lane(g) ? 1 : 0)]++;
+        for (int64_t g = 0; g < G; g++) nl->internal_of_user[g] = fill[3 * (size_t)lv.level[g] + cls[g]]++;
     }
     std::vector<GateRec> recs(G);
     for (int64_t g = 0; g < G; g++) {
@@ -463,32 +483,39 @@ T *pool_get(Pool &pool, int64_t n) {
 }
 
 // Enqueue the level chain of a job whose sources are already in the arena.
-Failure enqueue_levels(gsim_ctx ctx, Job *j) {
+Failure enqueue_levels(gsim_ctx ctx, Job *j, const int64_t *src_t, const uint8_t *src_v) {
     Netlist &nl = *j->nl;
     hipStream_t s = j->stream;
-    HIP_TRY(launch_init_sources(j->d_src_off, nl.S, j->d_off, j->d_len, j->d_state, j->n_in, j->capacity, s));
     HIP_TRY(hipEventRecord(j->ev_start, s));
+    HIP_TRY(launch_init_sources(j->d_src_off, src_t, src_v, nl.S, j->n_in, j->d_off, j->d_len, j->d_K,
+                                j->d_state, j->capacity, s));
     EvalArgs a;
     a.rec = nl.d_rec;
     a.S = nl.S;
     a.blockbase = j->d_blocksum;
     a.off = j->d_off;
     a.len = j->d_len;
-    a.T = j->d_T;
-    a.V = j->d_V;
+    a.K = j->d_K;
     a.state = j->d_state;
     a.lut = ctx->d_lut;
-    for (const LevelRange &r : nl.levels) {
-        const int64_t n = r.n_wave + r.n_lane;
+    const bool timing = !j->ev_levels.empty();
+    for (size_t l = 0; l < nl.levels.size(); l++) {
+        const LevelRange &r = nl.levels[l];
+        const int64_t n = r.size();
         HIP_TRY(launch_size(nl.d_rec, r.begin, n, nl.S, j->d_len, j->d_off, j->d_blocksum, s));
         HIP_TRY(launch_level_scan(j->d_blocksum, (n + kSizeBlock - 1) / kSizeBlock, j->d_state, s));
+        if (timing) HIP_TRY(hipEventRecord(j->ev_levels[2 * l], s));
         a.lvl_begin = r.begin;
         a.g_begin = r.begin;
-        a.n = r.n_wave;
-        HIP_TRY(launch_eval_wave(a, s));
-        a.g_begin = r.begin + r.n_wave;
+        a.n = r.n_small;
+        HIP_TRY(launch_eval_wave(a, kWindowSmall, s));
+        a.g_begin = r.begin + r.n_small;
+        a.n = r.n_large;
+        HIP_TRY(launch_eval_wave(a, kWindowLarge, s));
+        a.g_begin = r.begin + r.n_small + r.n_large;
         a.n = r.n_lane;
         HIP_TRY(launch_eval_lane(a, s));
+        if (timing) HIP_TRY(hipEventRecord(j->ev_levels[2 * l + 1], s));
     }
     HIP_TRY(hipEventRecord(j->ev_end, s));
     HIP_TRY(launch_count_out(j->d_len, nl.S, nl.G, j->d_partial, j->n_partial, j->d_state, s));
@@ -499,7 +526,7 @@ Failure enqueue_levels(gsim_ctx ctx, Job *j) {
 
 int64_t default_capacity(const Netlist &nl, int64_t n_in) {
     // Twice the pin-read volume of a circuit whose every net is as long as
-    // the mean source waveform, plus the sources.
+    // the mean source waveform, plus the sources (in transitions).
     const double mean = nl.S > 0 ? (double)n_in / (double)nl.S : 0.0;
     const double est = (double)n_in + 2.0 * (double)nl.P * mean + 1024.0;
     return (int64_t)std::min(est, 9.0e18);
@@ -535,13 +562,12 @@ Failure start_job(gsim_ctx ctx, gsim_netlist nlh, int64_t n_in, hipStream_t stre
     if (ctx->opt_arena <= 0) {
         // fit the automatic estimate into what the budget leaves
         const uint64_t room = pool.budget() > pool.live() ? pool.budget() - pool.live() : 0;
-        const int64_t fit = (int64_t)(room / 9 * 95 / 100);
+        const int64_t fit = (int64_t)(room / sizeof(uint64_t) * 95 / 100);
         if (cap > fit) cap = std::max(n_in, fit - (4 << 20));
     }
     j->capacity = cap;
-    j->d_T = pool_get<int64_t>(pool, cap);
-    j->d_V = j->d_T ? pool_get<uint8_t>(pool, cap) : nullptr;
-    if (!j->d_T || !j->d_V) {
+    j->d_K = pool_get<uint64_t>(pool, cap);
+    if (!j->d_K) {
         free_job_buffers(ctx, j.get());
         return fail(GSIM_E_OOM, "no device memory for an output arena of %lld transitions", (long long)cap);
     }
@@ -551,6 +577,15 @@ Failure start_job(gsim_ctx ctx, gsim_netlist nlh, int64_t n_in, hipStream_t stre
         (void)hipGetLastError();
         destroy_job(ctx, j.get());
         return fail(GSIM_E_DEVICE, "event or pinned-memory creation failed");
+    }
+    if (ctx->opt_timing) {
+        j->ev_levels.resize(2 * nl.levels.size(), nullptr);
+        for (hipEvent_t &e : j->ev_levels)
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                destroy_job(ctx, j.get());
+                return fail(GSIM_E_DEVICE, "event creation failed");
+            }
     }
     out = std::move(j);
     return kOk;
@@ -570,11 +605,14 @@ Failure run_host(gsim_ctx ctx, gsim_netlist nlh, const int64_t *src_off, const i
     if (f.st != GSIM_OK) return f;
     hipStream_t s = j->stream;
     auto cleanup = [&](Failure e) { destroy_job(ctx, j.get()); return e; };
+    j->d_src_t = pool_get<int64_t>(*ctx->pool, n_in);
+    j->d_src_v = pool_get<uint8_t>(*ctx->pool, n_in);
+    if (!j->d_src_t || !j->d_src_v) return cleanup(fail(GSIM_E_OOM, "no device memory to stage the stimuli"));
     if (hipMemcpyAsync(j->d_src_off, src_off, sizeof(int64_t) * (size_t)(nl.S + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
-        (n_in > 0 && hipMemcpyAsync(j->d_T, t, sizeof(int64_t) * (size_t)n_in, hipMemcpyHostToDevice, s) != hipSuccess) ||
-        (n_in > 0 && hipMemcpyAsync(j->d_V, v, (size_t)n_in, hipMemcpyHostToDevice, s) != hipSuccess))
+        (n_in > 0 && hipMemcpyAsync(j->d_src_t, t, sizeof(int64_t) * (size_t)n_in, hipMemcpyHostToDevice, s) != hipSuccess) ||
+        (n_in > 0 && hipMemcpyAsync(j->d_src_v, v, (size_t)n_in, hipMemcpyHostToDevice, s) != hipSuccess))
         return cleanup(fail(GSIM_E_DEVICE, "stimulus upload: %s", hipGetErrorString(hipGetLastError())));
-    f = enqueue_levels(ctx, j.get());
+    f = enqueue_levels(ctx, j.get(), j->d_src_t, j->d_src_v);
     if (f.st != GSIM_OK) return cleanup(f);
     const int64_t id = ctx->next_id++;
     ctx->jobs[id] = std::move(j);
@@ -608,11 +646,9 @@ Failure run_device(gsim_ctx ctx, gsim_netlist nlh, const int64_t *d_src_off, con
     if (f.st != GSIM_OK) return f;
     hipStream_t s = j->stream;
     auto cleanup = [&](Failure e) { destroy_job(ctx, j.get()); return e; };
-    if (hipMemcpyAsync(j->d_src_off, d_src_off, sizeof(int64_t) * (size_t)(nl.S + 1), hipMemcpyDeviceToDevice, s) != hipSuccess ||
-        (n_in > 0 && hipMemcpyAsync(j->d_T, d_t, sizeof(int64_t) * (size_t)n_in, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
-        (n_in > 0 && hipMemcpyAsync(j->d_V, d_v, (size_t)n_in, hipMemcpyDeviceToDevice, s) != hipSuccess))
+    if (hipMemcpyAsync(j->d_src_off, d_src_off, sizeof(int64_t) * (size_t)(nl.S + 1), hipMemcpyDeviceToDevice, s) != hipSuccess)
         return cleanup(fail(GSIM_E_DEVICE, "stimulus copy: %s", hipGetErrorString(hipGetLastError())));
-    f = enqueue_levels(ctx, j.get());
+    f = enqueue_levels(ctx, j.get(), d_t, d_v);
     if (f.st != GSIM_OK) return cleanup(f);
     const int64_t id = ctx->next_id++;
     ctx->jobs[id] = std::move(j);
@@ -641,8 +677,8 @@ Failure wait_job(gsim_ctx ctx, Job *j) {
     if (j->failed)
         return fail(GSIM_E_OOM, "output arena of %lld transitions overflowed; set GSIM_OPT_ARENA_TRANSITIONS larger",
                     (long long)j->capacity);
-    if (j->h_state->carry_error)
-        return fail(GSIM_E_DEVICE, "internal consistency check failed (code %d)", j->h_state->carry_error);
+    if (j->h_state->check_error)
+        return fail(GSIM_E_DEVICE, "internal consistency check failed (code %d)", j->h_state->check_error);
     return kOk;
 }
 
@@ -680,37 +716,36 @@ Failure fetch(gsim_ctx ctx, Job *j, const int64_t *nets, int64_t n, int64_t *out
     if (!d_st || !d_sv || !d_meta) { release(); return fail(GSIM_E_OOM, "no device memory for the fetch staging buffer"); }
     hipStream_t s = ctx->stream;
     std::vector<int64_t> meta(3 * max_batch);
-    int64_t i = 0;
+    // Walk the requested nets in order, filling the staging buffer; a net
+    // that does not fit in what is left is split across batches.
+    int64_t i = 0, done_in_net = 0;  // next net, transitions of it already copied
     while (i < n) {
-        // nets [i, e) whose total fits the staging buffer (a single larger net is copied directly)
-        const int64_t li = len[internal[i]];
-        if (li > stage) {
-            const int64_t a = off[internal[i]];
-            hipError_t e1 = hipMemcpy(out_t + out_off[i], j->d_T + a, sizeof(int64_t) * (size_t)li, hipMemcpyDeviceToHost);
-            hipError_t e2 = hipMemcpy(out_v + out_off[i], j->d_V + a, (size_t)li, hipMemcpyDeviceToHost);
-            if (e1 != hipSuccess || e2 != hipSuccess) { release(); return fail(GSIM_E_DEVICE, "fetch copy failed"); }
-            i++;
-            continue;
+        int64_t nb = 0, acc = 0;
+        const int64_t dst0 = out_off[i] + done_in_net;
+        while (i < n && nb < max_batch && acc < stage) {
+            const int64_t li = len[internal[i]] - done_in_net;
+            const int64_t take = std::min(li, stage - acc);
+            meta[nb] = off[internal[i]] + done_in_net;
+            meta[max_batch + nb] = take;
+            meta[2 * max_batch + nb] = acc;
+            nb++;
+            acc += take;
+            if (take == li) {
+                i++;
+                done_in_net = 0;
+            } else {
+                done_in_net += take;
+            }
         }
-        int64_t e = i, acc = 0;
-        while (e < n && e - i < max_batch && acc + len[internal[e]] <= stage) {
-            meta[e - i] = off[internal[e]];
-            meta[max_batch + (e - i)] = len[internal[e]];
-            meta[2 * max_batch + (e - i)] = acc;
-            acc += len[internal[e]];
-            e++;
-        }
-        const int64_t nb = e - i;
         hipError_t err = hipMemcpyAsync(d_meta, meta.data(), sizeof(int64_t) * 3 * (size_t)max_batch, hipMemcpyHostToDevice, s);
         if (err == hipSuccess)
-            err = launch_gather(d_meta, d_meta + max_batch, d_meta + 2 * max_batch, nb, j->d_T, j->d_V, d_st, d_sv, s);
+            err = launch_gather(d_meta, d_meta + max_batch, d_meta + 2 * max_batch, nb, j->d_K, d_st, d_sv, s);
         if (err == hipSuccess && acc > 0)
-            err = hipMemcpyAsync(out_t + out_off[i], d_st, sizeof(int64_t) * (size_t)acc, hipMemcpyDeviceToHost, s);
+            err = hipMemcpyAsync(out_t + dst0, d_st, sizeof(int64_t) * (size_t)acc, hipMemcpyDeviceToHost, s);
         if (err == hipSuccess && acc > 0)
-            err = hipMemcpyAsync(out_v + out_off[i], d_sv, (size_t)acc, hipMemcpyDeviceToHost, s);
+            err = hipMemcpyAsync(out_v + dst0, d_sv, (size_t)acc, hipMemcpyDeviceToHost, s);
         if (err == hipSuccess) err = hipStreamSynchronize(s);
         if (err != hipSuccess) { release(); return fail(GSIM_E_DEVICE, "fetch: %s", hipGetErrorString(err)); }
-        i = e;
     }
     release();
     return kOk;
@@ -789,6 +824,10 @@ gsim_status sim_set_option(gsim_ctx ctx, int option, int64_t value) {
         if (value < 0 || value > 1) return record(ctx, fail(GSIM_E_ARG, "level loop option must be 0 or 1"));
         ctx->opt_level_loop = (int)value;
         return GSIM_OK;
+    case GSIM_OPT_KERNEL_TIMING:
+        if (value < 0 || value > 1) return record(ctx, fail(GSIM_E_ARG, "timing option must be 0 or 1"));
+        ctx->opt_timing = (int)value;
+        return GSIM_OK;
     }
     return record(ctx, fail(GSIM_E_ARG, "unknown option %d", option));
 }
@@ -865,6 +904,15 @@ gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out) {
     out->arena_used = j->h_state->arena_top;
     out->arena_capacity = j->capacity;
     out->device_ms = ms;
+    out->eval_ms = 0.0;
+    out->eval_launches = 0;
+    for (size_t l = 0; l + 1 < j->ev_levels.size(); l += 2) {
+        float e = 0.f;
+        if (hipEventElapsedTime(&e, j->ev_levels[l], j->ev_levels[l + 1]) != hipSuccess)
+            return record(ctx, fail(GSIM_E_DEVICE, "event timing failed"));
+        out->eval_ms += e;
+        out->eval_launches++;
+    }
     return GSIM_OK;
 }
 

@@ -11,14 +11,26 @@ constexpr uint8_t kX = 2;
 constexpr int64_t kInf = INT64_MAX;
 constexpr int64_t kTimeLimit = int64_t(1) << 62;  // times live in [0, 2^62)
 
-// Transitions per pin loaded per round of the wavefront kernel (one per lane).
-constexpr int kTile = 64;
-// Tentative (not yet final) output transitions the wavefront kernel can hold
-// between rounds. A tentative transition appears after the round's horizon H
-// and at most the gate's largest pin delay after it, and tentative appearance
-// times are distinct integers, so a gate whose largest pin delay is at most
-// kCarryCap never needs more.
-constexpr int kCarryCap = 256;
+// Device transitions are packed into one 64-bit word: time << 2 | value.
+// Times are below 2^62, so the word is unsigned-ordered by time first; no two
+// transitions of one waveform share a time. kNoKey sorts after every
+// transition.
+constexpr uint64_t kNoKey = ~uint64_t(0);
+__host__ __device__ constexpr uint64_t pack_key(int64_t t, uint32_t v) {
+    return ((uint64_t)t << 2) | (uint64_t)v;
+}
+__host__ __device__ constexpr int64_t key_time(uint64_t k) { return (int64_t)(k >> 2); }
+__host__ __device__ constexpr uint32_t key_value(uint64_t k) { return (uint32_t)(k & 3); }
+
+// Wavefront evaluate kernel: input transitions in flight per round (over all
+// pins of the gate), and the delay classes it serves. A tentative output
+// transition appears after the round's horizon H and at most the gate's
+// largest pin delay after it, and tentative appearance times are distinct
+// integers, so a gate whose largest pin delay is at most the class's window
+// never holds more tentative transitions than that.
+constexpr int kRoundSlots = 256;
+constexpr int kWindowSmall = 64;
+constexpr int kWindowLarge = 256;
 // Gates handled per sizing block.
 constexpr int kSizeBlock = 256;
 
@@ -44,7 +56,7 @@ struct DevState {
     int64_t pin_reads;       // sum of reserved bounds = sum over pins of read lengths
     int64_t n_out;           // output transitions (filled by the final reduction)
     int32_t overflow;        // arena exhausted: later levels are skipped
-    int32_t carry_error;     // wavefront kernel exceeded its tentative window (never expected)
+    int32_t check_error;     // an internal consistency check failed (never expected)
 };
 
 struct EvalArgs {
@@ -56,24 +68,25 @@ struct EvalArgs {
     const int64_t *blockbase;  // per sizing block: absolute arena base
     int64_t *off;            // [S+G] arena offset of each net
     int64_t *len;            // [S+G] transitions of each net
-    int64_t *T;              // arena times
-    uint8_t *V;              // arena values
+    uint64_t *K;             // arena of packed transitions
     DevState *state;
     const uint8_t *lut;      // [kNumTypes][256] gate value by packed pin values
 };
 
 // Kernel launchers (kernels.hip). All are asynchronous on `s`.
-hipError_t launch_init_sources(const int64_t *d_src_off, int64_t S, int64_t *off, int64_t *len,
-                               DevState *state, int64_t n_in, int64_t capacity, hipStream_t s);
+hipError_t launch_init_sources(const int64_t *d_src_off, const int64_t *d_t, const uint8_t *d_v,
+                               int64_t S, int64_t n_in, int64_t *off, int64_t *len, uint64_t *K,
+                               DevState *state, int64_t capacity, hipStream_t s);
 hipError_t launch_size(const GateRec *rec, int64_t lvl_begin, int64_t n, int64_t S,
                        const int64_t *len, int64_t *off, int64_t *blocksum, hipStream_t s);
 hipError_t launch_level_scan(int64_t *blocksum, int64_t nb, DevState *state, hipStream_t s);
-hipError_t launch_eval_wave(const EvalArgs &a, hipStream_t s);
+// window: kWindowSmall or kWindowLarge (every gate of the launch has dmax <= window)
+hipError_t launch_eval_wave(const EvalArgs &a, int window, hipStream_t s);
 hipError_t launch_eval_lane(const EvalArgs &a, hipStream_t s);
 hipError_t launch_count_out(const int64_t *len, int64_t S, int64_t G, int64_t *partial,
                             int64_t n_partial, DevState *state, hipStream_t s);
 hipError_t launch_gather(const int64_t *src_off, const int64_t *n_items, const int64_t *dst_off,
-                         int64_t n_nets, const int64_t *T, const uint8_t *V, int64_t *out_t,
-                         uint8_t *out_v, hipStream_t s);
+                         int64_t n_nets, const uint64_t *K, int64_t *out_t, uint8_t *out_v,
+                         hipStream_t s);
 
 }  // namespace gsim

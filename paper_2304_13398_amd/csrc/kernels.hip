@@ -12,24 +12,30 @@
 //            advances the arena top (a device bump allocator).
 //   eval   : the output waveform of every gate of the level (Algorithm 2 with
 //            the Eq. 1 denial and the Fig. 3 drop), written at its base.
+// Transitions live in the arena packed as time << 2 | value (8 bytes).
 #include "gsim_internal.h"
 
 namespace gsim {
 
 namespace {
 
-__device__ __forceinline__ int64_t readlane64(int64_t x, int lane) {
-    int lo = __builtin_amdgcn_readlane((int)(uint32_t)x, lane);
-    int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), lane);
-    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_down_u64(uint64_t x, int d) {
+    const uint32_t lo = (uint32_t)__shfl_down((int)(uint32_t)x, d, 64);
+    const uint32_t hi = (uint32_t)__shfl_down((int)(uint32_t)(x >> 32), d, 64);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ int64_t shfl_down64(int64_t x, int d) {
-    int lo = __shfl_down((int)(uint32_t)x, d, 64);
-    int hi = __shfl_down((int)(uint32_t)((uint64_t)x >> 32), d, 64);
-    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    return (int64_t)shfl_down_u64((uint64_t)x, d);
 }
 
+__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
@@ -42,7 +48,7 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
 
 // Delay of one pin for a new output value: 1 -> rise, 0 -> fall, X -> the
 // smaller of the two.
-__device__ __forceinline__ int64_t pin_delay(int32_t rise, int32_t fall, uint8_t v) {
+__device__ __forceinline__ int32_t pin_delay(int32_t rise, int32_t fall, uint32_t v) {
     return v == 1 ? rise : v == 0 ? fall : (rise < fall ? rise : fall);
 }
 
@@ -51,42 +57,46 @@ __device__ __forceinline__ int wave_incl_sum(int x) {
     const int lane = lane_id();
 #pragma unroll
     for (int s = 1; s < 64; s <<= 1) {
-        int o = __shfl_up(x, s, 64);
+        const int o = __shfl_up(x, s, 64);
         if (lane >= s) x += o;
     }
     return x;
 }
 
 // Wave-wide inclusive suffix minimum (over lanes >= this lane).
-__device__ __forceinline__ int64_t wave_suffix_min(int64_t x) {
+__device__ __forceinline__ uint64_t wave_suffix_min(uint64_t x) {
     const int lane = lane_id();
 #pragma unroll
     for (int s = 1; s < 64; s <<= 1) {
-        int64_t o = shfl_down64(x, s);
-        if (lane + s < 64) x = min64(x, o);
+        const uint64_t o = shfl_down_u64(x, s);
+        if (lane + s < 64) x = umin64(x, o);
     }
     return x;
 }
 
 // -------------------------------------------------------------------------
-// Sources: copied into the arena at [0, n_in) by the host; here their
-// offsets and lengths, and the job state.
-__global__ void init_sources_kernel(const int64_t *__restrict__ src_off, int64_t S,
-                                    int64_t *__restrict__ off, int64_t *__restrict__ len,
-                                    DevState *state, int64_t n_in, int64_t capacity) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < S) {
-        int64_t a = src_off[i];
+// Sources: packed into the arena at [0, n_in); their offsets and lengths; the
+// job state.
+__global__ void init_sources_kernel(const int64_t *__restrict__ src_off,
+                                    const int64_t *__restrict__ t, const uint8_t *__restrict__ v,
+                                    int64_t S, int64_t n_in, int64_t *__restrict__ off,
+                                    int64_t *__restrict__ len, uint64_t *__restrict__ K,
+                                    DevState *state, int64_t capacity) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = i0; i < n_in; i += stride) K[i] = pack_key(t[i], v[i]);
+    for (int64_t i = i0; i < S; i += stride) {
+        const int64_t a = src_off[i];
         off[i] = a;
         len[i] = src_off[i + 1] - a;
     }
-    if (i == 0) {
+    if (i0 == 0) {
         state->arena_top = n_in;
         state->capacity = capacity;
         state->pin_reads = 0;
         state->n_out = 0;
         state->overflow = 0;
-        state->carry_error = 0;
+        state->check_error = 0;
     }
 }
 
@@ -108,14 +118,13 @@ __global__ __launch_bounds__(kSizeBlock) void size_kernel(const GateRec *__restr
         for (int p = 0; p < kMaxPins; p++)
             if (p < k) w += len[r.net[p]];
     }
-    // inclusive scan within the wave (64-bit)
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     int64_t x = w;
 #pragma unroll
     for (int s = 1; s < 64; s <<= 1) {
-        int lo = __shfl_up((int)(uint32_t)x, s, 64);
-        int hi = __shfl_up((int)(uint32_t)((uint64_t)x >> 32), s, 64);
-        int64_t o = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+        const int lo = __shfl_up((int)(uint32_t)x, s, 64);
+        const int hi = __shfl_up((int)(uint32_t)((uint64_t)x >> 32), s, 64);
+        const int64_t o = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
         if (lane >= s) x += o;
     }
     if (lane == 63) wsum[wv] = x;
@@ -144,9 +153,9 @@ __global__ __launch_bounds__(1024) void level_scan_kernel(int64_t *__restrict__ 
         int64_t x = w;
 #pragma unroll
         for (int s = 1; s < 64; s <<= 1) {
-            int lo = __shfl_up((int)(uint32_t)x, s, 64);
-            int hi = __shfl_up((int)(uint32_t)((uint64_t)x >> 32), s, 64);
-            int64_t o = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+            const int lo = __shfl_up((int)(uint32_t)x, s, 64);
+            const int hi = __shfl_up((int)(uint32_t)((uint64_t)x >> 32), s, 64);
+            const int64_t o = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
             if (lane >= s) x += o;
         }
         if (lane == 63) wsum[wv] = x;
@@ -189,179 +198,215 @@ __global__ __launch_bounds__(1024) void level_scan_kernel(int64_t *__restrict__ 
 // same as keeping, among the survivors, those whose value differs from the
 // previous survivor's (X before the first).
 //
-// The wave walks the inputs in rounds of up to 64 transitions per pin. The
-// round's horizon H is the smallest last-loaded time over pins that have more
-// transitions beyond the tile; every input transition at or before H is in
-// the round. Each lane takes one transition per pin: it finds, by binary
-// search in the other pins' tiles, how many of their transitions are before
-// or at its time, which gives its rank in the merged order, whether it is the
-// first transition at that time, the pin values just before and just after
-// that time, hence e before/after and the candidate. Candidates are scattered
-// by merged rank, and survivors come from a reverse suffix minimum over the
-// wave. A survivor with r <= H is final (later candidates appear after H); the
-// others stay tentative in LDS and are re-tested against the next rounds. At
-// most (largest pin delay) of them exist (distinct integer appearance times in
-// (H, H + dmax]), so gates with dmax <= kCarryCap are handled exactly.
+// The wave walks the inputs in rounds of up to 256 transitions (T = 256/K per
+// pin for K pins). The round's horizon H is the smallest last-loaded time over
+// pins that have more transitions beyond their tile (capped so the round spans
+// less than 2^30 ps); every input transition at or before H is in the round.
+// In-round times are rebased to 32 bits in LDS. Each lane takes T/64
+// transitions per pin: binary search in the other pins' tiles gives how many
+// of their transitions are before or at its time, hence its rank in the merged
+// order, whether it is the first transition at that time, the pin values just
+// before and just after that time, e before/after and the candidate.
+// Candidates are scattered by merged rank, and survivors come from a reverse
+// suffix minimum over the wave. A survivor with r <= H is final (later
+// candidates appear after H); the others stay tentative in LDS and are
+// re-tested against the next rounds -- at most `window` of them exist (see
+// kWindowSmall). The next round's tiles are prefetched into registers while
+// the current one is processed.
+template <int W>
 struct WaveLds {
-    int64_t tt[kMaxPins][kTile];        // tile times (kInf beyond the pin's end)
-    int64_t sr[kMaxPins * kTile];       // candidate appearance time by merged rank (kInf: none)
-    int64_t qr[kCarryCap + kMaxPins * kTile];  // tentative survivors, then this round's
-    uint8_t tv[kMaxPins][kTile];
-    uint8_t sv[kMaxPins * kTile];
-    uint8_t qv[kCarryCap + kMaxPins * kTile];
+    uint64_t seq[W + kRoundSlots];  // tentative survivors [0, nq), then this round's;
+                                    // the round's candidate slots alias seq[W, W + 256)
+    uint32_t tile[kRoundSlots];     // K tiles of T rebased keys (time - base) << 2 | value
     uint8_t lut[256];
 };
 
-// Number of entries of the sorted 64-entry tile `a` that are < t.
-__device__ __forceinline__ int count_less(const int64_t *a, int64_t t) {
+template <int K>
+struct Tiling {
+    static constexpr int T = K == 1 ? 256 : K == 2 ? 128 : 64;  // transitions per pin per round
+    static constexpr int E = T / 64;                              // per lane per pin
+    static constexpr int LOG2T = K == 1 ? 8 : K == 2 ? 7 : 6;
+};
+
+constexpr uint32_t kNoKey32 = 0xFFFFFFFFu;
+constexpr int64_t kSpan = (int64_t(1) << 30) - 2;  // largest in-round time offset
+
+// Entries of the sorted tile a[0, 2^LOG2T) whose key is < x.
+template <int LOG2T>
+__device__ __forceinline__ int count_less32(const uint32_t *a, uint32_t x) {
     int lo = 0;
 #pragma unroll
-    for (int s = 32; s >= 1; s >>= 1)
-        if (a[lo + s - 1] < t) lo += s;
-    lo += a[lo] < t ? 1 : 0;  // lo <= 63 here
+    for (int s = 1 << (LOG2T - 1); s >= 1; s >>= 1)
+        if (a[lo + s - 1] < x) lo += s;
+    lo += a[lo] < x ? 1 : 0;  // lo <= 2^LOG2T - 1 here
     return lo;
 }
 
-__global__ __launch_bounds__(64) void eval_wave_kernel(EvalArgs A) {
-    __shared__ WaveLds L;
+template <int K, int W>
+__device__ __forceinline__ void eval_gate(const EvalArgs &A, const GateRec &R, int64_t gate,
+                                          WaveLds<W> &L) {
+    using Tl = Tiling<K>;
+    constexpr int T = Tl::T, E = Tl::E;
     const int lane = lane_id();
-    const int64_t gi = blockIdx.x;
-    if (gi >= A.n) return;
-    const int64_t gate = A.g_begin + gi;
-    const GateRec R = A.rec[gate];
-    const int k = R.k;
     const int64_t S = A.S;
     int64_t *len = A.len;
     int64_t *off = A.off;
+    uint64_t *Kar = A.K;
 
-    if (A.state->overflow) {
-        if (lane == 0) { len[S + gate] = 0; off[S + gate] = 0; }
-        return;
-    }
     const int64_t ob = A.blockbase[(gate - A.lvl_begin) / kSizeBlock] + off[S + gate];
-
-    int64_t pb[kMaxPins], pl[kMaxPins], cur[kMaxPins];
-    uint8_t cval[kMaxPins];
+    int64_t pb[K], pl[K], cur[K];
+    uint32_t cval[K];
     int64_t reserved = 0;  // slots sized for this gate: the sum of its input lengths
 #pragma unroll
-    for (int p = 0; p < kMaxPins; p++) {
-        pb[p] = 0; pl[p] = 0; cur[p] = 0; cval[p] = kX;
-        if (p < k) { pb[p] = off[R.net[p]]; pl[p] = len[R.net[p]]; reserved += pl[p]; }
+    for (int p = 0; p < K; p++) {
+        pb[p] = off[R.net[p]];
+        pl[p] = len[R.net[p]];
+        cur[p] = 0;
+        cval[p] = kX;
+        reserved += pl[p];
     }
-    reinterpret_cast<uint32_t *>(L.lut)[lane] =
-        reinterpret_cast<const uint32_t *>(A.lut + (int)R.type * 256)[lane];
+    int32_t drise[K], dfall[K];
+#pragma unroll
+    for (int p = 0; p < K; p++) { drise[p] = R.rise[p]; dfall[p] = R.fall[p]; }
 
-    const int64_t *__restrict__ T = A.T;
-    const uint8_t *__restrict__ V = A.V;
-    uint8_t last_val = kX;   // value of the last final survivor
-    int nq = 0;              // tentative survivors held in L.qr/L.qv[0, nq)
+    // first tiles
+    uint64_t pre[K][E];
+#pragma unroll
+    for (int p = 0; p < K; p++)
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            const int64_t idx = lane + 64 * e;
+            pre[p][e] = idx < pl[p] ? Kar[pb[p] + idx] : kNoKey;
+        }
+
+    uint32_t last_val = kX;  // value of the last final survivor
+    int nq = 0;              // tentative survivors in L.seq[0, nq)
     int64_t out_n = 0;
+    uint64_t *slots = L.seq + W;
 
     for (;;) {
         bool more = false;
 #pragma unroll
-        for (int p = 0; p < kMaxPins; p++) more |= cur[p] < pl[p];
+        for (int p = 0; p < K; p++) more |= cur[p] < pl[p];
         if (!more) break;
 
-        // ---- load one tile per pin, find the horizon H
-        int64_t my_t[kMaxPins];
-        int64_t rem[kMaxPins];
-        int64_t H = kInf;
+        // ---- horizon, base, in-round counts
+        int64_t rem[K];
+        int64_t H = kInf, base = kInf;
 #pragma unroll
-        for (int p = 0; p < kMaxPins; p++) {
+        for (int p = 0; p < K; p++) {
             rem[p] = pl[p] - cur[p];
-            int64_t x = kInf;
-            uint8_t y = 0;
-            if (lane < rem[p]) {
-                x = T[pb[p] + cur[p] + lane];
-                y = V[pb[p] + cur[p] + lane];
-            }
-            L.tt[p][lane] = x;
-            L.tv[p][lane] = y;
-            my_t[p] = x;
-            if (rem[p] > kTile) H = min64(H, readlane64(x, kTile - 1));
+            if (rem[p] > T) H = min64(H, key_time(readlane_u64(pre[p][E - 1], 63)));
+            if (rem[p] > 0) base = min64(base, key_time(readlane_u64(pre[p][0], 0)));
         }
-        int m[kMaxPins];
+        H = min64(H, base + kSpan);
+        int m[K];
         int M = 0;
 #pragma unroll
-        for (int p = 0; p < kMaxPins; p++) {
-            m[p] = __popcll(__ballot(lane < rem[p] && my_t[p] <= H));
+        for (int p = 0; p < K; p++) {
+            m[p] = 0;
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                const int64_t idx = lane + 64 * e;
+                const uint64_t key = pre[p][e];
+                const bool in = idx < rem[p] && key_time(key) <= H;
+                m[p] += __popcll(__ballot(in));
+                L.tile[p * T + 64 * e + lane] =
+                    in ? (uint32_t)((key_time(key) - base) << 2) | key_value(key) : kNoKey32;
+            }
             M += m[p];
         }
+        // prefetch the next round's tiles
+        uint64_t nxt[K][E];
+#pragma unroll
+        for (int p = 0; p < K; p++)
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                const int64_t idx = cur[p] + m[p] + lane + 64 * e;
+                nxt[p][e] = idx < pl[p] ? Kar[pb[p] + idx] : kNoKey;
+            }
         __syncthreads();
 
         // ---- candidates, scattered by merged rank
 #pragma unroll
-        for (int p = 0; p < kMaxPins; p++) {
-            if (p >= k || lane >= m[p]) continue;
-            const int64_t t = my_t[p];
-            int lb[kMaxPins];
-            bool eq[kMaxPins];
-            bool leader = true;
-            int rank = lane;
+        for (int p = 0; p < K; p++) {
 #pragma unroll
-            for (int q = 0; q < kMaxPins; q++) {
-                if (q >= k) { lb[q] = 0; eq[q] = false; continue; }
-                if (q == p) { lb[q] = lane; eq[q] = true; continue; }
-                lb[q] = count_less(L.tt[q], t);
-                eq[q] = lb[q] < kTile && L.tt[q][lb[q] < kTile ? lb[q] : 0] == t;
-                if (q < p) {
-                    leader = leader && !eq[q];
-                    rank += lb[q] + (eq[q] ? 1 : 0);
-                } else {
-                    rank += lb[q];
+            for (int e = 0; e < E; e++) {
+                const int j = lane + 64 * e;
+                if (j >= m[p]) continue;
+                const uint32_t key = L.tile[p * T + j];
+                const uint32_t tk = key & ~3u;
+                int lb[K];
+                bool eq[K];
+                bool leader = true;
+                int rank = j;
+#pragma unroll
+                for (int q = 0; q < K; q++) {
+                    if (q == p) { lb[q] = j; eq[q] = true; continue; }
+                    lb[q] = count_less32<Tl::LOG2T>(L.tile + q * T, tk);
+                    eq[q] = (L.tile[q * T + (lb[q] < T ? lb[q] : T - 1)] & ~3u) == tk && lb[q] < T;
+                    if (q < p) {
+                        leader = leader && !eq[q];
+                        rank += lb[q] + (eq[q] ? 1 : 0);
+                    } else {
+                        rank += lb[q];
+                    }
                 }
+                uint64_t slot = kNoKey;
+                if (leader) {
+                    int pack_after = 0, pack_before = 0;
+#pragma unroll
+                    for (int q = 0; q < K; q++) {
+                        uint32_t va, vb;
+                        if (q == p) {
+                            va = key & 3u;
+                            vb = j > 0 ? (L.tile[p * T + j - 1] & 3u) : cval[p];
+                        } else {
+                            const int ub = lb[q] + (eq[q] ? 1 : 0);
+                            va = ub > 0 ? (L.tile[q * T + ub - 1] & 3u) : cval[q];
+                            vb = lb[q] > 0 ? (L.tile[q * T + lb[q] - 1] & 3u) : cval[q];
+                        }
+                        pack_after |= (int)va << (2 * q);
+                        pack_before |= (int)vb << (2 * q);
+                    }
+                    const uint32_t ea = L.lut[pack_after];
+                    const uint32_t eb = L.lut[pack_before];
+                    if (ea != eb) {
+                        int32_t d = INT32_MAX;
+#pragma unroll
+                        for (int q = 0; q < K; q++)
+                            if (eq[q]) {
+                                const int32_t dq = pin_delay(drise[q], dfall[q], ea);
+                                d = dq < d ? dq : d;
+                            }
+                        slot = pack_key(base + (int64_t)(tk >> 2) + d, ea);
+                    }
+                }
+                slots[rank] = slot;
             }
-            int64_t r = kInf;
-            uint8_t sv = 0xFF;
-            if (leader) {
-                int pack_after = 0, pack_before = 0;
-#pragma unroll
-                for (int q = 0; q < kMaxPins; q++) {
-                    if (q >= k) continue;
-                    const int ub = lb[q] + (eq[q] ? 1 : 0);
-                    const uint8_t va = ub > 0 ? L.tv[q][ub - 1] : cval[q];
-                    const uint8_t vb = lb[q] > 0 ? L.tv[q][lb[q] - 1] : cval[q];
-                    pack_after |= (int)va << (2 * q);
-                    pack_before |= (int)vb << (2 * q);
-                }
-                const uint8_t ea = L.lut[pack_after];
-                const uint8_t eb = L.lut[pack_before];
-                if (ea != eb) {
-                    int64_t d = kInf;
-#pragma unroll
-                    for (int q = 0; q < kMaxPins; q++)
-                        if (q < k && eq[q]) d = min64(d, pin_delay(R.rise[q], R.fall[q], ea));
-                    r = t + d;
-                    sv = ea;
-                }
-            }
-            L.sr[rank] = r;
-            L.sv[rank] = sv;
         }
         __syncthreads();
 
         // ---- survivors among this round's candidates (reverse suffix minimum)
-        int64_t r4[4];
-        uint8_t v4[4];
+        uint64_t r4[4];
         int64_t lmin = kInf;
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             const int s = lane * 4 + j;
-            r4[j] = s < M ? L.sr[s] : kInf;
-            v4[j] = s < M ? L.sv[s] : 0xFF;
-            lmin = min64(lmin, r4[j]);
+            r4[j] = s < M ? slots[s] : kNoKey;
+            lmin = min64(lmin, key_time(r4[j]));
         }
-        const int64_t suf = wave_suffix_min(lmin);
-        const int64_t round_min = readlane64(suf, 0);
+        const int64_t suf = (int64_t)wave_suffix_min((uint64_t)lmin);
+        const int64_t round_min = (int64_t)readlane_u64((uint64_t)suf, 0);
         int64_t later = shfl_down64(suf, 1);
         if (lane == 63) later = kInf;
         bool keep4[4];
         int nkeep = 0;
 #pragma unroll
         for (int j = 3; j >= 0; j--) {
-            keep4[j] = v4[j] != 0xFF && r4[j] < later;
-            later = min64(later, r4[j]);
+            const int64_t rj = key_time(r4[j]);
+            keep4[j] = r4[j] != kNoKey && rj < later;
+            later = min64(later, rj);
             nkeep += keep4[j] ? 1 : 0;
         }
         // tentative survivors of earlier rounds outlive this round iff they
@@ -369,15 +414,16 @@ __global__ __launch_bounds__(64) void eval_wave_kernel(EvalArgs A) {
         int ncs = 0;
         for (int c0 = 0; c0 < nq; c0 += 64) {
             const int c = c0 + lane;
-            ncs += __popcll(__ballot(c < nq && L.qr[c] < round_min));
+            ncs += __popcll(__ballot(c < nq && key_time(L.seq[c]) < round_min));
         }
         const int incl = wave_incl_sum(nkeep);
         const int nsurv = __builtin_amdgcn_readlane(incl, 63);
+        __syncthreads();  // every lane has read its slots before they are overwritten
         {
             int pos = ncs + incl - nkeep;
 #pragma unroll
             for (int j = 0; j < 4; j++)
-                if (keep4[j]) { L.qr[pos] = r4[j]; L.qv[pos] = v4[j]; pos++; }
+                if (keep4[j]) L.seq[pos++] = r4[j];
         }
         const int nseq = ncs + nsurv;
         __syncthreads();
@@ -386,63 +432,84 @@ __global__ __launch_bounds__(64) void eval_wave_kernel(EvalArgs A) {
         int nf = 0;
         for (int c0 = 0; c0 < nseq; c0 += 64) {
             const int c = c0 + lane;
-            nf += __popcll(__ballot(c < nseq && L.qr[c] <= H));
+            nf += __popcll(__ballot(c < nseq && key_time(L.seq[c]) <= H));
         }
         for (int c0 = 0; c0 < nf; c0 += 64) {
             const int j = c0 + lane;
             const bool in = j < nf;
-            const uint8_t v = in ? L.qv[j] : 0;
-            const uint8_t vp = j == 0 ? last_val : (in ? L.qv[j - 1] : 0);
+            const uint64_t kj = in ? L.seq[j] : 0;
+            const uint32_t v = key_value(kj);
+            const uint32_t vp = j == 0 ? last_val : (in ? key_value(L.seq[j - 1]) : 0u);
             const bool keep = in && v != vp;
             const uint64_t mask = __ballot(keep);
             const int64_t at = out_n + lanes_below(mask);
-            if (keep && at < reserved) {
-                A.T[ob + at] = L.qr[j];
-                A.V[ob + at] = v;
-            }
+            if (keep && at < reserved) Kar[ob + at] = kj;
             out_n += __popcll(mask);
         }
-        if (nf > 0) last_val = L.qv[nf - 1];
+        if (nf > 0) last_val = key_value(L.seq[nf - 1]);
 
         // ---- keep the tentative ones at the front for the next round
         int ntent = nseq - nf;
-        if (ntent > kCarryCap) {  // cannot happen for dmax <= kCarryCap
-            if (lane == 0) A.state->carry_error = 1;
-            ntent = kCarryCap;
+        if (ntent > W) {  // cannot happen when dmax <= W
+            if (lane == 0) A.state->check_error = 1;
+            ntent = W;
         }
         if (nf > 0 && ntent > 0) {
-            int64_t rr[kCarryCap / 64];
-            uint8_t vv[kCarryCap / 64];
+            uint64_t rr[W / 64];
 #pragma unroll
-            for (int c = 0; c < kCarryCap / 64; c++) {
+            for (int c = 0; c < W / 64; c++) {
                 const int j = c * 64 + lane;
-                if (j < ntent) { rr[c] = L.qr[nf + j]; vv[c] = L.qv[nf + j]; }
+                if (j < ntent) rr[c] = L.seq[nf + j];
             }
             __syncthreads();
 #pragma unroll
-            for (int c = 0; c < kCarryCap / 64; c++) {
+            for (int c = 0; c < W / 64; c++) {
                 const int j = c * 64 + lane;
-                if (j < ntent) { L.qr[j] = rr[c]; L.qv[j] = vv[c]; }
+                if (j < ntent) L.seq[j] = rr[c];
             }
         }
         nq = ntent;
 
 #pragma unroll
-        for (int p = 0; p < kMaxPins; p++) {
+        for (int p = 0; p < K; p++) {
             if (m[p] > 0) {
-                cval[p] = L.tv[p][m[p] - 1];
+                cval[p] = L.tile[p * T + m[p] - 1] & 3u;
                 cur[p] += m[p];
             }
+#pragma unroll
+            for (int e = 0; e < E; e++) pre[p][e] = nxt[p][e];
         }
         __syncthreads();
     }
     if (out_n > reserved) {  // cannot happen: at most one output per distinct input time
-        if (lane == 0) A.state->carry_error = 2;
+        if (lane == 0) A.state->check_error = 2;
         out_n = reserved;
     }
     if (lane == 0) {
         len[S + gate] = out_n;
         off[S + gate] = ob;
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(64) void eval_wave_kernel(EvalArgs A) {
+    __shared__ WaveLds<W> L;
+    const int lane = lane_id();
+    const int64_t gi = blockIdx.x;
+    if (gi >= A.n) return;
+    const int64_t gate = A.g_begin + gi;
+    const GateRec R = A.rec[gate];
+    if (A.state->overflow) {
+        if (lane == 0) { A.len[A.S + gate] = 0; A.off[A.S + gate] = 0; }
+        return;
+    }
+    reinterpret_cast<uint32_t *>(L.lut)[lane] =
+        reinterpret_cast<const uint32_t *>(A.lut + (int)R.type * 256)[lane];
+    switch (R.k) {
+    case 1: eval_gate<1, W>(A, R, gate, L); break;
+    case 2: eval_gate<2, W>(A, R, gate, L); break;
+    case 3: eval_gate<3, W>(A, R, gate, L); break;
+    default: eval_gate<4, W>(A, R, gate, L); break;
     }
 }
 
@@ -464,47 +531,48 @@ __global__ __launch_bounds__(64) void eval_lane_kernel(EvalArgs A) {
     const int k = R.k;
     const int64_t ob = A.blockbase[(gate - A.lvl_begin) / kSizeBlock] + A.off[S + gate];
     int64_t pb[kMaxPins], pl[kMaxPins], idx[kMaxPins];
-    uint8_t cv[kMaxPins];
+    uint32_t cv[kMaxPins];
     int64_t reserved = 0;
     for (int p = 0; p < kMaxPins; p++) {
         pb[p] = 0; pl[p] = 0; idx[p] = 0; cv[p] = kX;
         if (p < k) { pb[p] = A.off[R.net[p]]; pl[p] = A.len[R.net[p]]; reserved += pl[p]; }
     }
     const uint8_t *lut = A.lut + (int)R.type * 256;
-    int64_t *T = A.T;
-    uint8_t *V = A.V;
-    uint8_t prev = kX;
+    uint64_t *Kar = A.K;
+    uint32_t prev = kX;
     int64_t n = 0;
     for (;;) {
         int64_t te = kInf;
         for (int p = 0; p < k; p++)
-            if (idx[p] < pl[p]) te = min64(te, T[pb[p] + idx[p]]);
+            if (idx[p] < pl[p]) te = min64(te, key_time(Kar[pb[p] + idx[p]]));
         if (te == kInf) break;
         int changed = 0;
         int pack = 0;
         for (int p = 0; p < k; p++) {
-            if (idx[p] < pl[p] && T[pb[p] + idx[p]] == te) {
-                cv[p] = V[pb[p] + idx[p]];
-                idx[p]++;
-                changed |= 1 << p;
+            if (idx[p] < pl[p]) {
+                const uint64_t kp = Kar[pb[p] + idx[p]];
+                if (key_time(kp) == te) {
+                    cv[p] = key_value(kp);
+                    idx[p]++;
+                    changed |= 1 << p;
+                }
             }
             pack |= (int)cv[p] << (2 * p);
         }
-        const uint8_t e = lut[pack];
+        const uint32_t e = lut[pack];
         if (e != prev) {
             int64_t d = kInf;
             for (int p = 0; p < k; p++)
                 if (changed & (1 << p)) d = min64(d, pin_delay(R.rise[p], R.fall[p], e));
             const int64_t tr = te + d;
-            while (n > 0 && T[ob + n - 1] >= tr) n--;
-            const uint8_t cur = n > 0 ? V[ob + n - 1] : kX;
+            while (n > 0 && key_time(Kar[ob + n - 1]) >= tr) n--;
+            const uint32_t cur = n > 0 ? key_value(Kar[ob + n - 1]) : kX;
             if (e != cur) {
                 if (n >= reserved) {  // cannot happen: at most one output per distinct input time
-                    A.state->carry_error = 2;
+                    A.state->check_error = 2;
                     break;
                 }
-                T[ob + n] = tr;
-                V[ob + n] = e;
+                Kar[ob + n] = pack_key(tr, e);
                 n++;
             }
         }
@@ -540,21 +608,21 @@ __global__ __launch_bounds__(64) void count_final_kernel(const int64_t *__restri
 }
 
 // -------------------------------------------------------------------------
-// Gather: net i's n_items[i] transitions from the arena at src_off[i] to the
-// staging buffers at dst_off[i]. One block per net.
+// Gather: net i's n_items[i] transitions from the arena at src_off[i],
+// unpacked into the staging buffers at dst_off[i]. One block per net.
 __global__ __launch_bounds__(256) void gather_kernel(const int64_t *__restrict__ src_off,
                                                      const int64_t *__restrict__ n_items,
                                                      const int64_t *__restrict__ dst_off,
                                                      int64_t n_nets,
-                                                     const int64_t *__restrict__ T,
-                                                     const uint8_t *__restrict__ V,
+                                                     const uint64_t *__restrict__ K,
                                                      int64_t *__restrict__ out_t,
                                                      uint8_t *__restrict__ out_v) {
     for (int64_t i = blockIdx.x; i < n_nets; i += gridDim.x) {
         const int64_t a = src_off[i], n = n_items[i], d = dst_off[i];
         for (int64_t j = threadIdx.x; j < n; j += 256) {
-            out_t[d + j] = T[a + j];
-            out_v[d + j] = V[a + j];
+            const uint64_t k = K[a + j];
+            out_t[d + j] = key_time(k);
+            out_v[d + j] = (uint8_t)key_value(k);
         }
     }
 }
@@ -564,11 +632,14 @@ __global__ __launch_bounds__(256) void gather_kernel(const int64_t *__restrict__
 // -------------------------------------------------------------------------
 // Launchers.
 
-hipError_t launch_init_sources(const int64_t *d_src_off, int64_t S, int64_t *off, int64_t *len,
-                               DevState *state, int64_t n_in, int64_t capacity, hipStream_t s) {
-    const int64_t nb = (S + 255) / 256 > 0 ? (S + 255) / 256 : 1;
-    init_sources_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(d_src_off, S, off, len, state,
-                                                                n_in, capacity);
+hipError_t launch_init_sources(const int64_t *d_src_off, const int64_t *d_t, const uint8_t *d_v,
+                               int64_t S, int64_t n_in, int64_t *off, int64_t *len, uint64_t *K,
+                               DevState *state, int64_t capacity, hipStream_t s) {
+    const int64_t work = n_in > S ? n_in : S;
+    int64_t nb = (work + 255) / 256;
+    nb = nb < 1 ? 1 : nb > 8192 ? 8192 : nb;
+    init_sources_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(d_src_off, d_t, d_v, S, n_in,
+                                                                off, len, K, state, capacity);
     return hipGetLastError();
 }
 
@@ -586,9 +657,12 @@ hipError_t launch_level_scan(int64_t *blocksum, int64_t nb, DevState *state, hip
     return hipGetLastError();
 }
 
-hipError_t launch_eval_wave(const EvalArgs &a, hipStream_t s) {
+hipError_t launch_eval_wave(const EvalArgs &a, int window, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    eval_wave_kernel<<<dim3((unsigned)a.n), dim3(64), 0, s>>>(a);
+    if (window == kWindowSmall)
+        eval_wave_kernel<kWindowSmall><<<dim3((unsigned)a.n), dim3(64), 0, s>>>(a);
+    else
+        eval_wave_kernel<kWindowLarge><<<dim3((unsigned)a.n), dim3(64), 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -609,11 +683,11 @@ hipError_t launch_count_out(const int64_t *len, int64_t S, int64_t G, int64_t *p
 }
 
 hipError_t launch_gather(const int64_t *src_off, const int64_t *n_items, const int64_t *dst_off,
-                         int64_t n_nets, const int64_t *T, const uint8_t *V, int64_t *out_t,
-                         uint8_t *out_v, hipStream_t s) {
+                         int64_t n_nets, const uint64_t *K, int64_t *out_t, uint8_t *out_v,
+                         hipStream_t s) {
     if (n_nets == 0) return hipSuccess;
     const int64_t nb = n_nets < 65536 ? n_nets : 65536;
-    gather_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(src_off, n_items, dst_off, n_nets, T, V,
+    gather_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(src_off, n_items, dst_off, n_nets, K,
                                                           out_t, out_v);
     return hipGetLastError();
 }

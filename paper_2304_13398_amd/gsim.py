@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG, "libgsim.so")
 OK, E_ARG, E_CYCLE, E_WAVEFORM, E_OOM, E_DEVICE, E_HANDLE, E_OVERFLOW = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "OK", -1: "GSIM_E_ARG", -2: "GSIM_E_CYCLE", -3: "GSIM_E_WAVEFORM",
                 -4: "GSIM_E_OOM", -5: "GSIM_E_DEVICE", -6: "GSIM_E_HANDLE", -7: "GSIM_E_OVERFLOW"}
-OPT_ARENA_TRANSITIONS, OPT_KERNEL, OPT_LEVEL_LOOP = 1, 2, 3
+OPT_ARENA_TRANSITIONS, OPT_KERNEL, OPT_LEVEL_LOOP, OPT_KERNEL_TIMING = 1, 2, 3, 4
 
 EXPORTED = ("sim_create", "sim_destroy", "sim_last_error", "sim_set_option", "sim_load_netlist",
             "sim_unload_netlist", "sim_netlist_info", "sim_run", "sim_run_device", "sim_wait",
@@ -41,7 +41,8 @@ class NetlistInfo(ctypes.Structure):
 class JobStats(ctypes.Structure):
     _fields_ = [("n_in", ctypes.c_int64), ("n_out", ctypes.c_int64),
                 ("pin_reads", ctypes.c_int64), ("arena_used", ctypes.c_int64),
-                ("arena_capacity", ctypes.c_int64), ("device_ms", ctypes.c_double)]
+                ("arena_capacity", ctypes.c_int64), ("device_ms", ctypes.c_double),
+                ("eval_ms", ctypes.c_double), ("eval_launches", ctypes.c_int64)]
 
 
 _lib = None
