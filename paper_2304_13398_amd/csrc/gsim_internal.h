@@ -28,7 +28,7 @@ __host__ __device__ constexpr uint32_t key_value(uint64_t k) { return (uint32_t)
 // largest pin delay after it, and tentative appearance times are distinct
 // integers, so a gate whose largest pin delay is at most the class's window
 // never holds more tentative transitions than that.
-constexpr int kRoundSlots = 256;
+constexpr int kRoundSlots = 512;
 constexpr int kWindowSmall = 64;
 constexpr int kWindowLarge = 256;
 // Gates handled per sizing block.

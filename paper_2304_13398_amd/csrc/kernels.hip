@@ -184,6 +184,44 @@ __global__ __launch_bounds__(1024) void level_scan_kernel(int64_t *__restrict__ 
 }
 
 // -------------------------------------------------------------------------
+// Wave-wide scans with DPP (GFX9 row shifts and row broadcasts): inclusive,
+// in lane order, 12 VALU operations and no LDS traffic.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t identity, uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)x, CTRL, ROW_MASK, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
+
+__device__ __forceinline__ uint32_t wave_prefix_min(uint32_t x) {
+    x = umin32(x, dpp_u32<kDppRowShr1>(~0u, x));
+    x = umin32(x, dpp_u32<kDppRowShr2>(~0u, x));
+    x = umin32(x, dpp_u32<kDppRowShr4>(~0u, x));
+    x = umin32(x, dpp_u32<kDppRowShr8>(~0u, x));
+    x = umin32(x, dpp_u32<kDppRowBcast15, 0xa>(~0u, x));
+    x = umin32(x, dpp_u32<kDppRowBcast31, 0xc>(~0u, x));
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t x) {
+    x += dpp_u32<kDppRowShr1>(0u, x);
+    x += dpp_u32<kDppRowShr2>(0u, x);
+    x += dpp_u32<kDppRowShr4>(0u, x);
+    x += dpp_u32<kDppRowShr8>(0u, x);
+    x += dpp_u32<kDppRowBcast15, 0xa>(0u, x);
+    x += dpp_u32<kDppRowBcast31, 0xc>(0u, x);
+    return x;
+}
+
+// The value of the previous lane (identity on lane 0).
+__device__ __forceinline__ uint32_t wave_shift_up(uint32_t identity, uint32_t x) {
+    return dpp_u32<kDppWaveShr1>(identity, x);
+}
+
+// -------------------------------------------------------------------------
 // Wavefront-per-gate evaluation.
 //
 // The per-gate procedure (Algorithm 2 with Eq. 1 and the Fig. 3 drop) is
@@ -198,55 +236,52 @@ __global__ __launch_bounds__(1024) void level_scan_kernel(int64_t *__restrict__ 
 // same as keeping, among the survivors, those whose value differs from the
 // previous survivor's (X before the first).
 //
-// The wave walks the inputs in rounds of up to 256 transitions (T = 256/K per
-// pin for K pins). The round's horizon H is the smallest last-loaded time over
-// pins that have more transitions beyond their tile (capped so the round spans
-// less than 2^30 ps); every input transition at or before H is in the round.
-// In-round times are rebased to 32 bits in LDS. Each lane takes T/64
-// transitions per pin: binary search in the other pins' tiles gives how many
-// of their transitions are before or at its time, hence its rank in the merged
-// order, whether it is the first transition at that time, the pin values just
-// before and just after that time, e before/after and the candidate.
-// Candidates are scattered by merged rank, and survivors come from a reverse
-// suffix minimum over the wave. A survivor with r <= H is final (later
-// candidates appear after H); the others stay tentative in LDS and are
-// re-tested against the next rounds -- at most `window` of them exist (see
-// kWindowSmall). The next round's tiles are prefetched into registers while
-// the current one is processed.
+// The wave walks the inputs in rounds of up to 512 transitions (T = 512/K per
+// pin for K pins, a multiple of 64). The round's horizon H is the smallest
+// last-loaded time over pins that have more transitions beyond their tile,
+// capped so the round spans less than 2^30 ps; every input transition at or
+// before H is in the round. All in-round times, and the appearance times of
+// candidates and of tentative survivors, are held as 32-bit offsets from the
+// round's base, packed with the value as offset << 2 | value. Each lane takes
+// T/64 transitions per pin; a branch-free binary search in each other pin's
+// tile gives how many of its transitions are before the lane's time and
+// whether one is at it -- hence the merged rank, whether this is the first
+// transition at that time, and the pin values just before and just after it
+// (each tile starts with a holder of the pin's value before the round and ends
+// with a terminator). Candidates are scattered by merged rank; survivors come
+// from a suffix minimum over the round (DPP scans). A survivor with r <= H is
+// final (later candidates appear after H); the others stay tentative in LDS
+// and are re-tested against the next rounds -- at most W of them exist for
+// gates whose largest pin delay is at most W (see kWindowSmall). The next
+// round's tiles are prefetched into registers while the current one runs.
 template <int W>
 struct WaveLds {
-    uint64_t seq[W + kRoundSlots];  // tentative survivors [0, nq), then this round's;
-                                    // the round's candidate slots alias seq[W, W + 256)
-    uint32_t tile[kRoundSlots];     // K tiles of T rebased keys (time - base) << 2 | value
+    uint32_t seq[W + kRoundSlots];  // tentative survivors [0, nq), then this round's;
+                                    // the round's candidate slots alias seq[W, W + 512)
+    uint32_t tile[kRoundSlots + 8]; // K tiles of [value holder, T rebased keys, terminator]
     uint8_t lut[256];
 };
 
 template <int K>
 struct Tiling {
-    static constexpr int T = K == 1 ? 256 : K == 2 ? 128 : 64;  // transitions per pin per round
+    static constexpr int T = K == 1 ? 512 : K == 2 ? 256 : 128;  // transitions per pin per round
     static constexpr int E = T / 64;                              // per lane per pin
-    static constexpr int LOG2T = K == 1 ? 8 : K == 2 ? 7 : 6;
+    static constexpr int STRIDE = T + 2;                          // tile stride in LDS
 };
+static_assert(kRoundSlots == 512, "tiling assumes 512-transition rounds");
 
 constexpr uint32_t kNoKey32 = 0xFFFFFFFFu;
-constexpr int64_t kSpan = (int64_t(1) << 30) - 2;  // largest in-round time offset
-
-// Entries of the sorted tile a[0, 2^LOG2T) whose key is < x.
-template <int LOG2T>
-__device__ __forceinline__ int count_less32(const uint32_t *a, uint32_t x) {
-    int lo = 0;
-#pragma unroll
-    for (int s = 1 << (LOG2T - 1); s >= 1; s >>= 1)
-        if (a[lo + s - 1] < x) lo += s;
-    lo += a[lo] < x ? 1 : 0;  // lo <= 2^LOG2T - 1 here
-    return lo;
-}
+// Largest in-round time offset: candidate offsets (time + delay <= kSpan +
+// kWindowLarge) and tentative offsets stay below 2^30 - 1, so offset << 2 |
+// value never reaches kNoKey32 >> 2 << 2.
+constexpr int64_t kSpan = (int64_t(1) << 30) - 2 - 2 * kWindowLarge;
 
 template <int K, int W>
 __device__ __forceinline__ void eval_gate(const EvalArgs &A, const GateRec &R, int64_t gate,
                                           WaveLds<W> &L) {
     using Tl = Tiling<K>;
-    constexpr int T = Tl::T, E = Tl::E;
+    constexpr int T = Tl::T, E = Tl::E, ST = Tl::STRIDE;
+    constexpr int SPL = kRoundSlots / 64;  // slots per lane
     const int lane = lane_id();
     const int64_t S = A.S;
     int64_t *len = A.len;
@@ -269,7 +304,6 @@ __device__ __forceinline__ void eval_gate(const EvalArgs &A, const GateRec &R, i
 #pragma unroll
     for (int p = 0; p < K; p++) { drise[p] = R.rise[p]; dfall[p] = R.fall[p]; }
 
-    // first tiles
     uint64_t pre[K][E];
 #pragma unroll
     for (int p = 0; p < K; p++)
@@ -278,30 +312,41 @@ __device__ __forceinline__ void eval_gate(const EvalArgs &A, const GateRec &R, i
             const int64_t idx = lane + 64 * e;
             pre[p][e] = idx < pl[p] ? Kar[pb[p] + idx] : kNoKey;
         }
+    // terminators after each tile
+    if (lane < K) L.tile[lane * ST + T + 1] = kNoKey32;
 
     uint32_t last_val = kX;  // value of the last final survivor
-    int nq = 0;              // tentative survivors in L.seq[0, nq)
+    int nq = 0;              // tentative survivors in L.seq[0, nq), offsets from base_prev
+    int64_t base_prev = 0;
     int64_t out_n = 0;
-    uint64_t *slots = L.seq + W;
+    uint32_t *slots = L.seq + W;
 
     for (;;) {
-        bool more = false;
-#pragma unroll
-        for (int p = 0; p < K; p++) more |= cur[p] < pl[p];
-        if (!more) break;
-
-        // ---- horizon, base, in-round counts
         int64_t rem[K];
-        int64_t H = kInf, base = kInf;
+        bool more = nq > 0;
 #pragma unroll
         for (int p = 0; p < K; p++) {
             rem[p] = pl[p] - cur[p];
+            more |= rem[p] > 0;
+        }
+        if (!more) break;
+
+        // ---- base (earliest pending time), horizon, in-round counts
+        int64_t H = kInf, base = kInf;
+#pragma unroll
+        for (int p = 0; p < K; p++) {
             if (rem[p] > T) H = min64(H, key_time(readlane_u64(pre[p][E - 1], 63)));
             if (rem[p] > 0) base = min64(base, key_time(readlane_u64(pre[p][0], 0)));
+        }
+        if (nq > 0) {
+            base = min64(base, base_prev + (int64_t)(L.seq[0] >> 2));
+            const uint32_t shift = (uint32_t)(base - base_prev) << 2;
+            for (int c = lane; c < nq; c += 64) L.seq[c] -= shift;
         }
         H = min64(H, base + kSpan);
         int m[K];
         int M = 0;
+        bool all_in = true;
 #pragma unroll
         for (int p = 0; p < K; p++) {
             m[p] = 0;
@@ -311,12 +356,15 @@ __device__ __forceinline__ void eval_gate(const EvalArgs &A, const GateRec &R, i
                 const uint64_t key = pre[p][e];
                 const bool in = idx < rem[p] && key_time(key) <= H;
                 m[p] += __popcll(__ballot(in));
-                L.tile[p * T + 64 * e + lane] =
+                L.tile[p * ST + 1 + 64 * e + lane] =
                     in ? (uint32_t)((key_time(key) - base) << 2) | key_value(key) : kNoKey32;
             }
+            if (lane == 0) L.tile[p * ST] = cval[p];
             M += m[p];
+            all_in = all_in && m[p] == rem[p];
         }
-        // prefetch the next round's tiles
+        // split horizon: with every remaining input in this round, all survivors are final
+        const uint32_t hsplit = all_in ? kNoKey32 : (uint32_t)(H - base) << 2 | 3u;
         uint64_t nxt[K][E];
 #pragma unroll
         for (int p = 0; p < K; p++)
@@ -334,52 +382,53 @@ __device__ __forceinline__ void eval_gate(const EvalArgs &A, const GateRec &R, i
             for (int e = 0; e < E; e++) {
                 const int j = lane + 64 * e;
                 if (j >= m[p]) continue;
-                const uint32_t key = L.tile[p * T + j];
+                const uint32_t *tp = L.tile + p * ST + 1;
+                const uint32_t key = tp[j];
                 const uint32_t tk = key & ~3u;
-                int lb[K];
-                bool eq[K];
                 bool leader = true;
                 int rank = j;
+                uint32_t pack_after = 0, pack_before = 0, changed = 1u << p;
 #pragma unroll
                 for (int q = 0; q < K; q++) {
-                    if (q == p) { lb[q] = j; eq[q] = true; continue; }
-                    lb[q] = count_less32<Tl::LOG2T>(L.tile + q * T, tk);
-                    eq[q] = (L.tile[q * T + (lb[q] < T ? lb[q] : T - 1)] & ~3u) == tk && lb[q] < T;
-                    if (q < p) {
-                        leader = leader && !eq[q];
-                        rank += lb[q] + (eq[q] ? 1 : 0);
+                    uint32_t va, vb;
+                    if (q == p) {
+                        va = key & 3u;
+                        vb = tp[j - 1] & 3u;
                     } else {
-                        rank += lb[q];
-                    }
-                }
-                uint64_t slot = kNoKey;
-                if (leader) {
-                    int pack_after = 0, pack_before = 0;
+                        const uint32_t *a = L.tile + q * ST + 1;
 #pragma unroll
-                    for (int q = 0; q < K; q++) {
-                        uint32_t va, vb;
-                        if (q == p) {
-                            va = key & 3u;
-                            vb = j > 0 ? (L.tile[p * T + j - 1] & 3u) : cval[p];
+                        for (int s = T / 2; s >= 1; s >>= 1)
+                            if (a[s - 1] < tk) a += s;
+                        if (a[0] < tk) a += 1;
+                        const int lb = (int)(a - (L.tile + q * ST + 1));
+                        const uint32_t x0 = a[0];
+                        const bool eq = (x0 & ~3u) == tk;
+                        vb = a[-1] & 3u;
+                        va = eq ? (x0 & 3u) : vb;
+                        if (q < p) {
+                            leader = leader && !eq;
+                            rank += lb + (eq ? 1 : 0);
                         } else {
-                            const int ub = lb[q] + (eq[q] ? 1 : 0);
-                            va = ub > 0 ? (L.tile[q * T + ub - 1] & 3u) : cval[q];
-                            vb = lb[q] > 0 ? (L.tile[q * T + lb[q] - 1] & 3u) : cval[q];
+                            rank += lb;
                         }
-                        pack_after |= (int)va << (2 * q);
-                        pack_before |= (int)vb << (2 * q);
+                        changed |= eq ? (1u << q) : 0u;
                     }
+                    pack_after |= va << (2 * q);
+                    pack_before |= vb << (2 * q);
+                }
+                uint32_t slot = kNoKey32;
+                if (leader) {
                     const uint32_t ea = L.lut[pack_after];
                     const uint32_t eb = L.lut[pack_before];
                     if (ea != eb) {
                         int32_t d = INT32_MAX;
 #pragma unroll
                         for (int q = 0; q < K; q++)
-                            if (eq[q]) {
+                            if (changed & (1u << q)) {
                                 const int32_t dq = pin_delay(drise[q], dfall[q], ea);
                                 d = dq < d ? dq : d;
                             }
-                        slot = pack_key(base + (int64_t)(tk >> 2) + d, ea);
+                        slot = (tk + ((uint32_t)d << 2)) | ea;
                     }
                 }
                 slots[rank] = slot;
@@ -387,43 +436,43 @@ __device__ __forceinline__ void eval_gate(const EvalArgs &A, const GateRec &R, i
         }
         __syncthreads();
 
-        // ---- survivors among this round's candidates (reverse suffix minimum)
-        uint64_t r4[4];
-        int64_t lmin = kInf;
+        // ---- survivors among this round's candidates: lane l holds slots
+        // [(63 - l) * SPL, +SPL), so a prefix over lanes is a suffix over slots
+        uint32_t sk[SPL];
+        uint32_t lmin = kNoKey32;
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int s = lane * 4 + j;
-            r4[j] = s < M ? slots[s] : kNoKey;
-            lmin = min64(lmin, key_time(r4[j]));
+        for (int j = 0; j < SPL; j++) {
+            const int s = (63 - lane) * SPL + j;
+            sk[j] = s < M ? slots[s] : kNoKey32;
+            lmin = umin32(lmin, sk[j]);
         }
-        const int64_t suf = (int64_t)wave_suffix_min((uint64_t)lmin);
-        const int64_t round_min = (int64_t)readlane_u64((uint64_t)suf, 0);
-        int64_t later = shfl_down64(suf, 1);
-        if (lane == 63) later = kInf;
-        bool keep4[4];
+        const uint32_t incl_min = wave_prefix_min(lmin);
+        const uint32_t round_min = (uint32_t)__builtin_amdgcn_readlane((int)incl_min, 63);
+        uint32_t later = wave_shift_up(kNoKey32, incl_min);
+        uint32_t keepmask = 0;
         int nkeep = 0;
 #pragma unroll
-        for (int j = 3; j >= 0; j--) {
-            const int64_t rj = key_time(r4[j]);
-            keep4[j] = r4[j] != kNoKey && rj < later;
-            later = min64(later, rj);
-            nkeep += keep4[j] ? 1 : 0;
+        for (int j = SPL - 1; j >= 0; j--) {
+            const bool keep = sk[j] != kNoKey32 && (sk[j] >> 2) < (later >> 2);
+            later = umin32(later, sk[j]);
+            keepmask |= keep ? (1u << j) : 0u;
+            nkeep += keep ? 1 : 0;
         }
         // tentative survivors of earlier rounds outlive this round iff they
         // appear before every candidate of this round (they are increasing)
         int ncs = 0;
         for (int c0 = 0; c0 < nq; c0 += 64) {
             const int c = c0 + lane;
-            ncs += __popcll(__ballot(c < nq && key_time(L.seq[c]) < round_min));
+            ncs += __popcll(__ballot(c < nq && (L.seq[c] >> 2) < (round_min >> 2)));
         }
-        const int incl = wave_incl_sum(nkeep);
-        const int nsurv = __builtin_amdgcn_readlane(incl, 63);
+        const uint32_t incl_cnt = wave_prefix_sum((uint32_t)nkeep);
+        const int nsurv = __builtin_amdgcn_readlane((int)incl_cnt, 63);
         __syncthreads();  // every lane has read its slots before they are overwritten
         {
-            int pos = ncs + incl - nkeep;
+            int pos = ncs + nsurv - (int)incl_cnt;  // survivors of lanes > l come first
 #pragma unroll
-            for (int j = 0; j < 4; j++)
-                if (keep4[j]) L.seq[pos++] = r4[j];
+            for (int j = 0; j < SPL; j++)
+                if (keepmask & (1u << j)) L.seq[pos++] = sk[j];
         }
         const int nseq = ncs + nsurv;
         __syncthreads();
@@ -432,21 +481,21 @@ __device__ __forceinline__ void eval_gate(const EvalArgs &A, const GateRec &R, i
         int nf = 0;
         for (int c0 = 0; c0 < nseq; c0 += 64) {
             const int c = c0 + lane;
-            nf += __popcll(__ballot(c < nseq && key_time(L.seq[c]) <= H));
+            nf += __popcll(__ballot(c < nseq && L.seq[c] <= hsplit));
         }
         for (int c0 = 0; c0 < nf; c0 += 64) {
             const int j = c0 + lane;
             const bool in = j < nf;
-            const uint64_t kj = in ? L.seq[j] : 0;
-            const uint32_t v = key_value(kj);
-            const uint32_t vp = j == 0 ? last_val : (in ? key_value(L.seq[j - 1]) : 0u);
+            const uint32_t kj = in ? L.seq[j] : 0u;
+            const uint32_t v = kj & 3u;
+            const uint32_t vp = j == 0 ? last_val : (in ? (L.seq[j - 1] & 3u) : 0u);
             const bool keep = in && v != vp;
             const uint64_t mask = __ballot(keep);
             const int64_t at = out_n + lanes_below(mask);
-            if (keep && at < reserved) Kar[ob + at] = kj;
+            if (keep && at < reserved) Kar[ob + at] = pack_key(base + (int64_t)(kj >> 2), v);
             out_n += __popcll(mask);
         }
-        if (nf > 0) last_val = key_value(L.seq[nf - 1]);
+        if (nf > 0) last_val = L.seq[nf - 1] & 3u;
 
         // ---- keep the tentative ones at the front for the next round
         int ntent = nseq - nf;
@@ -455,7 +504,7 @@ __device__ __forceinline__ void eval_gate(const EvalArgs &A, const GateRec &R, i
             ntent = W;
         }
         if (nf > 0 && ntent > 0) {
-            uint64_t rr[W / 64];
+            uint32_t rr[W / 64];
 #pragma unroll
             for (int c = 0; c < W / 64; c++) {
                 const int j = c * 64 + lane;
@@ -469,11 +518,12 @@ __device__ __forceinline__ void eval_gate(const EvalArgs &A, const GateRec &R, i
             }
         }
         nq = ntent;
+        base_prev = base;
 
 #pragma unroll
         for (int p = 0; p < K; p++) {
             if (m[p] > 0) {
-                cval[p] = L.tile[p * T + m[p] - 1] & 3u;
+                cval[p] = L.tile[p * ST + m[p]] & 3u;
                 cur[p] += m[p];
             }
 #pragma unroll

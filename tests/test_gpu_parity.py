@@ -277,3 +277,38 @@ def test_run_device_from_torch(sim):
     assert_same(got, want, nl)
     sim.release(j)
     sim.unload_netlist(h)
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_time_gaps_beyond_32_bits(sim, kernel):
+    """Source times spread over ~2^40 ps with dense bursts: rounds whose span
+    would exceed the 32-bit in-round offsets, and tentative transitions left
+    when a round's horizon is capped."""
+    rng = np.random.default_rng(21)
+    S = 6
+    waves = []
+    for s in range(S):
+        bursts = np.sort(rng.choice(2 ** 40, size=5, replace=False))
+        ts = np.unique(np.concatenate([b + np.sort(rng.choice(200, size=40, replace=False))
+                                       for b in bursts]))
+        vals, prev = [], 2
+        for _ in ts:
+            v = int(rng.choice([c for c in range(4) if c != prev]))
+            vals.append(v)
+            prev = v
+        waves.append(list(zip(ts.tolist(), vals)))
+    nl = W.make_netlist(G=400, S=S, L=8, types=W.TYPES_ALL, dmin=0, dmax=60, seed=21,
+                        name="time-gaps")
+    check(sim, nl, P.stimulus_of(waves), kernel)
+
+
+def test_one_huge_gap_at_round_edge(sim):
+    """A burst, a gap of 2^31 ps, then a second burst, through a chain of gates."""
+    a = [(t, 1 if i % 2 == 0 else 0) for i, t in enumerate(range(0, 300, 3))]
+    b = [(t, 0 if i % 2 == 0 else 1) for i, t in enumerate(range(1, 301, 3))]
+    a += [(2 ** 31 + t, 0 if i % 2 else 1) for i, t in enumerate(range(0, 30, 2))]
+    b += [(2 ** 31 + 7 + t, 1 if i % 2 else 0) for i, t in enumerate(range(0, 30, 2))]
+    gates = [(W.XOR2, [0, 1]), (W.AND2, [0, 2]), (W.OR2, [3, 1]), (W.NOT, [4]), (W.XNOR2, [5, 2])]
+    k = sum(len(g[1]) for g in gates)
+    nl = P.netlist_of(2, gates, [40] * k, [7] * k)
+    check(sim, nl, P.stimulus_of([a, b]))
