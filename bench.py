@@ -21,6 +21,27 @@ import time
 import numpy as np
 
 HBM_PEAK_GBPS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "eval_wave_cfg2_hbm_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2304_13398_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic_bytes_per_launch():
+    """HBM bytes per evaluate launch from the committed FETCH_SIZE/WRITE_SIZE
+    profile (already scaled by the copy calibration), or None if the profile is
+    missing or was taken on other kernel source than the one built now."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src_hash = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if f"sha256 prefix: {src_hash}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:"):
+            return float(line.split(":")[1])
+    return None
 
 
 def parse():
@@ -161,6 +182,8 @@ def main():
     b_eval = float(sum(per_level))
     achieved = b_eval / (eval_ms / 1000.0) / 1e9
     b_pin = 8.0 * stats[-1].pin_reads + 8.0 * n_out
+    traffic_per_launch = measured_traffic_bytes_per_launch()
+    avg_launch_s = eval_ms / launches / 1000.0
 
     out = {
         "metric": "output transitions/sec",
@@ -193,7 +216,8 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": (traffic_per_launch / avg_launch_s / 1e9) if traffic_per_launch else None,
+            "traffic_bytes_per_launch": traffic_per_launch,
             "algorithmic_bytes_per_launch": b_eval / launches,
             "avg_launch_ms": eval_ms / launches,
             "launches_per_step": launches,
