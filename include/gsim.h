@@ -83,16 +83,19 @@ enum gsim_option {
     /* Output storage per job, in transitions; 0 = automatic (see sim_run).
      * A run that needs more ends with GSIM_E_OOM from sim_wait. */
     GSIM_OPT_ARENA_TRANSITIONS = 1,
-    /* Evaluate-kernel choice: 0 = automatic (wavefront per gate; gates whose
-     * largest pin delay exceeds the wavefront kernel's window go to the lane
-     * kernel), 1 = lane-per-gate kernel for every gate. */
+    /* Evaluate-kernel choice for netlists loaded afterwards: 0 = automatic
+     * (wavefront per gate; gates whose largest pin delay exceeds the wavefront
+     * kernel's window go to the lane kernel), 1 = lane-per-gate kernel for
+     * every gate. */
     GSIM_OPT_KERNEL = 2,
-    /* Level loop: 0 = one stream-ordered launch chain per run, 1 = the chain
-     * captured once in a HIP graph and replayed. */
-    GSIM_OPT_LEVEL_LOOP = 3,
-    /* 1 = bracket every level's evaluate launches with HIP events on the job's
-     * stream; sim_job_stats then reports their summed device time. */
-    GSIM_OPT_KERNEL_TIMING = 4
+    /* 1 = bracket every step's evaluate launches with HIP events on the
+     * executor's stream; sim_job_stats then reports their summed device time
+     * over the steps the job took part in. */
+    GSIM_OPT_KERNEL_TIMING = 4,
+    /* Dynamic binning: a gate whose inputs hold fewer than this many
+     * transitions in a run is evaluated by the lane-per-gate kernel instead of
+     * the wavefront-per-gate kernel (0 = never). Picked by the autotuner. */
+    GSIM_OPT_LANE_THRESHOLD = 5
 };
 
 /* ---- context ------------------------------------------------------------ */
@@ -136,29 +139,68 @@ gsim_status sim_netlist_info(gsim_ctx ctx, gsim_netlist nl, gsim_netlist_info *o
 
 /* ---- runs ----------------------------------------------------------------- */
 
-/* Start one re-simulation of `nl` over host-resident source waveforms:
+/* Jobs run on an executor, one per HIP stream (NULL = the context's stream).
+ * The executor advances its jobs one topological level per step, every
+ * admitted job in the same kernel launches, with no host synchronisation
+ * between levels (one host-to-device round trip per job, Section 3). A job is
+ * admitted when its device storage fits the context's HBM budget; until then
+ * it waits in the executor's queue. */
+
+/* Queue one re-simulation of `nl` over host-resident source waveforms:
  *   src_off [S+1] source s's transitions are t/v[src_off[s] .. src_off[s+1]-1]
  *   t [N_in], v [N_in] with N_in = src_off[S]
- * The stimuli are validated and copied to the device (one transfer), then every
- * level runs on `hip_stream` (a hipStream_t; NULL = the context's stream)
- * without host synchronisation. Returns after enqueueing. Output storage is
+ * The stimuli are validated and copied to the device (one transfer) before the
+ * call returns; nothing runs yet. Output storage per job is
  * GSIM_OPT_ARENA_TRANSITIONS, or by default an estimate of twice the pin-read
  * volume of an input-length-preserving circuit, capped by the budget.
  * Errors: GSIM_E_ARG, GSIM_E_WAVEFORM, GSIM_E_OVERFLOW, GSIM_E_OOM, GSIM_E_HANDLE. */
+gsim_status sim_submit(gsim_ctx ctx, gsim_netlist nl, const int64_t *src_off, const int64_t *t,
+                       const uint8_t *v, void *hip_stream, gsim_job *out);
+
+/* As sim_submit, but the three arrays are device pointers (e.g. owned by
+ * PyTorch) holding N_in = src_off[S] transitions; the caller keeps them alive
+ * and unmodified until the job completes. They are validated on the host only
+ * if `validate` is non-zero (one device-to-host copy); otherwise the caller
+ * guarantees the waveform conventions. */
+gsim_status sim_submit_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_off,
+                              const int64_t *d_t, const uint8_t *d_v, int64_t n_in, int validate,
+                              void *hip_stream, gsim_job *out);
+
+/* sim_submit, then drive the executor until every level of the job is
+ * enqueued; returns without waiting for the device. GSIM_E_OOM if the job
+ * cannot be admitted because unreleased jobs hold the budget. */
 gsim_status sim_run(gsim_ctx ctx, gsim_netlist nl, const int64_t *src_off, const int64_t *t,
                     const uint8_t *v, void *hip_stream, gsim_job *out);
 
-/* As sim_run, but the three arrays are device pointers (e.g. owned by PyTorch)
- * holding N_in = src_off[S] transitions; the caller keeps them alive and
- * unmodified until the job completes. They are validated on the host only if
- * `validate` is non-zero (one device-to-host copy); otherwise the caller
- * guarantees the waveform conventions. */
+/* sim_submit_device, then as sim_run. */
 gsim_status sim_run_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_off,
-                           const int64_t *d_t, const uint8_t *d_v, int64_t n_in,
-                           int validate, void *hip_stream, gsim_job *out);
+                           const int64_t *d_t, const uint8_t *d_v, int64_t n_in, int validate,
+                           void *hip_stream, gsim_job *out);
 
-/* Block until the job's device work is done. GSIM_E_OOM if its output storage
- * overflowed (the job then holds no results). */
+/* Batched execution of `n_sets` stimulus sets over one resident netlist:
+ * src_off[i], t[i], v[i] are set i's host arrays (as sim_submit); out[n_sets]
+ * receives the job handles. All sets that fit the budget run together, level
+ * by level, in shared launches; the others are admitted as released jobs free
+ * memory (wait, fetch and release in submission order when the sets do not all
+ * fit). Errors as sim_submit; on error no job is created. */
+gsim_status sim_run_batch(gsim_ctx ctx, gsim_netlist nl, int32_t n_sets,
+                          const int64_t *const *src_off, const int64_t *const *t,
+                          const uint8_t *const *v, void *hip_stream, gsim_job *out);
+
+/* One scheduling pass of the executor on `hip_stream`: admit queued jobs that
+ * fit, enqueue the next level of every admitted job, then block until at most
+ * `max_ahead` steps are unfinished on the device (0 = do not block; at most
+ * 31). Reports the number of admitted jobs with levels left and of queued jobs.
+ * Used by serving loops (continuous batching: jobs join at the next step). */
+gsim_status sim_drive(gsim_ctx ctx, void *hip_stream, int32_t max_ahead, int32_t *n_active,
+                      int32_t *n_queued);
+
+/* Non-blocking: *done = 1 if the job's results are ready (or it failed). */
+gsim_status sim_job_done(gsim_ctx ctx, gsim_job job, int32_t *done);
+
+/* Drive the job's executor until the job is enqueued, then block until its
+ * device work is done. GSIM_E_OOM if its output storage overflowed or could
+ * not be allocated (the job then holds no results). */
 gsim_status sim_wait(gsim_ctx ctx, gsim_job job);
 
 typedef struct {

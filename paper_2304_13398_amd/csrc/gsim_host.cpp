@@ -1,6 +1,7 @@
 // Host runtime of libgsim: validation, levelizer, netlist upload, device
-// memory pool, the per-job level chain, and waveform fetch. Exposes the C ABI
-// declared in include/gsim.h.
+// memory pool, the job executor (admission by HBM budget, one step per level
+// covering every active job), and waveform fetch. Exposes the C ABI declared
+// in include/gsim.h.
 #include "gsim.h"
 #include "gsim_internal.h"
 
@@ -8,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -284,45 +286,79 @@ class Pool {
 
 // ---------------------------------------------------------------------------
 
-// Gates of one level, in three consecutive groups: wavefront kernel with the
-// small tentative window, wavefront kernel with the large window, lane kernel.
+// Gates of one level in three consecutive groups by largest pin delay:
+// <= kWindowSmall, <= kWindowLarge, larger. The first two groups bound the
+// wavefront work lists of a step (the lane list may take any gate).
 struct LevelRange {
-    int64_t begin, n_small, n_large, n_lane;
-    int64_t size() const { return n_small + n_large + n_lane; }
+    int64_t begin, n, n_small, n_large;
 };
-
-// Evaluate-kernel class of a gate by its largest pin delay.
-enum GateClass { kClassSmall = 0, kClassLarge = 1, kClassLane = 2 };
 
 struct Netlist {
     int64_t S = 0, G = 0, P = 0;
     int32_t n_levels = 0, max_delay = 0;
     int64_t max_path_delay = 0;
-    int64_t lane_gates = 0;
+    int64_t lane_gates = 0;  // gates whose largest delay needs the lane kernel
     std::vector<LevelRange> levels;
     std::vector<int64_t> internal_of_user;  // [G]
-    std::vector<int64_t> arity_sum_level;   // unused reserve
     GateRec *d_rec = nullptr;
-    int64_t max_level_blocks = 0;
-    int kernel_mode = 0;
+    int64_t active_jobs = 0;
 };
 
+// Device time of one step's evaluate launches (with GSIM_OPT_KERNEL_TIMING).
+struct StepTiming {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~StepTiming() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+struct Executor;
+
+enum JobPhase { kQueued, kActive, kEnqueued };
+
 struct Job {
-    int64_t nl_id = 0;
+    int64_t id = 0, nl_id = 0;
     Netlist *nl = nullptr;
-    hipStream_t stream = nullptr;
-    int64_t n_in = 0, capacity = 0;
-    int64_t *d_off = nullptr, *d_len = nullptr, *d_blocksum = nullptr, *d_partial = nullptr;
-    int64_t *d_src_off = nullptr;
-    int64_t *d_src_t = nullptr;   // host stimuli staged on the device (sim_run only)
+    Executor *ex = nullptr;
+    JobPhase phase = kQueued;
+    int32_t next_level = 0;
+    int64_t n_in = 0, capacity = 0, capacity_request = 0;
+    int64_t *d_off = nullptr, *d_len = nullptr, *d_partial = nullptr, *d_src_off = nullptr;
+    int64_t *d_src_t = nullptr;   // host stimuli staged on the device
     uint8_t *d_src_v = nullptr;
+    const int64_t *src_t = nullptr;  // stimuli the sources are packed from (staged or caller's)
+    const uint8_t *src_v = nullptr;
     uint64_t *d_K = nullptr;      // arena of packed transitions
     DevState *d_state = nullptr;
     DevState *h_state = nullptr;  // pinned
     hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_done = nullptr;
-    std::vector<hipEvent_t> ev_levels;  // with kernel timing: before/after each level's evaluate
-    bool waited = false, failed = false;
+    std::vector<std::shared_ptr<StepTiming>> timing;
     int64_t n_partial = 0;
+    bool waited = false, failed = false;
+};
+
+constexpr int kMaxJobsPerStep = 256;
+constexpr int kRing = 32;  // steps whose descriptors may be in flight
+
+// One executor per stream: its jobs advance one level per step, all active
+// jobs in the same launches.
+struct Executor {
+    hipStream_t stream = nullptr;
+    uint32_t *d_counts = nullptr;  // 2 x kNumClasses list lengths (this step / next step)
+    int parity = 0;
+    JobDesc *d_jobs = nullptr;
+    int64_t jobs_cap = 0;
+    int64_t *d_blocksum = nullptr;
+    int64_t blocksum_cap = 0;
+    uint64_t *d_list = nullptr;    // kNumClasses lists of list_cap entries
+    int64_t list_cap = 0;
+    JobDesc *h_ring = nullptr;     // pinned [kRing][kMaxJobsPerStep]
+    hipEvent_t ring_ev[kRing] = {};
+    bool ring_used[kRing] = {};
+    int64_t steps = 0;
+    std::vector<Job *> active;     // admitted, levels left to enqueue
+    std::deque<Job *> queue;       // submitted, waiting for memory
 };
 
 }  // namespace
@@ -336,10 +372,11 @@ struct gsim_ctx_s {
     int64_t next_id = 1;
     std::map<int64_t, std::unique_ptr<Netlist>> netlists;
     std::map<int64_t, std::unique_ptr<Job>> jobs;
+    std::map<hipStream_t, std::unique_ptr<Executor>> executors;
     int64_t opt_arena = 0;
     int opt_kernel = 0;
-    int opt_level_loop = 0;
     int opt_timing = 0;
+    int32_t opt_lane_threshold = 0;
 };
 
 namespace {
@@ -361,35 +398,12 @@ Failure set_device(gsim_ctx ctx) {
     return kOk;
 }
 
-void free_job_buffers(gsim_ctx ctx, Job *j) {
-    Pool &pool = *ctx->pool;
-    pool.put(j->d_off);
-    pool.put(j->d_len);
-    pool.put(j->d_blocksum);
-    pool.put(j->d_partial);
-    pool.put(j->d_src_off);
-    pool.put(j->d_src_t);
-    pool.put(j->d_src_v);
-    pool.put(j->d_K);
-    pool.put(j->d_state);
-    j->d_off = j->d_len = j->d_blocksum = j->d_partial = j->d_src_off = j->d_src_t = nullptr;
-    j->d_src_v = nullptr;
-    j->d_K = nullptr;
-    j->d_state = nullptr;
+template <class T>
+T *pool_get(Pool &pool, int64_t n) {
+    return (T *)pool.get(sizeof(T) * (size_t)std::max<int64_t>(n, 1));
 }
 
-void destroy_job(gsim_ctx ctx, Job *j) {
-    if (j->ev_done) (void)hipEventSynchronize(j->ev_done);
-    free_job_buffers(ctx, j);
-    if (j->h_state) (void)hipHostFree(j->h_state);
-    if (j->ev_start) (void)hipEventDestroy(j->ev_start);
-    if (j->ev_end) (void)hipEventDestroy(j->ev_end);
-    if (j->ev_done) (void)hipEventDestroy(j->ev_done);
-    for (hipEvent_t e : j->ev_levels) (void)hipEventDestroy(e);
-    j->ev_levels.clear();
-    j->h_state = nullptr;
-    j->ev_start = j->ev_end = j->ev_done = nullptr;
-}
+// ---- netlists ---------------------------------------------------------------
 
 Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
                      const int64_t *pin_net, const int32_t *rise, const int32_t *fall, gsim_netlist *out) {
@@ -404,27 +418,24 @@ Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, co
     nl->n_levels = lv.n_levels;
     nl->max_delay = lv.max_delay;
     nl->max_path_delay = lv.max_path_delay;
-    nl->kernel_mode = ctx->opt_kernel;
 
-    // Gate order: by level; inside a level, wavefront-kernel gates first, then
-    // lane-kernel gates (largest pin delay beyond the wavefront window, or all
-    // gates when the lane kernel is forced), each in the caller's order.
+    // Gate order: by level; inside a level by delay group (see LevelRange),
+    // each group in the caller's order.
     auto gate_dmax = [&](int64_t g) {
         int32_t d = 0;
         for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++) d = std::max(d, std::max(rise[p], fall[p]));
         return d;
     };
-    auto gate_class = [&](int64_t g) {
-        if (ctx->opt_kernel == 1) return (int)kClassLane;
+    auto group_of = [&](int64_t g) {
         const int32_t d = gate_dmax(g);
-        return d <= kWindowSmall ? (int)kClassSmall : d <= kWindowLarge ? (int)kClassLarge : (int)kClassLane;
+        return d <= kWindowSmall ? 0 : d <= kWindowLarge ? 1 : 2;
     };
     const int32_t L = lv.n_levels;
     std::vector<int64_t> cnt(3 * ((size_t)L + 1), 0);
-    std::vector<int> cls(G);
+    std::vector<int> grp(G);
     for (int64_t g = 0; g < G; g++) {
-        cls[g] = gate_class(g);
-        cnt[3 * (size_t)lv.level[g] + cls[g]]++;
+        grp[g] = group_of(g);
+        cnt[3 * (size_t)lv.level[g] + grp[g]]++;
     }
     std::vector<int64_t> start(cnt.size() + 1, 0);
     for (size_t i = 0; i < cnt.size(); i++) start[i + 1] = start[i] + cnt[i];
@@ -432,16 +443,15 @@ Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, co
     for (int32_t l = 1; l <= L; l++) {
         LevelRange &r = nl->levels[l - 1];
         r.begin = start[3 * (size_t)l];
-        r.n_small = cnt[3 * (size_t)l + kClassSmall];
-        r.n_large = cnt[3 * (size_t)l + kClassLarge];
-        r.n_lane = cnt[3 * (size_t)l + kClassLane];
-        nl->lane_gates += r.n_lane;
-        nl->max_level_blocks = std::max(nl->max_level_blocks, (r.size() + kSizeBlock - 1) / kSizeBlock);
+        r.n_small = cnt[3 * (size_t)l];
+        r.n_large = cnt[3 * (size_t)l + 1];
+        r.n = r.n_small + r.n_large + cnt[3 * (size_t)l + 2];
+        nl->lane_gates += cnt[3 * (size_t)l + 2];
     }
     nl->internal_of_user.resize(G);
     {
         std::vector<int64_t> fill(start.begin(), start.end() - 1);
-        for (int64_t g = 0; g < G; g++) nl->internal_of_user[g] = fill[3 * (size_t)lv.level[g] + cls[g]]++;
+        for (int64_t g = 0; g < G; g++) nl->internal_of_user[g] = fill[3 * (size_t)lv.level[g] + grp[g]]++;
     }
     std::vector<GateRec> recs(G);
     for (int64_t g = 0; g < G; g++) {
@@ -456,7 +466,8 @@ Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, co
             r.rise[i] = rise[p];
             r.fall[i] = fall[p];
         }
-        r.dmax = gate_dmax(g);
+        // the lane-kernel option routes every gate to the lane kernel
+        r.dmax = ctx->opt_kernel == 1 ? INT32_MAX : gate_dmax(g);
         r.user_gate = (int32_t)g;
         recs[nl->internal_of_user[g]] = r;
     }
@@ -471,57 +482,96 @@ Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, co
             return fail(GSIM_E_DEVICE, "netlist upload: %s", hipGetErrorString(e));
         }
     }
+    if (ctx->opt_kernel == 1) nl->lane_gates = G;
     const int64_t id = ctx->next_id++;
     ctx->netlists[id] = std::move(nl);
     *out = id;
     return kOk;
 }
 
-template <class T>
-T *pool_get(Pool &pool, int64_t n) {
-    return (T *)pool.get(sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+// ---- executors ----------------------------------------------------------------
+
+Failure get_executor(gsim_ctx ctx, hipStream_t stream, Executor **out) {
+    if (!stream) stream = ctx->stream;
+    auto it = ctx->executors.find(stream);
+    if (it != ctx->executors.end()) {
+        *out = it->second.get();
+        return kOk;
+    }
+    auto ex = std::make_unique<Executor>();
+    ex->stream = stream;
+    ex->d_counts = pool_get<uint32_t>(*ctx->pool, 2 * kNumClasses);
+    if (!ex->d_counts) return fail(GSIM_E_OOM, "no device memory for the executor");
+    HIP_TRY(hipHostMalloc((void **)&ex->h_ring, sizeof(JobDesc) * kRing * kMaxJobsPerStep, hipHostMallocDefault));
+    for (int i = 0; i < kRing; i++) HIP_TRY(hipEventCreateWithFlags(&ex->ring_ev[i], hipEventDisableTiming));
+    HIP_TRY(launch_clear_u32(ex->d_counts, 2 * kNumClasses, stream));
+    *out = ex.get();
+    ctx->executors[stream] = std::move(ex);
+    return kOk;
 }
 
-// Enqueue the level chain of a job whose sources are already in the arena.
-Failure enqueue_levels(gsim_ctx ctx, Job *j, const int64_t *src_t, const uint8_t *src_v) {
-    Netlist &nl = *j->nl;
-    hipStream_t s = j->stream;
-    HIP_TRY(hipEventRecord(j->ev_start, s));
-    HIP_TRY(launch_init_sources(j->d_src_off, src_t, src_v, nl.S, j->n_in, j->d_off, j->d_len, j->d_K,
-                                j->d_state, j->capacity, s));
-    EvalArgs a;
-    a.rec = nl.d_rec;
-    a.S = nl.S;
-    a.blockbase = j->d_blocksum;
-    a.off = j->d_off;
-    a.len = j->d_len;
-    a.K = j->d_K;
-    a.state = j->d_state;
-    a.lut = ctx->d_lut;
-    const bool timing = !j->ev_levels.empty();
-    for (size_t l = 0; l < nl.levels.size(); l++) {
-        const LevelRange &r = nl.levels[l];
-        const int64_t n = r.size();
-        HIP_TRY(launch_size(nl.d_rec, r.begin, n, nl.S, j->d_len, j->d_off, j->d_blocksum, s));
-        HIP_TRY(launch_level_scan(j->d_blocksum, (n + kSizeBlock - 1) / kSizeBlock, j->d_state, s));
-        if (timing) HIP_TRY(hipEventRecord(j->ev_levels[2 * l], s));
-        a.lvl_begin = r.begin;
-        a.g_begin = r.begin;
-        a.n = r.n_small;
-        HIP_TRY(launch_eval_wave(a, kWindowSmall, s));
-        a.g_begin = r.begin + r.n_small;
-        a.n = r.n_large;
-        HIP_TRY(launch_eval_wave(a, kWindowLarge, s));
-        a.g_begin = r.begin + r.n_small + r.n_large;
-        a.n = r.n_lane;
-        HIP_TRY(launch_eval_lane(a, s));
-        if (timing) HIP_TRY(hipEventRecord(j->ev_levels[2 * l + 1], s));
-    }
-    HIP_TRY(hipEventRecord(j->ev_end, s));
-    HIP_TRY(launch_count_out(j->d_len, nl.S, nl.G, j->d_partial, j->n_partial, j->d_state, s));
-    HIP_TRY(hipMemcpyAsync(j->h_state, j->d_state, sizeof(DevState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipEventRecord(j->ev_done, s));
+void destroy_executor(gsim_ctx ctx, Executor *ex) {
+    (void)hipStreamSynchronize(ex->stream);
+    Pool &pool = *ctx->pool;
+    pool.put(ex->d_counts);
+    pool.put(ex->d_jobs);
+    pool.put(ex->d_blocksum);
+    pool.put(ex->d_list);
+    if (ex->h_ring) (void)hipHostFree(ex->h_ring);
+    for (int i = 0; i < kRing; i++)
+        if (ex->ring_ev[i]) (void)hipEventDestroy(ex->ring_ev[i]);
+}
+
+// Grow a step scratch buffer; the stream is drained first because queued
+// steps may still read the old one.
+template <class T>
+Failure ensure_cap(gsim_ctx ctx, Executor *ex, T *&buf, int64_t &cap, int64_t need) {
+    if (need <= cap) return kOk;
+    const int64_t ncap = std::max<int64_t>(need, std::max<int64_t>(2 * cap, 1024));
+    HIP_TRY(hipStreamSynchronize(ex->stream));
+    ctx->pool->put(buf);
+    buf = pool_get<T>(*ctx->pool, ncap);
+    cap = buf ? ncap : 0;
+    if (!buf) return fail(GSIM_E_OOM, "no device memory for step scratch (%lld entries)", (long long)ncap);
     return kOk;
+}
+
+// ---- jobs ----------------------------------------------------------------------
+
+void free_job_buffers(gsim_ctx ctx, Job *j) {
+    Pool &pool = *ctx->pool;
+    pool.put(j->d_off);
+    pool.put(j->d_len);
+    pool.put(j->d_partial);
+    pool.put(j->d_src_off);
+    pool.put(j->d_src_t);
+    pool.put(j->d_src_v);
+    pool.put(j->d_K);
+    pool.put(j->d_state);
+    j->d_off = j->d_len = j->d_partial = j->d_src_off = j->d_src_t = nullptr;
+    j->d_src_v = nullptr;
+    j->d_K = nullptr;
+    j->d_state = nullptr;
+}
+
+void destroy_job(gsim_ctx ctx, Job *j) {
+    if (j->phase != kQueued && j->ev_done) (void)hipEventSynchronize(j->ev_done);
+    if (j->ex) {
+        auto &act = j->ex->active;
+        act.erase(std::remove(act.begin(), act.end(), j), act.end());
+        auto &q = j->ex->queue;
+        q.erase(std::remove(q.begin(), q.end(), j), q.end());
+        if (j->phase == kActive) (void)hipStreamSynchronize(j->ex->stream);
+    }
+    if (j->nl) j->nl->active_jobs--;
+    free_job_buffers(ctx, j);
+    if (j->h_state) (void)hipHostFree(j->h_state);
+    if (j->ev_start) (void)hipEventDestroy(j->ev_start);
+    if (j->ev_end) (void)hipEventDestroy(j->ev_end);
+    if (j->ev_done) (void)hipEventDestroy(j->ev_done);
+    j->timing.clear();
+    j->h_state = nullptr;
+    j->ev_start = j->ev_end = j->ev_done = nullptr;
 }
 
 int64_t default_capacity(const Netlist &nl, int64_t n_in) {
@@ -532,127 +582,258 @@ int64_t default_capacity(const Netlist &nl, int64_t n_in) {
     return (int64_t)std::min(est, 9.0e18);
 }
 
-Failure start_job(gsim_ctx ctx, gsim_netlist nlh, int64_t n_in, hipStream_t stream,
-                  std::unique_ptr<Job> &out) {
+// Create a queued job: host stimuli are staged on the device now (the caller's
+// arrays may go away when the call returns); device stimuli are used in place.
+Failure submit(gsim_ctx ctx, gsim_netlist nlh, const int64_t *src_off, const int64_t *t, const uint8_t *v,
+               bool device_arrays, int64_t n_in_device, int validate, hipStream_t stream, Job **out) {
+    if (!src_off) return fail(GSIM_E_ARG, "null src_off");
     auto it = ctx->netlists.find(nlh);
     if (it == ctx->netlists.end()) return fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nlh);
     Netlist &nl = *it->second;
     Failure f = set_device(ctx);
     if (f.st != GSIM_OK) return f;
+    Executor *ex = nullptr;
+    f = get_executor(ctx, stream, &ex);
+    if (f.st != GSIM_OK) return f;
+    int64_t n_in = 0;
+    if (!device_arrays) {
+        f = validate_stimulus(nl.S, src_off, t, v, nl.max_path_delay);
+        if (f.st != GSIM_OK) return f;
+        n_in = src_off[nl.S];
+    } else {
+        n_in = n_in_device;
+        if (n_in < 0 || (n_in > 0 && (!t || !v))) return fail(GSIM_E_ARG, "bad device stimulus");
+        if (validate) {
+            std::vector<int64_t> so(nl.S + 1), tt(n_in);
+            std::vector<uint8_t> vv(n_in);
+            HIP_TRY(hipStreamSynchronize(ex->stream));
+            HIP_TRY(hipMemcpy(so.data(), src_off, sizeof(int64_t) * (size_t)(nl.S + 1), hipMemcpyDeviceToHost));
+            if (so[nl.S] != n_in)
+                return fail(GSIM_E_ARG, "src_off[S] = %lld but n_in = %lld", (long long)so[nl.S], (long long)n_in);
+            if (n_in > 0) {
+                HIP_TRY(hipMemcpy(tt.data(), t, sizeof(int64_t) * (size_t)n_in, hipMemcpyDeviceToHost));
+                HIP_TRY(hipMemcpy(vv.data(), v, (size_t)n_in, hipMemcpyDeviceToHost));
+            }
+            f = validate_stimulus(nl.S, so.data(), tt.data(), vv.data(), nl.max_path_delay);
+            if (f.st != GSIM_OK) return f;
+        }
+    }
     auto j = std::make_unique<Job>();
     j->nl_id = nlh;
     j->nl = &nl;
-    j->stream = stream ? stream : ctx->stream;
+    j->ex = ex;
     j->n_in = n_in;
+    j->capacity_request = ctx->opt_arena;
+    Pool &pool = *ctx->pool;
+    j->d_src_off = pool_get<int64_t>(pool, nl.S + 1);
+    if (!j->d_src_off) return fail(GSIM_E_OOM, "no device memory for the stimulus offsets");
+    auto cleanup = [&](Failure e) { free_job_buffers(ctx, j.get()); return e; };
+    hipStream_t s = ex->stream;
+    if (!device_arrays) {
+        j->d_src_t = pool_get<int64_t>(pool, n_in);
+        j->d_src_v = pool_get<uint8_t>(pool, n_in);
+        if (!j->d_src_t || !j->d_src_v) return cleanup(fail(GSIM_E_OOM, "no device memory to stage the stimuli"));
+        if (hipMemcpyAsync(j->d_src_off, src_off, sizeof(int64_t) * (size_t)(nl.S + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+            (n_in > 0 && hipMemcpyAsync(j->d_src_t, t, sizeof(int64_t) * (size_t)n_in, hipMemcpyHostToDevice, s) != hipSuccess) ||
+            (n_in > 0 && hipMemcpyAsync(j->d_src_v, v, (size_t)n_in, hipMemcpyHostToDevice, s) != hipSuccess))
+            return cleanup(fail(GSIM_E_DEVICE, "stimulus upload: %s", hipGetErrorString(hipGetLastError())));
+        j->src_t = j->d_src_t;
+        j->src_v = j->d_src_v;
+    } else {
+        if (hipMemcpyAsync(j->d_src_off, src_off, sizeof(int64_t) * (size_t)(nl.S + 1), hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return cleanup(fail(GSIM_E_DEVICE, "stimulus copy: %s", hipGetErrorString(hipGetLastError())));
+        j->src_t = t;
+        j->src_v = v;
+    }
+    j->id = ctx->next_id++;
+    nl.active_jobs++;
+    Job *raw = j.get();
+    ctx->jobs[j->id] = std::move(j);
+    ex->queue.push_back(raw);
+    *out = raw;
+    return kOk;
+}
+
+// Emit the work that closes a job after its last level.
+Failure finish_job(Job *j, hipStream_t s) {
+    HIP_TRY(hipEventRecord(j->ev_end, s));
+    HIP_TRY(launch_count_out(j->d_len, j->nl->S, j->nl->G, j->d_partial, j->n_partial, j->d_state, s));
+    HIP_TRY(hipMemcpyAsync(j->h_state, j->d_state, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(j->ev_done, s));
+    j->phase = kEnqueued;
+    return kOk;
+}
+
+// Allocate a queued job's device storage and pack its sources into the arena.
+// Returns GSIM_E_OOM (and leaves the job queued) if the budget has no room.
+Failure admit(gsim_ctx ctx, Executor *ex, Job *j) {
+    Netlist &nl = *j->nl;
     Pool &pool = *ctx->pool;
     const int64_t N = nl.S + nl.G;
     j->n_partial = std::max<int64_t>(1, std::min<int64_t>(1024, (nl.G + 255) / 256));
-    j->d_off = pool_get<int64_t>(pool, N);
-    j->d_len = pool_get<int64_t>(pool, N);
-    j->d_blocksum = pool_get<int64_t>(pool, std::max<int64_t>(nl.max_level_blocks, 1));
-    j->d_partial = pool_get<int64_t>(pool, j->n_partial);
-    j->d_src_off = pool_get<int64_t>(pool, nl.S + 1);
-    j->d_state = pool_get<DevState>(pool, 1);
-    if (!j->d_off || !j->d_len || !j->d_blocksum || !j->d_partial || !j->d_src_off || !j->d_state) {
-        free_job_buffers(ctx, j.get());
-        return fail(GSIM_E_OOM, "no device memory for the job's per-net tables");
-    }
-    int64_t cap = ctx->opt_arena > 0 ? ctx->opt_arena : default_capacity(nl, n_in);
-    cap = std::max(cap, n_in);
-    if (ctx->opt_arena <= 0) {
+    int64_t cap = j->capacity_request > 0 ? j->capacity_request : default_capacity(nl, j->n_in);
+    cap = std::max(cap, j->n_in);
+    if (j->capacity_request <= 0) {
         // fit the automatic estimate into what the budget leaves
         const uint64_t room = pool.budget() > pool.live() ? pool.budget() - pool.live() : 0;
-        const int64_t fit = (int64_t)(room / sizeof(uint64_t) * 95 / 100);
-        if (cap > fit) cap = std::max(n_in, fit - (4 << 20));
+        const int64_t fit = (int64_t)(room / sizeof(uint64_t) * 90 / 100) - (int64_t)(N * 2 + 4096);
+        if (cap > fit) cap = std::max(j->n_in, fit);
     }
     j->capacity = cap;
+    j->d_off = pool_get<int64_t>(pool, N);
+    j->d_len = pool_get<int64_t>(pool, N);
+    j->d_partial = pool_get<int64_t>(pool, j->n_partial);
+    j->d_state = pool_get<DevState>(pool, 1);
     j->d_K = pool_get<uint64_t>(pool, cap);
-    if (!j->d_K) {
-        free_job_buffers(ctx, j.get());
-        return fail(GSIM_E_OOM, "no device memory for an output arena of %lld transitions", (long long)cap);
+    if (!j->d_off || !j->d_len || !j->d_partial || !j->d_state || !j->d_K) {
+        pool.put(j->d_off); pool.put(j->d_len); pool.put(j->d_partial); pool.put(j->d_state); pool.put(j->d_K);
+        j->d_off = j->d_len = j->d_partial = nullptr;
+        j->d_state = nullptr;
+        j->d_K = nullptr;
+        return fail(GSIM_E_OOM, "no device memory for a job of %lld transitions of output storage", (long long)cap);
     }
-    if (hipHostMalloc((void **)&j->h_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess ||
-        hipEventCreate(&j->ev_start) != hipSuccess || hipEventCreate(&j->ev_end) != hipSuccess ||
-        hipEventCreateWithFlags(&j->ev_done, hipEventDisableTiming) != hipSuccess) {
-        (void)hipGetLastError();
-        destroy_job(ctx, j.get());
-        return fail(GSIM_E_DEVICE, "event or pinned-memory creation failed");
-    }
-    if (ctx->opt_timing) {
-        j->ev_levels.resize(2 * nl.levels.size(), nullptr);
-        for (hipEvent_t &e : j->ev_levels)
-            if (hipEventCreate(&e) != hipSuccess) {
-                (void)hipGetLastError();
-                destroy_job(ctx, j.get());
-                return fail(GSIM_E_DEVICE, "event creation failed");
-            }
-    }
-    out = std::move(j);
-    return kOk;
-}
-
-Failure run_host(gsim_ctx ctx, gsim_netlist nlh, const int64_t *src_off, const int64_t *t,
-                 const uint8_t *v, void *stream, gsim_job *out) {
-    if (!out || !src_off) return fail(GSIM_E_ARG, "null argument");
-    auto it = ctx->netlists.find(nlh);
-    if (it == ctx->netlists.end()) return fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nlh);
-    Netlist &nl = *it->second;
-    Failure f = validate_stimulus(nl.S, src_off, t, v, nl.max_path_delay);
-    if (f.st != GSIM_OK) return f;
-    const int64_t n_in = src_off[nl.S];
-    std::unique_ptr<Job> j;
-    f = start_job(ctx, nlh, n_in, (hipStream_t)stream, j);
-    if (f.st != GSIM_OK) return f;
-    hipStream_t s = j->stream;
-    auto cleanup = [&](Failure e) { destroy_job(ctx, j.get()); return e; };
-    j->d_src_t = pool_get<int64_t>(*ctx->pool, n_in);
-    j->d_src_v = pool_get<uint8_t>(*ctx->pool, n_in);
-    if (!j->d_src_t || !j->d_src_v) return cleanup(fail(GSIM_E_OOM, "no device memory to stage the stimuli"));
-    if (hipMemcpyAsync(j->d_src_off, src_off, sizeof(int64_t) * (size_t)(nl.S + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
-        (n_in > 0 && hipMemcpyAsync(j->d_src_t, t, sizeof(int64_t) * (size_t)n_in, hipMemcpyHostToDevice, s) != hipSuccess) ||
-        (n_in > 0 && hipMemcpyAsync(j->d_src_v, v, (size_t)n_in, hipMemcpyHostToDevice, s) != hipSuccess))
-        return cleanup(fail(GSIM_E_DEVICE, "stimulus upload: %s", hipGetErrorString(hipGetLastError())));
-    f = enqueue_levels(ctx, j.get(), j->d_src_t, j->d_src_v);
-    if (f.st != GSIM_OK) return cleanup(f);
-    const int64_t id = ctx->next_id++;
-    ctx->jobs[id] = std::move(j);
-    *out = id;
-    return kOk;
-}
-
-Failure run_device(gsim_ctx ctx, gsim_netlist nlh, const int64_t *d_src_off, const int64_t *d_t,
-                   const uint8_t *d_v, int64_t n_in, int validate, void *stream, gsim_job *out) {
-    if (!out || !d_src_off || n_in < 0 || (n_in > 0 && (!d_t || !d_v))) return fail(GSIM_E_ARG, "bad argument");
-    auto it = ctx->netlists.find(nlh);
-    if (it == ctx->netlists.end()) return fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nlh);
-    Netlist &nl = *it->second;
-    Failure f = set_device(ctx);
-    if (f.st != GSIM_OK) return f;
-    if (validate) {
-        std::vector<int64_t> so(nl.S + 1), tt(n_in);
-        std::vector<uint8_t> vv(n_in);
-        HIP_TRY(hipStreamSynchronize(stream ? (hipStream_t)stream : ctx->stream));
-        HIP_TRY(hipMemcpy(so.data(), d_src_off, sizeof(int64_t) * (size_t)(nl.S + 1), hipMemcpyDeviceToHost));
-        if (so[nl.S] != n_in) return fail(GSIM_E_ARG, "src_off[S] = %lld but n_in = %lld", (long long)so[nl.S], (long long)n_in);
-        if (n_in > 0) {
-            HIP_TRY(hipMemcpy(tt.data(), d_t, sizeof(int64_t) * (size_t)n_in, hipMemcpyDeviceToHost));
-            HIP_TRY(hipMemcpy(vv.data(), d_v, (size_t)n_in, hipMemcpyDeviceToHost));
+    if (!j->h_state) {
+        if (hipHostMalloc((void **)&j->h_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess ||
+            hipEventCreate(&j->ev_start) != hipSuccess || hipEventCreate(&j->ev_end) != hipSuccess ||
+            hipEventCreateWithFlags(&j->ev_done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(GSIM_E_DEVICE, "event or pinned-memory creation failed");
         }
-        f = validate_stimulus(nl.S, so.data(), tt.data(), vv.data(), nl.max_path_delay);
-        if (f.st != GSIM_OK) return f;
     }
-    std::unique_ptr<Job> j;
-    f = start_job(ctx, nlh, n_in, (hipStream_t)stream, j);
+    hipStream_t s = ex->stream;
+    HIP_TRY(hipEventRecord(j->ev_start, s));
+    HIP_TRY(launch_init_sources(j->d_src_off, j->src_t, j->src_v, nl.S, j->n_in, j->d_off, j->d_len, j->d_K,
+                                j->d_state, j->capacity, s));
+    j->phase = kActive;
+    j->next_level = 0;
+    if (nl.n_levels == 0) return finish_job(j, s);
+    ex->active.push_back(j);
+    return kOk;
+}
+
+// Admit queued jobs in order while they fit. A job that does not fit while
+// nothing else holds memory on this executor can never run: it fails.
+Failure admit_queued(gsim_ctx ctx, Executor *ex) {
+    while (!ex->queue.empty() && (int)ex->active.size() < kMaxJobsPerStep) {
+        Job *j = ex->queue.front();
+        Failure f = admit(ctx, ex, j);
+        if (f.st == GSIM_E_OOM) break;
+        ex->queue.pop_front();
+        if (f.st != GSIM_OK) {
+            j->failed = true;
+            return f;
+        }
+    }
+    return kOk;
+}
+
+// Enqueue one step: the next level of every active job.
+Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
+    std::vector<Job *> &act = ex->active;
+    if (act.empty()) return kOk;
+    const int slot = (int)(ex->steps % kRing);
+    if (ex->ring_used[slot]) HIP_TRY(hipEventSynchronize(ex->ring_ev[slot]));
+    JobDesc *desc = ex->h_ring + (size_t)slot * kMaxJobsPerStep;
+    const int n = (int)act.size();
+    int64_t n_sblocks = 0, n_items = 0, n_small = 0, n_large = 0;
+    for (int i = 0; i < n; i++) {
+        Job *j = act[i];
+        const LevelRange &r = j->nl->levels[j->next_level];
+        JobDesc &d = desc[i];
+        d.rec = j->nl->d_rec;
+        d.S = j->nl->S;
+        d.off = j->d_off;
+        d.len = j->d_len;
+        d.K = j->d_K;
+        d.state = j->d_state;
+        d.lvl_begin = r.begin;
+        d.n_gates = r.n;
+        d.sblock_begin = n_sblocks;
+        d.pad = 0;
+        n_sblocks += (r.n + kSizeBlock - 1) / kSizeBlock;
+        n_items += r.n;
+        n_small += r.n_small;
+        n_large += r.n_large;
+    }
+    Failure f = ensure_cap(ctx, ex, ex->d_jobs, ex->jobs_cap, n);
+    if (f.st == GSIM_OK) f = ensure_cap(ctx, ex, ex->d_blocksum, ex->blocksum_cap, n_sblocks);
+    if (f.st == GSIM_OK && n_items > ex->list_cap) {
+        int64_t cap = ex->list_cap;
+        f = ensure_cap(ctx, ex, ex->d_list, cap, kNumClasses * n_items);
+        ex->list_cap = cap / kNumClasses;
+    }
     if (f.st != GSIM_OK) return f;
-    hipStream_t s = j->stream;
-    auto cleanup = [&](Failure e) { destroy_job(ctx, j.get()); return e; };
-    if (hipMemcpyAsync(j->d_src_off, d_src_off, sizeof(int64_t) * (size_t)(nl.S + 1), hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return cleanup(fail(GSIM_E_DEVICE, "stimulus copy: %s", hipGetErrorString(hipGetLastError())));
-    f = enqueue_levels(ctx, j.get(), d_t, d_v);
-    if (f.st != GSIM_OK) return cleanup(f);
-    const int64_t id = ctx->next_id++;
-    ctx->jobs[id] = std::move(j);
-    *out = id;
+    hipStream_t s = ex->stream;
+    HIP_TRY(hipMemcpyAsync(ex->d_jobs, desc, sizeof(JobDesc) * (size_t)n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(ex->ring_ev[slot], s));
+    ex->ring_used[slot] = true;
+    StepArgs a;
+    a.jobs = ex->d_jobs;
+    a.n_jobs = n;
+    a.lane_threshold = ctx->opt_lane_threshold;
+    a.n_sblocks = n_sblocks;
+    a.blocksum = ex->d_blocksum;
+    for (int c = 0; c < kNumClasses; c++) a.list[c] = ex->d_list + (size_t)c * ex->list_cap;
+    a.count = ex->d_counts + ex->parity * kNumClasses;
+    a.next_count = ex->d_counts + (1 - ex->parity) * kNumClasses;
+    a.lut = ctx->d_lut;
+    HIP_TRY(launch_size(a, s));
+    HIP_TRY(launch_level_scan(a, s));
+    std::shared_ptr<StepTiming> tm;
+    if (ctx->opt_timing) {
+        tm = std::make_shared<StepTiming>();
+        HIP_TRY(hipEventCreate(&tm->a));
+        HIP_TRY(hipEventCreate(&tm->b));
+        HIP_TRY(hipEventRecord(tm->a, s));
+    }
+    HIP_TRY(launch_eval(a, kClassSmall, n_small, s));
+    HIP_TRY(launch_eval(a, kClassLarge, n_large, s));
+    HIP_TRY(launch_eval(a, kClassLane, n_items, s));
+    if (tm) HIP_TRY(hipEventRecord(tm->b, s));
+    ex->parity ^= 1;
+    ex->steps++;
+    std::vector<Job *> still;
+    still.reserve(n);
+    for (Job *j : act) {
+        if (tm) j->timing.push_back(tm);
+        j->next_level++;
+        if (j->next_level == j->nl->n_levels) {
+            f = finish_job(j, s);
+            if (f.st != GSIM_OK) return f;
+        } else {
+            still.push_back(j);
+        }
+    }
+    act.swap(still);
+    return kOk;
+}
+
+// One scheduling pass: admit what fits, enqueue one step, then block until at
+// most `max_ahead` steps are unfinished on the device (0: no bound).
+Failure drive(gsim_ctx ctx, Executor *ex, int max_ahead) {
+    Failure f = admit_queued(ctx, ex);
+    if (f.st != GSIM_OK) return f;
+    f = enqueue_step(ctx, ex);
+    if (f.st != GSIM_OK) return f;
+    if (max_ahead > 0 && ex->steps > max_ahead) {
+        const int64_t older = ex->steps - 1 - max_ahead;
+        HIP_TRY(hipEventSynchronize(ex->ring_ev[older % kRing]));
+    }
+    return kOk;
+}
+
+// Drive until every level of `j` is enqueued.
+Failure drive_until_enqueued(gsim_ctx ctx, Job *j) {
+    Executor *ex = j->ex;
+    while (j->phase != kEnqueued && !j->failed) {
+        const int64_t before = ex->steps;
+        const size_t queued = ex->queue.size();
+        Failure f = drive(ctx, ex, 0);
+        if (f.st != GSIM_OK) return f;
+        if (ex->steps == before && ex->queue.size() == queued && j->phase == kQueued)
+            return fail(GSIM_E_OOM, "job %lld cannot be admitted: the HBM budget is held by unreleased jobs",
+                        (long long)j->id);
+    }
     return kOk;
 }
 
@@ -664,8 +845,10 @@ Failure find_job(gsim_ctx ctx, gsim_job id, Job **out) {
 }
 
 Failure wait_job(gsim_ctx ctx, Job *j) {
-    if (!j->waited) {
+    if (!j->waited && !j->failed) {
         Failure f = set_device(ctx);
+        if (f.st != GSIM_OK) return f;
+        f = drive_until_enqueued(ctx, j);
         if (f.st != GSIM_OK) return f;
         HIP_TRY(hipEventSynchronize(j->ev_done));
         j->waited = true;
@@ -675,8 +858,8 @@ Failure wait_job(gsim_ctx ctx, Job *j) {
         }
     }
     if (j->failed)
-        return fail(GSIM_E_OOM, "output arena of %lld transitions overflowed; set GSIM_OPT_ARENA_TRANSITIONS larger",
-                    (long long)j->capacity);
+        return fail(GSIM_E_OOM, "output arena of %lld transitions overflowed or could not be allocated; "
+                    "set GSIM_OPT_ARENA_TRANSITIONS larger", (long long)j->capacity);
     if (j->h_state->check_error)
         return fail(GSIM_E_DEVICE, "internal consistency check failed (code %d)", j->h_state->check_error);
     return kOk;
@@ -752,13 +935,12 @@ Failure fetch(gsim_ctx ctx, Job *j, const int64_t *nets, int64_t n, int64_t *out
 }
 
 }  // namespace
-
 // ===========================================================================
 // C ABI.
 
 extern "C" {
 
-const char *sim_version(void) { return "gsim 0.1 (gfx950)"; }
+const char *sim_version(void) { return "gsim 0.2 (gfx950)"; }
 
 const char *sim_last_error(gsim_ctx ctx) {
     if (ctx) return ctx->err.c_str();
@@ -800,6 +982,8 @@ gsim_status sim_destroy(gsim_ctx ctx) {
     (void)hipSetDevice(ctx->device);
     for (auto &kv : ctx->jobs) destroy_job(ctx, kv.second.get());
     ctx->jobs.clear();
+    for (auto &kv : ctx->executors) destroy_executor(ctx, kv.second.get());
+    ctx->executors.clear();
     for (auto &kv : ctx->netlists) ctx->pool->put(kv.second->d_rec);
     ctx->netlists.clear();
     ctx->pool->put(ctx->d_lut);
@@ -820,13 +1004,13 @@ gsim_status sim_set_option(gsim_ctx ctx, int option, int64_t value) {
         if (value < 0 || value > 1) return record(ctx, fail(GSIM_E_ARG, "kernel option must be 0 or 1"));
         ctx->opt_kernel = (int)value;
         return GSIM_OK;
-    case GSIM_OPT_LEVEL_LOOP:
-        if (value < 0 || value > 1) return record(ctx, fail(GSIM_E_ARG, "level loop option must be 0 or 1"));
-        ctx->opt_level_loop = (int)value;
-        return GSIM_OK;
     case GSIM_OPT_KERNEL_TIMING:
         if (value < 0 || value > 1) return record(ctx, fail(GSIM_E_ARG, "timing option must be 0 or 1"));
         ctx->opt_timing = (int)value;
+        return GSIM_OK;
+    case GSIM_OPT_LANE_THRESHOLD:
+        if (value < 0 || value > INT32_MAX) return record(ctx, fail(GSIM_E_ARG, "lane threshold out of range"));
+        ctx->opt_lane_threshold = (int32_t)value;
         return GSIM_OK;
     }
     return record(ctx, fail(GSIM_E_ARG, "unknown option %d", option));
@@ -843,9 +1027,9 @@ gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl) {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     auto it = ctx->netlists.find(nl);
     if (it == ctx->netlists.end()) return record(ctx, fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nl));
-    for (auto &kv : ctx->jobs)
-        if (kv.second->nl_id == nl)
-            return record(ctx, fail(GSIM_E_ARG, "netlist %lld still has job %lld", (long long)nl, (long long)kv.first));
+    if (it->second->active_jobs > 0)
+        return record(ctx, fail(GSIM_E_ARG, "netlist %lld still has %lld unreleased jobs", (long long)nl,
+                                (long long)it->second->active_jobs));
     ctx->pool->put(it->second->d_rec);
     ctx->netlists.erase(it);
     return GSIM_OK;
@@ -867,17 +1051,112 @@ gsim_status sim_netlist_info(gsim_ctx ctx, gsim_netlist nl, gsim_netlist_info *o
     return GSIM_OK;
 }
 
+gsim_status sim_submit(gsim_ctx ctx, gsim_netlist nl, const int64_t *src_off, const int64_t *t,
+                       const uint8_t *v, void *hip_stream, gsim_job *out) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    if (!out) return record(ctx, fail(GSIM_E_ARG, "null output"));
+    Job *j = nullptr;
+    Failure f = submit(ctx, nl, src_off, t, v, false, 0, 0, (hipStream_t)hip_stream, &j);
+    if (f.st == GSIM_OK) *out = j->id;
+    return record(ctx, f);
+}
+
+gsim_status sim_submit_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_off, const int64_t *d_t,
+                              const uint8_t *d_v, int64_t n_in, int validate, void *hip_stream,
+                              gsim_job *out) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    if (!out) return record(ctx, fail(GSIM_E_ARG, "null output"));
+    Job *j = nullptr;
+    Failure f = submit(ctx, nl, d_src_off, d_t, d_v, true, n_in, validate, (hipStream_t)hip_stream, &j);
+    if (f.st == GSIM_OK) *out = j->id;
+    return record(ctx, f);
+}
+
 gsim_status sim_run(gsim_ctx ctx, gsim_netlist nl, const int64_t *src_off, const int64_t *t,
                     const uint8_t *v, void *hip_stream, gsim_job *out) {
-    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
-    return record(ctx, run_host(ctx, nl, src_off, t, v, hip_stream, out));
+    gsim_status st = sim_submit(ctx, nl, src_off, t, v, hip_stream, out);
+    if (st != GSIM_OK) return st;
+    Job *j = nullptr;
+    Failure f = find_job(ctx, *out, &j);
+    if (f.st == GSIM_OK) f = drive_until_enqueued(ctx, j);
+    return record(ctx, f);
 }
 
 gsim_status sim_run_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_off,
                            const int64_t *d_t, const uint8_t *d_v, int64_t n_in, int validate,
                            void *hip_stream, gsim_job *out) {
+    gsim_status st = sim_submit_device(ctx, nl, d_src_off, d_t, d_v, n_in, validate, hip_stream, out);
+    if (st != GSIM_OK) return st;
+    Job *j = nullptr;
+    Failure f = find_job(ctx, *out, &j);
+    if (f.st == GSIM_OK) f = drive_until_enqueued(ctx, j);
+    return record(ctx, f);
+}
+
+gsim_status sim_run_batch(gsim_ctx ctx, gsim_netlist nl, int32_t n_sets, const int64_t *const *src_off,
+                          const int64_t *const *t, const uint8_t *const *v, void *hip_stream,
+                          gsim_job *out) {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
-    return record(ctx, run_device(ctx, nl, d_src_off, d_t, d_v, n_in, validate, hip_stream, out));
+    if (n_sets < 0 || (n_sets > 0 && (!src_off || !t || !v || !out)))
+        return record(ctx, fail(GSIM_E_ARG, "bad batch arguments"));
+    std::vector<Job *> made;
+    for (int32_t i = 0; i < n_sets; i++) {
+        Job *j = nullptr;
+        Failure f = submit(ctx, nl, src_off[i], t[i], v[i], false, 0, 0, (hipStream_t)hip_stream, &j);
+        if (f.st != GSIM_OK) {
+            for (Job *m : made) {
+                destroy_job(ctx, m);
+                ctx->jobs.erase(m->id);
+            }
+            return record(ctx, f);
+        }
+        made.push_back(j);
+        out[i] = j->id;
+    }
+    // drive while jobs can be admitted or have levels left; jobs that do not
+    // fit yet are admitted by later calls as released jobs free memory
+    if (!made.empty()) {
+        Executor *ex = made.front()->ex;
+        for (;;) {
+            const int64_t before = ex->steps;
+            Failure f = drive(ctx, ex, 0);
+            if (f.st != GSIM_OK) return record(ctx, f);
+            if (ex->steps == before) break;
+        }
+    }
+    return GSIM_OK;
+}
+
+gsim_status sim_drive(gsim_ctx ctx, void *hip_stream, int32_t max_ahead, int32_t *n_active,
+                      int32_t *n_queued) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    if (max_ahead < 0 || max_ahead >= kRing) return record(ctx, fail(GSIM_E_ARG, "max_ahead must be in [0, %d)", kRing));
+    Failure f = set_device(ctx);
+    Executor *ex = nullptr;
+    if (f.st == GSIM_OK) f = get_executor(ctx, (hipStream_t)hip_stream, &ex);
+    if (f.st == GSIM_OK) f = drive(ctx, ex, max_ahead);
+    if (f.st == GSIM_OK) {
+        if (n_active) *n_active = (int32_t)ex->active.size();
+        if (n_queued) *n_queued = (int32_t)ex->queue.size();
+    }
+    return record(ctx, f);
+}
+
+gsim_status sim_job_done(gsim_ctx ctx, gsim_job job, int32_t *done) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    if (!done) return record(ctx, fail(GSIM_E_ARG, "null output"));
+    Job *j = nullptr;
+    Failure f = find_job(ctx, job, &j);
+    if (f.st != GSIM_OK) return record(ctx, f);
+    *done = 0;
+    if (j->failed || j->waited) {
+        *done = 1;
+    } else if (j->phase == kEnqueued) {
+        const hipError_t e = hipEventQuery(j->ev_done);
+        if (e == hipSuccess) *done = 1;
+        else if (e != hipErrorNotReady) return record(ctx, fail(GSIM_E_DEVICE, "event query: %s", hipGetErrorString(e)));
+    }
+    return GSIM_OK;
 }
 
 gsim_status sim_wait(gsim_ctx ctx, gsim_job job) {
@@ -906,9 +1185,9 @@ gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out) {
     out->device_ms = ms;
     out->eval_ms = 0.0;
     out->eval_launches = 0;
-    for (size_t l = 0; l + 1 < j->ev_levels.size(); l += 2) {
+    for (const auto &tm : j->timing) {
         float e = 0.f;
-        if (hipEventElapsedTime(&e, j->ev_levels[l], j->ev_levels[l + 1]) != hipSuccess)
+        if (hipEventElapsedTime(&e, tm->a, tm->b) != hipSuccess)
             return record(ctx, fail(GSIM_E_DEVICE, "event timing failed"));
         out->eval_ms += e;
         out->eval_launches++;

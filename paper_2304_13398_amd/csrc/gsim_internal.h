@@ -34,6 +34,9 @@ constexpr int kWindowLarge = 256;
 // Gates handled per sizing block.
 constexpr int kSizeBlock = 256;
 
+// Evaluate-kernel classes (one work list each per step).
+enum GateClass { kClassSmall = 0, kClassLarge = 1, kClassLane = 2, kNumClasses = 3 };
+
 // One gate, 64 bytes, in level order. Nets are internal ids: sources keep
 // their id, the gate at internal position i drives net S + i.
 struct alignas(64) GateRec {
@@ -59,34 +62,48 @@ struct DevState {
     int32_t check_error;     // an internal consistency check failed (never expected)
 };
 
-struct EvalArgs {
-    const GateRec *rec;      // all gates, level order
-    int64_t g_begin;         // first gate of this launch (internal index)
-    int64_t n;               // gates in this launch
-    int64_t lvl_begin;       // first gate of the level (sizing blocks are relative to it)
+// One job's share of a step: the gates of its current level.
+struct JobDesc {
+    const GateRec *rec;      // the job's netlist, level order
     int64_t S;
-    const int64_t *blockbase;  // per sizing block: absolute arena base
     int64_t *off;            // [S+G] arena offset of each net
     int64_t *len;            // [S+G] transitions of each net
     uint64_t *K;             // arena of packed transitions
     DevState *state;
-    const uint8_t *lut;      // [kNumTypes][256] gate value by packed pin values
+    int64_t lvl_begin;       // first gate of the level
+    int64_t n_gates;         // gates of the level
+    int64_t sblock_begin;    // first sizing block of this job in the step
+    int64_t pad;
+};
+static_assert(sizeof(JobDesc) == 80, "JobDesc layout");
+
+// A step: one level of each of n_jobs jobs.
+struct StepArgs {
+    const JobDesc *jobs;
+    int32_t n_jobs;
+    int32_t lane_threshold;  // gates reading fewer input transitions go to the lane kernel
+    int64_t n_sblocks;       // sizing blocks over all jobs
+    int64_t *blocksum;       // [n_sblocks]: block totals, then absolute arena bases
+    uint64_t *list[kNumClasses];  // work lists: job << 32 | gate
+    uint32_t *count;         // [kNumClasses] list lengths of this step
+    uint32_t *next_count;    // [kNumClasses] list lengths of the next step (cleared here)
+    const uint8_t *lut;      // [12][256] gate value by packed pin values
 };
 
 // Kernel launchers (kernels.hip). All are asynchronous on `s`.
 hipError_t launch_init_sources(const int64_t *d_src_off, const int64_t *d_t, const uint8_t *d_v,
                                int64_t S, int64_t n_in, int64_t *off, int64_t *len, uint64_t *K,
                                DevState *state, int64_t capacity, hipStream_t s);
-hipError_t launch_size(const GateRec *rec, int64_t lvl_begin, int64_t n, int64_t S,
-                       const int64_t *len, int64_t *off, int64_t *blocksum, hipStream_t s);
-hipError_t launch_level_scan(int64_t *blocksum, int64_t nb, DevState *state, hipStream_t s);
-// window: kWindowSmall or kWindowLarge (every gate of the launch has dmax <= window)
-hipError_t launch_eval_wave(const EvalArgs &a, int window, hipStream_t s);
-hipError_t launch_eval_lane(const EvalArgs &a, hipStream_t s);
+// size + classify (grid: n_sblocks), then per-job scan (grid: n_jobs)
+hipError_t launch_size(const StepArgs &a, hipStream_t s);
+hipError_t launch_level_scan(const StepArgs &a, hipStream_t s);
+// evaluate the work list of class `cls`; `max_items` bounds the list length
+hipError_t launch_eval(const StepArgs &a, int cls, int64_t max_items, hipStream_t s);
 hipError_t launch_count_out(const int64_t *len, int64_t S, int64_t G, int64_t *partial,
                             int64_t n_partial, DevState *state, hipStream_t s);
 hipError_t launch_gather(const int64_t *src_off, const int64_t *n_items, const int64_t *dst_off,
                          int64_t n_nets, const uint64_t *K, int64_t *out_t, uint8_t *out_v,
                          hipStream_t s);
+hipError_t launch_clear_u32(uint32_t *p, int64_t n, hipStream_t s);
 
 }  // namespace gsim

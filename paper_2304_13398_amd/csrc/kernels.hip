@@ -101,22 +101,40 @@ __global__ void init_sources_kernel(const int64_t *__restrict__ src_off,
 }
 
 // -------------------------------------------------------------------------
-// Per-level sizing: w_g and its block-local exclusive scan.
-__global__ __launch_bounds__(kSizeBlock) void size_kernel(const GateRec *__restrict__ rec,
-                                                          int64_t lvl_begin, int64_t n,
-                                                          int64_t S,
-                                                          const int64_t *__restrict__ len,
-                                                          int64_t *__restrict__ off,
-                                                          int64_t *__restrict__ blocksum) {
+// A step covers the current level of several jobs; sizing blocks are laid out
+// job after job. The job of a block (or of a work-list entry) is looked up in
+// the step's job table.
+__device__ __forceinline__ int job_of_block(const JobDesc *jobs, int n_jobs, int64_t b) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].sblock_begin <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Per-level sizing and binning: w_g (the sum of the gate's input lengths, an
+// upper bound of its output length), its block-local exclusive scan, and the
+// gate's evaluate class -- lane kernel if its largest delay exceeds the large
+// window or it reads fewer than lane_threshold transitions, else the
+// wavefront kernel of its delay window -- appended to that class's work list.
+__global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
     __shared__ int64_t wsum[kSizeBlock / 64];
-    const int64_t i = (int64_t)blockIdx.x * kSizeBlock + threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int j = job_of_block(A.jobs, A.n_jobs, b);
+    const JobDesc &J = A.jobs[j];
+    const int64_t i = (b - J.sblock_begin) * kSizeBlock + threadIdx.x;
+    const int64_t g = J.lvl_begin + i;
     int64_t w = 0;
-    if (i < n) {
-        const GateRec &r = rec[lvl_begin + i];
+    int cls = -1;
+    if (i < J.n_gates) {
+        const GateRec &r = J.rec[g];
         const int k = r.k;
 #pragma unroll
         for (int p = 0; p < kMaxPins; p++)
-            if (p < k) w += len[r.net[p]];
+            if (p < k) w += J.len[r.net[p]];
+        cls = (r.dmax > kWindowLarge || w < A.lane_threshold) ? kClassLane
+              : r.dmax <= kWindowSmall ? kClassSmall : kClassLarge;
     }
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     int64_t x = w;
@@ -128,22 +146,37 @@ __global__ __launch_bounds__(kSizeBlock) void size_kernel(const GateRec *__restr
         if (lane >= s) x += o;
     }
     if (lane == 63) wsum[wv] = x;
+#pragma unroll
+    for (int c = 0; c < kNumClasses; c++) {
+        const uint64_t mask = __ballot(cls == c);
+        if (mask == 0) continue;
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&A.count[c], (uint32_t)__popcll(mask));
+        base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+        if (cls == c) A.list[c][base + lanes_below(mask)] = ((uint64_t)(uint32_t)j << 32) | (uint64_t)g;
+    }
+    if (b == 0 && threadIdx.x < kNumClasses) A.next_count[threadIdx.x] = 0;
     __syncthreads();
     int64_t before = 0, total = 0;
 #pragma unroll
-    for (int j = 0; j < kSizeBlock / 64; j++) {
-        if (j < wv) before += wsum[j];
-        total += wsum[j];
+    for (int q = 0; q < kSizeBlock / 64; q++) {
+        if (q < wv) before += wsum[q];
+        total += wsum[q];
     }
-    if (i < n) off[S + lvl_begin + i] = before + x - w;
-    if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
+    if (i < J.n_gates) J.off[J.S + g] = before + x - w;
+    if (threadIdx.x == 0) A.blocksum[b] = total;
 }
 
-// One block: block totals -> absolute bases; bump the arena top.
-__global__ __launch_bounds__(1024) void level_scan_kernel(int64_t *__restrict__ blocksum,
-                                                          int64_t nb, DevState *state) {
+// One block per job: the job's block totals -> absolute arena bases; bump the
+// job's arena top (a device bump allocator); flag overflow.
+__global__ __launch_bounds__(1024) void level_scan_kernel(StepArgs A) {
     __shared__ int64_t wsum[16];
     __shared__ int64_t carry_s;
+    const JobDesc &J = A.jobs[blockIdx.x];
+    DevState *state = J.state;
+    int64_t *blocksum = A.blocksum + J.sblock_begin;
+    const int64_t nb = (J.n_gates + kSizeBlock - 1) / kSizeBlock;
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     if (threadIdx.x == 0) carry_s = state->arena_top;
     __syncthreads();
@@ -161,9 +194,9 @@ __global__ __launch_bounds__(1024) void level_scan_kernel(int64_t *__restrict__ 
         if (lane == 63) wsum[wv] = x;
         __syncthreads();
         int64_t before = 0, total = 0;
-        for (int j = 0; j < 16; j++) {
-            if (j < wv) before += wsum[j];
-            total += wsum[j];
+        for (int q = 0; q < 16; q++) {
+            if (q < wv) before += wsum[q];
+            total += wsum[q];
         }
         const int64_t base = carry_s;
         if (i < nb) blocksum[i] = base + before + x - w;
@@ -277,18 +310,18 @@ constexpr uint32_t kNoKey32 = 0xFFFFFFFFu;
 constexpr int64_t kSpan = (int64_t(1) << 30) - 2 - 2 * kWindowLarge;
 
 template <int K, int W>
-__device__ __forceinline__ void eval_gate(const EvalArgs &A, const GateRec &R, int64_t gate,
-                                          WaveLds<W> &L) {
+__device__ __forceinline__ void eval_gate(const JobDesc &J, const int64_t *blockbase,
+                                          const GateRec &R, int64_t gate, WaveLds<W> &L) {
     using Tl = Tiling<K>;
     constexpr int T = Tl::T, E = Tl::E, ST = Tl::STRIDE;
     constexpr int SPL = kRoundSlots / 64;  // slots per lane
     const int lane = lane_id();
-    const int64_t S = A.S;
-    int64_t *len = A.len;
-    int64_t *off = A.off;
-    uint64_t *Kar = A.K;
+    const int64_t S = J.S;
+    int64_t *len = J.len;
+    int64_t *off = J.off;
+    uint64_t *Kar = J.K;
 
-    const int64_t ob = A.blockbase[(gate - A.lvl_begin) / kSizeBlock] + off[S + gate];
+    const int64_t ob = blockbase[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + off[S + gate];
     int64_t pb[K], pl[K], cur[K];
     uint32_t cval[K];
     int64_t reserved = 0;  // slots sized for this gate: the sum of its input lengths
@@ -500,7 +533,7 @@ __device__ __forceinline__ void eval_gate(const EvalArgs &A, const GateRec &R, i
         // ---- keep the tentative ones at the front for the next round
         int ntent = nseq - nf;
         if (ntent > W) {  // cannot happen when dmax <= W
-            if (lane == 0) A.state->check_error = 1;
+            if (lane == 0) J.state->check_error = 1;
             ntent = W;
         }
         if (nf > 0 && ntent > 0) {
@@ -532,7 +565,7 @@ __device__ __forceinline__ void eval_gate(const EvalArgs &A, const GateRec &R, i
         __syncthreads();
     }
     if (out_n > reserved) {  // cannot happen: at most one output per distinct input time
-        if (lane == 0) A.state->check_error = 2;
+        if (lane == 0) J.state->check_error = 2;
         out_n = reserved;
     }
     if (lane == 0) {
@@ -541,25 +574,28 @@ __device__ __forceinline__ void eval_gate(const EvalArgs &A, const GateRec &R, i
     }
 }
 
+// One wavefront per entry of the class-W work list.
 template <int W>
-__global__ __launch_bounds__(64) void eval_wave_kernel(EvalArgs A) {
+__global__ __launch_bounds__(64) void eval_wave_kernel(StepArgs A, int cls) {
     __shared__ WaveLds<W> L;
     const int lane = lane_id();
-    const int64_t gi = blockIdx.x;
-    if (gi >= A.n) return;
-    const int64_t gate = A.g_begin + gi;
-    const GateRec R = A.rec[gate];
-    if (A.state->overflow) {
-        if (lane == 0) { A.len[A.S + gate] = 0; A.off[A.S + gate] = 0; }
+    const int64_t item = blockIdx.x;
+    if (item >= (int64_t)A.count[cls]) return;
+    const uint64_t e = A.list[cls][item];
+    const JobDesc &J = A.jobs[(int)(e >> 32)];
+    const int64_t gate = (int64_t)(uint32_t)e;
+    const GateRec R = J.rec[gate];
+    if (J.state->overflow) {
+        if (lane == 0) { J.len[J.S + gate] = 0; J.off[J.S + gate] = 0; }
         return;
     }
     reinterpret_cast<uint32_t *>(L.lut)[lane] =
         reinterpret_cast<const uint32_t *>(A.lut + (int)R.type * 256)[lane];
     switch (R.k) {
-    case 1: eval_gate<1, W>(A, R, gate, L); break;
-    case 2: eval_gate<2, W>(A, R, gate, L); break;
-    case 3: eval_gate<3, W>(A, R, gate, L); break;
-    default: eval_gate<4, W>(A, R, gate, L); break;
+    case 1: eval_gate<1, W>(J, A.blocksum, R, gate, L); break;
+    case 2: eval_gate<2, W>(J, A.blocksum, R, gate, L); break;
+    case 3: eval_gate<3, W>(J, A.blocksum, R, gate, L); break;
+    default: eval_gate<4, W>(J, A.blocksum, R, gate, L); break;
     }
 }
 
@@ -567,28 +603,30 @@ __global__ __launch_bounds__(64) void eval_wave_kernel(EvalArgs A) {
 // Lane-per-gate evaluation: the sequential procedure on one lane, with the
 // gate's reserved output region used directly as the list of scheduled
 // transitions (denials pop its tail). Exact for any delay.
-__global__ __launch_bounds__(64) void eval_lane_kernel(EvalArgs A) {
-    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gi >= A.n) return;
-    const int64_t gate = A.g_begin + gi;
-    const int64_t S = A.S;
-    if (A.state->overflow) {
-        A.len[S + gate] = 0;
-        A.off[S + gate] = 0;
+__global__ __launch_bounds__(64) void eval_lane_kernel(StepArgs A) {
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= (int64_t)A.count[kClassLane]) return;
+    const uint64_t e = A.list[kClassLane][item];
+    const JobDesc &J = A.jobs[(int)(e >> 32)];
+    const int64_t gate = (int64_t)(uint32_t)e;
+    const int64_t S = J.S;
+    if (J.state->overflow) {
+        J.len[S + gate] = 0;
+        J.off[S + gate] = 0;
         return;
     }
-    const GateRec R = A.rec[gate];
+    const GateRec R = J.rec[gate];
     const int k = R.k;
-    const int64_t ob = A.blockbase[(gate - A.lvl_begin) / kSizeBlock] + A.off[S + gate];
+    const int64_t ob = A.blocksum[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + J.off[S + gate];
     int64_t pb[kMaxPins], pl[kMaxPins], idx[kMaxPins];
     uint32_t cv[kMaxPins];
     int64_t reserved = 0;
     for (int p = 0; p < kMaxPins; p++) {
         pb[p] = 0; pl[p] = 0; idx[p] = 0; cv[p] = kX;
-        if (p < k) { pb[p] = A.off[R.net[p]]; pl[p] = A.len[R.net[p]]; reserved += pl[p]; }
+        if (p < k) { pb[p] = J.off[R.net[p]]; pl[p] = J.len[R.net[p]]; reserved += pl[p]; }
     }
     const uint8_t *lut = A.lut + (int)R.type * 256;
-    uint64_t *Kar = A.K;
+    uint64_t *Kar = J.K;
     uint32_t prev = kX;
     int64_t n = 0;
     for (;;) {
@@ -619,7 +657,7 @@ __global__ __launch_bounds__(64) void eval_lane_kernel(EvalArgs A) {
             const uint32_t cur = n > 0 ? key_value(Kar[ob + n - 1]) : kX;
             if (e != cur) {
                 if (n >= reserved) {  // cannot happen: at most one output per distinct input time
-                    A.state->check_error = 2;
+                    J.state->check_error = 2;
                     break;
                 }
                 Kar[ob + n] = pack_key(tr, e);
@@ -628,8 +666,13 @@ __global__ __launch_bounds__(64) void eval_lane_kernel(EvalArgs A) {
         }
         prev = e;
     }
-    A.len[S + gate] = n;
-    A.off[S + gate] = ob;
+    J.len[S + gate] = n;
+    J.off[S + gate] = ob;
+}
+
+__global__ void clear_u32_kernel(uint32_t *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // -------------------------------------------------------------------------
@@ -693,33 +736,32 @@ hipError_t launch_init_sources(const int64_t *d_src_off, const int64_t *d_t, con
     return hipGetLastError();
 }
 
-hipError_t launch_size(const GateRec *rec, int64_t lvl_begin, int64_t n, int64_t S,
-                       const int64_t *len, int64_t *off, int64_t *blocksum, hipStream_t s) {
-    const int64_t nb = (n + kSizeBlock - 1) / kSizeBlock;
-    if (nb == 0) return hipSuccess;
-    size_kernel<<<dim3((unsigned)nb), dim3(kSizeBlock), 0, s>>>(rec, lvl_begin, n, S, len, off,
-                                                                blocksum);
+hipError_t launch_size(const StepArgs &a, hipStream_t s) {
+    if (a.n_sblocks == 0) return hipSuccess;
+    size_kernel<<<dim3((unsigned)a.n_sblocks), dim3(kSizeBlock), 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_level_scan(int64_t *blocksum, int64_t nb, DevState *state, hipStream_t s) {
-    level_scan_kernel<<<dim3(1), dim3(1024), 0, s>>>(blocksum, nb, state);
+hipError_t launch_level_scan(const StepArgs &a, hipStream_t s) {
+    if (a.n_jobs == 0) return hipSuccess;
+    level_scan_kernel<<<dim3((unsigned)a.n_jobs), dim3(1024), 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_eval_wave(const EvalArgs &a, int window, hipStream_t s) {
-    if (a.n == 0) return hipSuccess;
-    if (window == kWindowSmall)
-        eval_wave_kernel<kWindowSmall><<<dim3((unsigned)a.n), dim3(64), 0, s>>>(a);
+hipError_t launch_eval(const StepArgs &a, int cls, int64_t max_items, hipStream_t s) {
+    if (max_items <= 0) return hipSuccess;
+    if (cls == kClassSmall)
+        eval_wave_kernel<kWindowSmall><<<dim3((unsigned)max_items), dim3(64), 0, s>>>(a, cls);
+    else if (cls == kClassLarge)
+        eval_wave_kernel<kWindowLarge><<<dim3((unsigned)max_items), dim3(64), 0, s>>>(a, cls);
     else
-        eval_wave_kernel<kWindowLarge><<<dim3((unsigned)a.n), dim3(64), 0, s>>>(a);
+        eval_lane_kernel<<<dim3((unsigned)((max_items + 63) / 64)), dim3(64), 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_eval_lane(const EvalArgs &a, hipStream_t s) {
-    if (a.n == 0) return hipSuccess;
-    const int64_t nb = (a.n + 63) / 64;
-    eval_lane_kernel<<<dim3((unsigned)nb), dim3(64), 0, s>>>(a);
+hipError_t launch_clear_u32(uint32_t *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    clear_u32_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(p, n);
     return hipGetLastError();
 }
 

@@ -18,10 +18,11 @@ LIB_PATH = os.path.join(PKG, "libgsim.so")
 OK, E_ARG, E_CYCLE, E_WAVEFORM, E_OOM, E_DEVICE, E_HANDLE, E_OVERFLOW = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "OK", -1: "GSIM_E_ARG", -2: "GSIM_E_CYCLE", -3: "GSIM_E_WAVEFORM",
                 -4: "GSIM_E_OOM", -5: "GSIM_E_DEVICE", -6: "GSIM_E_HANDLE", -7: "GSIM_E_OVERFLOW"}
-OPT_ARENA_TRANSITIONS, OPT_KERNEL, OPT_LEVEL_LOOP, OPT_KERNEL_TIMING = 1, 2, 3, 4
+OPT_ARENA_TRANSITIONS, OPT_KERNEL, OPT_KERNEL_TIMING, OPT_LANE_THRESHOLD = 1, 2, 4, 5
 
 EXPORTED = ("sim_create", "sim_destroy", "sim_last_error", "sim_set_option", "sim_load_netlist",
-            "sim_unload_netlist", "sim_netlist_info", "sim_run", "sim_run_device", "sim_wait",
+            "sim_unload_netlist", "sim_netlist_info", "sim_submit", "sim_submit_device", "sim_run",
+            "sim_run_device", "sim_run_batch", "sim_drive", "sim_job_done", "sim_wait",
             "sim_job_stats", "sim_fetch_waveforms", "sim_release_job", "sim_levelize",
             "sim_validate_stimulus", "sim_version")
 
@@ -72,8 +73,13 @@ def load_library(path: str = LIB_PATH):
         "sim_load_netlist": ([P, i64, i64, P, P, P, P, P, P], st),
         "sim_unload_netlist": ([P, i64], st),
         "sim_netlist_info": ([P, i64, P], st),
+        "sim_submit": ([P, i64, P, P, P, P, P], st),
+        "sim_submit_device": ([P, i64, P, P, P, i64, ctypes.c_int, P, P], st),
         "sim_run": ([P, i64, P, P, P, P, P], st),
         "sim_run_device": ([P, i64, P, P, P, i64, ctypes.c_int, P, P], st),
+        "sim_run_batch": ([P, i64, i32, P, P, P, P, P], st),
+        "sim_drive": ([P, P, i32, P, P], st),
+        "sim_job_done": ([P, i64, P], st),
         "sim_wait": ([P, i64], st),
         "sim_job_stats": ([P, i64, P], st),
         "sim_fetch_waveforms": ([P, i64, P, i64, P, P, P, i64], st),
@@ -192,6 +198,54 @@ class Sim:
                                          ctypes.byref(j)))
         self._job_nets[j.value] = self._nl_nets.get(h, 0)
         return j.value
+
+    def submit(self, h: int, st, stream: int | None = None) -> int:
+        """Queue a job over host-resident stimuli (nothing runs until driven)."""
+        off, t, v = _c(st.off, np.int64), _c(st.t, np.int64), _c(st.v, np.uint8)
+        j = ctypes.c_int64()
+        self._ck(self.lib.sim_submit(self.ctx, h, _p(off), _p(t), _p(v),
+                                     ctypes.c_void_p(stream) if stream else None, ctypes.byref(j)))
+        self._job_nets[j.value] = self._nl_nets.get(h, 0)
+        return j.value
+
+    def submit_device(self, h: int, d_off: int, d_t: int, d_v: int, n_in: int,
+                      stream: int | None = None, validate: bool = False) -> int:
+        j = ctypes.c_int64()
+        self._ck(self.lib.sim_submit_device(self.ctx, h, ctypes.c_void_p(d_off),
+                                            ctypes.c_void_p(d_t), ctypes.c_void_p(d_v), n_in,
+                                            1 if validate else 0,
+                                            ctypes.c_void_p(stream) if stream else None,
+                                            ctypes.byref(j)))
+        self._job_nets[j.value] = self._nl_nets.get(h, 0)
+        return j.value
+
+    def run_batch(self, h: int, stims, stream: int | None = None):
+        """Batched execution of several stimulus sets over one netlist: job handles."""
+        n = len(stims)
+        arrs = [(_c(s.off, np.int64), _c(s.t, np.int64), _c(s.v, np.uint8)) for s in stims]
+        P = ctypes.c_void_p
+        offs = (P * n)(*[a[0].ctypes.data for a in arrs])
+        ts = (P * n)(*[a[1].ctypes.data for a in arrs])
+        vs = (P * n)(*[a[2].ctypes.data for a in arrs])
+        out = np.zeros(n, dtype=np.int64)
+        self._ck(self.lib.sim_run_batch(self.ctx, h, n, ctypes.cast(offs, P), ctypes.cast(ts, P),
+                                        ctypes.cast(vs, P), ctypes.c_void_p(stream) if stream else None,
+                                        _p(out)))
+        for j in out.tolist():
+            self._job_nets[j] = self._nl_nets.get(h, 0)
+        return out.tolist()
+
+    def drive(self, max_ahead: int = 0, stream: int | None = None):
+        """One scheduling pass: (active jobs, queued jobs)."""
+        a, q = ctypes.c_int32(), ctypes.c_int32()
+        self._ck(self.lib.sim_drive(self.ctx, ctypes.c_void_p(stream) if stream else None,
+                                    max_ahead, ctypes.byref(a), ctypes.byref(q)))
+        return a.value, q.value
+
+    def done(self, job: int) -> bool:
+        d = ctypes.c_int32()
+        self._ck(self.lib.sim_job_done(self.ctx, job, ctypes.byref(d)))
+        return bool(d.value)
 
     def wait(self, job: int):
         self._ck(self.lib.sim_wait(self.ctx, job))

@@ -1,0 +1,115 @@
+"""Executor paths on the GPU: batched stimulus sets, jobs of different netlists
+sharing launches (continuous batching), dynamic binning by input volume, and
+admission limited by the HBM budget. Every result is compared exactly with
+the oracle run on the same job alone."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2304_13398_amd import gsim as G
+from paper_2304_13398_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sim():
+    s = G.Sim(0)
+    yield s
+    s.close()
+
+
+def fetch_gates(sim, j, nl):
+    return sim.fetch(j, np.arange(nl.S, nl.S + nl.G))
+
+
+def same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_batch_of_uneven_sets(sim):
+    nl = W.config2_netlist(G=6000, S=48, L=30, seed=3)
+    rng = np.random.default_rng(3)
+    sets = [W.make_stimulus(S=nl.S, n_per_src=int(n), window=1_000_000, seed=100 + i)
+            for i, n in enumerate(W.loguniform_int(rng, 50, 1500, size=7))]
+    say(f"batch: G={nl.G} sets={len(sets)} lengths={[s.n for s in sets]}")
+    h = sim.load_netlist(nl)
+    jobs = sim.run_batch(h, sets)
+    for j, st in zip(jobs, sets):
+        sim.wait(j)
+        assert same(fetch_gates(sim, j, nl), O.o1_simulate(nl, st))
+        sim.release(j)
+    sim.unload_netlist(h)
+
+
+def test_continuous_batching_mixed_netlists(sim):
+    """Jobs of three netlists (different sizes and depths) join a running
+    executor at different steps; each result equals the job run alone."""
+    nls = [W.config1(seed=4)[0], W.config2_netlist(G=4000, S=40, L=25, seed=5),
+           W.config3(G=5000, S=120, L=40, seed=6)[0]]
+    hs = [sim.load_netlist(nl) for nl in nls]
+    rng = np.random.default_rng(7)
+    pending = []
+    for k in range(9):
+        which = k % 3
+        nl = nls[which]
+        n = int(rng.integers(20, 400))
+        st = W.make_stimulus(S=nl.S, n_per_src=n, window=100_000, seed=200 + k)
+        j = sim.submit(hs[which], st)
+        pending.append((j, nl, st))
+        for _ in range(int(rng.integers(1, 6))):   # a few steps before the next arrival
+            sim.drive()
+    say(f"mixed: {len(pending)} jobs submitted")
+    while any(not sim.done(j) for j, _, _ in pending):
+        sim.drive(max_ahead=2)
+    for j, nl, st in pending:
+        sim.wait(j)
+        assert same(fetch_gates(sim, j, nl), O.o1_simulate(nl, st)), f"job {j}"
+        sim.release(j)
+    for h in hs:
+        sim.unload_netlist(h)
+
+
+@pytest.mark.parametrize("threshold", [0, 200, 1 << 30])
+def test_dynamic_binning_thresholds(sim, threshold):
+    """Gates reading fewer than `threshold` input transitions go to the lane
+    kernel: none, some, all."""
+    nl, st = W.config2(G=8000, S=40, L=30, n_per_src=150)
+    sim.set_option(G.OPT_LANE_THRESHOLD, threshold)
+    try:
+        got = sim.simulate(nl, st)
+    finally:
+        sim.set_option(G.OPT_LANE_THRESHOLD, 0)
+    assert same(got, O.o1_simulate(nl, st))
+
+
+def test_admission_waves_under_a_small_budget():
+    """A context whose HBM budget holds about two jobs: five sets are admitted
+    as earlier ones are released, and every result is still exact."""
+    nl = W.config2_netlist(G=3000, S=32, L=20, seed=8)
+    sets = [W.make_stimulus(S=nl.S, n_per_src=300, window=1_000_000, seed=300 + i) for i in range(5)]
+    with G.Sim(0) as probe:
+        h = probe.load_netlist(nl)
+        j = probe.run(h, sets[0])
+        probe.wait(j)
+        need = probe.stats(j).arena_used
+        probe.release(j)
+        probe.unload_netlist(h)
+    arena = int(need * 1.5)
+    per_job = arena * 8 + 64 << 20     # arena + per-net tables and pool rounding
+    with G.Sim(0, hbm_budget_bytes=2 * per_job + (96 << 20)) as s:
+        s.set_option(G.OPT_ARENA_TRANSITIONS, arena)
+        h = s.load_netlist(nl)
+        jobs = s.run_batch(h, sets)
+        for j, st in zip(jobs, sets):
+            s.wait(j)
+            assert same(fetch_gates(s, j, nl), O.o1_simulate(nl, st))
+            s.release(j)
+        s.unload_netlist(h)
