@@ -52,8 +52,15 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--gates", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-levels", type=int, default=10,
+    ap.add_argument("--cpu-levels", type=int, default=25,
                     help="levels of the workload the oracle runs for the CPU baseline")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched section (64 stimulus sets over the 1M-gate netlist)")
+    ap.add_argument("--batched-sets", type=int, default=64)
+    ap.add_argument("--no-served", action="store_true",
+                    help="skip the served section (Poisson requests over 8 resident netlists)")
+    ap.add_argument("--served-jobs", type=int, default=300)
+    ap.add_argument("--served-rates", default="50,200", help="request rates (jobs/s), comma separated")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="instead of the workload, time a plain device-to-device copy of BYTES "
                          "(the practical HBM ceiling, and the reference for the profiler's "
@@ -79,6 +86,131 @@ def copy_probe(nbytes, reps=5):
     print(json.dumps({"copy_probe_bytes": nbytes, "ms_per_copy": ms,
                       "read_plus_write_gbps": gbps}), flush=True)
     return 0
+
+
+def _gen_stimulus(args):
+    from paper_2304_13398_amd import workloads as W
+    S, n, window, seed = args
+    return W.make_stimulus(S=S, n_per_src=n, window=window, seed=seed)
+
+
+def pool_map(fn, items):
+    """Map over CPU worker processes started fresh (spawn): this process holds
+    the GPU, and forked children would inherit its runtime state."""
+    import concurrent.futures
+    import multiprocessing
+    workers = max(1, min(16, len(os.sched_getaffinity(0)), len(items)))
+    if workers == 1:
+        return [fn(x) for x in items]
+    with concurrent.futures.ProcessPoolExecutor(
+            max_workers=workers, mp_context=multiprocessing.get_context("spawn")) as ex:
+        return list(ex.map(fn, items))
+
+
+def bench_batched(G, sim, nl, h, n_sets, seed):
+    """Batched: n_sets stimulus sets over the resident netlist, per-set
+    transitions per PI log-uniform in [50, 5000]; all sets through the
+    executor (shared launches, admitted as HBM allows) vs one set per launch
+    chain. The lane threshold is autotuned on a sample set first."""
+    from paper_2304_13398_amd import autotune
+    from paper_2304_13398_amd import workloads as W
+    rng = np.random.default_rng(seed + 7_000_001)
+    ns = W.loguniform_int(rng, 50, 5000, size=n_sets)
+    t = time.perf_counter()
+    sets = pool_map(_gen_stimulus, [(nl.S, int(n), 1_000_000, seed * 1000 + i)
+                                    for i, n in enumerate(ns)])
+    print(f"[bench] batched: {n_sets} sets generated in {time.perf_counter() - t:.1f}s "
+          f"({sum(x.n for x in sets)} transitions)", file=sys.stderr, flush=True)
+    tuner = autotune.Autotuner(sim, candidates=(0, 64, 192, 512), reps=1)
+    median = sets[int(np.argsort(ns)[len(ns) // 2])]
+    thr, tms = tuner.tune(nl, h, median)
+
+    def one_per_launch():
+        t0 = time.perf_counter()
+        n_out = 0
+        for st in sets:
+            j = sim.run(h, st)
+            sim.wait(j)
+            n_out += sim.stats(j).n_out
+            sim.release(j)
+        return n_out, time.perf_counter() - t0
+
+    def batched():
+        t0 = time.perf_counter()
+        pending = sim.run_batch(h, sets)
+        n_out = 0
+        while pending:
+            sim.drive(max_ahead=2)         # admit sets as memory frees, advance all
+            for j in [j for j in pending if sim.done(j)]:
+                n_out += sim.stats(j).n_out
+                sim.release(j)
+                pending.remove(j)
+        return n_out, time.perf_counter() - t0
+
+    n1, t1 = one_per_launch()
+    n2, t2 = batched()
+    assert n1 == n2, "batched and one-per-launch runs disagree on the output size"
+    print(f"[bench] batched: one-per-launch {t1:.2f}s, batched {t2:.2f}s", file=sys.stderr, flush=True)
+    return {
+        "workload": f"{n_sets} stimulus sets over the 1M-gate netlist, transitions per PI "
+                    f"log-uniform 50-5,000 (mean {float(ns.mean()):.0f})",
+        "sets": n_sets, "n_in": int(sum(x.n for x in sets)), "n_out": int(n2),
+        "batched_transitions_per_s": n2 / t2, "batched_s": t2,
+        "one_per_launch_transitions_per_s": n1 / t1, "one_per_launch_s": t1,
+        "speedup": t1 / t2,
+        "tuned_lane_threshold": thr, "tuning_ms": tms,
+        "includes": "stimulus upload (pageable H2D), all levels, per-set completion wait",
+    }
+
+
+def bench_served(G, sim, n_jobs, rates, seed):
+    """Served: Poisson requests over 8 resident netlists (10k-2M gates), each
+    request log-uniform 20-2,000 transitions per PI and asking for its
+    netlist's primary outputs; continuous batching vs one job at a time."""
+    from paper_2304_13398_amd import autotune, serve
+    t = time.perf_counter()
+    nls = serve.served_netlists(seed=seed)
+    rng = np.random.default_rng(seed + 5_000_011)
+    items = []
+    for k, nl in enumerate(nls):
+        for i, n in enumerate(W_loguniform(rng, 20, 2000, 6)):
+            items.append((nl.S, int(n), 1_000_000, seed * 100_000 + k * 1000 + i))
+    stims = pool_map(_gen_stimulus, items)
+    pool = [stims[6 * k:6 * k + 6] for k in range(len(nls))]
+    hs = [sim.load_netlist(nl) for nl in nls]
+    print(f"[bench] served: netlists and stimuli ready in {time.perf_counter() - t:.1f}s",
+          file=sys.stderr, flush=True)
+    tuner = autotune.Autotuner(sim, candidates=(0, 64, 192, 512), reps=1)
+    tuned = []
+    for nl, h, p in zip(nls, hs, pool):
+        tuned.append(tuner.tune(nl, h, sorted(p, key=lambda x: x.n)[len(p) // 2])[0])
+        big = max(p, key=lambda x: x.n)
+        j = sim.run(h, big)          # learn the arena use of the largest request
+        sim.wait(j)
+        sim.release(j)
+    out = {"workload": "8 resident netlists of 10k-2M gates (mid-size generator, 60 levels); "
+                       "requests uniform over netlists, 20-2,000 transitions per PI (log-uniform), "
+                       "Poisson arrivals; each request fetches its primary outputs",
+           "jobs_per_rate": n_jobs, "tuned_lane_thresholds": tuned, "rates": {}}
+    for rate in rates:
+        reqs = serve.served_workload(n_jobs, rate, nls, pool, seed=seed + int(rate))
+        rc, mc = serve.serve_continuous(sim, hs, reqs, max_ahead=2)
+        rs, ms = serve.serve_sequential(sim, hs, reqs)
+        out["rates"][str(rate)] = {"continuous": serve.summarize(rc, mc),
+                                   "sequential": serve.summarize(rs, ms)}
+        print(f"[bench] served rate {rate}: continuous p50/p99 "
+              f"{out['rates'][str(rate)]['continuous']['p50_ms']:.1f}/"
+              f"{out['rates'][str(rate)]['continuous']['p99_ms']:.1f} ms, sequential "
+              f"{out['rates'][str(rate)]['sequential']['p50_ms']:.1f}/"
+              f"{out['rates'][str(rate)]['sequential']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    for h in hs:
+        sim.unload_netlist(h)
+    return out
+
+
+def W_loguniform(rng, lo, hi, n):
+    from paper_2304_13398_amd import workloads as W
+    return W.loguniform_int(rng, lo, hi, size=n)
 
 
 def algorithmic_bytes(nl, lengths):
@@ -241,8 +373,14 @@ def main():
             "sample": f"oracle O1 (single thread, plain C) on levels 1-{lv} of the same workload "
                       f"({n_gates} gates, {int(o_off[-1])} output transitions, {cpu_s:.1f}s)",
         }
-    print(json.dumps(out), flush=True)
+    sim.set_option(G.OPT_KERNEL_TIMING, 0)
+    if not args.no_batched:
+        out["batched"] = bench_batched(G, sim, nl, h, args.batched_sets, args.seed)
     sim.unload_netlist(h)
+    if not args.no_served:
+        rates = [float(x) for x in args.served_rates.split(",") if x]
+        out["served"] = bench_served(G, sim, args.served_jobs, rates, args.seed)
+    print(json.dumps(out), flush=True)
     sim.close()
     return 0
 

@@ -128,6 +128,10 @@ gsim_status sim_load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *
                              gsim_netlist *out);
 gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl);
 
+/* Per-netlist setting of GSIM_OPT_LANE_THRESHOLD (-1 = follow the context's
+ * option); other options are per context. Applies to jobs stepped afterwards. */
+gsim_status sim_set_netlist_option(gsim_ctx ctx, gsim_netlist nl, int option, int64_t value);
+
 typedef struct {
     int64_t S, G, P;
     int32_t levels;          /* longest path length in gates (0 if G = 0) */
@@ -151,8 +155,9 @@ gsim_status sim_netlist_info(gsim_ctx ctx, gsim_netlist nl, gsim_netlist_info *o
  *   t [N_in], v [N_in] with N_in = src_off[S]
  * The stimuli are validated and copied to the device (one transfer) before the
  * call returns; nothing runs yet. Output storage per job is
- * GSIM_OPT_ARENA_TRANSITIONS, or by default an estimate of twice the pin-read
- * volume of an input-length-preserving circuit, capped by the budget.
+ * GSIM_OPT_ARENA_TRANSITIONS, or by default 1.5x the largest arena use per
+ * input transition seen on this netlist (before any: twice the pin-read volume
+ * of an input-length-preserving circuit), capped by the budget.
  * Errors: GSIM_E_ARG, GSIM_E_WAVEFORM, GSIM_E_OVERFLOW, GSIM_E_OOM, GSIM_E_HANDLE. */
 gsim_status sim_submit(gsim_ctx ctx, gsim_netlist nl, const int64_t *src_off, const int64_t *t,
                        const uint8_t *v, void *hip_stream, gsim_job *out);
@@ -195,12 +200,16 @@ gsim_status sim_run_batch(gsim_ctx ctx, gsim_netlist nl, int32_t n_sets,
 gsim_status sim_drive(gsim_ctx ctx, void *hip_stream, int32_t max_ahead, int32_t *n_active,
                       int32_t *n_queued);
 
-/* Non-blocking: *done = 1 if the job's results are ready (or it failed). */
+/* Non-blocking: *done = 1 if the job's results are ready (or it failed). A job
+ * found to have overflowed automatically sized storage is queued again with
+ * twice the storage and reports 0. */
 gsim_status sim_job_done(gsim_ctx ctx, gsim_job job, int32_t *done);
 
 /* Drive the job's executor until the job is enqueued, then block until its
- * device work is done. GSIM_E_OOM if its output storage overflowed or could
- * not be allocated (the job then holds no results). */
+ * device work is done. A job whose automatically sized output storage
+ * overflowed is re-run with twice the storage (up to 6 times) before this
+ * returns. GSIM_E_OOM if storage set with GSIM_OPT_ARENA_TRANSITIONS overflowed,
+ * or storage could not be allocated (the job then holds no results). */
 gsim_status sim_wait(gsim_ctx ctx, gsim_job job);
 
 typedef struct {
@@ -213,6 +222,7 @@ typedef struct {
     double eval_ms;          /* with GSIM_OPT_KERNEL_TIMING: summed device time of the
                                 evaluate launches, else 0 */
     int64_t eval_launches;   /* levels timed for eval_ms */
+    int64_t retries;         /* automatic re-runs after an output-storage overflow */
 } gsim_job_stats;
 /* Statistics of a finished job (waits for it). */
 gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out);
@@ -224,6 +234,17 @@ gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out);
  *   filled (size query). GSIM_E_ARG if cap < out_off[n]. */
 gsim_status sim_fetch_waveforms(gsim_ctx ctx, gsim_job job, const int64_t *nets, int64_t n,
                                 int64_t *out_off, int64_t *out_t, uint8_t *out_v, int64_t cap);
+
+/* Fingerprint of each requested net's waveform (nets as sim_fetch_waveforms;
+ * NULL = all S+G nets in id order), computed on the device: with
+ * mix(x) the SplitMix64 finaliser (x += 0x9E3779B97F4A7C15;
+ * x = (x ^ x>>30) * 0xBF58476D1CE4E5B9; x = (x ^ x>>27) * 0x94D049BB133111EB;
+ * x ^ x>>31) and key_i = time_i << 2 | value_i for the net's n transitions,
+ *   out = mix(n) + sum_i mix(key_i ^ mix(i))   (mod 2^64).
+ * out[n] is caller-allocated. Lets a caller compare large results without
+ * copying them. */
+gsim_status sim_fetch_hashes(gsim_ctx ctx, gsim_job job, const int64_t *nets, int64_t n,
+                             uint64_t *out);
 
 /* Free a job's device storage. */
 gsim_status sim_release_job(gsim_ctx ctx, gsim_job job);

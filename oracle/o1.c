@@ -341,3 +341,89 @@ int64_t o1_gate(int type, const int64_t *const *in_t, const uint8_t *const *in_v
     free(w.v);
     return n;
 }
+
+/* ---- Memory-light mode for full-size parity checks ------------------------
+ * Same procedure as o1_simulate, but each gate's waveform is reduced to its
+ * length and a 64-bit fingerprint, and freed as soon as its last reader has
+ * been evaluated. Fingerprint of a waveform of n transitions with
+ * key_i = time_i * 4 + value_i:  fp = mix(n) + sum_i mix(key_i XOR mix(i))
+ * (mod 2^64), mix being the SplitMix64 finaliser. */
+static uint64_t fp_mix(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+static uint64_t fingerprint(const int64_t *t, const uint8_t *v, int64_t n) {
+    uint64_t acc = fp_mix((uint64_t)n);
+    for (int64_t i = 0; i < n; i++)
+        acc += fp_mix((((uint64_t)t[i] << 2) | v[i]) ^ fp_mix((uint64_t)i));
+    return acc;
+}
+
+/* Fingerprints of arbitrary CSR waveforms (for cross-checking test helpers). */
+void o1_fingerprints(int64_t n_nets, const int64_t *off, const int64_t *t, const uint8_t *v,
+                     uint64_t *out) {
+    for (int64_t i = 0; i < n_nets; i++)
+        out[i] = fingerprint(t + off[i], v + off[i], off[i + 1] - off[i]);
+}
+
+/* Returns 0, or the same codes as o1_simulate's status. Fills len[G], fp[G]. */
+int o1_simulate_fingerprints(int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
+                             const int64_t *pin_net, const int32_t *rise, const int32_t *fall,
+                             const int64_t *src_off, const int64_t *src_t, const uint8_t *src_v,
+                             int64_t *len, uint64_t *fp) {
+    for (int64_t g = 0; g < G; g++) {
+        if (type[g] >= T_COUNT || pin_off[g + 1] - pin_off[g] != arity_of(type[g])) return -3;
+        for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++)
+            if (pin_net[p] < 0 || pin_net[p] >= S + G || pin_net[p] == S + g) return -3;
+    }
+    int64_t *order = (int64_t *)malloc((size_t)(G ? G : 1) * sizeof(int64_t));
+    int64_t *readers_left = (int64_t *)calloc((size_t)(G ? G : 1), sizeof(int64_t));
+    o1_wave *w = (o1_wave *)calloc((size_t)(G ? G : 1), sizeof(o1_wave));
+    if (!order || !readers_left || !w) { free(order); free(readers_left); free(w); return -1; }
+    int rc = topological_order(S, G, pin_off, pin_net, order);
+    if (rc) { free(order); free(readers_left); free(w); return rc; }
+    for (int64_t p = 0; p < (G ? pin_off[G] : 0); p++)
+        if (pin_net[p] >= S) readers_left[pin_net[p] - S]++;
+    for (int64_t idx = 0; idx < G; idx++) {
+        int64_t g = order[idx];
+        const int64_t *in_t[4];
+        const uint8_t *in_v[4];
+        int64_t in_n[4];
+        int k = arity_of(type[g]);
+        for (int i = 0; i < k; i++) {
+            int64_t net = pin_net[pin_off[g] + i];
+            if (net < S) {
+                in_t[i] = src_t + src_off[net];
+                in_v[i] = src_v + src_off[net];
+                in_n[i] = src_off[net + 1] - src_off[net];
+            } else {
+                in_t[i] = w[net - S].t;
+                in_v[i] = w[net - S].v;
+                in_n[i] = w[net - S].n;
+            }
+        }
+        if (o1_process_cell(type[g], in_t, in_v, in_n, rise + pin_off[g], fall + pin_off[g], &w[g])) {
+            rc = -1;
+            break;
+        }
+        len[g] = w[g].n;
+        fp[g] = fingerprint(w[g].t, w[g].v, w[g].n);
+        for (int i = 0; i < k; i++) {
+            int64_t net = pin_net[pin_off[g] + i];
+            if (net >= S && --readers_left[net - S] == 0) {
+                free(w[net - S].t); free(w[net - S].v);
+                w[net - S].t = NULL; w[net - S].v = NULL;
+            }
+        }
+        if (readers_left[g] == 0) {
+            free(w[g].t); free(w[g].v);
+            w[g].t = NULL; w[g].v = NULL;
+        }
+    }
+    for (int64_t g = 0; g < G; g++) { free(w[g].t); free(w[g].v); }
+    free(order); free(readers_left); free(w);
+    return rc;
+}

@@ -80,6 +80,9 @@ class _O1:
         lib.o1_gate.argtypes = [ctypes.c_int, P, P, P, P, P, P, P, i64]
         lib.o1_calculate_signal.restype = ctypes.c_uint8
         lib.o1_calculate_signal.argtypes = [ctypes.c_int, P]
+        lib.o1_simulate_fingerprints.restype = ctypes.c_int
+        lib.o1_simulate_fingerprints.argtypes = [i64, i64, P, P, P, P, P, P, P, P, P, P]
+        lib.o1_fingerprints.argtypes = [i64, P, P, P, P]
         self.lib = lib
 
 
@@ -132,6 +135,32 @@ def o1_simulate(nl, st, lib: str | None = None):
     finally:
         L.o1_free(h)
     return off, t, v
+
+
+def o1_fingerprints_of(off, t, v, lib: str | None = None):
+    """Fingerprint (see o1.c) of each waveform of CSR arrays."""
+    L = o1_lib(lib).lib
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    t = np.ascontiguousarray(t, dtype=np.int64)
+    v = np.ascontiguousarray(v, dtype=np.uint8)
+    out = np.zeros(max(len(off) - 1, 1), dtype=np.uint64)
+    L.o1_fingerprints(len(off) - 1, _ptr(off), _ptr(t), _ptr(v), _ptr(out))
+    return out[:len(off) - 1]
+
+
+def o1_simulate_fingerprints(nl, st, lib: str | None = None):
+    """O1 on a whole netlist, keeping only each gate's output length and
+    fingerprint (waveforms are freed after their last reader): (len[G], fp[G])."""
+    L = o1_lib(lib).lib
+    arrs = [np.ascontiguousarray(a, dtype=d) for a, d in (
+        (nl.type, np.uint8), (nl.pin_off, np.int64), (nl.pin_net, np.int64), (nl.rise, np.int32),
+        (nl.fall, np.int32), (st.off, np.int64), (st.t, np.int64), (st.v, np.uint8))]
+    ln = np.zeros(max(nl.G, 1), dtype=np.int64)
+    fp = np.zeros(max(nl.G, 1), dtype=np.uint64)
+    rc = L.o1_simulate_fingerprints(nl.S, nl.G, *[_ptr(a) for a in arrs], _ptr(ln), _ptr(fp))
+    if rc:
+        raise OracleError({-1: "out of memory", -2: "cycle", -3: "malformed netlist"}.get(rc, str(rc)))
+    return ln[:nl.G], fp[:nl.G]
 
 
 def o1_gate(gtype, waves, rise, fall, lib: str | None = None):

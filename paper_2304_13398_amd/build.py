@@ -29,11 +29,9 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC, *COMMON]
+    cmd = [HIPCC, *COMMON, *DEVICE]
     if src.endswith(".hip"):
-        cmd += ["-x", "hip", *DEVICE]
-    else:
-        cmd += ["-D__HIP_PLATFORM_AMD__"]
+        cmd += ["-x", "hip"]
     cmd += ["-c", path, "-o", obj]
     subprocess.check_call(cmd)
     return obj

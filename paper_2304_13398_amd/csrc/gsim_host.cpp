@@ -226,62 +226,138 @@ Failure validate_stimulus(int64_t S, const int64_t *src_off, const int64_t *t, c
 }
 
 // ---------------------------------------------------------------------------
-// Device memory: a budgeted caching pool. Released blocks are kept for reuse
-// and only returned to HIP when the budget needs room.
+// Device memory: the context reserves its whole HBM budget as one slab on
+// first use and carves every buffer out of it (best fit, free neighbours
+// merged on release). After that no call reaches hipMalloc/hipFree, whose cost
+// for multi-GB job arenas would dominate short jobs.
 
 class Pool {
   public:
-    explicit Pool(uint64_t budget) : budget_(budget) {}
-    ~Pool() { trim(); }
+    explicit Pool(uint64_t budget) : budget_(budget & ~uint64_t(kAlign - 1)) {}
+    ~Pool() {
+        if (slab_) (void)hipFree(slab_);
+    }
 
     void *get(size_t bytes) {
-        bytes = round(bytes);
-        auto it = cache_.lower_bound(bytes);
-        if (it != cache_.end() && it->first <= bytes + bytes / 4 + (64u << 20)) {
-            void *p = it->second;
-            cached_ -= it->first;
-            live_ += it->first;
-            sizes_[p] = it->first;
-            cache_.erase(it);
-            return p;
+        if (!slab_ && !reserve()) return nullptr;
+        bytes = (bytes + kAlign - 1) & ~size_t(kAlign - 1);
+        if (bytes == 0) bytes = kAlign;
+        auto it = by_size_.lower_bound(bytes);  // best fit
+        if (it == by_size_.end()) return nullptr;
+        const uint64_t off = it->second, sz = it->first;
+        by_size_.erase(it);
+        by_off_.erase(off);
+        if (sz > bytes) insert_free(off + bytes, sz - bytes);
+        used_[off] = bytes;
+        live_ += bytes;
+        return slab_ + off;
+    }
+    void put(void *p) {
+        if (!p) return;
+        const uint64_t off = (uint64_t)((char *)p - slab_);
+        auto it = used_.find(off);
+        if (it == used_.end()) return;
+        uint64_t start = off, size = it->second;
+        live_ -= size;
+        used_.erase(it);
+        auto next = by_off_.find(start + size);  // merge with the free range after
+        if (next != by_off_.end()) {
+            erase_free(next->first, next->second);
+            size += next->second;
         }
-        if (live_ + cached_ + bytes > budget_) trim();
-        if (live_ + bytes > budget_) return nullptr;
-        void *p = nullptr;
-        if (hipMalloc(&p, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            trim();
-            if (hipMalloc(&p, bytes) != hipSuccess) {
-                (void)hipGetLastError();
-                return nullptr;
+        auto prev = by_off_.lower_bound(start);  // and with the one before
+        if (prev != by_off_.begin()) {
+            --prev;
+            if (prev->first + prev->second == start) {
+                start = prev->first;
+                size += prev->second;
+                erase_free(prev->first, prev->second);
             }
         }
-        live_ += bytes;
-        sizes_[p] = bytes;
+        insert_free(start, size);
+    }
+    uint64_t budget() const { return budget_; }
+    uint64_t live() const { return live_; }
+    // Largest block that can still be allocated.
+    uint64_t largest_free() const {
+        if (!slab_) return budget_;
+        return by_size_.empty() ? 0 : by_size_.rbegin()->first;
+    }
+
+  private:
+    static constexpr uint64_t kAlign = 4096;
+    bool reserve() {
+        // take the budget, or as much of it as the device gives
+        uint64_t want = budget_;
+        while (want >= (uint64_t(64) << 20)) {
+            void *p = nullptr;
+            if (hipMalloc(&p, want) == hipSuccess) {
+                slab_ = (char *)p;
+                budget_ = want;
+                insert_free(0, want);
+                return true;
+            }
+            (void)hipGetLastError();
+            want = (want / 10 * 9) & ~uint64_t(kAlign - 1);
+        }
+        return false;
+    }
+    void insert_free(uint64_t off, uint64_t size) {
+        by_off_[off] = size;
+        by_size_.emplace(size, off);
+    }
+    void erase_free(uint64_t off, uint64_t size) {
+        by_off_.erase(off);
+        auto range = by_size_.equal_range(size);
+        for (auto i = range.first; i != range.second; ++i)
+            if (i->second == off) {
+                by_size_.erase(i);
+                break;
+            }
+    }
+    uint64_t budget_, live_ = 0;
+    char *slab_ = nullptr;
+    std::map<uint64_t, uint64_t> by_off_;        // free ranges: offset -> size
+    std::multimap<uint64_t, uint64_t> by_size_;  // free ranges: size -> offset
+    std::unordered_map<uint64_t, uint64_t> used_;
+};
+
+// Pinned host buffers, kept for reuse by power-of-two size class (pinning and
+// unpinning multi-MB buffers per job is slow).
+class PinnedCache {
+  public:
+    ~PinnedCache() {
+        for (auto &kv : free_) (void)hipHostFree(kv.second);
+    }
+    void *get(size_t bytes) {
+        size_t c = 4096;
+        while (c < bytes) c <<= 1;
+        auto it = free_.find(c);
+        if (it != free_.end()) {
+            void *p = it->second;
+            free_.erase(it);
+            size_[p] = c;
+            return p;
+        }
+        void *p = nullptr;
+        if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        size_[p] = c;
         return p;
     }
     void put(void *p) {
         if (!p) return;
-        auto it = sizes_.find(p);
-        if (it == sizes_.end()) return;
-        live_ -= it->second;
-        cached_ += it->second;
-        cache_.emplace(it->second, p);
-        sizes_.erase(it);
+        auto it = size_.find(p);
+        if (it == size_.end()) return;
+        free_.emplace(it->second, p);
+        size_.erase(it);
     }
-    void trim() {
-        for (auto &kv : cache_) (void)hipFree(kv.second);
-        cache_.clear();
-        cached_ = 0;
-    }
-    uint64_t budget() const { return budget_; }
-    uint64_t live() const { return live_; }
 
   private:
-    static size_t round(size_t b) { return (b + (2u << 20) - 1) & ~size_t((2u << 20) - 1); }
-    uint64_t budget_, live_ = 0, cached_ = 0;
-    std::multimap<size_t, void *> cache_;
-    std::unordered_map<void *, size_t> sizes_;
+    std::multimap<size_t, void *> free_;
+    std::unordered_map<void *, size_t> size_;
 };
 
 // ---------------------------------------------------------------------------
@@ -302,6 +378,9 @@ struct Netlist {
     std::vector<int64_t> internal_of_user;  // [G]
     GateRec *d_rec = nullptr;
     int64_t active_jobs = 0;
+    int64_t max_level_n = 0;        // gates of the largest level
+    int32_t lane_threshold = -1;    // -1: the context's GSIM_OPT_LANE_THRESHOLD
+    double arena_per_input = 0.0;   // largest arena use per input transition seen so far
 };
 
 // Device time of one step's evaluate launches (with GSIM_OPT_KERNEL_TIMING).
@@ -324,21 +403,28 @@ struct Job {
     JobPhase phase = kQueued;
     int32_t next_level = 0;
     int64_t n_in = 0, capacity = 0, capacity_request = 0;
-    int64_t *d_off = nullptr, *d_len = nullptr, *d_partial = nullptr, *d_src_off = nullptr;
-    int64_t *d_src_t = nullptr;   // host stimuli staged on the device
-    uint8_t *d_src_v = nullptr;
-    const int64_t *src_t = nullptr;  // stimuli the sources are packed from (staged or caller's)
-    const uint8_t *src_v = nullptr;
+    int64_t *d_off = nullptr, *d_len = nullptr, *d_partial = nullptr;
+    int64_t *d_src_off = nullptr;    // host submissions: device copy of the offsets
+    // host submissions: pinned copies of the caller's stimuli, uploaded into
+    // the job's arena at admission (a queued job holds no device memory)
+    int64_t *h_src_off = nullptr, *h_t = nullptr;
+    uint8_t *h_v = nullptr;
+    // device submissions: the caller's arrays, used in place
+    const int64_t *dev_src_off = nullptr, *dev_t = nullptr;
+    const uint8_t *dev_v = nullptr;
     uint64_t *d_K = nullptr;      // arena of packed transitions
     DevState *d_state = nullptr;
     DevState *h_state = nullptr;  // pinned
     hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_done = nullptr;
     std::vector<std::shared_ptr<StepTiming>> timing;
     int64_t n_partial = 0;
+    int32_t retries = 0;          // automatic re-runs after an arena overflow
     bool waited = false, failed = false;
 };
 
 constexpr int kMaxJobsPerStep = 256;
+constexpr int64_t kStage = int64_t(8) << 20;       // fetch staging buffer, transitions
+constexpr int64_t kStageBatch = int64_t(1) << 16;  // nets per gather batch
 constexpr int kRing = 32;  // steps whose descriptors may be in flight
 
 // One executor per stream: its jobs advance one level per step, all active
@@ -367,12 +453,17 @@ struct gsim_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
     std::unique_ptr<Pool> pool;
+    PinnedCache pinned;
     uint8_t *d_lut = nullptr;
     std::string err;
     int64_t next_id = 1;
     std::map<int64_t, std::unique_ptr<Netlist>> netlists;
     std::map<int64_t, std::unique_ptr<Job>> jobs;
     std::map<hipStream_t, std::unique_ptr<Executor>> executors;
+    int64_t arenas_held = 0;  // jobs that hold an output arena (admitted, not yet released)
+    int64_t *d_stage_t = nullptr;  // fetch staging buffers, kStage transitions
+    uint8_t *d_stage_v = nullptr;
+    int64_t *d_stage_meta = nullptr;
     int64_t opt_arena = 0;
     int opt_kernel = 0;
     int opt_timing = 0;
@@ -447,6 +538,7 @@ Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, co
         r.n_large = cnt[3 * (size_t)l + 1];
         r.n = r.n_small + r.n_large + cnt[3 * (size_t)l + 2];
         nl->lane_gates += cnt[3 * (size_t)l + 2];
+        nl->max_level_n = std::max(nl->max_level_n, r.n);
     }
     nl->internal_of_user.resize(G);
     {
@@ -522,17 +614,17 @@ void destroy_executor(gsim_ctx ctx, Executor *ex) {
         if (ex->ring_ev[i]) (void)hipEventDestroy(ex->ring_ev[i]);
 }
 
-// Grow a step scratch buffer; the stream is drained first because queued
-// steps may still read the old one.
+// Grow a step scratch buffer (the old one is kept if the new allocation fails).
 template <class T>
 Failure ensure_cap(gsim_ctx ctx, Executor *ex, T *&buf, int64_t &cap, int64_t need) {
     if (need <= cap) return kOk;
     const int64_t ncap = std::max<int64_t>(need, std::max<int64_t>(2 * cap, 1024));
-    HIP_TRY(hipStreamSynchronize(ex->stream));
+    T *nbuf = pool_get<T>(*ctx->pool, ncap);
+    if (!nbuf) return fail(GSIM_E_OOM, "no device memory for step scratch (%lld entries)", (long long)ncap);
+    HIP_TRY(hipStreamSynchronize(ex->stream));  // queued steps may still read the old buffer
     ctx->pool->put(buf);
-    buf = pool_get<T>(*ctx->pool, ncap);
-    cap = buf ? ncap : 0;
-    if (!buf) return fail(GSIM_E_OOM, "no device memory for step scratch (%lld entries)", (long long)ncap);
+    buf = nbuf;
+    cap = ncap;
     return kOk;
 }
 
@@ -540,16 +632,14 @@ Failure ensure_cap(gsim_ctx ctx, Executor *ex, T *&buf, int64_t &cap, int64_t ne
 
 void free_job_buffers(gsim_ctx ctx, Job *j) {
     Pool &pool = *ctx->pool;
+    if (j->d_K) ctx->arenas_held--;
     pool.put(j->d_off);
     pool.put(j->d_len);
     pool.put(j->d_partial);
     pool.put(j->d_src_off);
-    pool.put(j->d_src_t);
-    pool.put(j->d_src_v);
     pool.put(j->d_K);
     pool.put(j->d_state);
-    j->d_off = j->d_len = j->d_partial = j->d_src_off = j->d_src_t = nullptr;
-    j->d_src_v = nullptr;
+    j->d_off = j->d_len = j->d_partial = j->d_src_off = nullptr;
     j->d_K = nullptr;
     j->d_state = nullptr;
 }
@@ -565,7 +655,12 @@ void destroy_job(gsim_ctx ctx, Job *j) {
     }
     if (j->nl) j->nl->active_jobs--;
     free_job_buffers(ctx, j);
-    if (j->h_state) (void)hipHostFree(j->h_state);
+    ctx->pinned.put(j->h_state);
+    ctx->pinned.put(j->h_src_off);
+    ctx->pinned.put(j->h_t);
+    ctx->pinned.put(j->h_v);
+    j->h_src_off = j->h_t = nullptr;
+    j->h_v = nullptr;
     if (j->ev_start) (void)hipEventDestroy(j->ev_start);
     if (j->ev_end) (void)hipEventDestroy(j->ev_end);
     if (j->ev_done) (void)hipEventDestroy(j->ev_done);
@@ -575,10 +670,16 @@ void destroy_job(gsim_ctx ctx, Job *j) {
 }
 
 int64_t default_capacity(const Netlist &nl, int64_t n_in) {
-    // Twice the pin-read volume of a circuit whose every net is as long as
-    // the mean source waveform, plus the sources (in transitions).
-    const double mean = nl.S > 0 ? (double)n_in / (double)nl.S : 0.0;
-    const double est = (double)n_in + 2.0 * (double)nl.P * mean + 1024.0;
+    double est;
+    if (nl.arena_per_input > 0.0) {
+        // 1.5x the largest arena use per input transition seen on this netlist
+        est = 1.5 * nl.arena_per_input * (double)n_in + 4096.0;
+    } else {
+        // twice the pin-read volume of a circuit whose every net is as long as
+        // the mean source waveform, plus the sources (in transitions)
+        const double mean = nl.S > 0 ? (double)n_in / (double)nl.S : 0.0;
+        est = (double)n_in + 2.0 * (double)nl.P * mean + 1024.0;
+    }
     return (int64_t)std::min(est, 9.0e18);
 }
 
@@ -624,26 +725,26 @@ Failure submit(gsim_ctx ctx, gsim_netlist nlh, const int64_t *src_off, const int
     j->ex = ex;
     j->n_in = n_in;
     j->capacity_request = ctx->opt_arena;
-    Pool &pool = *ctx->pool;
-    j->d_src_off = pool_get<int64_t>(pool, nl.S + 1);
-    if (!j->d_src_off) return fail(GSIM_E_OOM, "no device memory for the stimulus offsets");
-    auto cleanup = [&](Failure e) { free_job_buffers(ctx, j.get()); return e; };
-    hipStream_t s = ex->stream;
     if (!device_arrays) {
-        j->d_src_t = pool_get<int64_t>(pool, n_in);
-        j->d_src_v = pool_get<uint8_t>(pool, n_in);
-        if (!j->d_src_t || !j->d_src_v) return cleanup(fail(GSIM_E_OOM, "no device memory to stage the stimuli"));
-        if (hipMemcpyAsync(j->d_src_off, src_off, sizeof(int64_t) * (size_t)(nl.S + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
-            (n_in > 0 && hipMemcpyAsync(j->d_src_t, t, sizeof(int64_t) * (size_t)n_in, hipMemcpyHostToDevice, s) != hipSuccess) ||
-            (n_in > 0 && hipMemcpyAsync(j->d_src_v, v, (size_t)n_in, hipMemcpyHostToDevice, s) != hipSuccess))
-            return cleanup(fail(GSIM_E_DEVICE, "stimulus upload: %s", hipGetErrorString(hipGetLastError())));
-        j->src_t = j->d_src_t;
-        j->src_v = j->d_src_v;
+        const size_t S1 = (size_t)nl.S + 1;
+        j->h_src_off = (int64_t *)ctx->pinned.get(sizeof(int64_t) * S1);
+        j->h_t = (int64_t *)ctx->pinned.get(sizeof(int64_t) * (size_t)std::max<int64_t>(n_in, 1));
+        j->h_v = (uint8_t *)ctx->pinned.get((size_t)std::max<int64_t>(n_in, 1));
+        if (!j->h_src_off || !j->h_t || !j->h_v) {
+            ctx->pinned.put(j->h_src_off);
+            ctx->pinned.put(j->h_t);
+            ctx->pinned.put(j->h_v);
+            return fail(GSIM_E_OOM, "no pinned host memory to hold the stimuli");
+        }
+        std::memcpy(j->h_src_off, src_off, sizeof(int64_t) * S1);
+        if (n_in > 0) {
+            std::memcpy(j->h_t, t, sizeof(int64_t) * (size_t)n_in);
+            std::memcpy(j->h_v, v, (size_t)n_in);
+        }
     } else {
-        if (hipMemcpyAsync(j->d_src_off, src_off, sizeof(int64_t) * (size_t)(nl.S + 1), hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return cleanup(fail(GSIM_E_DEVICE, "stimulus copy: %s", hipGetErrorString(hipGetLastError())));
-        j->src_t = t;
-        j->src_v = v;
+        j->dev_src_off = src_off;
+        j->dev_t = t;
+        j->dev_v = v;
     }
     j->id = ctx->next_id++;
     nl.active_jobs++;
@@ -670,14 +771,40 @@ Failure admit(gsim_ctx ctx, Executor *ex, Job *j) {
     Netlist &nl = *j->nl;
     Pool &pool = *ctx->pool;
     const int64_t N = nl.S + nl.G;
+    {
+        // step scratch for the active set with this job, before its arena
+        int64_t sblocks = 0, items = 0;
+        for (Job *a : ex->active) {
+            sblocks += (a->nl->max_level_n + kSizeBlock - 1) / kSizeBlock;
+            items += a->nl->max_level_n;
+        }
+        sblocks += (nl.max_level_n + kSizeBlock - 1) / kSizeBlock;
+        items += nl.max_level_n;
+        Failure f = ensure_cap(ctx, ex, ex->d_jobs, ex->jobs_cap, (int64_t)ex->active.size() + 1);
+        if (f.st == GSIM_OK) f = ensure_cap(ctx, ex, ex->d_blocksum, ex->blocksum_cap, sblocks);
+        if (f.st == GSIM_OK && items > ex->list_cap) {
+            int64_t cap = ex->list_cap * kNumClasses;
+            f = ensure_cap(ctx, ex, ex->d_list, cap, kNumClasses * items);
+            ex->list_cap = cap / kNumClasses;
+        }
+        if (f.st != GSIM_OK) return f;
+    }
     j->n_partial = std::max<int64_t>(1, std::min<int64_t>(1024, (nl.G + 255) / 256));
+    // host stimuli are uploaded into the arena itself: times over the first
+    // n_in slots (packed in place), values as bytes in its last slots
+    const int64_t staged = j->h_t ? j->n_in + (j->n_in + 7) / 8 + 1 : j->n_in;
     int64_t cap = j->capacity_request > 0 ? j->capacity_request : default_capacity(nl, j->n_in);
-    cap = std::max(cap, j->n_in);
+    cap = std::max(cap, staged);
     if (j->capacity_request <= 0) {
-        // fit the automatic estimate into what the budget leaves
-        const uint64_t room = pool.budget() > pool.live() ? pool.budget() - pool.live() : 0;
+        // An automatic estimate that does not fit what the budget leaves waits
+        // for memory; only when no other job holds an arena is a job started
+        // with what is left (an overflow then re-runs it larger).
+        const uint64_t room = pool.largest_free();
         const int64_t fit = (int64_t)(room / sizeof(uint64_t) * 90 / 100) - (int64_t)(N * 2 + 4096);
-        if (cap > fit) cap = std::max(j->n_in, fit);
+        if (cap > fit) {
+            if (ctx->arenas_held > 0) return fail(GSIM_E_OOM, "waiting for device memory");
+            cap = std::max(staged, fit);
+        }
     }
     j->capacity = cap;
     j->d_off = pool_get<int64_t>(pool, N);
@@ -685,16 +812,19 @@ Failure admit(gsim_ctx ctx, Executor *ex, Job *j) {
     j->d_partial = pool_get<int64_t>(pool, j->n_partial);
     j->d_state = pool_get<DevState>(pool, 1);
     j->d_K = pool_get<uint64_t>(pool, cap);
-    if (!j->d_off || !j->d_len || !j->d_partial || !j->d_state || !j->d_K) {
+    if (j->h_t) j->d_src_off = pool_get<int64_t>(pool, nl.S + 1);
+    if (!j->d_off || !j->d_len || !j->d_partial || !j->d_state || !j->d_K || (j->h_t && !j->d_src_off)) {
         pool.put(j->d_off); pool.put(j->d_len); pool.put(j->d_partial); pool.put(j->d_state); pool.put(j->d_K);
-        j->d_off = j->d_len = j->d_partial = nullptr;
+        pool.put(j->d_src_off);
+        j->d_off = j->d_len = j->d_partial = j->d_src_off = nullptr;
         j->d_state = nullptr;
         j->d_K = nullptr;
         return fail(GSIM_E_OOM, "no device memory for a job of %lld transitions of output storage", (long long)cap);
     }
+    ctx->arenas_held++;
     if (!j->h_state) {
-        if (hipHostMalloc((void **)&j->h_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess ||
-            hipEventCreate(&j->ev_start) != hipSuccess || hipEventCreate(&j->ev_end) != hipSuccess ||
+        j->h_state = (DevState *)ctx->pinned.get(sizeof(DevState));
+        if (!j->h_state || hipEventCreate(&j->ev_start) != hipSuccess || hipEventCreate(&j->ev_end) != hipSuccess ||
             hipEventCreateWithFlags(&j->ev_done, hipEventDisableTiming) != hipSuccess) {
             (void)hipGetLastError();
             return fail(GSIM_E_DEVICE, "event or pinned-memory creation failed");
@@ -702,7 +832,21 @@ Failure admit(gsim_ctx ctx, Executor *ex, Job *j) {
     }
     hipStream_t s = ex->stream;
     HIP_TRY(hipEventRecord(j->ev_start, s));
-    HIP_TRY(launch_init_sources(j->d_src_off, j->src_t, j->src_v, nl.S, j->n_in, j->d_off, j->d_len, j->d_K,
+    const int64_t *src_off = j->dev_src_off, *src_t = j->dev_t;
+    const uint8_t *src_v = j->dev_v;
+    if (j->h_t) {
+        uint8_t *vbytes = (uint8_t *)(j->d_K + (cap - (j->n_in + 7) / 8 - 1));
+        HIP_TRY(hipMemcpyAsync(j->d_src_off, j->h_src_off, sizeof(int64_t) * (size_t)(nl.S + 1),
+                               hipMemcpyHostToDevice, s));
+        if (j->n_in > 0) {
+            HIP_TRY(hipMemcpyAsync(j->d_K, j->h_t, sizeof(int64_t) * (size_t)j->n_in, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(vbytes, j->h_v, (size_t)j->n_in, hipMemcpyHostToDevice, s));
+        }
+        src_off = j->d_src_off;
+        src_t = (const int64_t *)j->d_K;
+        src_v = vbytes;
+    }
+    HIP_TRY(launch_init_sources(src_off, src_t, src_v, nl.S, j->n_in, j->d_off, j->d_len, j->d_K,
                                 j->d_state, j->capacity, s));
     j->phase = kActive;
     j->next_level = 0;
@@ -711,14 +855,17 @@ Failure admit(gsim_ctx ctx, Executor *ex, Job *j) {
     return kOk;
 }
 
-// Admit queued jobs in order while they fit. A job that does not fit while
-// nothing else holds memory on this executor can never run: it fails.
+// Admit queued jobs that fit, first fit in submission order: a job that does
+// not fit now does not hold back smaller ones behind it.
 Failure admit_queued(gsim_ctx ctx, Executor *ex) {
-    while (!ex->queue.empty() && (int)ex->active.size() < kMaxJobsPerStep) {
-        Job *j = ex->queue.front();
+    for (auto it = ex->queue.begin(); it != ex->queue.end() && (int)ex->active.size() < kMaxJobsPerStep;) {
+        Job *j = *it;
         Failure f = admit(ctx, ex, j);
-        if (f.st == GSIM_E_OOM) break;
-        ex->queue.pop_front();
+        if (f.st == GSIM_E_OOM) {
+            ++it;
+            continue;
+        }
+        it = ex->queue.erase(it);
         if (f.st != GSIM_OK) {
             j->failed = true;
             return f;
@@ -749,6 +896,7 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
         d.lvl_begin = r.begin;
         d.n_gates = r.n;
         d.sblock_begin = n_sblocks;
+        d.lane_threshold = j->nl->lane_threshold >= 0 ? j->nl->lane_threshold : ctx->opt_lane_threshold;
         d.pad = 0;
         n_sblocks += (r.n + kSizeBlock - 1) / kSizeBlock;
         n_items += r.n;
@@ -758,7 +906,7 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
     Failure f = ensure_cap(ctx, ex, ex->d_jobs, ex->jobs_cap, n);
     if (f.st == GSIM_OK) f = ensure_cap(ctx, ex, ex->d_blocksum, ex->blocksum_cap, n_sblocks);
     if (f.st == GSIM_OK && n_items > ex->list_cap) {
-        int64_t cap = ex->list_cap;
+        int64_t cap = ex->list_cap * kNumClasses;
         f = ensure_cap(ctx, ex, ex->d_list, cap, kNumClasses * n_items);
         ex->list_cap = cap / kNumClasses;
     }
@@ -770,7 +918,7 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
     StepArgs a;
     a.jobs = ex->d_jobs;
     a.n_jobs = n;
-    a.lane_threshold = ctx->opt_lane_threshold;
+    a.pad = 0;
     a.n_sblocks = n_sblocks;
     a.blocksum = ex->d_blocksum;
     for (int c = 0; c < kNumClasses; c++) a.list[c] = ex->d_list + (size_t)c * ex->list_cap;
@@ -844,24 +992,88 @@ Failure find_job(gsim_ctx ctx, gsim_job id, Job **out) {
     return kOk;
 }
 
+constexpr int kMaxRetries = 6;
+
+// A finished job whose automatically sized arena overflowed goes back to the
+// front of its executor's queue with twice the storage; returns true if so.
+bool requeue_if_overflowed(gsim_ctx ctx, Job *j) {
+    if (!j->h_state->overflow || ctx == nullptr) return false;
+    if (j->capacity_request > 0 && j->retries == 0) return false;  // caller-sized: report it
+    if (j->retries >= kMaxRetries) return false;
+    j->retries++;
+    j->capacity_request = 2 * j->capacity;
+    Pool &pool = *ctx->pool;
+    if (j->d_K) ctx->arenas_held--;
+    pool.put(j->d_off); pool.put(j->d_len); pool.put(j->d_partial); pool.put(j->d_state); pool.put(j->d_K);
+    j->d_off = j->d_len = j->d_partial = nullptr;
+    j->d_state = nullptr;
+    j->d_K = nullptr;
+    j->timing.clear();
+    j->phase = kQueued;
+    j->ex->queue.push_front(j);
+    return true;
+}
+
+// Record what a finished job taught about arena use on its netlist.
+void learn(Job *j) {
+    if (!j->h_state->overflow && j->n_in > 0)
+        j->nl->arena_per_input = std::max(j->nl->arena_per_input,
+                                          (double)j->h_state->arena_top / (double)j->n_in);
+}
+
 Failure wait_job(gsim_ctx ctx, Job *j) {
-    if (!j->waited && !j->failed) {
+    while (!j->waited && !j->failed) {
         Failure f = set_device(ctx);
         if (f.st != GSIM_OK) return f;
         f = drive_until_enqueued(ctx, j);
         if (f.st != GSIM_OK) return f;
         HIP_TRY(hipEventSynchronize(j->ev_done));
+        if (requeue_if_overflowed(ctx, j)) continue;
         j->waited = true;
+        learn(j);
         if (j->h_state->overflow) {
             j->failed = true;
             free_job_buffers(ctx, j);
         }
     }
     if (j->failed)
-        return fail(GSIM_E_OOM, "output arena of %lld transitions overflowed or could not be allocated; "
-                    "set GSIM_OPT_ARENA_TRANSITIONS larger", (long long)j->capacity);
+        return fail(GSIM_E_OOM, "output arena of %lld transitions overflowed or could not be allocated "
+                    "(after %d automatic retries); set GSIM_OPT_ARENA_TRANSITIONS larger",
+                    (long long)j->capacity, (int)j->retries);
     if (j->h_state->check_error)
         return fail(GSIM_E_DEVICE, "internal consistency check failed (code %d)", j->h_state->check_error);
+    return kOk;
+}
+
+// Internal ids of the requested nets (all nets in id order when nets is null).
+Failure internal_ids(const Netlist &nl, const int64_t *nets, int64_t n, std::vector<int64_t> &ids) {
+    const int64_t N = nl.S + nl.G;
+    ids.resize(n);
+    for (int64_t i = 0; i < n; i++) {
+        const int64_t u = nets ? nets[i] : i;
+        if (u < 0 || u >= N) return fail(GSIM_E_ARG, "net %lld out of range", (long long)u);
+        ids[i] = u < nl.S ? u : nl.S + nl.internal_of_user[u - nl.S];
+    }
+    return kOk;
+}
+
+// Arena offset and length of each requested net, gathered on the device in
+// batches of kStageBatch (one small copy each way per batch).
+Failure net_meta(gsim_ctx ctx, Job *j, const std::vector<int64_t> &ids, std::vector<int64_t> &off,
+                 std::vector<int64_t> &len) {
+    const int64_t n = (int64_t)ids.size();
+    off.resize(n);
+    len.resize(n);
+    hipStream_t s = ctx->stream;
+    int64_t *d_ids = ctx->d_stage_meta, *d_off = d_ids + kStageBatch, *d_len = d_off + kStageBatch;
+    for (int64_t i0 = 0; i0 < n; i0 += kStageBatch) {
+        const int64_t m = std::min<int64_t>(kStageBatch, n - i0);
+        HIP_TRY(hipMemcpyAsync(d_ids, ids.data() + i0, sizeof(int64_t) * (size_t)m, hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_gather_meta(d_ids, m, j->d_off, j->d_len, d_off, d_len, s));
+        HIP_TRY(hipMemcpyAsync(off.data() + i0, d_off, sizeof(int64_t) * (size_t)m, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(len.data() + i0, d_len, sizeof(int64_t) * (size_t)m, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     return kOk;
 }
 
@@ -870,45 +1082,34 @@ Failure fetch(gsim_ctx ctx, Job *j, const int64_t *nets, int64_t n, int64_t *out
     Failure f = wait_job(ctx, j);
     if (f.st != GSIM_OK) return f;
     Netlist &nl = *j->nl;
-    const int64_t N = nl.S + nl.G;
-    if (!nets) n = N;
+    if (!nets) n = nl.S + nl.G;
     if (n < 0 || !out_off) return fail(GSIM_E_ARG, "bad net list");
-    std::vector<int64_t> internal(n);
-    for (int64_t i = 0; i < n; i++) {
-        const int64_t u = nets ? nets[i] : i;
-        if (u < 0 || u >= N) return fail(GSIM_E_ARG, "net %lld out of range", (long long)u);
-        internal[i] = u < nl.S ? u : nl.S + nl.internal_of_user[u - nl.S];
-    }
-    std::vector<int64_t> off(N), len(N);
-    HIP_TRY(hipMemcpy(off.data(), j->d_off, sizeof(int64_t) * (size_t)N, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(len.data(), j->d_len, sizeof(int64_t) * (size_t)N, hipMemcpyDeviceToHost));
+    std::vector<int64_t> ids, off, len;
+    f = internal_ids(nl, nets, n, ids);
+    if (f.st == GSIM_OK) f = net_meta(ctx, j, ids, off, len);
+    if (f.st != GSIM_OK) return f;
     out_off[0] = 0;
-    for (int64_t i = 0; i < n; i++) out_off[i + 1] = out_off[i] + len[internal[i]];
+    for (int64_t i = 0; i < n; i++) out_off[i + 1] = out_off[i] + len[i];
     if (!out_t) return kOk;
     if (!out_v) return fail(GSIM_E_ARG, "null out_v");
     if (cap < out_off[n]) return fail(GSIM_E_ARG, "capacity %lld < %lld transitions", (long long)cap, (long long)out_off[n]);
-    // Gather in batches through a device staging buffer.
-    const int64_t total = out_off[n];
-    const int64_t stage = std::max<int64_t>(1, std::min<int64_t>(total, int64_t(64) << 20));
-    Pool &pool = *ctx->pool;
-    int64_t *d_st = pool_get<int64_t>(pool, stage);
-    uint8_t *d_sv = pool_get<uint8_t>(pool, stage);
-    const int64_t max_batch = 1 << 16;
-    int64_t *d_meta = pool_get<int64_t>(pool, 3 * max_batch);
-    auto release = [&]() { pool.put(d_st); pool.put(d_sv); pool.put(d_meta); };
-    if (!d_st || !d_sv || !d_meta) { release(); return fail(GSIM_E_OOM, "no device memory for the fetch staging buffer"); }
+    // Gather in batches through the staging buffers; a net that does not fit
+    // in what is left of a batch is split across batches.
+    const int64_t stage = kStage;
+    int64_t *d_st = ctx->d_stage_t;
+    uint8_t *d_sv = ctx->d_stage_v;
+    const int64_t max_batch = kStageBatch;
+    int64_t *d_meta = ctx->d_stage_meta;
     hipStream_t s = ctx->stream;
     std::vector<int64_t> meta(3 * max_batch);
-    // Walk the requested nets in order, filling the staging buffer; a net
-    // that does not fit in what is left is split across batches.
     int64_t i = 0, done_in_net = 0;  // next net, transitions of it already copied
     while (i < n) {
         int64_t nb = 0, acc = 0;
         const int64_t dst0 = out_off[i] + done_in_net;
         while (i < n && nb < max_batch && acc < stage) {
-            const int64_t li = len[internal[i]] - done_in_net;
+            const int64_t li = len[i] - done_in_net;
             const int64_t take = std::min(li, stage - acc);
-            meta[nb] = off[internal[i]] + done_in_net;
+            meta[nb] = off[i] + done_in_net;
             meta[max_batch + nb] = take;
             meta[2 * max_batch + nb] = acc;
             nb++;
@@ -920,17 +1121,37 @@ Failure fetch(gsim_ctx ctx, Job *j, const int64_t *nets, int64_t n, int64_t *out
                 done_in_net += take;
             }
         }
-        hipError_t err = hipMemcpyAsync(d_meta, meta.data(), sizeof(int64_t) * 3 * (size_t)max_batch, hipMemcpyHostToDevice, s);
-        if (err == hipSuccess)
-            err = launch_gather(d_meta, d_meta + max_batch, d_meta + 2 * max_batch, nb, j->d_K, d_st, d_sv, s);
-        if (err == hipSuccess && acc > 0)
-            err = hipMemcpyAsync(out_t + dst0, d_st, sizeof(int64_t) * (size_t)acc, hipMemcpyDeviceToHost, s);
-        if (err == hipSuccess && acc > 0)
-            err = hipMemcpyAsync(out_v + dst0, d_sv, (size_t)acc, hipMemcpyDeviceToHost, s);
-        if (err == hipSuccess) err = hipStreamSynchronize(s);
-        if (err != hipSuccess) { release(); return fail(GSIM_E_DEVICE, "fetch: %s", hipGetErrorString(err)); }
+        HIP_TRY(hipMemcpyAsync(d_meta, meta.data(), sizeof(int64_t) * 3 * (size_t)max_batch, hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_gather(d_meta, d_meta + max_batch, d_meta + 2 * max_batch, nb, j->d_K, d_st, d_sv, s));
+        if (acc > 0) {
+            HIP_TRY(hipMemcpyAsync(out_t + dst0, d_st, sizeof(int64_t) * (size_t)acc, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(out_v + dst0, d_sv, (size_t)acc, hipMemcpyDeviceToHost, s));
+        }
+        HIP_TRY(hipStreamSynchronize(s));
     }
-    release();
+    return kOk;
+}
+
+Failure fetch_hashes(gsim_ctx ctx, Job *j, const int64_t *nets, int64_t n, uint64_t *out) {
+    Failure f = wait_job(ctx, j);
+    if (f.st != GSIM_OK) return f;
+    Netlist &nl = *j->nl;
+    if (!nets) n = nl.S + nl.G;
+    if (n < 0 || (n > 0 && !out)) return fail(GSIM_E_ARG, "bad net list");
+    std::vector<int64_t> ids;
+    f = internal_ids(nl, nets, n, ids);
+    if (f.st != GSIM_OK) return f;
+    hipStream_t s = ctx->stream;
+    int64_t *d_ids = ctx->d_stage_meta, *d_off = d_ids + kStageBatch, *d_len = d_off + kStageBatch;
+    uint64_t *d_h = (uint64_t *)ctx->d_stage_t;
+    for (int64_t i0 = 0; i0 < n; i0 += kStageBatch) {
+        const int64_t m = std::min<int64_t>(kStageBatch, n - i0);
+        HIP_TRY(hipMemcpyAsync(d_ids, ids.data() + i0, sizeof(int64_t) * (size_t)m, hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_gather_meta(d_ids, m, j->d_off, j->d_len, d_off, d_len, s));
+        HIP_TRY(launch_hash(d_off, d_len, m, j->d_K, d_h, s));
+        HIP_TRY(hipMemcpyAsync(out + i0, d_h, sizeof(uint64_t) * (size_t)m, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     return kOk;
 }
 
@@ -967,6 +1188,11 @@ gsim_status sim_create(int device, uint64_t hbm_budget_bytes, gsim_ctx *out) {
     ctx->pool = std::make_unique<Pool>(budget);
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess)
         return record(nullptr, fail(GSIM_E_DEVICE, "stream creation failed"));
+    ctx->d_stage_t = (int64_t *)ctx->pool->get(sizeof(int64_t) * kStage);
+    ctx->d_stage_v = (uint8_t *)ctx->pool->get(kStage);
+    ctx->d_stage_meta = (int64_t *)ctx->pool->get(sizeof(int64_t) * 3 * kStageBatch);
+    if (!ctx->d_stage_t || !ctx->d_stage_v || !ctx->d_stage_meta)
+        return record(nullptr, fail(GSIM_E_OOM, "no device memory for the fetch staging buffers"));
     std::vector<uint8_t> lut = build_lut();
     ctx->d_lut = (uint8_t *)ctx->pool->get(lut.size());
     if (!ctx->d_lut || hipMemcpy(ctx->d_lut, lut.data(), lut.size(), hipMemcpyHostToDevice) != hipSuccess) {
@@ -987,6 +1213,9 @@ gsim_status sim_destroy(gsim_ctx ctx) {
     for (auto &kv : ctx->netlists) ctx->pool->put(kv.second->d_rec);
     ctx->netlists.clear();
     ctx->pool->put(ctx->d_lut);
+    ctx->pool->put(ctx->d_stage_t);
+    ctx->pool->put(ctx->d_stage_v);
+    ctx->pool->put(ctx->d_stage_meta);
     ctx->pool.reset();
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -1032,6 +1261,16 @@ gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl) {
                                 (long long)it->second->active_jobs));
     ctx->pool->put(it->second->d_rec);
     ctx->netlists.erase(it);
+    return GSIM_OK;
+}
+
+gsim_status sim_set_netlist_option(gsim_ctx ctx, gsim_netlist nl, int option, int64_t value) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    auto it = ctx->netlists.find(nl);
+    if (it == ctx->netlists.end()) return record(ctx, fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nl));
+    if (option != GSIM_OPT_LANE_THRESHOLD) return record(ctx, fail(GSIM_E_ARG, "option %d is not per netlist", option));
+    if (value < -1 || value > INT32_MAX) return record(ctx, fail(GSIM_E_ARG, "lane threshold out of range"));
+    it->second->lane_threshold = (int32_t)value;
     return GSIM_OK;
 }
 
@@ -1153,8 +1392,11 @@ gsim_status sim_job_done(gsim_ctx ctx, gsim_job job, int32_t *done) {
         *done = 1;
     } else if (j->phase == kEnqueued) {
         const hipError_t e = hipEventQuery(j->ev_done);
-        if (e == hipSuccess) *done = 1;
-        else if (e != hipErrorNotReady) return record(ctx, fail(GSIM_E_DEVICE, "event query: %s", hipGetErrorString(e)));
+        if (e == hipSuccess) {
+            if (!requeue_if_overflowed(ctx, j)) *done = 1;
+        } else if (e != hipErrorNotReady) {
+            return record(ctx, fail(GSIM_E_DEVICE, "event query: %s", hipGetErrorString(e)));
+        }
     }
     return GSIM_OK;
 }
@@ -1185,6 +1427,7 @@ gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out) {
     out->device_ms = ms;
     out->eval_ms = 0.0;
     out->eval_launches = 0;
+    out->retries = j->retries;
     for (const auto &tm : j->timing) {
         float e = 0.f;
         if (hipEventElapsedTime(&e, tm->a, tm->b) != hipSuccess)
@@ -1202,6 +1445,15 @@ gsim_status sim_fetch_waveforms(gsim_ctx ctx, gsim_job job, const int64_t *nets,
     Failure f = find_job(ctx, job, &j);
     if (f.st == GSIM_OK) f = set_device(ctx);
     if (f.st == GSIM_OK) f = fetch(ctx, j, nets, n, out_off, out_t, out_v, cap);
+    return record(ctx, f);
+}
+
+gsim_status sim_fetch_hashes(gsim_ctx ctx, gsim_job job, const int64_t *nets, int64_t n, uint64_t *out) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    Job *j = nullptr;
+    Failure f = find_job(ctx, job, &j);
+    if (f.st == GSIM_OK) f = set_device(ctx);
+    if (f.st == GSIM_OK) f = fetch_hashes(ctx, j, nets, n, out);
     return record(ctx, f);
 }
 

@@ -73,7 +73,8 @@ struct JobDesc {
     int64_t lvl_begin;       // first gate of the level
     int64_t n_gates;         // gates of the level
     int64_t sblock_begin;    // first sizing block of this job in the step
-    int64_t pad;
+    int32_t lane_threshold;  // gates reading fewer input transitions go to the lane kernel
+    int32_t pad;
 };
 static_assert(sizeof(JobDesc) == 80, "JobDesc layout");
 
@@ -81,7 +82,7 @@ static_assert(sizeof(JobDesc) == 80, "JobDesc layout");
 struct StepArgs {
     const JobDesc *jobs;
     int32_t n_jobs;
-    int32_t lane_threshold;  // gates reading fewer input transitions go to the lane kernel
+    int32_t pad;
     int64_t n_sblocks;       // sizing blocks over all jobs
     int64_t *blocksum;       // [n_sblocks]: block totals, then absolute arena bases
     uint64_t *list[kNumClasses];  // work lists: job << 32 | gate
@@ -105,5 +106,10 @@ hipError_t launch_gather(const int64_t *src_off, const int64_t *n_items, const i
                          int64_t n_nets, const uint64_t *K, int64_t *out_t, uint8_t *out_v,
                          hipStream_t s);
 hipError_t launch_clear_u32(uint32_t *p, int64_t n, hipStream_t s);
+// per-net fingerprints (see hash_kernel) and off/len of a list of nets
+hipError_t launch_hash(const int64_t *nets_off, const int64_t *nets_len, int64_t n_nets,
+                       const uint64_t *K, uint64_t *out, hipStream_t s);
+hipError_t launch_gather_meta(const int64_t *net, int64_t n, const int64_t *off, const int64_t *len,
+                              int64_t *out_off, int64_t *out_len, hipStream_t s);
 
 }  // namespace gsim

@@ -77,11 +77,12 @@ __device__ __forceinline__ uint64_t wave_suffix_min(uint64_t x) {
 // -------------------------------------------------------------------------
 // Sources: packed into the arena at [0, n_in); their offsets and lengths; the
 // job state.
-__global__ void init_sources_kernel(const int64_t *__restrict__ src_off,
-                                    const int64_t *__restrict__ t, const uint8_t *__restrict__ v,
-                                    int64_t S, int64_t n_in, int64_t *__restrict__ off,
-                                    int64_t *__restrict__ len, uint64_t *__restrict__ K,
-                                    DevState *state, int64_t capacity) {
+// `t` may be the arena itself (each element is read, then overwritten by the
+// same thread), so no restrict on t and K.
+__global__ void init_sources_kernel(const int64_t *__restrict__ src_off, const int64_t *t,
+                                    const uint8_t *__restrict__ v, int64_t S, int64_t n_in,
+                                    int64_t *__restrict__ off, int64_t *__restrict__ len,
+                                    uint64_t *K, DevState *state, int64_t capacity) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t i = i0; i < n_in; i += stride) K[i] = pack_key(t[i], v[i]);
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
 #pragma unroll
         for (int p = 0; p < kMaxPins; p++)
             if (p < k) w += J.len[r.net[p]];
-        cls = (r.dmax > kWindowLarge || w < A.lane_threshold) ? kClassLane
+        cls = (r.dmax > kWindowLarge || w < J.lane_threshold) ? kClassLane
               : r.dmax <= kWindowSmall ? kClassSmall : kClassLarge;
     }
     const int lane = lane_id(), wv = threadIdx.x >> 6;
@@ -576,7 +577,7 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, const int64_t *block
 
 // One wavefront per entry of the class-W work list.
 template <int W>
-__global__ __launch_bounds__(64) void eval_wave_kernel(StepArgs A, int cls) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void eval_wave_kernel(StepArgs A, int cls) {
     __shared__ WaveLds<W> L;
     const int lane = lane_id();
     const int64_t item = blockIdx.x;
@@ -670,6 +671,46 @@ __global__ __launch_bounds__(64) void eval_lane_kernel(StepArgs A) {
     J.off[S + gate] = ob;
 }
 
+// -------------------------------------------------------------------------
+// Per-net fingerprint: mix(n) + sum over transitions i of mix(key_i ^ mix(i))
+// (mod 2^64), key_i = time << 2 | value, mix = the SplitMix64 finaliser. The
+// index inside mix binds each transition to its position, so reordering is
+// detected; the sum lets a wavefront reduce one net's transitions in parallel.
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+__global__ __launch_bounds__(256) void hash_kernel(const int64_t *__restrict__ nets_off,
+                                                   const int64_t *__restrict__ nets_len,
+                                                   int64_t n_nets, const uint64_t *__restrict__ K,
+                                                   uint64_t *__restrict__ out) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * 256) >> 6;
+    for (int64_t i = wave; i < n_nets; i += n_waves) {
+        const int64_t a = nets_off[i], n = nets_len[i];
+        uint64_t acc = 0;
+        for (int64_t j = lane; j < n; j += 64) acc += mix64(K[a + j] ^ mix64((uint64_t)j));
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1) acc += shfl_down_u64(acc, s);
+        if (lane == 0) out[i] = acc + mix64((uint64_t)n);
+    }
+}
+
+// off/len of requested nets: out_off[i] = off[net[i]], out_len[i] = len[net[i]]
+__global__ void gather_meta_kernel(const int64_t *__restrict__ net, int64_t n,
+                                   const int64_t *__restrict__ off, const int64_t *__restrict__ len,
+                                   int64_t *__restrict__ out_off, int64_t *__restrict__ out_len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        out_off[i] = off[net[i]];
+        out_len[i] = len[net[i]];
+    }
+}
+
 __global__ void clear_u32_kernel(uint32_t *p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -756,6 +797,22 @@ hipError_t launch_eval(const StepArgs &a, int cls, int64_t max_items, hipStream_
         eval_wave_kernel<kWindowLarge><<<dim3((unsigned)max_items), dim3(64), 0, s>>>(a, cls);
     else
         eval_lane_kernel<<<dim3((unsigned)((max_items + 63) / 64)), dim3(64), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash(const int64_t *nets_off, const int64_t *nets_len, int64_t n_nets,
+                       const uint64_t *K, uint64_t *out, hipStream_t s) {
+    if (n_nets <= 0) return hipSuccess;
+    const int64_t waves = n_nets < (1 << 16) ? n_nets : (1 << 16);
+    hash_kernel<<<dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s>>>(nets_off, nets_len, n_nets, K, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_meta(const int64_t *net, int64_t n, const int64_t *off, const int64_t *len,
+                              int64_t *out_off, int64_t *out_len, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    gather_meta_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(net, n, off, len, out_off,
+                                                                              out_len);
     return hipGetLastError();
 }
 

@@ -21,9 +21,9 @@ STATUS_NAMES = {0: "OK", -1: "GSIM_E_ARG", -2: "GSIM_E_CYCLE", -3: "GSIM_E_WAVEF
 OPT_ARENA_TRANSITIONS, OPT_KERNEL, OPT_KERNEL_TIMING, OPT_LANE_THRESHOLD = 1, 2, 4, 5
 
 EXPORTED = ("sim_create", "sim_destroy", "sim_last_error", "sim_set_option", "sim_load_netlist",
-            "sim_unload_netlist", "sim_netlist_info", "sim_submit", "sim_submit_device", "sim_run",
+            "sim_unload_netlist", "sim_set_netlist_option", "sim_netlist_info", "sim_submit", "sim_submit_device", "sim_run",
             "sim_run_device", "sim_run_batch", "sim_drive", "sim_job_done", "sim_wait",
-            "sim_job_stats", "sim_fetch_waveforms", "sim_release_job", "sim_levelize",
+            "sim_job_stats", "sim_fetch_waveforms", "sim_fetch_hashes", "sim_release_job", "sim_levelize",
             "sim_validate_stimulus", "sim_version")
 
 
@@ -43,7 +43,8 @@ class JobStats(ctypes.Structure):
     _fields_ = [("n_in", ctypes.c_int64), ("n_out", ctypes.c_int64),
                 ("pin_reads", ctypes.c_int64), ("arena_used", ctypes.c_int64),
                 ("arena_capacity", ctypes.c_int64), ("device_ms", ctypes.c_double),
-                ("eval_ms", ctypes.c_double), ("eval_launches", ctypes.c_int64)]
+                ("eval_ms", ctypes.c_double), ("eval_launches", ctypes.c_int64),
+                ("retries", ctypes.c_int64)]
 
 
 _lib = None
@@ -73,6 +74,7 @@ def load_library(path: str = LIB_PATH):
         "sim_load_netlist": ([P, i64, i64, P, P, P, P, P, P], st),
         "sim_unload_netlist": ([P, i64], st),
         "sim_netlist_info": ([P, i64, P], st),
+        "sim_set_netlist_option": ([P, i64, ctypes.c_int, i64], st),
         "sim_submit": ([P, i64, P, P, P, P, P], st),
         "sim_submit_device": ([P, i64, P, P, P, i64, ctypes.c_int, P, P], st),
         "sim_run": ([P, i64, P, P, P, P, P], st),
@@ -83,6 +85,7 @@ def load_library(path: str = LIB_PATH):
         "sim_wait": ([P, i64], st),
         "sim_job_stats": ([P, i64, P], st),
         "sim_fetch_waveforms": ([P, i64, P, i64, P, P, P, i64], st),
+        "sim_fetch_hashes": ([P, i64, P, i64, P], st),
         "sim_release_job": ([P, i64], st),
         "sim_levelize": ([i64, i64, P, P, P, P, P, P, P], st),
         "sim_validate_stimulus": ([i64, P, P, P, i64], st),
@@ -173,6 +176,9 @@ class Sim:
     def unload_netlist(self, h: int):
         self._ck(self.lib.sim_unload_netlist(self.ctx, h))
         self._nl_nets.pop(h, None)
+
+    def set_netlist_option(self, h: int, option: int, value: int):
+        self._ck(self.lib.sim_set_netlist_option(self.ctx, h, option, int(value)))
 
     def netlist_info(self, h: int) -> NetlistInfo:
         info = NetlistInfo()
@@ -270,6 +276,17 @@ class Sim:
         self._ck(self.lib.sim_fetch_waveforms(self.ctx, job, _p(nets), n, _p(off), _p(t), _p(v),
                                               total))
         return off, t[:total], v[:total]
+
+    def hashes(self, job: int, nets=None) -> np.ndarray:
+        """Per-net fingerprints (see sim_fetch_hashes) of ``nets`` (all if None)."""
+        if nets is None:
+            n = self._job_nets[job]
+        else:
+            nets = _c(nets, np.int64)
+            n = len(nets)
+        out = np.zeros(max(n, 1), dtype=np.uint64)
+        self._ck(self.lib.sim_fetch_hashes(self.ctx, job, _p(nets), n, _p(out)))
+        return out[:n]
 
     def release(self, job: int):
         self._ck(self.lib.sim_release_job(self.ctx, job))

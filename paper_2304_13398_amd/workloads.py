@@ -199,21 +199,26 @@ def _distinct_sorted_times(rng, rows, n, window):
 
 def _values_no_repeat(rng, lengths, probs):
     """Values drawn from ``probs`` over {0,1,X,Z}; a value equal to the previous
-    one of the same source (X before the first) is drawn again."""
+    one of the same source (X before the first) is drawn again, all such
+    positions at once, until none is left. Only redrawn positions and their
+    successors can change status, so later passes look at those alone."""
     n = int(lengths.sum())
     v = rng.choice(4, size=n, p=probs).astype(np.uint8)
     starts = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.int64)
-    is_start = np.zeros(n, dtype=bool)
+    is_start = np.zeros(n + 1, dtype=bool)
     is_start[starts[lengths > 0]] = True
-    while True:
-        prev = np.empty(n, dtype=np.uint8)
-        prev[1:] = v[:-1]
-        prev[is_start] = VX
-        bad = v == prev
-        k = int(bad.sum())
-        if k == 0:
-            return v
-        v[bad] = rng.choice(4, size=k, p=probs).astype(np.uint8)
+
+    def bad_among(idx):
+        prev = np.where(is_start[idx], VX, v[np.maximum(idx - 1, 0)])
+        return idx[v[idx] == prev]
+
+    bad = bad_among(np.arange(n, dtype=np.int64))
+    while len(bad):
+        v[bad] = rng.choice(4, size=len(bad), p=probs).astype(np.uint8)
+        cand = np.union1d(bad, bad + 1)
+        cand = cand[cand < n]
+        bad = bad_among(cand)
+    return v
 
 
 def make_stimulus(*, S, n_per_src, window, probs=(0.45, 0.45, 0.05, 0.05), seed=1) -> Stimulus:

@@ -113,3 +113,26 @@ def test_admission_waves_under_a_small_budget():
             assert same(fetch_gates(s, j, nl), O.o1_simulate(nl, st))
             s.release(j)
         s.unload_netlist(h)
+
+
+def test_learned_arena_size_and_automatic_retry(sim):
+    """A dense stimulus teaches the netlist's arena use per input transition;
+    sparse stimuli then need more per input transition than 1.5x that, so
+    their first runs overflow and are re-run with twice the storage. Results
+    stay exact."""
+    nl = W.config2_netlist(G=6000, S=32, L=40, seed=9)
+    h = sim.load_netlist(nl)
+    dense = W.make_stimulus(S=nl.S, n_per_src=3000, window=1_000_000, seed=31)
+    j = sim.run(h, dense)
+    sim.wait(j)
+    sim.release(j)
+    retries = []
+    for n in (40, 15, 5):
+        st = W.make_stimulus(S=nl.S, n_per_src=n, window=1_000_000, seed=32 + n)
+        j = sim.run(h, st)
+        sim.wait(j)
+        retries.append(sim.stats(j).retries)
+        assert same(fetch_gates(sim, j, nl), O.o1_simulate(nl, st))
+        sim.release(j)
+    say(f"retries per sparse job: {retries}")
+    sim.unload_netlist(h)

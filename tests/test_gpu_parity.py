@@ -312,3 +312,19 @@ def test_one_huge_gap_at_round_edge(sim):
     k = sum(len(g[1]) for g in gates)
     nl = P.netlist_of(2, gates, [40] * k, [7] * k)
     check(sim, nl, P.stimulus_of([a, b]))
+
+
+def test_fingerprints_match_oracle(sim):
+    from tests import net_hash
+    nl, st = W.config2(G=20_000, S=64)
+    off, t, v = O.o1_simulate(nl, st)
+    h = sim.load_netlist(nl)
+    j = sim.run(h, st)
+    got = sim.hashes(j)                      # all nets, sources first
+    src = net_hash.fingerprints(st.off, st.t, st.v)
+    assert np.array_equal(got[:nl.S], src)
+    assert np.array_equal(got[nl.S:], net_hash.fingerprints(off, t, v))
+    sub = np.array([nl.S + 3, 1, nl.S + nl.G - 1])
+    assert np.array_equal(sim.hashes(j, sub), got[sub])
+    sim.release(j)
+    sim.unload_netlist(h)
