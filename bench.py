@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-levels", type=int, default=25,
                     help="levels of the workload the oracle runs for the CPU baseline")
+    ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-configuration latency")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched section (64 stimulus sets over the 1M-gate netlist)")
     ap.add_argument("--batched-sets", type=int, default=64)
@@ -208,6 +209,62 @@ def bench_served(G, sim, n_jobs, rates, seed):
     return out
 
 
+def bench_tiny_latency(G, sim, seed, reps=200):
+    """Latency of the tiny configuration (1,000 gates, 32 PIs, 20 levels, 100
+    transitions per PI): one job at a time, stimuli resident in HBM (submit to
+    completion), and from host stimuli to every gate output in host memory."""
+    import torch
+    from paper_2304_13398_amd import workloads as W
+    nl, st = W.config1(seed=seed)
+    h = sim.load_netlist(nl)
+    dev = torch.device("cuda:0")
+    d = [torch.from_numpy(a).to(dev) for a in (st.off, st.t, st.v)]
+    stream = torch.cuda.current_stream()
+    gates = np.arange(nl.S, nl.S + nl.G)
+    resident, host = [], []
+    for i in range(reps + 5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        j = sim.run_device(h, d[0].data_ptr(), d[1].data_ptr(), d[2].data_ptr(), st.n,
+                           stream=stream.cuda_stream)
+        sim.wait(j)
+        t1 = time.perf_counter()
+        sim.release(j)
+        t2 = time.perf_counter()
+        j = sim.run(h, st)
+        sim.wait(j)
+        off, t, v = sim.fetch(j, gates)
+        t3 = time.perf_counter()
+        sim.release(j)
+        if i >= 5:
+            resident.append((t1 - t0) * 1e6)
+            host.append((t3 - t2) * 1e6)
+    n_out = int(off[-1])
+    sim.unload_netlist(h)
+    return {
+        "workload": "tiny: 1,000 gates, 32 PIs, 20 levels, 10 gate types, 100 transitions per PI",
+        "n_out": n_out,
+        "resident_p50_us": float(np.percentile(resident, 50)),
+        "resident_p99_us": float(np.percentile(resident, 99)),
+        "host_to_host_p50_us": float(np.percentile(host, 50)),
+        "host_to_host_p99_us": float(np.percentile(host, 99)),
+        "runs": reps,
+    }
+
+
+def workload_stats(nl, lengths):
+    """The paper's workload statistics (Table 2 columns and Eq. 5): coefficient
+    of variation of the given (source) waveform lengths and of the generated
+    ones, and the mean generated length per level."""
+    src = lengths[:nl.S].astype(np.float64)
+    gen = lengths[nl.S:nl.S + nl.G].astype(np.float64)
+    cv = lambda a: float(a.std() / a.mean()) if len(a) and a.mean() > 0 else None
+    per_level = [float(gen[nl.level == lv].mean()) for lv in range(1, int(nl.level.max()) + 1)]
+    return {"wcv_given": cv(src), "wcv_generated": cv(gen),
+            "given_transitions": int(src.sum()), "generated_transitions": int(gen.sum()),
+            "mean_generated_length_per_level": [round(x, 1) for x in per_level]}
+
+
 def W_loguniform(rng, lo, hi, n):
     from paper_2304_13398_amd import workloads as W
     return W.loguniform_int(rng, lo, hi, size=n)
@@ -342,7 +399,7 @@ def main():
         "device_ms_per_step": dev_ms,
         "hbm_gbps_step": (b_eval / (dev_ms / 1000.0) / 1e9),
         "roofline": {
-            "kernel": "eval_wave_kernel (+ eval_lane_kernel, none here)",
+            "kernel": "eval_wave_kernel<64> (every gate here has delays <= 64 ps)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
@@ -357,14 +414,21 @@ def main():
         },
     }
 
+    out["workload_stats"] = workload_stats(nl, lengths)
+
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         lv = min(args.cpu_levels, info.levels)
         n_gates = int(np.searchsorted(nl.level, lv, side="right"))
         sub = nl.prefix(n_gates)
         t1 = time.perf_counter()
-        o_off, _, _ = O.o1_simulate(sub, st)
+        o_off, _, o_v = O.o1_simulate(sub, st)
         cpu_s = time.perf_counter() - t1
+        gate_of = np.repeat(np.arange(n_gates), np.diff(o_off))
+        lvl = nl.level[gate_of]
+        out["workload_stats"]["x_fraction_per_level"] = {
+            "levels": f"1-{lv} (from the oracle sample)",
+            "values": [round(float((o_v[lvl == l] == 2).mean()), 4) for l in range(1, lv + 1)]}
         out["cpu_baseline"] = {
             "value": float(o_off[-1]) / cpu_s,
             "unit": "transitions/s",
@@ -374,6 +438,8 @@ def main():
                       f"({n_gates} gates, {int(o_off[-1])} output transitions, {cpu_s:.1f}s)",
         }
     sim.set_option(G.OPT_KERNEL_TIMING, 0)
+    if not args.no_tiny:
+        out["tiny_latency"] = bench_tiny_latency(G, sim, args.seed)
     if not args.no_batched:
         out["batched"] = bench_batched(G, sim, nl, h, args.batched_sets, args.seed)
     sim.unload_netlist(h)

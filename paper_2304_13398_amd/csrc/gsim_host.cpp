@@ -362,11 +362,14 @@ class PinnedCache {
 
 // ---------------------------------------------------------------------------
 
-// Gates of one level in three consecutive groups by largest pin delay:
-// <= kWindowSmall, <= kWindowLarge, larger. The first two groups bound the
-// wavefront work lists of a step (the lane list may take any gate).
+// Gates of one level in consecutive groups, one per work list: by largest
+// pin delay (<= kWindowSmall, <= kWindowLarge) and pin count for the
+// wavefront kernels, then the gates whose delays need the lane kernel. The
+// group sizes bound the wavefront work lists of a step (the lane list may
+// take any gate).
 struct LevelRange {
-    int64_t begin, n, n_small, n_large;
+    int64_t begin, n;
+    int64_t n_list[kNumLists];
 };
 
 struct Netlist {
@@ -431,13 +434,13 @@ constexpr int kRing = 32;  // steps whose descriptors may be in flight
 // jobs in the same launches.
 struct Executor {
     hipStream_t stream = nullptr;
-    uint32_t *d_counts = nullptr;  // 2 x kNumClasses list lengths (this step / next step)
+    uint32_t *d_counts = nullptr;  // 2 x kNumLists list lengths (this step / next step)
     int parity = 0;
     JobDesc *d_jobs = nullptr;
     int64_t jobs_cap = 0;
     int64_t *d_blocksum = nullptr;
     int64_t blocksum_cap = 0;
-    uint64_t *d_list = nullptr;    // kNumClasses lists of list_cap entries
+    uint64_t *d_list = nullptr;    // kNumLists lists of list_cap entries
     int64_t list_cap = 0;
     JobDesc *h_ring = nullptr;     // pinned [kRing][kMaxJobsPerStep]
     hipEvent_t ring_ev[kRing] = {};
@@ -518,32 +521,37 @@ Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, co
         return d;
     };
     auto group_of = [&](int64_t g) {
+        if (ctx->opt_kernel == 1) return kListLane;  // every gate on the lane kernel
         const int32_t d = gate_dmax(g);
-        return d <= kWindowSmall ? 0 : d <= kWindowLarge ? 1 : 2;
+        const int k = (int)(pin_off[g + 1] - pin_off[g]);
+        return d <= kWindowSmall ? wave_list(0, k) : d <= kWindowLarge ? wave_list(1, k) : kListLane;
     };
     const int32_t L = lv.n_levels;
-    std::vector<int64_t> cnt(3 * ((size_t)L + 1), 0);
+    constexpr size_t NL = kNumLists;
+    std::vector<int64_t> cnt(NL * ((size_t)L + 1), 0);
     std::vector<int> grp(G);
     for (int64_t g = 0; g < G; g++) {
         grp[g] = group_of(g);
-        cnt[3 * (size_t)lv.level[g] + grp[g]]++;
+        cnt[NL * (size_t)lv.level[g] + grp[g]]++;
     }
     std::vector<int64_t> start(cnt.size() + 1, 0);
     for (size_t i = 0; i < cnt.size(); i++) start[i + 1] = start[i] + cnt[i];
     nl->levels.resize(L);
     for (int32_t l = 1; l <= L; l++) {
         LevelRange &r = nl->levels[l - 1];
-        r.begin = start[3 * (size_t)l];
-        r.n_small = cnt[3 * (size_t)l];
-        r.n_large = cnt[3 * (size_t)l + 1];
-        r.n = r.n_small + r.n_large + cnt[3 * (size_t)l + 2];
-        nl->lane_gates += cnt[3 * (size_t)l + 2];
+        r.begin = start[NL * (size_t)l];
+        r.n = 0;
+        for (int c = 0; c < kNumLists; c++) {
+            r.n_list[c] = cnt[NL * (size_t)l + c];
+            r.n += r.n_list[c];
+        }
+        nl->lane_gates += r.n_list[kListLane];
         nl->max_level_n = std::max(nl->max_level_n, r.n);
     }
     nl->internal_of_user.resize(G);
     {
         std::vector<int64_t> fill(start.begin(), start.end() - 1);
-        for (int64_t g = 0; g < G; g++) nl->internal_of_user[g] = fill[3 * (size_t)lv.level[g] + grp[g]]++;
+        for (int64_t g = 0; g < G; g++) nl->internal_of_user[g] = fill[NL * (size_t)lv.level[g] + grp[g]]++;
     }
     std::vector<GateRec> recs(G);
     for (int64_t g = 0; g < G; g++) {
@@ -574,7 +582,6 @@ Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, co
             return fail(GSIM_E_DEVICE, "netlist upload: %s", hipGetErrorString(e));
         }
     }
-    if (ctx->opt_kernel == 1) nl->lane_gates = G;
     const int64_t id = ctx->next_id++;
     ctx->netlists[id] = std::move(nl);
     *out = id;
@@ -592,11 +599,11 @@ Failure get_executor(gsim_ctx ctx, hipStream_t stream, Executor **out) {
     }
     auto ex = std::make_unique<Executor>();
     ex->stream = stream;
-    ex->d_counts = pool_get<uint32_t>(*ctx->pool, 2 * kNumClasses);
+    ex->d_counts = pool_get<uint32_t>(*ctx->pool, 2 * kNumLists);
     if (!ex->d_counts) return fail(GSIM_E_OOM, "no device memory for the executor");
     HIP_TRY(hipHostMalloc((void **)&ex->h_ring, sizeof(JobDesc) * kRing * kMaxJobsPerStep, hipHostMallocDefault));
     for (int i = 0; i < kRing; i++) HIP_TRY(hipEventCreateWithFlags(&ex->ring_ev[i], hipEventDisableTiming));
-    HIP_TRY(launch_clear_u32(ex->d_counts, 2 * kNumClasses, stream));
+    HIP_TRY(launch_clear_u32(ex->d_counts, 2 * kNumLists, stream));
     *out = ex.get();
     ctx->executors[stream] = std::move(ex);
     return kOk;
@@ -783,9 +790,9 @@ Failure admit(gsim_ctx ctx, Executor *ex, Job *j) {
         Failure f = ensure_cap(ctx, ex, ex->d_jobs, ex->jobs_cap, (int64_t)ex->active.size() + 1);
         if (f.st == GSIM_OK) f = ensure_cap(ctx, ex, ex->d_blocksum, ex->blocksum_cap, sblocks);
         if (f.st == GSIM_OK && items > ex->list_cap) {
-            int64_t cap = ex->list_cap * kNumClasses;
-            f = ensure_cap(ctx, ex, ex->d_list, cap, kNumClasses * items);
-            ex->list_cap = cap / kNumClasses;
+            int64_t cap = ex->list_cap * kNumLists;
+            f = ensure_cap(ctx, ex, ex->d_list, cap, kNumLists * items);
+            ex->list_cap = cap / kNumLists;
         }
         if (f.st != GSIM_OK) return f;
     }
@@ -882,7 +889,8 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
     if (ex->ring_used[slot]) HIP_TRY(hipEventSynchronize(ex->ring_ev[slot]));
     JobDesc *desc = ex->h_ring + (size_t)slot * kMaxJobsPerStep;
     const int n = (int)act.size();
-    int64_t n_sblocks = 0, n_items = 0, n_small = 0, n_large = 0;
+    int64_t n_sblocks = 0, n_items = 0, n_lane = 0;
+    int64_t n_list[kNumLists] = {};
     for (int i = 0; i < n; i++) {
         Job *j = act[i];
         const LevelRange &r = j->nl->levels[j->next_level];
@@ -900,15 +908,17 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
         d.pad = 0;
         n_sblocks += (r.n + kSizeBlock - 1) / kSizeBlock;
         n_items += r.n;
-        n_small += r.n_small;
-        n_large += r.n_large;
+        for (int c = 0; c < kNumLists; c++) n_list[c] += r.n_list[c];
+        // the lane list takes the gates whose delays need it, plus any gate that
+        // reads fewer than lane_threshold transitions
+        n_lane += d.lane_threshold > 0 ? r.n : r.n_list[kListLane];
     }
     Failure f = ensure_cap(ctx, ex, ex->d_jobs, ex->jobs_cap, n);
     if (f.st == GSIM_OK) f = ensure_cap(ctx, ex, ex->d_blocksum, ex->blocksum_cap, n_sblocks);
     if (f.st == GSIM_OK && n_items > ex->list_cap) {
-        int64_t cap = ex->list_cap * kNumClasses;
-        f = ensure_cap(ctx, ex, ex->d_list, cap, kNumClasses * n_items);
-        ex->list_cap = cap / kNumClasses;
+        int64_t cap = ex->list_cap * kNumLists;
+        f = ensure_cap(ctx, ex, ex->d_list, cap, kNumLists * n_items);
+        ex->list_cap = cap / kNumLists;
     }
     if (f.st != GSIM_OK) return f;
     hipStream_t s = ex->stream;
@@ -921,9 +931,9 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
     a.pad = 0;
     a.n_sblocks = n_sblocks;
     a.blocksum = ex->d_blocksum;
-    for (int c = 0; c < kNumClasses; c++) a.list[c] = ex->d_list + (size_t)c * ex->list_cap;
-    a.count = ex->d_counts + ex->parity * kNumClasses;
-    a.next_count = ex->d_counts + (1 - ex->parity) * kNumClasses;
+    for (int c = 0; c < kNumLists; c++) a.list[c] = ex->d_list + (size_t)c * ex->list_cap;
+    a.count = ex->d_counts + ex->parity * kNumLists;
+    a.next_count = ex->d_counts + (1 - ex->parity) * kNumLists;
     a.lut = ctx->d_lut;
     HIP_TRY(launch_size(a, s));
     HIP_TRY(launch_level_scan(a, s));
@@ -934,9 +944,9 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
         HIP_TRY(hipEventCreate(&tm->b));
         HIP_TRY(hipEventRecord(tm->a, s));
     }
-    HIP_TRY(launch_eval(a, kClassSmall, n_small, s));
-    HIP_TRY(launch_eval(a, kClassLarge, n_large, s));
-    HIP_TRY(launch_eval(a, kClassLane, n_items, s));
+    HIP_TRY(launch_eval_wave(a, 0, n_list + wave_list(0, 1), s));
+    HIP_TRY(launch_eval_wave(a, 1, n_list + wave_list(1, 1), s));
+    HIP_TRY(launch_eval_lane(a, n_lane, s));
     if (tm) HIP_TRY(hipEventRecord(tm->b, s));
     ex->parity ^= 1;
     ex->steps++;

@@ -34,8 +34,13 @@ constexpr int kWindowLarge = 256;
 // Gates handled per sizing block.
 constexpr int kSizeBlock = 256;
 
-// Evaluate-kernel classes (one work list each per step).
-enum GateClass { kClassSmall = 0, kClassLarge = 1, kClassLane = 2, kNumClasses = 3 };
+// Evaluate work lists (one each per step): the wavefront kernel for each
+// delay window (small, large) and pin count (1-4), then the lane kernel.
+constexpr int kNumLists = 9;
+constexpr int kListLane = 8;
+__host__ __device__ constexpr int wave_list(int large_window, int pins) {
+    return large_window * 4 + pins - 1;
+}
 
 // One gate, 64 bytes, in level order. Nets are internal ids: sources keep
 // their id, the gate at internal position i drives net S + i.
@@ -85,9 +90,9 @@ struct StepArgs {
     int32_t pad;
     int64_t n_sblocks;       // sizing blocks over all jobs
     int64_t *blocksum;       // [n_sblocks]: block totals, then absolute arena bases
-    uint64_t *list[kNumClasses];  // work lists: job << 32 | gate
-    uint32_t *count;         // [kNumClasses] list lengths of this step
-    uint32_t *next_count;    // [kNumClasses] list lengths of the next step (cleared here)
+    uint64_t *list[kNumLists];  // work lists: job << 32 | gate
+    uint32_t *count;         // [kNumLists] list lengths of this step
+    uint32_t *next_count;    // [kNumLists] list lengths of the next step (cleared here)
     const uint8_t *lut;      // [12][256] gate value by packed pin values
 };
 
@@ -99,7 +104,11 @@ hipError_t launch_init_sources(const int64_t *d_src_off, const int64_t *d_t, con
 hipError_t launch_size(const StepArgs &a, hipStream_t s);
 hipError_t launch_level_scan(const StepArgs &a, hipStream_t s);
 // evaluate the work list of class `cls`; `max_items` bounds the list length
-hipError_t launch_eval(const StepArgs &a, int cls, int64_t max_items, hipStream_t s);
+// Wavefront kernel over the four pin-count lists of one delay window
+// (max_items[k-1]: upper bound of the k-pin list's length).
+hipError_t launch_eval_wave(const StepArgs &a, int large_window, const int64_t *max_items,
+                            hipStream_t s);
+hipError_t launch_eval_lane(const StepArgs &a, int64_t max_items, hipStream_t s);
 hipError_t launch_count_out(const int64_t *len, int64_t S, int64_t G, int64_t *partial,
                             int64_t n_partial, DevState *state, hipStream_t s);
 hipError_t launch_gather(const int64_t *src_off, const int64_t *n_items, const int64_t *dst_off,

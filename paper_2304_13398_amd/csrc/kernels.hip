@@ -52,28 +52,6 @@ __device__ __forceinline__ int32_t pin_delay(int32_t rise, int32_t fall, uint32_
     return v == 1 ? rise : v == 0 ? fall : (rise < fall ? rise : fall);
 }
 
-// Wave-wide inclusive prefix sum of an int.
-__device__ __forceinline__ int wave_incl_sum(int x) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int s = 1; s < 64; s <<= 1) {
-        const int o = __shfl_up(x, s, 64);
-        if (lane >= s) x += o;
-    }
-    return x;
-}
-
-// Wave-wide inclusive suffix minimum (over lanes >= this lane).
-__device__ __forceinline__ uint64_t wave_suffix_min(uint64_t x) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int s = 1; s < 64; s <<= 1) {
-        const uint64_t o = shfl_down_u64(x, s);
-        if (lane + s < 64) x = umin64(x, o);
-    }
-    return x;
-}
-
 // -------------------------------------------------------------------------
 // Sources: packed into the arena at [0, n_in); their offsets and lengths; the
 // job state.
@@ -116,9 +94,9 @@ __device__ __forceinline__ int job_of_block(const JobDesc *jobs, int n_jobs, int
 
 // Per-level sizing and binning: w_g (the sum of the gate's input lengths, an
 // upper bound of its output length), its block-local exclusive scan, and the
-// gate's evaluate class -- lane kernel if its largest delay exceeds the large
+// gate's work list -- lane kernel if its largest delay exceeds the large
 // window or it reads fewer than lane_threshold transitions, else the
-// wavefront kernel of its delay window -- appended to that class's work list.
+// wavefront kernel of its delay window and pin count -- appended to that list.
 __global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
     __shared__ int64_t wsum[kSizeBlock / 64];
     const int64_t b = blockIdx.x;
@@ -134,8 +112,8 @@ __global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
 #pragma unroll
         for (int p = 0; p < kMaxPins; p++)
             if (p < k) w += J.len[r.net[p]];
-        cls = (r.dmax > kWindowLarge || w < J.lane_threshold) ? kClassLane
-              : r.dmax <= kWindowSmall ? kClassSmall : kClassLarge;
+        cls = (r.dmax > kWindowLarge || w < J.lane_threshold) ? kListLane
+              : wave_list(r.dmax > kWindowSmall ? 1 : 0, k);
     }
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     int64_t x = w;
@@ -148,7 +126,7 @@ __global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
     }
     if (lane == 63) wsum[wv] = x;
 #pragma unroll
-    for (int c = 0; c < kNumClasses; c++) {
+    for (int c = 0; c < kNumLists; c++) {
         const uint64_t mask = __ballot(cls == c);
         if (mask == 0) continue;
         const int leader = __ffsll((unsigned long long)mask) - 1;
@@ -157,7 +135,7 @@ __global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
         base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
         if (cls == c) A.list[c][base + lanes_below(mask)] = ((uint64_t)(uint32_t)j << 32) | (uint64_t)g;
     }
-    if (b == 0 && threadIdx.x < kNumClasses) A.next_count[threadIdx.x] = 0;
+    if (b == 0 && threadIdx.x < kNumLists) A.next_count[threadIdx.x] = 0;
     __syncthreads();
     int64_t before = 0, total = 0;
 #pragma unroll
@@ -221,7 +199,9 @@ __global__ __launch_bounds__(1024) void level_scan_kernel(StepArgs A) {
 // Wave-wide scans with DPP (GFX9 row shifts and row broadcasts): inclusive,
 // in lane order, 12 VALU operations and no LDS traffic.
 constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
-constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+constexpr int kDppRowShl1 = 0x101, kDppRowShl2 = 0x102, kDppRowShl4 = 0x104, kDppRowShl8 = 0x108;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+constexpr int kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
 
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ uint32_t dpp_u32(uint32_t identity, uint32_t x) {
@@ -255,6 +235,11 @@ __device__ __forceinline__ uint32_t wave_shift_up(uint32_t identity, uint32_t x)
     return dpp_u32<kDppWaveShr1>(identity, x);
 }
 
+// The value of the next lane (identity on lane 63).
+__device__ __forceinline__ uint32_t wave_shift_down(uint32_t identity, uint32_t x) {
+    return dpp_u32<kDppWaveShl1>(identity, x);
+}
+
 // -------------------------------------------------------------------------
 // Wavefront-per-gate evaluation.
 //
@@ -270,52 +255,125 @@ __device__ __forceinline__ uint32_t wave_shift_up(uint32_t identity, uint32_t x)
 // same as keeping, among the survivors, those whose value differs from the
 // previous survivor's (X before the first).
 //
-// The wave walks the inputs in rounds of up to 512 transitions (T = 512/K per
-// pin for K pins, a multiple of 64). The round's horizon H is the smallest
+// The wave walks the inputs in rounds of up to 512 transitions (T = 512/K
+// per pin, 128 for three pins). The round's horizon H is the smallest
 // last-loaded time over pins that have more transitions beyond their tile,
-// capped so the round spans less than 2^30 ps; every input transition at or
-// before H is in the round. All in-round times, and the appearance times of
-// candidates and of tentative survivors, are held as 32-bit offsets from the
-// round's base, packed with the value as offset << 2 | value. Each lane takes
-// T/64 transitions per pin; a branch-free binary search in each other pin's
-// tile gives how many of its transitions are before the lane's time and
-// whether one is at it -- hence the merged rank, whether this is the first
-// transition at that time, and the pin values just before and just after it
-// (each tile starts with a holder of the pin's value before the round and ends
-// with a terminator). Candidates are scattered by merged rank; survivors come
-// from a suffix minimum over the round (DPP scans). A survivor with r <= H is
-// final (later candidates appear after H); the others stay tentative in LDS
-// and are re-tested against the next rounds -- at most W of them exist for
-// gates whose largest pin delay is at most W (see kWindowSmall). The next
-// round's tiles are prefetched into registers while the current one runs.
+// capped so the round spans less than 2^28 ps; every input transition at or
+// before H is in the round. In-round inputs are 32-bit keys
+// offset << 4 | value << 2 | pin (offset from the round's base), so the
+// merged order of the round is plain key order (by time; the order inside a
+// time group does not matter). The merge is done per lane:
+// lane l owns merged positions [8l, 8l + 8), finds where they start in the
+// two sorted lists it merges by a merge-path search, and takes the 8
+// smallest of the next 8 of each list with a bitonic network (four pins:
+// two pairwise merges through LDS, then one more). Pin values after each
+// merged transition come from a wave scan of "set pin p to v" updates; a
+// transition ends a time group when the next one has another time; the
+// group's candidate takes its delay from a per-gate table indexed by new
+// value and the set of pins in the group. Candidates appear at 32-bit
+// offsets (offset << 2 | value). Survivors come from a suffix minimum over
+// the round (DPP scans). A survivor with r <= H is final (later candidates
+// appear after H); the others stay tentative in LDS and are re-tested
+// against the next rounds -- at most W of them exist for gates whose largest
+// pin delay is at most W (see kWindowSmall). The next round's tiles are
+// prefetched into registers while the current one runs.
+constexpr int kMergePad = 8;                       // INF keys after each sorted list
+constexpr int kMergeBuf = 2 * (256 + kMergePad + 1);  // two pairwise-merge outputs with guards
+
 template <int W>
 struct WaveLds {
-    uint32_t seq[W + kRoundSlots];  // tentative survivors [0, nq), then this round's;
-                                    // the round's candidate slots alias seq[W, W + 512)
-    uint32_t tile[kRoundSlots + 8]; // K tiles of [value holder, T rebased keys, terminator]
+    uint32_t seq[W + kRoundSlots + 32];  // tentative survivors [0, nq), then this round's;
+                                         // the pairwise-merge buffers alias seq[W, W + kMergeBuf)
+    uint32_t tile[kRoundSlots + 4 * (kMergePad + 1)];  // K x [guard, T keys, 8 INF]
+    uint32_t dtab[48];                   // min delay by (new value, set of changed pins)
     uint8_t lut[256];
 };
+static_assert(kMergeBuf <= kRoundSlots + 32, "merge buffers must fit the survivor area");
 
 template <int K>
 struct Tiling {
     static constexpr int T = K == 1 ? 512 : K == 2 ? 256 : 128;  // transitions per pin per round
     static constexpr int E = T / 64;                              // per lane per pin
-    static constexpr int STRIDE = T + 2;                          // tile stride in LDS
+    static constexpr int STRIDE = T + 1 + kMergePad;              // tile stride in LDS
 };
 static_assert(kRoundSlots == 512, "tiling assumes 512-transition rounds");
 
 constexpr uint32_t kNoKey32 = 0xFFFFFFFFu;
-// Largest in-round time offset: candidate offsets (time + delay <= kSpan +
-// kWindowLarge) and tentative offsets stay below 2^30 - 1, so offset << 2 |
-// value never reaches kNoKey32 >> 2 << 2.
-constexpr int64_t kSpan = (int64_t(1) << 30) - 2 - 2 * kWindowLarge;
+constexpr uint32_t kNoTime28 = kNoKey32 >> 4;
+// Largest in-round time offset: input keys offset << 4 | value << 2 | pin stay
+// below kNoKey32, and candidate offsets (<= kSpan + kWindowLarge) stay below
+// 2^30, so candidate keys offset << 2 | value never reach kNoKey32 either.
+constexpr int64_t kSpan = (int64_t(1) << 28) - 2;
+
+__device__ __forceinline__ void cswap(uint32_t &a, uint32_t &b) {
+    const uint32_t lo = umin32(a, b);
+    b = a < b ? b : a;
+    a = lo;
+}
+
+// Merged positions [d, d + 8) of the sorted lists A[0, a) and B[0, b) (keys
+// distinct, each list followed by kMergePad kNoKey32 and preceded by one
+// readable guard word); positions past a + b come out as kNoKey32. NIT
+// search steps cover split ranges up to 2^NIT - 1.
+template <int NIT>
+__device__ __forceinline__ void merge8(const uint32_t *A, int a, const uint32_t *B, int b, int d,
+                                       uint32_t (&c)[8]) {
+    d = d < a + b ? d : a + b;
+    int lo = d - b > 0 ? d - b : 0;
+    int hi = d < a ? d : a;
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+        const int mid = (lo + hi) >> 1;
+        const bool less = A[mid] < B[d - 1 - mid];
+        const bool go = lo < hi;
+        lo = go && less ? mid + 1 : lo;
+        hi = go && !less ? mid : hi;
+    }
+    const uint32_t *pa = A + lo, *pb = B + (d - lo);
+#pragma unroll
+    for (int k = 0; k < 8; k++) c[k] = umin32(pa[k], pb[7 - k]);  // the 8 smallest, bitonic
+    cswap(c[0], c[4]); cswap(c[1], c[5]); cswap(c[2], c[6]); cswap(c[3], c[7]);
+    cswap(c[0], c[2]); cswap(c[1], c[3]); cswap(c[4], c[6]); cswap(c[5], c[7]);
+    cswap(c[0], c[1]); cswap(c[2], c[3]); cswap(c[4], c[5]); cswap(c[6], c[7]);
+}
+
+// Pin-state updates: bits [2p, 2p+2) hold pin p's new value, bits [8+2p,
+// 8+2p+2) mark pin p as set. compose(earlier, later) applies both in order.
+__device__ __forceinline__ uint32_t compose_upd(uint32_t e, uint32_t l) {
+    return (e & ~((l >> 8) & 0xFFu)) | l;
+}
+
+__device__ __forceinline__ uint32_t wave_prefix_compose(uint32_t x) {
+    x = compose_upd(dpp_u32<kDppRowShr1>(0u, x), x);
+    x = compose_upd(dpp_u32<kDppRowShr2>(0u, x), x);
+    x = compose_upd(dpp_u32<kDppRowShr4>(0u, x), x);
+    x = compose_upd(dpp_u32<kDppRowShr8>(0u, x), x);
+    x = compose_upd(dpp_u32<kDppRowBcast15, 0xa>(0u, x), x);
+    x = compose_upd(dpp_u32<kDppRowBcast31, 0xc>(0u, x), x);
+    return x;
+}
+
+// Inclusive minimum over this lane and every higher lane.
+__device__ __forceinline__ uint32_t wave_suffix_min(uint32_t x) {
+    x = umin32(x, dpp_u32<kDppRowShl1>(~0u, x));
+    x = umin32(x, dpp_u32<kDppRowShl2>(~0u, x));
+    x = umin32(x, dpp_u32<kDppRowShl4>(~0u, x));
+    x = umin32(x, dpp_u32<kDppRowShl8>(~0u, x));
+    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 16);
+    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 32);
+    const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
+    const uint32_t s2 = r3, s1 = umin32(r2, r3), s0 = umin32(r1, s1);
+    const int row = lane_id() >> 4;
+    const uint32_t later_rows = row == 0 ? s0 : row == 1 ? s1 : row == 2 ? s2 : kNoKey32;
+    return umin32(x, later_rows);
+}
 
 template <int K, int W>
 __device__ __forceinline__ void eval_gate(const JobDesc &J, const int64_t *blockbase,
                                           const GateRec &R, int64_t gate, WaveLds<W> &L) {
     using Tl = Tiling<K>;
     constexpr int T = Tl::T, E = Tl::E, ST = Tl::STRIDE;
-    constexpr int SPL = kRoundSlots / 64;  // slots per lane
+    constexpr int NIT1 = K == 2 ? 9 : 8;  // split range of the first merge: <= T
     const int lane = lane_id();
     const int64_t S = J.S;
     int64_t *len = J.len;
@@ -324,36 +382,47 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, const int64_t *block
 
     const int64_t ob = blockbase[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + off[S + gate];
     int64_t pb[K], pl[K], cur[K];
-    uint32_t cval[K];
     int64_t reserved = 0;  // slots sized for this gate: the sum of its input lengths
 #pragma unroll
     for (int p = 0; p < K; p++) {
         pb[p] = off[R.net[p]];
         pl[p] = len[R.net[p]];
         cur[p] = 0;
-        cval[p] = kX;
         reserved += pl[p];
     }
-    int32_t drise[K], dfall[K];
+    uint32_t state0 = 0;  // pin values before the round, 2 bits per pin
 #pragma unroll
-    for (int p = 0; p < K; p++) { drise[p] = R.rise[p]; dfall[p] = R.fall[p]; }
+    for (int p = 0; p < K; p++) state0 |= (uint32_t)kX << (2 * p);
 
+    // tiles are loaded from a uniform base with 32-bit lane offsets
     uint64_t pre[K][E];
 #pragma unroll
-    for (int p = 0; p < K; p++)
+    for (int p = 0; p < K; p++) {
+        const uint64_t *src = Kar + pb[p];
+        const int lim = (int)min64(pl[p], (int64_t)T);
 #pragma unroll
-        for (int e = 0; e < E; e++) {
-            const int64_t idx = lane + 64 * e;
-            pre[p][e] = idx < pl[p] ? Kar[pb[p] + idx] : kNoKey;
-        }
-    // terminators after each tile
-    if (lane < K) L.tile[lane * ST + T + 1] = kNoKey32;
+        for (int e = 0; e < E; e++) pre[p][e] = lane + 64 * e < lim ? src[lane + 64 * e] : kNoKey;
+    }
+    // INF keys after each tile; the delay table
+    if (lane < K * kMergePad) L.tile[(lane / kMergePad) * ST + 1 + T + lane % kMergePad] = kNoKey32;
+    if (lane < 48) {
+        const uint32_t ev = (uint32_t)lane >> 4, mask = (uint32_t)lane & 15u;
+        int32_t d = INT32_MAX;
+#pragma unroll
+        for (int q = 0; q < K; q++)
+            if (mask & (1u << q)) {
+                const int32_t dq = pin_delay(R.rise[q], R.fall[q], ev);
+                d = dq < d ? dq : d;
+            }
+        L.dtab[lane] = (uint32_t)d;
+    }
 
     uint32_t last_val = kX;  // value of the last final survivor
     int nq = 0;              // tentative survivors in L.seq[0, nq), offsets from base_prev
     int64_t base_prev = 0;
     int64_t out_n = 0;
-    uint32_t *slots = L.seq + W;
+    uint32_t *const AB = L.seq + W + 1;                    // pairwise merges (K >= 3)
+    uint32_t *const CD = AB + 256 + kMergePad + 1;
 
     for (;;) {
         int64_t rem[K];
@@ -379,119 +448,128 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, const int64_t *block
         }
         H = min64(H, base + kSpan);
         int m[K];
-        int M = 0;
         bool all_in = true;
+        const uint64_t hkey = H < kTimeLimit ? pack_key(H, 3u) : ~uint64_t(0);  // last key of the round
+        const uint32_t base4 = (uint32_t)pack_key(base, 0u);  // low word of base << 2
 #pragma unroll
         for (int p = 0; p < K; p++) {
             m[p] = 0;
+            const int lim = (int)min64(rem[p], (int64_t)T);
 #pragma unroll
             for (int e = 0; e < E; e++) {
-                const int64_t idx = lane + 64 * e;
                 const uint64_t key = pre[p][e];
-                const bool in = idx < rem[p] && key_time(key) <= H;
+                const bool in = lane + 64 * e < lim && key <= hkey;
                 m[p] += __popcll(__ballot(in));
-                L.tile[p * ST + 1 + 64 * e + lane] =
-                    in ? (uint32_t)((key_time(key) - base) << 2) | key_value(key) : kNoKey32;
+                // (t - base) << 2 | v < 2^30 equals the low word of key - (base << 2)
+                L.tile[p * ST + 1 + 64 * e + lane] = in ? (((uint32_t)key - base4) << 2) | (uint32_t)p : kNoKey32;
             }
-            if (lane == 0) L.tile[p * ST] = cval[p];
-            M += m[p];
             all_in = all_in && m[p] == rem[p];
         }
         // split horizon: with every remaining input in this round, all survivors are final
         const uint32_t hsplit = all_in ? kNoKey32 : (uint32_t)(H - base) << 2 | 3u;
         uint64_t nxt[K][E];
 #pragma unroll
-        for (int p = 0; p < K; p++)
-#pragma unroll
-            for (int e = 0; e < E; e++) {
-                const int64_t idx = cur[p] + m[p] + lane + 64 * e;
-                nxt[p][e] = idx < pl[p] ? Kar[pb[p] + idx] : kNoKey;
-            }
-        __syncthreads();
-
-        // ---- candidates, scattered by merged rank
-#pragma unroll
         for (int p = 0; p < K; p++) {
+            const uint64_t *src = Kar + pb[p] + cur[p] + m[p];
+            const int lim = (int)min64(rem[p] - m[p], (int64_t)T);
 #pragma unroll
-            for (int e = 0; e < E; e++) {
-                const int j = lane + 64 * e;
-                if (j >= m[p]) continue;
-                const uint32_t *tp = L.tile + p * ST + 1;
-                const uint32_t key = tp[j];
-                const uint32_t tk = key & ~3u;
-                bool leader = true;
-                int rank = j;
-                uint32_t pack_after = 0, pack_before = 0, changed = 1u << p;
-#pragma unroll
-                for (int q = 0; q < K; q++) {
-                    uint32_t va, vb;
-                    if (q == p) {
-                        va = key & 3u;
-                        vb = tp[j - 1] & 3u;
-                    } else {
-                        const uint32_t *a = L.tile + q * ST + 1;
-#pragma unroll
-                        for (int s = T / 2; s >= 1; s >>= 1)
-                            if (a[s - 1] < tk) a += s;
-                        if (a[0] < tk) a += 1;
-                        const int lb = (int)(a - (L.tile + q * ST + 1));
-                        const uint32_t x0 = a[0];
-                        const bool eq = (x0 & ~3u) == tk;
-                        vb = a[-1] & 3u;
-                        va = eq ? (x0 & 3u) : vb;
-                        if (q < p) {
-                            leader = leader && !eq;
-                            rank += lb + (eq ? 1 : 0);
-                        } else {
-                            rank += lb;
-                        }
-                        changed |= eq ? (1u << q) : 0u;
-                    }
-                    pack_after |= va << (2 * q);
-                    pack_before |= vb << (2 * q);
-                }
-                uint32_t slot = kNoKey32;
-                if (leader) {
-                    const uint32_t ea = L.lut[pack_after];
-                    const uint32_t eb = L.lut[pack_before];
-                    if (ea != eb) {
-                        int32_t d = INT32_MAX;
-#pragma unroll
-                        for (int q = 0; q < K; q++)
-                            if (changed & (1u << q)) {
-                                const int32_t dq = pin_delay(drise[q], dfall[q], ea);
-                                d = dq < d ? dq : d;
-                            }
-                        slot = (tk + ((uint32_t)d << 2)) | ea;
-                    }
-                }
-                slots[rank] = slot;
-            }
+            for (int e = 0; e < E; e++) nxt[p][e] = lane + 64 * e < lim ? src[lane + 64 * e] : kNoKey;
         }
         __syncthreads();
 
-        // ---- survivors among this round's candidates: lane l holds slots
-        // [(63 - l) * SPL, +SPL), so a prefix over lanes is a suffix over slots
-        uint32_t sk[SPL];
+        // ---- merged positions [8 lane, 8 lane + 8) of the round
+        uint32_t mk[8];
+        if constexpr (K == 1) {
+#pragma unroll
+            for (int k = 0; k < 8; k++) mk[k] = L.tile[1 + 8 * lane + k];
+        } else if constexpr (K == 2) {
+            merge8<9>(L.tile + 1, m[0], L.tile + ST + 1, m[1], 8 * lane, mk);
+        } else {
+            const bool hi_half = lane >= 32;
+            const uint32_t *A = L.tile + (hi_half ? 2 * ST : 0) + 1;
+            const uint32_t *B = K == 4 ? A + ST : (hi_half ? A + T : A + ST);  // 3 pins: C with nothing
+            const int a = hi_half ? m[2] : m[0];
+            const int b = hi_half ? (K == 4 ? m[K - 1] : 0) : m[1];
+            uint32_t h[8];
+            merge8<NIT1>(A, a, B, b, 8 * (lane & 31), h);
+            uint32_t *dst = (hi_half ? CD : AB) + 8 * (lane & 31);
+#pragma unroll
+            for (int k = 0; k < 8; k++) dst[k] = h[k];
+            if (lane < 2 * kMergePad) (lane < kMergePad ? AB : CD)[256 + (lane % kMergePad)] = kNoKey32;
+            __syncthreads();
+            merge8<9>(AB, m[0] + m[1], CD, m[2] + (K == 4 ? m[K - 1] : 0), 8 * lane, mk);
+        }
+
+        // ---- pin states: this lane's composed update, scanned over the wave
+        uint32_t upd = 0, trail_mask = 0;
+        const uint32_t t_last = mk[7] >> 4;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const uint32_t sh = K == 1 ? 0u : (mk[k] & 3u) * 2u;
+            const bool valid = mk[k] != kNoKey32;
+            if (valid) upd = (upd & ~(3u << sh)) | (((mk[k] >> 2) & 3u) << sh) | (0x300u << sh);
+            trail_mask |= (mk[k] >> 4) == t_last ? 1u << (sh >> 1) : 0u;
+        }
+        const uint32_t upd_incl = wave_prefix_compose(upd);
+        const uint32_t upd_excl = wave_shift_up(0u, upd_incl);
+        const uint32_t upd_all = (uint32_t)__builtin_amdgcn_readlane((int)upd_incl, 63);
+        const uint32_t next_first = wave_shift_down(kNoTime28, mk[0] >> 4);
+        const uint32_t prev_trail = wave_shift_up(kNoKey32, t_last << 4 | trail_mask);
+
+        // ---- gate value after each transition; time-group ends
+        uint32_t st = (state0 & ~(upd_excl >> 8) & 0xFFu) | (upd_excl & 0xFFu);
+        uint32_t evs = 0;  // gate value after each transition, 2 bits each
+        uint32_t ge = 0, e_lastge = 0;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const uint32_t sh = K == 1 ? 0u : (mk[k] & 3u) * 2u;
+            st = (st & ~(3u << sh)) | (((mk[k] >> 2) & 3u) << sh);
+            const uint32_t ek = L.lut[st];
+            evs |= ek << (2 * k);
+            const uint32_t tn = k < 7 ? mk[k + 1] >> 4 : next_first;
+            const bool end = mk[k] != kNoKey32 && (mk[k] >> 4) != tn;
+            ge |= end ? 1u << k : 0u;
+            e_lastge = end ? ek : e_lastge;
+        }
+        const uint32_t e0 = L.lut[state0];
+        const uint32_t e_from_prev = wave_shift_up(e0, e_lastge);
+
+        // ---- candidates at group ends
+        uint32_t sk[8];
+        {
+            uint32_t run_t = prev_trail >> 4, run_m = prev_trail & 15u;
+            uint32_t e_prev = e_from_prev;
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const uint32_t tk = mk[k] >> 4;
+                const uint32_t pbit = K == 1 ? 1u : 1u << (mk[k] & 3u);
+                run_m = tk == run_t ? run_m | pbit : pbit;
+                run_t = tk;
+                sk[k] = kNoKey32;
+                if ((ge >> k) & 1u) {
+                    const uint32_t ek = (evs >> (2 * k)) & 3u;
+                    if (ek != e_prev) sk[k] = ((tk + L.dtab[ek * 16 + run_m]) << 2) | ek;
+                    e_prev = ek;
+                }
+            }
+        }
+        state0 = (state0 & ~(upd_all >> 8) & 0xFFu) | (upd_all & 0xFFu);
+
+        // ---- survivors among this round's candidates
         uint32_t lmin = kNoKey32;
 #pragma unroll
-        for (int j = 0; j < SPL; j++) {
-            const int s = (63 - lane) * SPL + j;
-            sk[j] = s < M ? slots[s] : kNoKey32;
-            lmin = umin32(lmin, sk[j]);
-        }
-        const uint32_t incl_min = wave_prefix_min(lmin);
-        const uint32_t round_min = (uint32_t)__builtin_amdgcn_readlane((int)incl_min, 63);
-        uint32_t later = wave_shift_up(kNoKey32, incl_min);
+        for (int k = 0; k < 8; k++) lmin = umin32(lmin, sk[k]);
+        const uint32_t suf = wave_suffix_min(lmin);
+        const uint32_t round_min = (uint32_t)__builtin_amdgcn_readlane((int)suf, 0);
+        uint32_t later = wave_shift_down(kNoKey32, suf);
         uint32_t keepmask = 0;
-        int nkeep = 0;
 #pragma unroll
-        for (int j = SPL - 1; j >= 0; j--) {
-            const bool keep = sk[j] != kNoKey32 && (sk[j] >> 2) < (later >> 2);
-            later = umin32(later, sk[j]);
-            keepmask |= keep ? (1u << j) : 0u;
-            nkeep += keep ? 1 : 0;
+        for (int k = 7; k >= 0; k--) {
+            const bool keep = sk[k] != kNoKey32 && (sk[k] >> 2) < (later >> 2);
+            later = umin32(later, sk[k]);
+            keepmask |= keep ? (1u << k) : 0u;
         }
+        const int nkeep = __popc(keepmask);
         // tentative survivors of earlier rounds outlive this round iff they
         // appear before every candidate of this round (they are increasing)
         int ncs = 0;
@@ -501,12 +579,12 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, const int64_t *block
         }
         const uint32_t incl_cnt = wave_prefix_sum((uint32_t)nkeep);
         const int nsurv = __builtin_amdgcn_readlane((int)incl_cnt, 63);
-        __syncthreads();  // every lane has read its slots before they are overwritten
+        __syncthreads();  // the merge buffers are read before survivors overwrite them
         {
-            int pos = ncs + nsurv - (int)incl_cnt;  // survivors of lanes > l come first
+            int pos = ncs + (int)incl_cnt - nkeep;
 #pragma unroll
-            for (int j = 0; j < SPL; j++)
-                if (keepmask & (1u << j)) L.seq[pos++] = sk[j];
+            for (int k = 0; k < 8; k++)
+                if (keepmask & (1u << k)) L.seq[pos++] = sk[k];
         }
         const int nseq = ncs + nsurv;
         __syncthreads();
@@ -556,10 +634,7 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, const int64_t *block
 
 #pragma unroll
         for (int p = 0; p < K; p++) {
-            if (m[p] > 0) {
-                cval[p] = L.tile[p * ST + m[p]] & 3u;
-                cur[p] += m[p];
-            }
+            cur[p] += m[p];
 #pragma unroll
             for (int e = 0; e < E; e++) pre[p][e] = nxt[p][e];
         }
@@ -575,14 +650,12 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, const int64_t *block
     }
 }
 
-// One wavefront per entry of the class-W work list.
-template <int W>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void eval_wave_kernel(StepArgs A, int cls) {
-    __shared__ WaveLds<W> L;
+// One wavefront per work-list entry.
+template <int W, int K>
+__device__ __forceinline__ void eval_item(const StepArgs &A, int list, int64_t item, WaveLds<W> &L) {
     const int lane = lane_id();
-    const int64_t item = blockIdx.x;
-    if (item >= (int64_t)A.count[cls]) return;
-    const uint64_t e = A.list[cls][item];
+    if (item >= (int64_t)A.count[list]) return;
+    const uint64_t e = A.list[list][item];
     const JobDesc &J = A.jobs[(int)(e >> 32)];
     const int64_t gate = (int64_t)(uint32_t)e;
     const GateRec R = J.rec[gate];
@@ -592,12 +665,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void ev
     }
     reinterpret_cast<uint32_t *>(L.lut)[lane] =
         reinterpret_cast<const uint32_t *>(A.lut + (int)R.type * 256)[lane];
-    switch (R.k) {
-    case 1: eval_gate<1, W>(J, A.blocksum, R, gate, L); break;
-    case 2: eval_gate<2, W>(J, A.blocksum, R, gate, L); break;
-    case 3: eval_gate<3, W>(J, A.blocksum, R, gate, L); break;
-    default: eval_gate<4, W>(J, A.blocksum, R, gate, L); break;
-    }
+    eval_gate<K, W>(J, A.blocksum, R, gate, L);
+}
+
+// Every gate of the step whose largest delay is at most W, in one launch:
+// blocks [0, c4) take the four-pin list, [c4, c3) the three-pin list,
+// [c3, c2) the two-pin list and the rest the one-pin list (costliest gates
+// first, so the cheap ones fill the tail).
+template <int W>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void eval_wave_kernel(
+    StepArgs A, int list0, int64_t c4, int64_t c3, int64_t c2) {
+    __shared__ WaveLds<W> L;
+    const int64_t b = blockIdx.x;
+    if (b < c4) eval_item<W, 4>(A, list0 + 3, b, L);
+    else if (b < c3) eval_item<W, 3>(A, list0 + 2, b - c4, L);
+    else if (b < c2) eval_item<W, 2>(A, list0 + 1, b - c3, L);
+    else eval_item<W, 1>(A, list0, b - c2, L);
 }
 
 // -------------------------------------------------------------------------
@@ -606,8 +689,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void ev
 // transitions (denials pop its tail). Exact for any delay.
 __global__ __launch_bounds__(64) void eval_lane_kernel(StepArgs A) {
     const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= (int64_t)A.count[kClassLane]) return;
-    const uint64_t e = A.list[kClassLane][item];
+    if (item >= (int64_t)A.count[kListLane]) return;
+    const uint64_t e = A.list[kListLane][item];
     const JobDesc &J = A.jobs[(int)(e >> 32)];
     const int64_t gate = (int64_t)(uint32_t)e;
     const int64_t S = J.S;
@@ -789,14 +872,22 @@ hipError_t launch_level_scan(const StepArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_eval(const StepArgs &a, int cls, int64_t max_items, hipStream_t s) {
-    if (max_items <= 0) return hipSuccess;
-    if (cls == kClassSmall)
-        eval_wave_kernel<kWindowSmall><<<dim3((unsigned)max_items), dim3(64), 0, s>>>(a, cls);
-    else if (cls == kClassLarge)
-        eval_wave_kernel<kWindowLarge><<<dim3((unsigned)max_items), dim3(64), 0, s>>>(a, cls);
+hipError_t launch_eval_wave(const StepArgs &a, int large_window, const int64_t *max_items,
+                            hipStream_t s) {
+    const int64_t c4 = max_items[3], c3 = c4 + max_items[2], c2 = c3 + max_items[1];
+    const int64_t total = c2 + max_items[0];
+    if (total <= 0) return hipSuccess;
+    const int list0 = wave_list(large_window, 1);
+    if (large_window)
+        eval_wave_kernel<kWindowLarge><<<dim3((unsigned)total), dim3(64), 0, s>>>(a, list0, c4, c3, c2);
     else
-        eval_lane_kernel<<<dim3((unsigned)((max_items + 63) / 64)), dim3(64), 0, s>>>(a);
+        eval_wave_kernel<kWindowSmall><<<dim3((unsigned)total), dim3(64), 0, s>>>(a, list0, c4, c3, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_lane(const StepArgs &a, int64_t max_items, hipStream_t s) {
+    if (max_items <= 0) return hipSuccess;
+    eval_lane_kernel<<<dim3((unsigned)((max_items + 63) / 64)), dim3(64), 0, s>>>(a);
     return hipGetLastError();
 }
 

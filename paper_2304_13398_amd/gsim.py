@@ -277,6 +277,17 @@ class Sim:
                                               total))
         return off, t[:total], v[:total]
 
+    def lengths(self, job: int, nets=None) -> np.ndarray:
+        """Transition counts of ``nets`` (all if None), without copying waveforms."""
+        if nets is None:
+            n = self._job_nets[job]
+        else:
+            nets = _c(nets, np.int64)
+            n = len(nets)
+        off = np.zeros(n + 1, dtype=np.int64)
+        self._ck(self.lib.sim_fetch_waveforms(self.ctx, job, _p(nets), n, _p(off), None, None, 0))
+        return np.diff(off)
+
     def hashes(self, job: int, nets=None) -> np.ndarray:
         """Per-net fingerprints (see sim_fetch_hashes) of ``nets`` (all if None)."""
         if nets is None:

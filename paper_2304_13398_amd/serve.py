@@ -1,9 +1,10 @@
 """Request loop over resident netlists: continuous batching vs one job at a time.
 
 A request names a resident netlist, carries its source waveforms, and asks for
-the waveforms of that netlist's primary outputs (gate outputs no gate reads).
-Latency is measured from the request's arrival to the moment its requested
-waveforms are in host memory.
+the waveforms of the netlist's observed outputs (the gates of its deepest
+level) plus an 8-byte fingerprint of every net's waveform (sim_fetch_hashes),
+which lets a client compare whole results without copying them. Latency is
+measured from the request's arrival to the moment both are in host memory.
 
 * ``serve_continuous``: requests are submitted to the library's executor when
   they arrive; every scheduling pass (``sim_drive``) admits what fits the HBM
@@ -28,7 +29,8 @@ class Request:
     arrival: float          # seconds after the start of the run
     netlist: int            # index into the resident netlists
     stim: W.Stimulus
-    outputs: np.ndarray     # net ids to fetch
+    outputs: np.ndarray     # net ids whose waveforms are fetched
+    digest: bool = True     # also fetch the fingerprints of all nets
 
 
 @dataclasses.dataclass
@@ -36,6 +38,8 @@ class Result:
     latency: float
     n_out: int              # output transitions the job computed (all gates)
     fetched: int            # transitions returned to the caller
+    fingerprints: np.ndarray | None = None
+    request: Request | None = None
 
 
 def primary_outputs(nl) -> np.ndarray:
@@ -45,16 +49,22 @@ def primary_outputs(nl) -> np.ndarray:
     return np.nonzero(~read[nl.S:])[0] + nl.S
 
 
+def observed_outputs(nl) -> np.ndarray:
+    """Net ids of the gates of the deepest level."""
+    return np.nonzero(nl.level == nl.level.max())[0] + nl.S
+
+
 def poisson_arrivals(rng, rate: float, n: int) -> np.ndarray:
     return np.cumsum(rng.exponential(1.0 / rate, size=n))
 
 
 def _finish(sim, j, req, t0):
     off, t, v = sim.fetch(j, req.outputs)
+    fp = sim.hashes(j) if req.digest else None
     lat = time.perf_counter() - t0 - req.arrival
     n_out = sim.stats(j).n_out
     sim.release(j)
-    return Result(lat, int(n_out), int(off[-1]))
+    return Result(lat, int(n_out), int(off[-1]), fp, req)
 
 
 def serve_continuous(sim: G.Sim, handles, requests, max_ahead: int = 2):
@@ -110,7 +120,7 @@ def served_workload(n_jobs: int, rate: float, netlists, stim_pool, seed: int = 1
     that netlist's pre-generated pool, Poisson arrivals at ``rate`` per second."""
     rng = np.random.default_rng(seed)
     arrivals = poisson_arrivals(rng, rate, n_jobs)
-    outs = [primary_outputs(nl) for nl in netlists]
+    outs = [observed_outputs(nl) for nl in netlists]
     reqs = []
     for a in arrivals:
         k = int(rng.integers(len(netlists)))

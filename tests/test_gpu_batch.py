@@ -136,3 +136,31 @@ def test_learned_arena_size_and_automatic_retry(sim):
         sim.release(j)
     say(f"retries per sparse job: {retries}")
     sim.unload_netlist(h)
+
+
+def test_request_loop_results_equal_alone(sim):
+    """The served request loop on small resident netlists: every request's
+    fingerprints (all nets) equal those of the oracle run on that request
+    alone, under continuous batching and one-at-a-time service."""
+    from paper_2304_13398_amd import serve
+    from tests import net_hash
+    nls = serve.served_netlists(scale=0.01, seed=9)[:4]
+    pool = serve.make_stim_pool(nls, per_netlist=3, seed=9, lo=5, hi=60)
+    hs = [sim.load_netlist(nl) for nl in nls]
+    reqs = serve.served_workload(24, 2000.0, nls, pool, seed=9)
+    say(f"served: {len(reqs)} requests over netlists {[nl.G for nl in nls]}")
+    want = {}
+    for r in reqs:
+        key = id(r.stim)
+        if key not in want:
+            nl = nls[r.netlist]
+            off, t, v = O.o1_simulate(nl, r.stim)
+            want[key] = np.concatenate([net_hash.fingerprints(r.stim.off, r.stim.t, r.stim.v),
+                                        net_hash.fingerprints(off, t, v)])
+    for loop in (serve.serve_continuous, serve.serve_sequential):
+        res, _ = loop(sim, hs, reqs)
+        assert len(res) == len(reqs)
+        for x in res:
+            assert np.array_equal(x.fingerprints, want[id(x.request.stim)]), loop.__name__
+    for h in hs:
+        sim.unload_netlist(h)

@@ -19,7 +19,6 @@ import pytest
 from oracle import oracle as O
 from paper_2304_13398_amd import gsim as G
 from paper_2304_13398_amd import workloads as W
-from tests import oracle_pins as P
 
 pytestmark = pytest.mark.gpu
 
@@ -91,8 +90,7 @@ def check_full_size(sim, nl, st, prefix_levels, n_sample=3000):
     n_pre = int(np.searchsorted(nl.level, prefix_levels, side="right"))
     o_len, o_fp = O.o1_simulate_fingerprints(nl.prefix(n_pre), st)
     gates = np.arange(nl.S, nl.S + n_pre)
-    g_off, _, _ = _sizes(sim, j, gates)
-    assert np.array_equal(np.diff(g_off), o_len), "lengths differ on the first levels"
+    assert np.array_equal(sim.lengths(j, gates), o_len), "lengths differ on the first levels"
     assert np.array_equal(sim.hashes(j, gates), o_fp), "waveforms differ on the first levels"
     say(f"  levels 1-{prefix_levels}: {n_pre} gates exact")
 
@@ -127,19 +125,11 @@ def check_full_size(sim, nl, st, prefix_levels, n_sample=3000):
     if os.environ.get("GSIM_FULLSIZE_ORACLE") == "1":
         o_len, o_fp = O.o1_simulate_fingerprints(nl, st)
         all_gates = np.arange(nl.S, nl.S + nl.G)
-        g_off, _, _ = _sizes(sim, j, all_gates)
-        assert np.array_equal(np.diff(g_off), o_len)
+        assert np.array_equal(sim.lengths(j, all_gates), o_len)
         assert np.array_equal(sim.hashes(j, all_gates), o_fp)
         say(f"  all {nl.G} gates exact against the oracle")
     sim.release(j)
     sim.unload_netlist(h)
-
-
-def _sizes(sim, j, nets):
-    off = np.zeros(len(nets) + 1, dtype=np.int64)
-    nets = np.ascontiguousarray(nets, dtype=np.int64)
-    sim._ck(sim.lib.sim_fetch_waveforms(sim.ctx, j, G._p(nets), len(nets), G._p(off), None, None, 0))
-    return off, None, None
 
 
 def test_mid_full_size(sim):
