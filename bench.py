@@ -55,6 +55,10 @@ def parse():
     ap.add_argument("--cpu-levels", type=int, default=25,
                     help="levels of the workload the oracle runs for the CPU baseline")
     ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-configuration latency")
+    ap.add_argument("--no-skewed", action="store_true",
+                    help="skip the uneven-source-activity (WCV) runs")
+    ap.add_argument("--no-dataflow", action="store_true",
+                    help="skip the dependency-driven schedule measurement")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched section (64 stimulus sets over the 1M-gate netlist)")
     ap.add_argument("--batched-sets", type=int, default=64)
@@ -252,6 +256,44 @@ def bench_tiny_latency(G, sim, seed, reps=200):
     }
 
 
+def bench_skewed(G, sim, nl, h, seed, wcvs=(5.0, 20.0), steps=3):
+    """Uneven source activity on the resident 1M-gate netlist: the same
+    2,048,000 given transitions with per-source counts of coefficient of
+    variation WCV (the paper's Eq. 5), under both schedules."""
+    import torch
+    from paper_2304_13398_amd import workloads as W
+    out = {"workload": "1M-gate mid netlist, 2,048,000 given transitions, per-source counts "
+                       "log-normal with the stated WCV", "runs": {}}
+    for wcv in wcvs:
+        st = W.make_stimulus_skewed(S=nl.S, mean_per_src=1000, wcv=wcv, window=1_000_000, seed=seed)
+        dev = torch.device("cuda:0")
+        d = [torch.from_numpy(a).to(dev) for a in (st.off, st.t, st.v)]
+        stream = torch.cuda.current_stream()
+        row = {}
+        for name, sched in (("levels", 0), ("dataflow", 1)):
+            sim.set_option(G.OPT_SCHEDULE, sched)
+            times, n_out = [], 0
+            for i in range(steps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                j = sim.run_device(h, d[0].data_ptr(), d[1].data_ptr(), d[2].data_ptr(), st.n,
+                                   stream=stream.cuda_stream)
+                sim.wait(j)
+                if i > 0:
+                    times.append(time.perf_counter() - t0)
+                n_out = sim.stats(j).n_out
+                sim.release(j)
+            ms = statistics.median(times) * 1000.0
+            row[name] = {"ms_per_job": ms, "transitions_per_s": n_out / (ms / 1000.0), "n_out": int(n_out)}
+        sim.set_option(G.OPT_SCHEDULE, 0)
+        n = np.diff(st.off)
+        row["wcv_given"] = float(n.std() / n.mean())
+        out["runs"][str(wcv)] = row
+        print(f"[bench] skewed wcv {wcv}: levels {row['levels']['ms_per_job']:.1f} ms, "
+              f"dataflow {row['dataflow']['ms_per_job']:.1f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def workload_stats(nl, lengths):
     """The paper's workload statistics (Table 2 columns and Eq. 5): coefficient
     of variation of the given (source) waveform lengths and of the generated
@@ -416,6 +458,41 @@ def main():
 
     out["workload_stats"] = workload_stats(nl, lengths)
 
+    if not args.no_dataflow:
+        # the same jobs under the dependency-driven schedule (one persistent launch per job)
+        sim.set_option(G.OPT_SCHEDULE, 1)
+        dstats = []
+        finish(launch(), False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prev = None
+        for _ in range(args.steps):
+            j = launch()
+            if prev is not None:
+                sim.wait(prev)
+                dstats.append(sim.stats(prev))
+                sim.release(prev)
+            prev = j
+        sim.wait(prev)
+        dstats.append(sim.stats(prev))
+        sim.release(prev)
+        torch.cuda.synchronize()
+        dwall = time.perf_counter() - t0
+        sim.set_option(G.OPT_SCHEDULE, 0)
+        assert all(x.n_out == n_out for x in dstats), "dependency-driven runs disagree on the output size"
+        d_ms = dwall / args.steps * 1000.0
+        d_eval = statistics.median(x.eval_ms for x in dstats)
+        out["dataflow"] = {
+            "schedule": "dependency-driven: one persistent launch per job, no level barrier",
+            "ms_per_step": d_ms,
+            "value": n_out / (d_ms / 1000.0),
+            "kernel_ms": d_eval,
+            "algorithmic_gbps": b_eval / (d_eval / 1000.0) / 1e9,
+            "vs_levels": ms_per_step / d_ms,
+        }
+        print(f"[bench] dependency-driven: {d_ms:.2f} ms per step (levels {ms_per_step:.2f})",
+              file=sys.stderr, flush=True)
+
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         lv = min(args.cpu_levels, info.levels)
@@ -438,8 +515,14 @@ def main():
                       f"({n_gates} gates, {int(o_off[-1])} output transitions, {cpu_s:.1f}s)",
         }
     sim.set_option(G.OPT_KERNEL_TIMING, 0)
+    if not args.no_skewed:
+        out["skewed"] = bench_skewed(G, sim, nl, h, args.seed)
     if not args.no_tiny:
         out["tiny_latency"] = bench_tiny_latency(G, sim, args.seed)
+        if not args.no_dataflow:
+            sim.set_option(G.OPT_SCHEDULE, 1)
+            out["tiny_latency_dataflow"] = bench_tiny_latency(G, sim, args.seed)
+            sim.set_option(G.OPT_SCHEDULE, 0)
     if not args.no_batched:
         out["batched"] = bench_batched(G, sim, nl, h, args.batched_sets, args.seed)
     sim.unload_netlist(h)

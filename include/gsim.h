@@ -95,7 +95,13 @@ enum gsim_option {
     /* Dynamic binning: a gate whose inputs hold fewer than this many
      * transitions in a run is evaluated by the lane-per-gate kernel instead of
      * the wavefront-per-gate kernel (0 = never). Picked by the autotuner. */
-    GSIM_OPT_LANE_THRESHOLD = 5
+    GSIM_OPT_LANE_THRESHOLD = 5,
+    /* Schedule of later jobs: 0 = level by level (one launch chain per level,
+     * shared by every admitted job); 1 = dependency-driven (Section 3.3,
+     * Algorithm 1): one persistent launch per job in which a gate starts as
+     * soon as its last fan-in gate has finished, with no level barrier.
+     * Results are identical. */
+    GSIM_OPT_SCHEDULE = 6
 };
 
 /* ---- context ------------------------------------------------------------ */

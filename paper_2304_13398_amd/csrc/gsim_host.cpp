@@ -380,6 +380,13 @@ struct Netlist {
     std::vector<LevelRange> levels;
     std::vector<int64_t> internal_of_user;  // [G]
     GateRec *d_rec = nullptr;
+    // dependency-driven schedule: consumers of each gate's net (one entry per
+    // reading pin), each gate's count of pins that read gate nets, and the
+    // number of gates that read sources only (they come first in level order)
+    int64_t *d_fo_off = nullptr;
+    int32_t *d_fo = nullptr;
+    int32_t *d_pend0 = nullptr;
+    int64_t n_first = 0;
     int64_t active_jobs = 0;
     int64_t max_level_n = 0;        // gates of the largest level
     int32_t lane_threshold = -1;    // -1: the context's GSIM_OPT_LANE_THRESHOLD
@@ -421,6 +428,9 @@ struct Job {
     hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_done = nullptr;
     std::vector<std::shared_ptr<StepTiming>> timing;
     int64_t n_partial = 0;
+    bool dataflow = false;        // dependency-driven schedule (one launch for every gate)
+    int32_t *d_pend = nullptr, *d_queue = nullptr;
+    DfCtl *d_ctl = nullptr;
     int32_t retries = 0;          // automatic re-runs after an arena overflow
     bool waited = false, failed = false;
 };
@@ -470,6 +480,8 @@ struct gsim_ctx_s {
     int64_t opt_arena = 0;
     int opt_kernel = 0;
     int opt_timing = 0;
+    int opt_schedule = 0;
+    int64_t n_waves_resident = 0;  // persistent wavefronts of the dependency-driven schedule
     int32_t opt_lane_threshold = 0;
 };
 
@@ -571,14 +583,53 @@ Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, co
         r.user_gate = (int32_t)g;
         recs[nl->internal_of_user[g]] = r;
     }
+    // consumers of each gate, in internal ids, for the dependency-driven schedule
+    std::vector<int64_t> fo_off(G + 1, 0);
+    std::vector<int32_t> pend0(G, 0);
+    for (int64_t c = 0; c < G; c++)
+        for (int i = 0; i < recs[c].k; i++)
+            if (recs[c].net[i] >= S) {
+                fo_off[recs[c].net[i] - S + 1]++;
+                pend0[c]++;
+            }
+    for (int64_t g = 0; g < G; g++) fo_off[g + 1] += fo_off[g];
+    std::vector<int32_t> fo(std::max<int64_t>(fo_off[G], 1));
+    {
+        std::vector<int64_t> fill(fo_off.begin(), fo_off.end() - 1);
+        for (int64_t c = 0; c < G; c++)
+            for (int i = 0; i < recs[c].k; i++)
+                if (recs[c].net[i] >= S) fo[fill[recs[c].net[i] - S]++] = (int32_t)c;
+    }
+    while (nl->n_first < G && pend0[nl->n_first] == 0) nl->n_first++;
     f = set_device(ctx);
     if (f.st != GSIM_OK) return f;
     if (G > 0) {
+        nl->d_fo_off = pool_get<int64_t>(*ctx->pool, G + 1);
+        nl->d_fo = pool_get<int32_t>(*ctx->pool, (int64_t)fo.size());
+        nl->d_pend0 = pool_get<int32_t>(*ctx->pool, G);
+        if (!nl->d_fo_off || !nl->d_fo || !nl->d_pend0 ||
+            hipMemcpy(nl->d_fo_off, fo_off.data(), sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(nl->d_fo, fo.data(), sizeof(int32_t) * fo.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(nl->d_pend0, pend0.data(), sizeof(int32_t) * (size_t)G, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->pool->put(nl->d_fo_off);
+            ctx->pool->put(nl->d_fo);
+            ctx->pool->put(nl->d_pend0);
+            return fail(GSIM_E_OOM, "no device memory for the fanout table of %lld gates", (long long)G);
+        }
         nl->d_rec = (GateRec *)ctx->pool->get(sizeof(GateRec) * (size_t)G);
-        if (!nl->d_rec) return fail(GSIM_E_OOM, "no device memory for %lld gate records", (long long)G);
+        if (!nl->d_rec) {
+            ctx->pool->put(nl->d_fo_off);
+            ctx->pool->put(nl->d_fo);
+            ctx->pool->put(nl->d_pend0);
+            return fail(GSIM_E_OOM, "no device memory for %lld gate records", (long long)G);
+        }
         hipError_t e = hipMemcpy(nl->d_rec, recs.data(), sizeof(GateRec) * (size_t)G, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             ctx->pool->put(nl->d_rec);
+            ctx->pool->put(nl->d_fo_off);
+            ctx->pool->put(nl->d_fo);
+            ctx->pool->put(nl->d_pend0);
             return fail(GSIM_E_DEVICE, "netlist upload: %s", hipGetErrorString(e));
         }
     }
@@ -646,9 +697,14 @@ void free_job_buffers(gsim_ctx ctx, Job *j) {
     pool.put(j->d_src_off);
     pool.put(j->d_K);
     pool.put(j->d_state);
+    pool.put(j->d_pend);
+    pool.put(j->d_queue);
+    pool.put(j->d_ctl);
     j->d_off = j->d_len = j->d_partial = j->d_src_off = nullptr;
     j->d_K = nullptr;
     j->d_state = nullptr;
+    j->d_pend = j->d_queue = nullptr;
+    j->d_ctl = nullptr;
 }
 
 void destroy_job(gsim_ctx ctx, Job *j) {
@@ -732,6 +788,7 @@ Failure submit(gsim_ctx ctx, gsim_netlist nlh, const int64_t *src_off, const int
     j->ex = ex;
     j->n_in = n_in;
     j->capacity_request = ctx->opt_arena;
+    j->dataflow = ctx->opt_schedule == 1;
     if (!device_arrays) {
         const size_t S1 = (size_t)nl.S + 1;
         j->h_src_off = (int64_t *)ctx->pinned.get(sizeof(int64_t) * S1);
@@ -770,6 +827,45 @@ Failure finish_job(Job *j, hipStream_t s) {
     HIP_TRY(hipEventRecord(j->ev_done, s));
     j->phase = kEnqueued;
     return kOk;
+}
+
+// Every gate of an admitted job in one dependency-driven launch.
+Failure enqueue_dataflow(gsim_ctx ctx, Job *j, hipStream_t s) {
+    Netlist &nl = *j->nl;
+    DfArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.job.rec = nl.d_rec;
+    a.job.S = nl.S;
+    a.job.off = j->d_off;
+    a.job.len = j->d_len;
+    a.job.K = j->d_K;
+    a.job.state = j->d_state;
+    a.fo_off = nl.d_fo_off;
+    a.fo = nl.d_fo;
+    a.pend = j->d_pend;
+    a.queue = j->d_queue;
+    a.ctl = j->d_ctl;
+    a.lut = ctx->d_lut;
+    a.G = nl.G;
+    a.n_first = nl.n_first;
+    const int64_t n_waves = std::min<int64_t>(nl.G, ctx->n_waves_resident);
+    // reservation granule: at most 1/16 of the arena left idle over all wavefronts
+    a.chunk = std::min<int64_t>(int64_t(1) << 15, (j->capacity - j->n_in) / (16 * std::max<int64_t>(n_waves, 1)));
+    HIP_TRY(launch_df_init(a, nl.d_pend0, s));
+    std::shared_ptr<StepTiming> tm;
+    if (ctx->opt_timing) {
+        tm = std::make_shared<StepTiming>();
+        HIP_TRY(hipEventCreate(&tm->a));
+        HIP_TRY(hipEventCreate(&tm->b));
+        HIP_TRY(hipEventRecord(tm->a, s));
+    }
+    HIP_TRY(launch_dataflow(a, n_waves, s));
+    if (tm) {
+        HIP_TRY(hipEventRecord(tm->b, s));
+        j->timing.push_back(tm);
+    }
+    j->next_level = nl.n_levels;
+    return finish_job(j, s);
 }
 
 // Allocate a queued job's device storage and pack its sources into the arena.
@@ -820,10 +916,19 @@ Failure admit(gsim_ctx ctx, Executor *ex, Job *j) {
     j->d_state = pool_get<DevState>(pool, 1);
     j->d_K = pool_get<uint64_t>(pool, cap);
     if (j->h_t) j->d_src_off = pool_get<int64_t>(pool, nl.S + 1);
-    if (!j->d_off || !j->d_len || !j->d_partial || !j->d_state || !j->d_K || (j->h_t && !j->d_src_off)) {
+    if (j->dataflow) {
+        j->d_pend = pool_get<int32_t>(pool, std::max<int64_t>(nl.G, 1));
+        j->d_queue = pool_get<int32_t>(pool, std::max<int64_t>(nl.G, 1));
+        j->d_ctl = pool_get<DfCtl>(pool, 1);
+    }
+    if (!j->d_off || !j->d_len || !j->d_partial || !j->d_state || !j->d_K || (j->h_t && !j->d_src_off) ||
+        (j->dataflow && (!j->d_pend || !j->d_queue || !j->d_ctl))) {
         pool.put(j->d_off); pool.put(j->d_len); pool.put(j->d_partial); pool.put(j->d_state); pool.put(j->d_K);
         pool.put(j->d_src_off);
+        pool.put(j->d_pend); pool.put(j->d_queue); pool.put(j->d_ctl);
         j->d_off = j->d_len = j->d_partial = j->d_src_off = nullptr;
+        j->d_pend = j->d_queue = nullptr;
+        j->d_ctl = nullptr;
         j->d_state = nullptr;
         j->d_K = nullptr;
         return fail(GSIM_E_OOM, "no device memory for a job of %lld transitions of output storage", (long long)cap);
@@ -858,6 +963,7 @@ Failure admit(gsim_ctx ctx, Executor *ex, Job *j) {
     j->phase = kActive;
     j->next_level = 0;
     if (nl.n_levels == 0) return finish_job(j, s);
+    if (j->dataflow) return enqueue_dataflow(ctx, j, s);
     ex->active.push_back(j);
     return kOk;
 }
@@ -1050,6 +1156,8 @@ Failure wait_job(gsim_ctx ctx, Job *j) {
         return fail(GSIM_E_OOM, "output arena of %lld transitions overflowed or could not be allocated "
                     "(after %d automatic retries); set GSIM_OPT_ARENA_TRANSITIONS larger",
                     (long long)j->capacity, (int)j->retries);
+    if (j->h_state->check_error == 3)
+        return fail(GSIM_E_DEVICE, "the dependency-driven schedule made no progress and stopped");
     if (j->h_state->check_error)
         return fail(GSIM_E_DEVICE, "internal consistency check failed (code %d)", j->h_state->check_error);
     return kOk;
@@ -1196,6 +1304,13 @@ gsim_status sim_create(int device, uint64_t hbm_budget_bytes, gsim_ctx *out) {
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return record(nullptr, fail(GSIM_E_DEVICE, "hipMemGetInfo failed"));
     const uint64_t budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(free_b / 10 * 9);
     ctx->pool = std::make_unique<Pool>(budget);
+    {
+        // persistent wavefronts of the dependency-driven schedule: four per SIMD
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+            return record(nullptr, fail(GSIM_E_DEVICE, "hipGetDeviceProperties failed"));
+        ctx->n_waves_resident = (int64_t)prop.multiProcessorCount * 16;
+    }
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess)
         return record(nullptr, fail(GSIM_E_DEVICE, "stream creation failed"));
     ctx->d_stage_t = (int64_t *)ctx->pool->get(sizeof(int64_t) * kStage);
@@ -1220,7 +1335,12 @@ gsim_status sim_destroy(gsim_ctx ctx) {
     ctx->jobs.clear();
     for (auto &kv : ctx->executors) destroy_executor(ctx, kv.second.get());
     ctx->executors.clear();
-    for (auto &kv : ctx->netlists) ctx->pool->put(kv.second->d_rec);
+    for (auto &kv : ctx->netlists) {
+        ctx->pool->put(kv.second->d_rec);
+        ctx->pool->put(kv.second->d_fo_off);
+        ctx->pool->put(kv.second->d_fo);
+        ctx->pool->put(kv.second->d_pend0);
+    }
     ctx->netlists.clear();
     ctx->pool->put(ctx->d_lut);
     ctx->pool->put(ctx->d_stage_t);
@@ -1251,6 +1371,10 @@ gsim_status sim_set_option(gsim_ctx ctx, int option, int64_t value) {
         if (value < 0 || value > INT32_MAX) return record(ctx, fail(GSIM_E_ARG, "lane threshold out of range"));
         ctx->opt_lane_threshold = (int32_t)value;
         return GSIM_OK;
+    case GSIM_OPT_SCHEDULE:
+        if (value < 0 || value > 1) return record(ctx, fail(GSIM_E_ARG, "schedule option must be 0 or 1"));
+        ctx->opt_schedule = (int)value;
+        return GSIM_OK;
     }
     return record(ctx, fail(GSIM_E_ARG, "unknown option %d", option));
 }
@@ -1270,6 +1394,9 @@ gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl) {
         return record(ctx, fail(GSIM_E_ARG, "netlist %lld still has %lld unreleased jobs", (long long)nl,
                                 (long long)it->second->active_jobs));
     ctx->pool->put(it->second->d_rec);
+    ctx->pool->put(it->second->d_fo_off);
+    ctx->pool->put(it->second->d_fo);
+    ctx->pool->put(it->second->d_pend0);
     ctx->netlists.erase(it);
     return GSIM_OK;
 }

@@ -64,7 +64,8 @@ struct DevState {
     int64_t pin_reads;       // sum of reserved bounds = sum over pins of read lengths
     int64_t n_out;           // output transitions (filled by the final reduction)
     int32_t overflow;        // arena exhausted: later levels are skipped
-    int32_t check_error;     // an internal consistency check failed (never expected)
+    int32_t check_error;     // an internal consistency check failed (never expected); 3: the
+                             // dependency-driven schedule made no progress for too long
 };
 
 // One job's share of a step: the gates of its current level.
@@ -96,6 +97,28 @@ struct StepArgs {
     const uint8_t *lut;      // [12][256] gate value by packed pin values
 };
 
+// Dependency-driven schedule: one job per launch, no level barrier. A gate
+// becomes ready when the last of its fan-in gates has finished; ready gates
+// enter `queue` in that order and persistent wavefronts take them in turn.
+struct DfCtl {
+    uint32_t head;   // next queue slot to hand out
+    uint32_t tail;   // next queue slot to fill
+    uint32_t pad[2];
+};
+
+struct DfArgs {
+    JobDesc job;            // netlist and storage of the job (level fields unused)
+    const int64_t *fo_off;  // [G+1] consumers of each gate's output net, one per reading pin
+    const int32_t *fo;
+    int32_t *pend;          // [G] fan-in pins whose gate has not finished
+    int32_t *queue;         // [G] gates in the order they became ready; -1: not yet
+    DfCtl *ctl;
+    const uint8_t *lut;     // [12][256]
+    int64_t G;
+    int64_t n_first;        // gates reading sources only (the first level): ready at the start
+    int64_t chunk;          // arena reservation granule per wavefront, in transitions
+};
+
 // Kernel launchers (kernels.hip). All are asynchronous on `s`.
 hipError_t launch_init_sources(const int64_t *d_src_off, const int64_t *d_t, const uint8_t *d_v,
                                int64_t S, int64_t n_in, int64_t *off, int64_t *len, uint64_t *K,
@@ -109,6 +132,10 @@ hipError_t launch_level_scan(const StepArgs &a, hipStream_t s);
 hipError_t launch_eval_wave(const StepArgs &a, int large_window, const int64_t *max_items,
                             hipStream_t s);
 hipError_t launch_eval_lane(const StepArgs &a, int64_t max_items, hipStream_t s);
+// Dependency-driven schedule: reset the counters and queue, then run every
+// gate of the job with n_waves persistent wavefronts.
+hipError_t launch_df_init(const DfArgs &a, const int32_t *pend0, hipStream_t s);
+hipError_t launch_dataflow(const DfArgs &a, int64_t n_waves, hipStream_t s);
 hipError_t launch_count_out(const int64_t *len, int64_t S, int64_t G, int64_t *partial,
                             int64_t n_partial, DevState *state, hipStream_t s);
 hipError_t launch_gather(const int64_t *src_off, const int64_t *n_items, const int64_t *dst_off,

@@ -369,8 +369,8 @@ __device__ __forceinline__ uint32_t wave_suffix_min(uint32_t x) {
 }
 
 template <int K, int W>
-__device__ __forceinline__ void eval_gate(const JobDesc &J, const int64_t *blockbase,
-                                          const GateRec &R, int64_t gate, WaveLds<W> &L) {
+__device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const GateRec &R,
+                                          int64_t gate, WaveLds<W> &L) {
     using Tl = Tiling<K>;
     constexpr int T = Tl::T, E = Tl::E, ST = Tl::STRIDE;
     constexpr int NIT1 = K == 2 ? 9 : 8;  // split range of the first merge: <= T
@@ -380,7 +380,6 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, const int64_t *block
     int64_t *off = J.off;
     uint64_t *Kar = J.K;
 
-    const int64_t ob = blockbase[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + off[S + gate];
     int64_t pb[K], pl[K], cur[K];
     int64_t reserved = 0;  // slots sized for this gate: the sum of its input lengths
 #pragma unroll
@@ -665,7 +664,8 @@ __device__ __forceinline__ void eval_item(const StepArgs &A, int list, int64_t i
     }
     reinterpret_cast<uint32_t *>(L.lut)[lane] =
         reinterpret_cast<const uint32_t *>(A.lut + (int)R.type * 256)[lane];
-    eval_gate<K, W>(J, A.blocksum, R, gate, L);
+    const int64_t ob = A.blocksum[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + J.off[J.S + gate];
+    eval_gate<K, W>(J, ob, R, gate, L);
 }
 
 // Every gate of the step whose largest delay is at most W, in one launch:
@@ -687,40 +687,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void ev
 // Lane-per-gate evaluation: the sequential procedure on one lane, with the
 // gate's reserved output region used directly as the list of scheduled
 // transitions (denials pop its tail). Exact for any delay.
-__global__ __launch_bounds__(64) void eval_lane_kernel(StepArgs A) {
-    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= (int64_t)A.count[kListLane]) return;
-    const uint64_t e = A.list[kListLane][item];
-    const JobDesc &J = A.jobs[(int)(e >> 32)];
-    const int64_t gate = (int64_t)(uint32_t)e;
+__device__ void eval_seq(const JobDesc &J, const GateRec &R, int64_t gate, int64_t ob,
+                         const uint8_t *lut) {
     const int64_t S = J.S;
-    if (J.state->overflow) {
-        J.len[S + gate] = 0;
-        J.off[S + gate] = 0;
-        return;
-    }
-    const GateRec R = J.rec[gate];
     const int k = R.k;
-    const int64_t ob = A.blocksum[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + J.off[S + gate];
     int64_t pb[kMaxPins], pl[kMaxPins], idx[kMaxPins];
     uint32_t cv[kMaxPins];
     int64_t reserved = 0;
+#pragma unroll
     for (int p = 0; p < kMaxPins; p++) {
         pb[p] = 0; pl[p] = 0; idx[p] = 0; cv[p] = kX;
         if (p < k) { pb[p] = J.off[R.net[p]]; pl[p] = J.len[R.net[p]]; reserved += pl[p]; }
     }
-    const uint8_t *lut = A.lut + (int)R.type * 256;
     uint64_t *Kar = J.K;
     uint32_t prev = kX;
     int64_t n = 0;
     for (;;) {
         int64_t te = kInf;
-        for (int p = 0; p < k; p++)
+#pragma unroll
+        for (int p = 0; p < kMaxPins; p++)
             if (idx[p] < pl[p]) te = min64(te, key_time(Kar[pb[p] + idx[p]]));
         if (te == kInf) break;
         int changed = 0;
         int pack = 0;
-        for (int p = 0; p < k; p++) {
+#pragma unroll
+        for (int p = 0; p < kMaxPins; p++) {
             if (idx[p] < pl[p]) {
                 const uint64_t kp = Kar[pb[p] + idx[p]];
                 if (key_time(kp) == te) {
@@ -729,12 +720,13 @@ __global__ __launch_bounds__(64) void eval_lane_kernel(StepArgs A) {
                     changed |= 1 << p;
                 }
             }
-            pack |= (int)cv[p] << (2 * p);
+            if (p < k) pack |= (int)cv[p] << (2 * p);
         }
         const uint32_t e = lut[pack];
         if (e != prev) {
             int64_t d = kInf;
-            for (int p = 0; p < k; p++)
+#pragma unroll
+            for (int p = 0; p < kMaxPins; p++)
                 if (changed & (1 << p)) d = min64(d, pin_delay(R.rise[p], R.fall[p], e));
             const int64_t tr = te + d;
             while (n > 0 && key_time(Kar[ob + n - 1]) >= tr) n--;
@@ -752,6 +744,174 @@ __global__ __launch_bounds__(64) void eval_lane_kernel(StepArgs A) {
     }
     J.len[S + gate] = n;
     J.off[S + gate] = ob;
+}
+
+__global__ __launch_bounds__(64) void eval_lane_kernel(StepArgs A) {
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= (int64_t)A.count[kListLane]) return;
+    const uint64_t e = A.list[kListLane][item];
+    const JobDesc &J = A.jobs[(int)(e >> 32)];
+    const int64_t gate = (int64_t)(uint32_t)e;
+    if (J.state->overflow) {
+        J.len[J.S + gate] = 0;
+        J.off[J.S + gate] = 0;
+        return;
+    }
+    const GateRec R = J.rec[gate];
+    const int64_t ob = A.blocksum[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + J.off[J.S + gate];
+    eval_seq(J, R, gate, ob, A.lut + (int)R.type * 256);
+}
+
+// -------------------------------------------------------------------------
+// Dependency-driven schedule (the non-partitioned, dependency-triggered task
+// control of Section 3.3, Algorithm 1): no level barrier. Each wavefront
+// takes the next queue slot (a ticket), waits until a gate has been put
+// there, evaluates it into a region it reserves from the arena with one
+// atomic add (the bounded reservation w_g of Eq. 2), then decrements the
+// pending count of every consumer and queues those that reach zero. Every
+// gate enters the queue exactly once, so the G tickets are all filled and a
+// wavefront leaves when its ticket is past the end. Ordering across the
+// XCDs' L2 caches: outputs are published with an agent-scope release fence
+// before the decrements, and read after an agent-scope acquire fence.
+// Safety exit: a wavefront that sees no new queue entry for kDfSpinLimit
+// polls (each after a sleep of about 2k cycles: tens of seconds in all) flags
+// the job (check_error = 3) and leaves, and so does every wavefront that sees
+// the flag.
+constexpr uint32_t kDfSpinLimit = 1u << 24;
+
+__global__ void df_init_kernel(DfArgs A, const int32_t *__restrict__ pend0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < A.G) {
+        A.pend[i] = pend0[i];
+        A.queue[i] = i < A.n_first ? (int32_t)i : -1;
+    }
+    if (i == 0) {
+        A.ctl->head = 0;
+        A.ctl->tail = (uint32_t)A.n_first;
+    }
+}
+
+__device__ __forceinline__ uint32_t load_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until queue slot t holds a gate; -1 if the job was flagged meanwhile.
+__device__ int32_t df_wait_slot(const DfArgs &A, uint32_t t, DevState *st) {
+    const int lane = lane_id();
+    uint32_t spins = 0, seen_tail = 0;
+    for (;;) {
+        uint32_t q = 0;
+        if (lane == 0) q = load_agent(reinterpret_cast<const uint32_t *>(A.queue + t));
+        q = (uint32_t)__builtin_amdgcn_readfirstlane((int)q);
+        if ((int32_t)q >= 0) return (int32_t)q;
+        if ((++spins & 31u) == 0) {  // now and then: an error elsewhere, or no progress
+            uint32_t err = 0, tl = 0;
+            if (lane == 0) {
+                err = load_agent(reinterpret_cast<const uint32_t *>(&st->check_error));
+                tl = load_agent(&A.ctl->tail);
+            }
+            err = (uint32_t)__builtin_amdgcn_readfirstlane((int)err);
+            tl = (uint32_t)__builtin_amdgcn_readfirstlane((int)tl);
+            if (err) return -1;
+            if (tl != seen_tail) {
+                seen_tail = tl;
+                spins = 0;
+            } else if (spins > kDfSpinLimit) {
+                if (lane == 0) atomicMax(&st->check_error, 3);
+                return -1;
+            }
+        }
+        __builtin_amdgcn_s_sleep(32);
+    }
+}
+
+// Tickets taken per atomic: a wavefront works through its tickets in order.
+// Queue slots are allocated in the order gates become ready, so while a
+// wavefront waits on its next slot no later slot holds a ready gate that
+// only it could run (the deadlock-freedom argument is unchanged).
+constexpr uint32_t kDfTickets = 2;
+// Arena space is reserved per wavefront in chunks of A.chunk transitions (or
+// one gate's bound if larger), so the arena top takes one atomic per chunk.
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void dataflow_kernel(DfArgs A) {
+    __shared__ WaveLds<kWindowLarge> L;
+    const int lane = lane_id();
+    const JobDesc &J = A.job;
+    DevState *st = J.state;
+    int64_t chunk_at = 0, chunk_end = 0;  // this wavefront's unused arena space
+    int64_t reads = 0;                    // sum of w_g over this wavefront's gates
+    bool stop = false;
+    while (!stop) {
+        uint32_t t0 = 0;
+        if (lane == 0) t0 = atomicAdd(&A.ctl->head, kDfTickets);
+        t0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)t0);
+        if ((int64_t)t0 >= A.G) break;
+        const uint32_t t1 = (uint32_t)min64((int64_t)t0 + kDfTickets, A.G);
+        for (uint32_t t = t0; t < t1; t++) {
+            const int32_t g = df_wait_slot(A, t, st);
+            if (g < 0) {
+                stop = true;
+                break;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+
+            const GateRec R = J.rec[g];
+            int64_t w = 0;
+#pragma unroll
+            for (int p = 0; p < kMaxPins; p++)
+                if (p < R.k) w += J.len[R.net[p]];
+            reads += w;
+            if (chunk_end - chunk_at < w) {
+                const int64_t want = w > A.chunk ? w : A.chunk;
+                int64_t at = 0;
+                if (lane == 0)
+                    at = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&st->arena_top),
+                                            (unsigned long long)want);
+                chunk_at = (int64_t)readlane_u64((uint64_t)at, 0);
+                chunk_end = chunk_at + want;
+            }
+            const int64_t ob = chunk_at;
+            chunk_at += w;
+            const bool full = ob + w > st->capacity;
+            if (full || load_agent(reinterpret_cast<const uint32_t *>(&st->overflow))) {
+                if (lane == 0) {
+                    if (full) atomicOr(&st->overflow, 1);
+                    J.len[J.S + g] = 0;
+                    J.off[J.S + g] = 0;
+                }
+            } else if (R.dmax > kWindowLarge) {
+                if (lane == 0) eval_seq(J, R, g, ob, A.lut + (int)R.type * 256);
+            } else {
+                reinterpret_cast<uint32_t *>(L.lut)[lane] =
+                    reinterpret_cast<const uint32_t *>(A.lut + (int)R.type * 256)[lane];
+                switch (R.k) {
+                case 1: eval_gate<1, kWindowLarge>(J, ob, R, g, L); break;
+                case 2: eval_gate<2, kWindowLarge>(J, ob, R, g, L); break;
+                case 3: eval_gate<3, kWindowLarge>(J, ob, R, g, L); break;
+                default: eval_gate<4, kWindowLarge>(J, ob, R, g, L); break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            // consumers whose last pending pin this was: queued with one atomic per batch
+            const int64_t f1 = A.fo_off[g + 1];
+            for (int64_t i0 = A.fo_off[g]; i0 < f1; i0 += 64) {
+                const int64_t i = i0 + lane;
+                const int32_t c = i < f1 ? A.fo[i] : -1;
+                const bool ready = c >= 0 && atomicSub(&A.pend[c], 1) == 1;
+                const uint64_t mask = __ballot(ready);
+                if (mask == 0) continue;
+                const int leader = __ffsll((unsigned long long)mask) - 1;
+                uint32_t base = 0;
+                if (lane == leader) base = atomicAdd(&A.ctl->tail, (uint32_t)__popcll(mask));
+                base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+                if (ready)
+                    __hip_atomic_store(A.queue + base + lanes_below(mask), c, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+    if (lane == 0 && reads > 0)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&st->pin_reads), (unsigned long long)reads);
 }
 
 // -------------------------------------------------------------------------
@@ -888,6 +1048,18 @@ hipError_t launch_eval_wave(const StepArgs &a, int large_window, const int64_t *
 hipError_t launch_eval_lane(const StepArgs &a, int64_t max_items, hipStream_t s) {
     if (max_items <= 0) return hipSuccess;
     eval_lane_kernel<<<dim3((unsigned)((max_items + 63) / 64)), dim3(64), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_df_init(const DfArgs &a, const int32_t *pend0, hipStream_t s) {
+    const int64_t n = a.G > 1 ? a.G : 1;
+    df_init_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(a, pend0);
+    return hipGetLastError();
+}
+
+hipError_t launch_dataflow(const DfArgs &a, int64_t n_waves, hipStream_t s) {
+    if (a.G <= 0 || n_waves <= 0) return hipSuccess;
+    dataflow_kernel<<<dim3((unsigned)n_waves), dim3(64), 0, s>>>(a);
     return hipGetLastError();
 }
 

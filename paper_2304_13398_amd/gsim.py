@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG, "libgsim.so")
 OK, E_ARG, E_CYCLE, E_WAVEFORM, E_OOM, E_DEVICE, E_HANDLE, E_OVERFLOW = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "OK", -1: "GSIM_E_ARG", -2: "GSIM_E_CYCLE", -3: "GSIM_E_WAVEFORM",
                 -4: "GSIM_E_OOM", -5: "GSIM_E_DEVICE", -6: "GSIM_E_HANDLE", -7: "GSIM_E_OVERFLOW"}
-OPT_ARENA_TRANSITIONS, OPT_KERNEL, OPT_KERNEL_TIMING, OPT_LANE_THRESHOLD = 1, 2, 4, 5
+OPT_ARENA_TRANSITIONS, OPT_KERNEL, OPT_KERNEL_TIMING, OPT_LANE_THRESHOLD, OPT_SCHEDULE = 1, 2, 4, 5, 6
 
 EXPORTED = ("sim_create", "sim_destroy", "sim_last_error", "sim_set_option", "sim_load_netlist",
             "sim_unload_netlist", "sim_set_netlist_option", "sim_netlist_info", "sim_submit", "sim_submit_device", "sim_run",

@@ -232,6 +232,46 @@ def make_stimulus(*, S, n_per_src, window, probs=(0.45, 0.45, 0.05, 0.05), seed=
     return Stimulus(off, t, v)
 
 
+def skewed_lengths(rng, S, mean, wcv, cap):
+    """Per-source transition counts with mean ``mean`` (so the total is
+    S * mean up to rounding) and a coefficient of variation near ``wcv``:
+    log-normal shape, its sigma found by bisection on the sample's own CV.
+    Counts are capped at ``cap`` (the distinct times of the window)."""
+    z = rng.standard_normal(S)
+
+    def lengths(sigma):
+        x = np.exp(sigma * (z - z.max()))  # scaled so the largest is 1: no overflow
+        n = np.minimum(np.rint(mean * S * x / x.sum()), cap).astype(np.int64)
+        return n
+
+    def cv(n):
+        return float(n.std() / n.mean()) if n.mean() > 0 else 0.0
+
+    lo, hi = 0.0, 8.0
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if cv(lengths(mid)) < wcv:
+            lo = mid
+        else:
+            hi = mid
+    return lengths(0.5 * (lo + hi))
+
+
+def make_stimulus_skewed(*, S, mean_per_src, wcv, window, probs=(0.45, 0.45, 0.05, 0.05),
+                         seed=1) -> Stimulus:
+    """Sources with uneven waveform lengths (the paper's WCV, Eq. 5: the
+    coefficient of variation of the given waveforms' lengths): counts from
+    ``skewed_lengths``, each source's times a uniform subset of [0, window]."""
+    r_n, r_t, r_v = _child_rngs(seed + 2_000_029, 3)
+    lengths = skewed_lengths(r_n, S, mean_per_src, wcv, window + 1)
+    t = np.concatenate([np.sort(r_t.choice(window + 1, size=int(n), replace=False))
+                        for n in lengths] + [np.zeros(0, dtype=np.int64)]).astype(np.int64)
+    v = _values_no_repeat(r_v, lengths, np.asarray(probs))
+    off = np.zeros(S + 1, dtype=np.int64)
+    np.cumsum(lengths, out=off[1:])
+    return Stimulus(off, t, v)
+
+
 # --------------------------------------------------------------------------
 # The benchmark configurations.
 
@@ -254,6 +294,14 @@ def config2_netlist(G=1_000_000, S=2048, L=60, seed=1):
 def config2(seed=1, G=1_000_000, S=2048, L=60, n_per_src=1000):
     nl = config2_netlist(G=G, S=S, L=L, seed=seed)
     st = make_stimulus(S=S, n_per_src=n_per_src, window=1_000_000, seed=seed)
+    return nl, st
+
+
+def config2_skewed(wcv, seed=1, G=1_000_000, S=2048, L=60, mean_per_src=1000):
+    """The mid netlist with uneven source activity: the same 2,048,000 given
+    transitions, per-source counts with coefficient of variation ``wcv``."""
+    nl = config2_netlist(G=G, S=S, L=L, seed=seed)
+    st = make_stimulus_skewed(S=S, mean_per_src=mean_per_src, wcv=wcv, window=1_000_000, seed=seed)
     return nl, st
 
 

@@ -30,3 +30,16 @@ def test_fingerprint_sees_order_and_values():
     assert base[1] == net_hash.mix(np.uint64(0))  # empty waveform
     assert net_hash.fingerprints(off, t, np.array([1, 2, 0], dtype=np.uint8))[0] != base[0]
     assert net_hash.fingerprints(off, np.array([1, 6, 9]), v)[0] != base[0]
+
+
+def test_skewed_lengths_hit_the_target_cv():
+    import numpy as np
+    from paper_2304_13398_amd import workloads as W
+    for wcv in (2.0, 5.0, 20.0):
+        st = W.make_stimulus_skewed(S=2048, mean_per_src=300, wcv=wcv, window=1_000_000, seed=3)
+        n = np.diff(st.off)
+        assert abs(n.std() / n.mean() - wcv) < 0.02 * wcv
+        assert abs(int(n.sum()) - 2048 * 300) < 2048
+        assert n.max() <= 1_000_001
+        again = W.make_stimulus_skewed(S=2048, mean_per_src=300, wcv=wcv, window=1_000_000, seed=3)
+        assert np.array_equal(st.t, again.t) and np.array_equal(st.v, again.v)

@@ -164,3 +164,31 @@ def test_request_loop_results_equal_alone(sim):
             assert np.array_equal(x.fingerprints, want[id(x.request.stim)]), loop.__name__
     for h in hs:
         sim.unload_netlist(h)
+
+
+def test_dependency_driven_batch_and_mix(sim):
+    """Jobs under the dependency-driven schedule: a batch of uneven sets and
+    jobs of two netlists submitted while others run; each equals the oracle."""
+    sim.set_option(G.OPT_SCHEDULE, 1)
+    try:
+        nl = W.config2_netlist(G=5000, S=40, L=25, seed=11)
+        nl2 = W.config3(G=4000, S=100, L=30, seed=12)[0]
+        h, h2 = sim.load_netlist(nl), sim.load_netlist(nl2)
+        rng = np.random.default_rng(11)
+        sets = [W.make_stimulus(S=nl.S, n_per_src=int(n), window=1_000_000, seed=300 + i)
+                for i, n in enumerate(W.loguniform_int(rng, 20, 800, size=5))]
+        jobs = sim.run_batch(h, sets)
+        st2 = W.make_stimulus(S=nl2.S, n_per_src=150, window=500_000, seed=399)
+        j2 = sim.submit(h2, st2)
+        sim.drive()
+        for j, st in zip(jobs, sets):
+            sim.wait(j)
+            assert same(fetch_gates(sim, j, nl), O.o1_simulate(nl, st))
+            sim.release(j)
+        sim.wait(j2)
+        assert same(fetch_gates(sim, j2, nl2), O.o1_simulate(nl2, st2))
+        sim.release(j2)
+        sim.unload_netlist(h)
+        sim.unload_netlist(h2)
+    finally:
+        sim.set_option(G.OPT_SCHEDULE, 0)

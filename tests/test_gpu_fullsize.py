@@ -132,10 +132,15 @@ def check_full_size(sim, nl, st, prefix_levels, n_sample=3000):
     sim.unload_netlist(h)
 
 
-def test_mid_full_size(sim):
+@pytest.mark.parametrize("schedule", [0, 1], ids=["levels", "dataflow"])
+def test_mid_full_size(sim, schedule):
     """1M gates, 2,048 PIs, 60 levels, 1,000 transitions per PI."""
     nl, st = W.config2()
-    check_full_size(sim, nl, st, prefix_levels=10)
+    sim.set_option(G.OPT_SCHEDULE, schedule)
+    try:
+        check_full_size(sim, nl, st, prefix_levels=10)
+    finally:
+        sim.set_option(G.OPT_SCHEDULE, 0)
 
 
 @pytest.mark.timeout(300)

@@ -1,4 +1,5 @@
-"""HIP path vs the CPU oracle O1, element by element, through the C ABI.
+"""HIP path vs the CPU oracle O1, element by element, through the C ABI,
+under both schedules (level by level; dependency-driven).
 
 Every comparison is exact (integer times and 2-bit values: tolerance 0).
 """
@@ -20,9 +21,13 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def sim():
+@pytest.fixture(scope="module", params=[0, 1], ids=["levels", "dataflow"])
+def sim(request):
+    """Every case runs under both schedules: level by level, and
+    dependency-driven (one persistent launch per job)."""
     s = G.Sim(0)
+    s.set_option(G.OPT_SCHEDULE, request.param)
+    say(f"schedule {request.param}")
     yield s
     s.close()
 
@@ -328,3 +333,11 @@ def test_fingerprints_match_oracle(sim):
     assert np.array_equal(sim.hashes(j, sub), got[sub])
     sim.release(j)
     sim.unload_netlist(h)
+
+
+@pytest.mark.parametrize("wcv", [4.0, 12.0])
+def test_skewed_source_activity(sim, wcv):
+    """Uneven source activity (coefficient of variation of the given lengths
+    as in the paper's WCV): heavy-tailed gate sizes, some silent sources."""
+    nl, st = W.config2_skewed(wcv, G=20_000, S=256, L=30, seed=5)
+    check(sim, nl, st)
