@@ -294,6 +294,30 @@ def bench_skewed(G, sim, nl, h, seed, wcvs=(5.0, 20.0), steps=3):
     return out
 
 
+def bench_windows(G, sim, nl, h, st, n_out_whole, ms_whole, n_windows=4):
+    """Exact time-window chunking of the mid job: device time and output
+    volume of the windows (each with its halo) against the whole job; the
+    windows' outputs inside their own ranges add up to the whole job's."""
+    from paper_2304_13398_amd import windows as WN
+    H = WN.window_halo(nl)
+    inner = WN.window_bounds(st, n_windows)
+    edges = [None] + inner + [None]
+    dev_ms, n_out = 0.0, 0
+    for k in range(len(edges) - 1):
+        lo, hi = edges[k], edges[k + 1]
+        sub = WN.window_stimulus(st, nl.S, 0 if lo is None else max(0, lo - H),
+                                 np.iinfo(np.int64).max if hi is None else hi)
+        j = sim.run(h, sub)
+        sim.wait(j)
+        s = sim.stats(j)
+        dev_ms += s.device_ms
+        n_out += s.n_out
+        sim.release(j)
+    return {"windows": len(edges) - 1, "halo_ps": H, "device_ms_sum": dev_ms,
+            "device_ms_whole": ms_whole, "n_out_sum": int(n_out), "n_out_whole": int(n_out_whole),
+            "overhead": dev_ms / ms_whole - 1.0}
+
+
 def workload_stats(nl, lengths):
     """The paper's workload statistics (Table 2 columns and Eq. 5): coefficient
     of variation of the given (source) waveform lengths and of the generated
@@ -515,6 +539,8 @@ def main():
                       f"({n_gates} gates, {int(o_off[-1])} output transitions, {cpu_s:.1f}s)",
         }
     sim.set_option(G.OPT_KERNEL_TIMING, 0)
+    out["time_windows"] = bench_windows(G, sim, nl, h, st, n_out, dev_ms)
+    print(f"[bench] time windows: {out['time_windows']}", file=sys.stderr, flush=True)
     if not args.no_skewed:
         out["skewed"] = bench_skewed(G, sim, nl, h, args.seed)
     if not args.no_tiny:

@@ -192,3 +192,19 @@ def test_dependency_driven_batch_and_mix(sim):
         sim.unload_netlist(h2)
     finally:
         sim.set_option(G.OPT_SCHEDULE, 0)
+
+
+@pytest.mark.parametrize("n_windows", [3, 8])
+def test_time_windows_on_the_gpu_equal_the_oracle(sim, n_windows):
+    """A job cut into exact time windows (halo from the netlist's delays), each
+    window run on the GPU, the pieces concatenated: equal to the oracle's run
+    of the whole job."""
+    from paper_2304_13398_amd import windows as WN
+    nl, st = W.config3(G=6000, S=150, L=30, n_per_src=120, seed=13)
+    run, close = WN.gpu_engine(sim, nl)
+    try:
+        got = WN.simulate_windowed(nl, st, run, n_windows)
+    finally:
+        close()
+    say(f"windows: {n_windows}, halo {WN.window_halo(nl)} ps")
+    assert same(got, O.o1_simulate(nl, st))
