@@ -444,13 +444,15 @@ constexpr int kRing = 32;  // steps whose descriptors may be in flight
 // jobs in the same launches.
 struct Executor {
     hipStream_t stream = nullptr;
-    uint32_t *d_counts = nullptr;  // 2 x kNumLists list lengths (this step / next step)
+    uint32_t *d_counts = nullptr;  // 2 x kCountWords step counters (this step / next step)
     int parity = 0;
     JobDesc *d_jobs = nullptr;
     int64_t jobs_cap = 0;
     int64_t *d_blocksum = nullptr;
     int64_t blocksum_cap = 0;
     uint64_t *d_list = nullptr;    // kNumLists lists of list_cap entries
+    uint64_t *d_keys = nullptr;    // kListLane key arrays of list_cap entries
+    uint64_t *d_sorted = nullptr;  // 2 sorted lists of list_cap entries
     int64_t list_cap = 0;
     JobDesc *h_ring = nullptr;     // pinned [kRing][kMaxJobsPerStep]
     hipEvent_t ring_ev[kRing] = {};
@@ -650,11 +652,11 @@ Failure get_executor(gsim_ctx ctx, hipStream_t stream, Executor **out) {
     }
     auto ex = std::make_unique<Executor>();
     ex->stream = stream;
-    ex->d_counts = pool_get<uint32_t>(*ctx->pool, 2 * kNumLists);
+    ex->d_counts = pool_get<uint32_t>(*ctx->pool, 2 * kCountWords);
     if (!ex->d_counts) return fail(GSIM_E_OOM, "no device memory for the executor");
     HIP_TRY(hipHostMalloc((void **)&ex->h_ring, sizeof(JobDesc) * kRing * kMaxJobsPerStep, hipHostMallocDefault));
     for (int i = 0; i < kRing; i++) HIP_TRY(hipEventCreateWithFlags(&ex->ring_ev[i], hipEventDisableTiming));
-    HIP_TRY(launch_clear_u32(ex->d_counts, 2 * kNumLists, stream));
+    HIP_TRY(launch_clear_u32(ex->d_counts, 2 * kCountWords, stream));
     *out = ex.get();
     ctx->executors[stream] = std::move(ex);
     return kOk;
@@ -667,6 +669,8 @@ void destroy_executor(gsim_ctx ctx, Executor *ex) {
     pool.put(ex->d_jobs);
     pool.put(ex->d_blocksum);
     pool.put(ex->d_list);
+    pool.put(ex->d_keys);
+    pool.put(ex->d_sorted);
     if (ex->h_ring) (void)hipHostFree(ex->h_ring);
     for (int i = 0; i < kRing; i++)
         if (ex->ring_ev[i]) (void)hipEventDestroy(ex->ring_ev[i]);
@@ -683,6 +687,31 @@ Failure ensure_cap(gsim_ctx ctx, Executor *ex, T *&buf, int64_t &cap, int64_t ne
     ctx->pool->put(buf);
     buf = nbuf;
     cap = ncap;
+    return kOk;
+}
+
+// Work lists, their keys and the two sorted lists, for `items` gates per step.
+Failure ensure_lists(gsim_ctx ctx, Executor *ex, int64_t items) {
+    if (items <= ex->list_cap) return kOk;
+    const int64_t L = std::max<int64_t>(items, std::max<int64_t>(2 * ex->list_cap, 1024));
+    Pool &pool = *ctx->pool;
+    uint64_t *nlist = pool_get<uint64_t>(pool, kNumLists * L);
+    uint64_t *nkeys = pool_get<uint64_t>(pool, kListLane * L);
+    uint64_t *nsorted = pool_get<uint64_t>(pool, 2 * L);
+    if (!nlist || !nkeys || !nsorted) {
+        pool.put(nlist);
+        pool.put(nkeys);
+        pool.put(nsorted);
+        return fail(GSIM_E_OOM, "no device memory for step work lists (%lld entries)", (long long)L);
+    }
+    HIP_TRY(hipStreamSynchronize(ex->stream));  // queued steps may still read the old lists
+    pool.put(ex->d_list);
+    pool.put(ex->d_keys);
+    pool.put(ex->d_sorted);
+    ex->d_list = nlist;
+    ex->d_keys = nkeys;
+    ex->d_sorted = nsorted;
+    ex->list_cap = L;
     return kOk;
 }
 
@@ -885,11 +914,7 @@ Failure admit(gsim_ctx ctx, Executor *ex, Job *j) {
         items += nl.max_level_n;
         Failure f = ensure_cap(ctx, ex, ex->d_jobs, ex->jobs_cap, (int64_t)ex->active.size() + 1);
         if (f.st == GSIM_OK) f = ensure_cap(ctx, ex, ex->d_blocksum, ex->blocksum_cap, sblocks);
-        if (f.st == GSIM_OK && items > ex->list_cap) {
-            int64_t cap = ex->list_cap * kNumLists;
-            f = ensure_cap(ctx, ex, ex->d_list, cap, kNumLists * items);
-            ex->list_cap = cap / kNumLists;
-        }
+        if (f.st == GSIM_OK) f = ensure_lists(ctx, ex, items);
         if (f.st != GSIM_OK) return f;
     }
     j->n_partial = std::max<int64_t>(1, std::min<int64_t>(1024, (nl.G + 255) / 256));
@@ -1021,11 +1046,7 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
     }
     Failure f = ensure_cap(ctx, ex, ex->d_jobs, ex->jobs_cap, n);
     if (f.st == GSIM_OK) f = ensure_cap(ctx, ex, ex->d_blocksum, ex->blocksum_cap, n_sblocks);
-    if (f.st == GSIM_OK && n_items > ex->list_cap) {
-        int64_t cap = ex->list_cap * kNumLists;
-        f = ensure_cap(ctx, ex, ex->d_list, cap, kNumLists * n_items);
-        ex->list_cap = cap / kNumLists;
-    }
+    if (f.st == GSIM_OK) f = ensure_lists(ctx, ex, n_items);
     if (f.st != GSIM_OK) return f;
     hipStream_t s = ex->stream;
     HIP_TRY(hipMemcpyAsync(ex->d_jobs, desc, sizeof(JobDesc) * (size_t)n, hipMemcpyHostToDevice, s));
@@ -1038,11 +1059,14 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
     a.n_sblocks = n_sblocks;
     a.blocksum = ex->d_blocksum;
     for (int c = 0; c < kNumLists; c++) a.list[c] = ex->d_list + (size_t)c * ex->list_cap;
-    a.count = ex->d_counts + ex->parity * kNumLists;
-    a.next_count = ex->d_counts + (1 - ex->parity) * kNumLists;
+    for (int c = 0; c < kListLane; c++) a.key[c] = ex->d_keys + (size_t)c * ex->list_cap;
+    for (int w = 0; w < 2; w++) a.sorted[w] = ex->d_sorted + (size_t)w * ex->list_cap;
+    a.count = ex->d_counts + ex->parity * kCountWords;
+    a.next_count = ex->d_counts + (1 - ex->parity) * kCountWords;
     a.lut = ctx->d_lut;
     HIP_TRY(launch_size(a, s));
     HIP_TRY(launch_level_scan(a, s));
+    HIP_TRY(launch_sort_lists(a, n_list, s));
     std::shared_ptr<StepTiming> tm;
     if (ctx->opt_timing) {
         tm = std::make_shared<StepTiming>();

@@ -41,6 +41,17 @@ constexpr int kListLane = 8;
 __host__ __device__ constexpr int wave_list(int large_window, int pins) {
     return large_window * 4 + pins - 1;
 }
+// Dispatch order of the wavefront lists: each gate gets a segment by its
+// estimated cost (half-octave buckets of w_g times a per-pin-count weight,
+// costliest first, then pin count), a counting sort by segment gives one
+// sorted list per delay window, and the evaluate launch takes it in order
+// (longest jobs first, so the short ones fill the tail of the level).
+constexpr int kCostBuckets = 32;
+constexpr int kSegments = kCostBuckets * 4;  // per delay window
+// Per-step counters: list lengths, segment sizes of both windows, sorted totals.
+constexpr int kSegCountAt = kNumLists;
+constexpr int kSortedTotalAt = kSegCountAt + 2 * kSegments;
+constexpr int kCountWords = kSortedTotalAt + 2;
 
 // One gate, 64 bytes, in level order. Nets are internal ids: sources keep
 // their id, the gate at internal position i drives net S + i.
@@ -92,8 +103,10 @@ struct StepArgs {
     int64_t n_sblocks;       // sizing blocks over all jobs
     int64_t *blocksum;       // [n_sblocks]: block totals, then absolute arena bases
     uint64_t *list[kNumLists];  // work lists: job << 32 | gate
-    uint32_t *count;         // [kNumLists] list lengths of this step
-    uint32_t *next_count;    // [kNumLists] list lengths of the next step (cleared here)
+    uint64_t *key[kListLane];   // per wavefront-list entry: segment << 32 | rank in segment
+    uint64_t *sorted[2];        // per delay window: the wavefront entries in dispatch order
+    uint32_t *count;         // [kCountWords] counters of this step (see kSegCountAt)
+    uint32_t *next_count;    // [kCountWords] counters of the next step (cleared here)
     const uint8_t *lut;      // [12][256] gate value by packed pin values
 };
 
@@ -131,6 +144,9 @@ hipError_t launch_level_scan(const StepArgs &a, hipStream_t s);
 // (max_items[k-1]: upper bound of the k-pin list's length).
 hipError_t launch_eval_wave(const StepArgs &a, int large_window, const int64_t *max_items,
                             hipStream_t s);
+// Counting-sort scatter of the wavefront lists into the two sorted lists
+// (max_items[c]: upper bound of list c's length, c < kListLane).
+hipError_t launch_sort_lists(const StepArgs &a, const int64_t *max_items, hipStream_t s);
 hipError_t launch_eval_lane(const StepArgs &a, int64_t max_items, hipStream_t s);
 // Dependency-driven schedule: reset the counters and queue, then run every
 // gate of the job with n_waves persistent wavefronts.

@@ -92,20 +92,42 @@ __device__ __forceinline__ int job_of_block(const JobDesc *jobs, int n_jobs, int
     return lo;
 }
 
+// Segment of a wavefront gate in the dispatch order: half-octave bucket of
+// its estimated cost w_g * weight (relative cost per input transition by
+// pin count, from the rounds' fill and length), costliest first, then pin
+// count from four down.
+__device__ __forceinline__ uint32_t cost_segment(int64_t w, int k) {
+    const uint64_t weight = k == 1 ? 2 : k == 2 ? 3 : k == 3 ? 5 : 4;
+    const uint64_t est = (uint64_t)(w > 0 ? w : 1) * weight;
+    const int lg = 63 - __clzll((long long)est);
+    const int half = lg > 0 ? (int)((est >> (lg - 1)) & 1u) : 0;
+    int bucket = 2 * lg + half - 16;
+    bucket = bucket < 0 ? 0 : bucket > kCostBuckets - 1 ? kCostBuckets - 1 : bucket;
+    return (uint32_t)((kCostBuckets - 1 - bucket) * 4 + (4 - k));
+}
+
 // Per-level sizing and binning: w_g (the sum of the gate's input lengths, an
 // upper bound of its output length), its block-local exclusive scan, and the
 // gate's work list -- lane kernel if its largest delay exceeds the large
 // window or it reads fewer than lane_threshold transitions, else the
-// wavefront kernel of its delay window and pin count -- appended to that list.
+// wavefront kernel of its delay window and pin count -- appended to that list,
+// with its segment in the dispatch order and its rank in that segment.
 __global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
+    static_assert(2 * kSegments == kSizeBlock, "one thread per segment of both windows");
     __shared__ int64_t wsum[kSizeBlock / 64];
+    __shared__ uint32_t l_cnt[kNumLists], l_base[kNumLists];
+    __shared__ uint32_t s_cnt[2 * kSegments], s_base[2 * kSegments];
     const int64_t b = blockIdx.x;
+    const int t = threadIdx.x;
+    s_cnt[t] = 0;
+    if (t < kNumLists) l_cnt[t] = 0;
     const int j = job_of_block(A.jobs, A.n_jobs, b);
     const JobDesc &J = A.jobs[j];
-    const int64_t i = (b - J.sblock_begin) * kSizeBlock + threadIdx.x;
+    const int64_t i = (b - J.sblock_begin) * kSizeBlock + t;
     const int64_t g = J.lvl_begin + i;
     int64_t w = 0;
     int cls = -1;
+    uint32_t seg_key = 0;  // window * kSegments + segment, for wavefront gates
     if (i < J.n_gates) {
         const GateRec &r = J.rec[g];
         const int k = r.k;
@@ -114,8 +136,9 @@ __global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
             if (p < k) w += J.len[r.net[p]];
         cls = (r.dmax > kWindowLarge || w < J.lane_threshold) ? kListLane
               : wave_list(r.dmax > kWindowSmall ? 1 : 0, k);
+        if (cls != kListLane) seg_key = (uint32_t)(cls / 4) * kSegments + cost_segment(w, k);
     }
-    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int lane = lane_id(), wv = t >> 6;
     int64_t x = w;
 #pragma unroll
     for (int s = 1; s < 64; s <<= 1) {
@@ -125,18 +148,25 @@ __global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
         if (lane >= s) x += o;
     }
     if (lane == 63) wsum[wv] = x;
-#pragma unroll
-    for (int c = 0; c < kNumLists; c++) {
-        const uint64_t mask = __ballot(cls == c);
-        if (mask == 0) continue;
-        const int leader = __ffsll((unsigned long long)mask) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&A.count[c], (uint32_t)__popcll(mask));
-        base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
-        if (cls == c) A.list[c][base + lanes_below(mask)] = ((uint64_t)(uint32_t)j << 32) | (uint64_t)g;
-    }
-    if (b == 0 && threadIdx.x < kNumLists) A.next_count[threadIdx.x] = 0;
+    if (b == 0)
+        for (int q = t; q < kCountWords; q += kSizeBlock) A.next_count[q] = 0;
     __syncthreads();
+    // list positions and segment ranks: block-local (LDS atomics), then one
+    // global atomic per list and per segment the block touches
+    const bool wave_gate = cls >= 0 && cls != kListLane;
+    uint32_t lpos = 0, spos = 0;
+    if (cls >= 0) lpos = atomicAdd(&l_cnt[cls], 1u);
+    if (wave_gate) spos = atomicAdd(&s_cnt[seg_key], 1u);
+    __syncthreads();
+    if (t < kNumLists && l_cnt[t]) l_base[t] = atomicAdd(&A.count[t], l_cnt[t]);
+    if (s_cnt[t]) s_base[t] = atomicAdd(&A.count[kSegCountAt + t], s_cnt[t]);
+    __syncthreads();
+    if (cls >= 0) {
+        const uint32_t pos = l_base[cls] + lpos;
+        A.list[cls][pos] = ((uint64_t)(uint32_t)j << 32) | (uint64_t)g;
+        if (wave_gate)
+            A.key[cls][pos] = ((uint64_t)(seg_key % kSegments) << 32) | (uint64_t)(s_base[seg_key] + spos);
+    }
     int64_t before = 0, total = 0;
 #pragma unroll
     for (int q = 0; q < kSizeBlock / 64; q++) {
@@ -144,7 +174,7 @@ __global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
         total += wsum[q];
     }
     if (i < J.n_gates) J.off[J.S + g] = before + x - w;
-    if (threadIdx.x == 0) A.blocksum[b] = total;
+    if (t == 0) A.blocksum[b] = total;
 }
 
 // One block per job: the job's block totals -> absolute arena bases; bump the
@@ -192,6 +222,44 @@ __global__ __launch_bounds__(1024) void level_scan_kernel(StepArgs A) {
             state->pin_reads += used;
             state->arena_top = top;
         }
+    }
+}
+
+// -------------------------------------------------------------------------
+// Counting-sort scatter of the wavefront lists: entry (c, pos) goes to
+// sorted[window][base of its segment + its rank]. The segment bases are an
+// exclusive scan of the segment sizes per window, redone by every block.
+struct ListBounds {
+    int64_t cum[kListLane + 1];  // cumulative upper bounds of the list lengths
+};
+
+__global__ __launch_bounds__(2 * kSegments) void sort_lists_kernel(StepArgs A, ListBounds lb) {
+    static_assert(2 * kSegments == 256, "one thread per segment of both windows");
+    __shared__ uint32_t seg_base[2 * kSegments];
+    __shared__ uint32_t wave_tot[4];
+    const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
+    const uint32_t cnt = A.count[kSegCountAt + t];
+    uint32_t x = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_up((int)x, d, 64);
+        if (lane >= d) x += o;
+    }
+    if (lane == 63) wave_tot[wv] = x;
+    __syncthreads();
+    // windows: waves 0-1 and 2-3
+    seg_base[t] = x - cnt + ((wv & 1) ? wave_tot[wv - 1] : 0u);
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + t;
+    int c = 0;
+#pragma unroll
+    for (int q = 1; q < kListLane; q++)
+        if (i >= lb.cum[q]) c = q;
+    const int64_t p = i - lb.cum[c];
+    if (i < lb.cum[kListLane] && p < (int64_t)A.count[c]) {
+        const uint64_t key = A.key[c][p];
+        const int win = c / 4;
+        A.sorted[win][seg_base[win * kSegments + (int)(key >> 32)] + (uint32_t)key] = A.list[c][p];
     }
 }
 
@@ -649,12 +717,19 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
     }
 }
 
-// One wavefront per work-list entry.
-template <int W, int K>
-__device__ __forceinline__ void eval_item(const StepArgs &A, int list, int64_t item, WaveLds<W> &L) {
+// Every gate of the step whose largest delay is at most W, in one launch, one
+// wavefront per entry of the window's sorted list (costliest first).
+template <int W>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void eval_wave_kernel(StepArgs A,
+                                                                                              int win) {
+    __shared__ WaveLds<W> L;
     const int lane = lane_id();
-    if (item >= (int64_t)A.count[list]) return;
-    const uint64_t e = A.list[list][item];
+    const int64_t item = blockIdx.x;
+    const int list0 = win * 4;
+    const int64_t total = (int64_t)A.count[list0] + A.count[list0 + 1] + A.count[list0 + 2] +
+                          A.count[list0 + 3];
+    if (item >= total) return;
+    const uint64_t e = A.sorted[win][item];
     const JobDesc &J = A.jobs[(int)(e >> 32)];
     const int64_t gate = (int64_t)(uint32_t)e;
     const GateRec R = J.rec[gate];
@@ -665,22 +740,12 @@ __device__ __forceinline__ void eval_item(const StepArgs &A, int list, int64_t i
     reinterpret_cast<uint32_t *>(L.lut)[lane] =
         reinterpret_cast<const uint32_t *>(A.lut + (int)R.type * 256)[lane];
     const int64_t ob = A.blocksum[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + J.off[J.S + gate];
-    eval_gate<K, W>(J, ob, R, gate, L);
-}
-
-// Every gate of the step whose largest delay is at most W, in one launch:
-// blocks [0, c4) take the four-pin list, [c4, c3) the three-pin list,
-// [c3, c2) the two-pin list and the rest the one-pin list (costliest gates
-// first, so the cheap ones fill the tail).
-template <int W>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void eval_wave_kernel(
-    StepArgs A, int list0, int64_t c4, int64_t c3, int64_t c2) {
-    __shared__ WaveLds<W> L;
-    const int64_t b = blockIdx.x;
-    if (b < c4) eval_item<W, 4>(A, list0 + 3, b, L);
-    else if (b < c3) eval_item<W, 3>(A, list0 + 2, b - c4, L);
-    else if (b < c2) eval_item<W, 2>(A, list0 + 1, b - c3, L);
-    else eval_item<W, 1>(A, list0, b - c2, L);
+    switch (R.k) {
+    case 1: eval_gate<1, W>(J, ob, R, gate, L); break;
+    case 2: eval_gate<2, W>(J, ob, R, gate, L); break;
+    case 3: eval_gate<3, W>(J, ob, R, gate, L); break;
+    default: eval_gate<4, W>(J, ob, R, gate, L); break;
+    }
 }
 
 // -------------------------------------------------------------------------
@@ -1034,14 +1099,22 @@ hipError_t launch_level_scan(const StepArgs &a, hipStream_t s) {
 
 hipError_t launch_eval_wave(const StepArgs &a, int large_window, const int64_t *max_items,
                             hipStream_t s) {
-    const int64_t c4 = max_items[3], c3 = c4 + max_items[2], c2 = c3 + max_items[1];
-    const int64_t total = c2 + max_items[0];
+    const int64_t total = max_items[0] + max_items[1] + max_items[2] + max_items[3];
     if (total <= 0) return hipSuccess;
-    const int list0 = wave_list(large_window, 1);
     if (large_window)
-        eval_wave_kernel<kWindowLarge><<<dim3((unsigned)total), dim3(64), 0, s>>>(a, list0, c4, c3, c2);
+        eval_wave_kernel<kWindowLarge><<<dim3((unsigned)total), dim3(64), 0, s>>>(a, 1);
     else
-        eval_wave_kernel<kWindowSmall><<<dim3((unsigned)total), dim3(64), 0, s>>>(a, list0, c4, c3, c2);
+        eval_wave_kernel<kWindowSmall><<<dim3((unsigned)total), dim3(64), 0, s>>>(a, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_lists(const StepArgs &a, const int64_t *max_items, hipStream_t s) {
+    ListBounds lb;
+    lb.cum[0] = 0;
+    for (int c = 0; c < kListLane; c++) lb.cum[c + 1] = lb.cum[c] + max_items[c];
+    if (lb.cum[kListLane] <= 0) return hipSuccess;
+    const int64_t blocks = (lb.cum[kListLane] + 2 * kSegments - 1) / (2 * kSegments);
+    sort_lists_kernel<<<dim3((unsigned)blocks), dim3(2 * kSegments), 0, s>>>(a, lb);
     return hipGetLastError();
 }
 
