@@ -324,7 +324,7 @@ __device__ __forceinline__ uint32_t wave_shift_down(uint32_t identity, uint32_t 
 // previous survivor's (X before the first).
 //
 // The wave walks the inputs in rounds of up to 512 transitions (T = 512/K
-// per pin, 128 for three pins). The round's horizon H is the smallest
+// per pin; 192, 192 and 128 for three pins). The round's horizon H is the smallest
 // last-loaded time over pins that have more transitions beyond their tile,
 // capped so the round spans less than 2^28 ps; every input transition at or
 // before H is in the round. In-round inputs are 32-bit keys
@@ -333,8 +333,9 @@ __device__ __forceinline__ uint32_t wave_shift_down(uint32_t identity, uint32_t 
 // time group does not matter). The merge is done per lane:
 // lane l owns merged positions [8l, 8l + 8), finds where they start in the
 // two sorted lists it merges by a merge-path search, and takes the 8
-// smallest of the next 8 of each list with a bitonic network (four pins:
-// two pairwise merges through LDS, then one more). Pin values after each
+// smallest of the next 8 of each list with a bitonic network (three pins:
+// the first two merged through LDS, then with the third; four pins: two
+// pairwise merges through LDS, then one more). Pin values after each
 // merged transition come from a wave scan of "set pin p to v" updates; a
 // transition ends a time group when the next one has another time; the
 // group's candidate takes its delay from a per-gate table indexed by new
@@ -352,7 +353,7 @@ template <int W>
 struct WaveLds {
     uint32_t seq[W + kRoundSlots + 32];  // tentative survivors [0, nq), then this round's;
                                          // the pairwise-merge buffers alias seq[W, W + kMergeBuf)
-    uint32_t tile[kRoundSlots + 4 * (kMergePad + 1)];  // K x [guard, T keys, 8 INF]
+    uint32_t tile[kRoundSlots + 4 * (kMergePad + 1)];  // K x [guard, T(p) keys, 8 INF]
     uint32_t dtab[48];                   // min delay by (new value, set of changed pins)
     uint8_t lut[256];
 };
@@ -360,9 +361,11 @@ static_assert(kMergeBuf <= kRoundSlots + 32, "merge buffers must fit the survivo
 
 template <int K>
 struct Tiling {
-    static constexpr int T = K == 1 ? 512 : K == 2 ? 256 : 128;  // transitions per pin per round
-    static constexpr int E = T / 64;                              // per lane per pin
-    static constexpr int STRIDE = T + 1 + kMergePad;              // tile stride in LDS
+    // transitions per pin per round; tile p of LDS is [guard, T(p) keys, 8 INF]
+    static constexpr int T(int p) { return K == 1 ? 512 : K == 2 ? 256 : K == 3 ? (p < 2 ? 192 : 128) : 128; }
+    static constexpr int E(int p) { return T(p) / 64; }  // per lane
+    static constexpr int EMAX = T(0) / 64;
+    static constexpr int OFF(int p) { return p == 0 ? 0 : OFF(p - 1) + T(p - 1) + 1 + kMergePad; }
 };
 static_assert(kRoundSlots == 512, "tiling assumes 512-transition rounds");
 
@@ -440,8 +443,7 @@ template <int K, int W>
 __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const GateRec &R,
                                           int64_t gate, WaveLds<W> &L) {
     using Tl = Tiling<K>;
-    constexpr int T = Tl::T, E = Tl::E, ST = Tl::STRIDE;
-    constexpr int NIT1 = K == 2 ? 9 : 8;  // split range of the first merge: <= T
+    constexpr int EM = Tl::EMAX;
     const int lane = lane_id();
     const int64_t S = J.S;
     int64_t *len = J.len;
@@ -462,16 +464,19 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
     for (int p = 0; p < K; p++) state0 |= (uint32_t)kX << (2 * p);
 
     // tiles are loaded from a uniform base with 32-bit lane offsets
-    uint64_t pre[K][E];
+    uint64_t pre[K][EM];
 #pragma unroll
     for (int p = 0; p < K; p++) {
         const uint64_t *src = Kar + pb[p];
-        const int lim = (int)min64(pl[p], (int64_t)T);
+        const int lim = (int)min64(pl[p], (int64_t)Tl::T(p));
 #pragma unroll
-        for (int e = 0; e < E; e++) pre[p][e] = lane + 64 * e < lim ? src[lane + 64 * e] : kNoKey;
+        for (int e = 0; e < EM; e++)
+            if (e < Tl::E(p)) pre[p][e] = lane + 64 * e < lim ? src[lane + 64 * e] : kNoKey;
     }
     // INF keys after each tile; the delay table
-    if (lane < K * kMergePad) L.tile[(lane / kMergePad) * ST + 1 + T + lane % kMergePad] = kNoKey32;
+#pragma unroll
+    for (int p = 0; p < K; p++)
+        if (lane < kMergePad) L.tile[Tl::OFF(p) + 1 + Tl::T(p) + lane] = kNoKey32;
     if (lane < 48) {
         const uint32_t ev = (uint32_t)lane >> 4, mask = (uint32_t)lane & 15u;
         int32_t d = INT32_MAX;
@@ -489,7 +494,7 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
     int64_t base_prev = 0;
     int64_t out_n = 0;
     uint32_t *const AB = L.seq + W + 1;                    // pairwise merges (K >= 3)
-    uint32_t *const CD = AB + 256 + kMergePad + 1;
+    uint32_t *const CD = AB + 256 + kMergePad + 1;         // (K == 4)
 
     for (;;) {
         int64_t rem[K];
@@ -505,7 +510,7 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         int64_t H = kInf, base = kInf;
 #pragma unroll
         for (int p = 0; p < K; p++) {
-            if (rem[p] > T) H = min64(H, key_time(readlane_u64(pre[p][E - 1], 63)));
+            if (rem[p] > Tl::T(p)) H = min64(H, key_time(readlane_u64(pre[p][Tl::E(p) - 1], 63)));
             if (rem[p] > 0) base = min64(base, key_time(readlane_u64(pre[p][0], 0)));
         }
         if (nq > 0) {
@@ -521,26 +526,28 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
 #pragma unroll
         for (int p = 0; p < K; p++) {
             m[p] = 0;
-            const int lim = (int)min64(rem[p], (int64_t)T);
+            const int lim = (int)min64(rem[p], (int64_t)Tl::T(p));
 #pragma unroll
-            for (int e = 0; e < E; e++) {
+            for (int e = 0; e < EM; e++) {
+                if (e >= Tl::E(p)) continue;
                 const uint64_t key = pre[p][e];
                 const bool in = lane + 64 * e < lim && key <= hkey;
                 m[p] += __popcll(__ballot(in));
                 // (t - base) << 2 | v < 2^30 equals the low word of key - (base << 2)
-                L.tile[p * ST + 1 + 64 * e + lane] = in ? (((uint32_t)key - base4) << 2) | (uint32_t)p : kNoKey32;
+                L.tile[Tl::OFF(p) + 1 + 64 * e + lane] = in ? (((uint32_t)key - base4) << 2) | (uint32_t)p : kNoKey32;
             }
             all_in = all_in && m[p] == rem[p];
         }
         // split horizon: with every remaining input in this round, all survivors are final
         const uint32_t hsplit = all_in ? kNoKey32 : (uint32_t)(H - base) << 2 | 3u;
-        uint64_t nxt[K][E];
+        uint64_t nxt[K][EM];
 #pragma unroll
         for (int p = 0; p < K; p++) {
             const uint64_t *src = Kar + pb[p] + cur[p] + m[p];
-            const int lim = (int)min64(rem[p] - m[p], (int64_t)T);
+            const int lim = (int)min64(rem[p] - m[p], (int64_t)Tl::T(p));
 #pragma unroll
-            for (int e = 0; e < E; e++) nxt[p][e] = lane + 64 * e < lim ? src[lane + 64 * e] : kNoKey;
+            for (int e = 0; e < EM; e++)
+                if (e < Tl::E(p)) nxt[p][e] = lane + 64 * e < lim ? src[lane + 64 * e] : kNoKey;
         }
         __syncthreads();
 
@@ -550,21 +557,33 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
 #pragma unroll
             for (int k = 0; k < 8; k++) mk[k] = L.tile[1 + 8 * lane + k];
         } else if constexpr (K == 2) {
-            merge8<9>(L.tile + 1, m[0], L.tile + ST + 1, m[1], 8 * lane, mk);
+            merge8<9>(L.tile + Tl::OFF(0) + 1, m[0], L.tile + Tl::OFF(1) + 1, m[1], 8 * lane, mk);
+        } else if constexpr (K == 3) {
+            // pins 0 and 1 (192 each) into AB by lanes 0-47, then AB with pin 2's tile
+            if (lane < 48) {
+                uint32_t h[8];
+                merge8<8>(L.tile + Tl::OFF(0) + 1, m[0], L.tile + Tl::OFF(1) + 1, m[1], 8 * lane, h);
+#pragma unroll
+                for (int k = 0; k < 8; k++) AB[8 * lane + k] = h[k];
+            } else if (lane < 48 + kMergePad) {
+                AB[384 + lane - 48] = kNoKey32;
+            }
+            __syncthreads();
+            merge8<8>(AB, m[0] + m[1], L.tile + Tl::OFF(2) + 1, m[2], 8 * lane, mk);
         } else {
             const bool hi_half = lane >= 32;
-            const uint32_t *A = L.tile + (hi_half ? 2 * ST : 0) + 1;
-            const uint32_t *B = K == 4 ? A + ST : (hi_half ? A + T : A + ST);  // 3 pins: C with nothing
+            const uint32_t *A = L.tile + (hi_half ? Tl::OFF(2) : Tl::OFF(0)) + 1;
+            const uint32_t *B = L.tile + (hi_half ? Tl::OFF(3) : Tl::OFF(1)) + 1;
             const int a = hi_half ? m[2] : m[0];
-            const int b = hi_half ? (K == 4 ? m[K - 1] : 0) : m[1];
+            const int b = hi_half ? m[K - 1] : m[1];
             uint32_t h[8];
-            merge8<NIT1>(A, a, B, b, 8 * (lane & 31), h);
+            merge8<8>(A, a, B, b, 8 * (lane & 31), h);
             uint32_t *dst = (hi_half ? CD : AB) + 8 * (lane & 31);
 #pragma unroll
             for (int k = 0; k < 8; k++) dst[k] = h[k];
             if (lane < 2 * kMergePad) (lane < kMergePad ? AB : CD)[256 + (lane % kMergePad)] = kNoKey32;
             __syncthreads();
-            merge8<9>(AB, m[0] + m[1], CD, m[2] + (K == 4 ? m[K - 1] : 0), 8 * lane, mk);
+            merge8<9>(AB, m[0] + m[1], CD, m[2] + m[K - 1], 8 * lane, mk);
         }
 
         // ---- pin states: this lane's composed update, scanned over the wave
@@ -703,7 +722,8 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         for (int p = 0; p < K; p++) {
             cur[p] += m[p];
 #pragma unroll
-            for (int e = 0; e < E; e++) pre[p][e] = nxt[p][e];
+            for (int e = 0; e < EM; e++)
+                if (e < Tl::E(p)) pre[p][e] = nxt[p][e];
         }
         __syncthreads();
     }
