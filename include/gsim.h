@@ -193,7 +193,9 @@ gsim_status sim_run_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_o
  * receives the job handles. All sets that fit the budget run together, level
  * by level, in shared launches; the others are admitted as released jobs free
  * memory (wait, fetch and release in submission order when the sets do not all
- * fit). Errors as sim_submit; on error no job is created. */
+ * fit). Sets are admitted first fit in the order given: a caller that releases
+ * jobs as they finish can pass the largest sets first, so they do not run
+ * alone at the end. Errors as sim_submit; on error no job is created. */
 gsim_status sim_run_batch(gsim_ctx ctx, gsim_netlist nl, int32_t n_sets,
                           const int64_t *const *src_off, const int64_t *const *t,
                           const uint8_t *const *v, void *hip_stream, gsim_job *out);
