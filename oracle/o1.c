@@ -427,3 +427,155 @@ int o1_simulate_fingerprints(int64_t S, int64_t G, const uint8_t *type, const in
     free(order); free(readers_left); free(w);
     return rc;
 }
+
+/* ------------------------------------------------------------------------
+ * Extended cell model (Section 2.3, delays of gates; Section 3.2, the delay
+ * matrix; Section 3.3, module functions). Test infrastructure, like the rest
+ * of this file.
+ *
+ *  - Module function: a built-in type (0-11) as above, or a user-defined
+ *    primitive (type 12 + u) whose value is read from table u, 256 entries
+ *    indexed by the packed pin values (pin i in bits 2i..2i+1); the table
+ *    covers every 0/1/X/Z combination, so no Z-as-X rule applies to it.
+ *  - Delay: the paper indexes the delay matrix by triggering pin, input edge
+ *    and output value. Here per pin i: dly[i][edge][out] with edge 0 = rise,
+ *    1 = fall and out 0 or 1; INT32_MAX means no relation (the paper's inf).
+ *    Readings (the paper does not define edges of a 4-value signal): a pin
+ *    change rises if its new value is 1 or it leaves 0 for X or Z, falls if
+ *    its new value is 0 or it leaves 1 for X or Z, and a change between X
+ *    and Z counts as both (the smaller delay). A new output value X takes the
+ *    smaller of the edge's delays to 0 and to 1. The delay of a candidate is
+ *    the minimum over the pins that changed at its time; when every one of
+ *    them is unrelated (infinite) the candidate never appears -- appending it
+ *    at infinite time and letting Eq. 1 deny it later is the same -- while
+ *    the previous evaluated value still becomes the new one.
+ *  - A gate is evaluated only at its input transitions, starting from an X
+ *    previous value (Algorithm 2), so a table's value for all-X inputs is
+ *    not output before the first input change.
+ * ------------------------------------------------------------------------ */
+#define O1X_NO_RELATION INT32_MAX
+
+static int edge_of(uint8_t old_v, uint8_t new_v) {
+    if (new_v == 1 || (old_v == 0 && (new_v == O1_X || new_v == O1_Z))) return 0;
+    if (new_v == 0 || (old_v == 1 && (new_v == O1_X || new_v == O1_Z))) return 1;
+    return 2; /* X <-> Z */
+}
+
+static int64_t edge_out_delay(const int32_t *d /* [2 edges][2 outs] */, int edge, uint8_t out) {
+    int64_t best = O1_INF;
+    for (int e = 0; e < 2; e++) {
+        if (edge != 2 && e != edge) continue;
+        for (int o = 0; o < 2; o++) {
+            if (out != O1_X && o != out) continue;
+            int32_t x = d[e * 2 + o];
+            if (x != O1X_NO_RELATION && x < best) best = x;
+        }
+    }
+    return best;
+}
+
+/* Algorithm 2 for one gate of the extended model. dly: [k][2][2]. */
+int o1x_process_cell(int type, const uint8_t *table, const int64_t *const *in_t,
+                     const uint8_t *const *in_v, const int64_t *in_n, int k,
+                     const int32_t *dly, o1_wave *out) {
+    uint8_t current_signals[4];
+    int64_t earliest_index[4];
+    int64_t earliest_timestamp[4];
+    int edge[4];
+    for (int i = 0; i < k; i++) {
+        current_signals[i] = O1_X;
+        earliest_index[i] = 0;
+        earliest_timestamp[i] = in_n[i] > 0 ? in_t[i][0] : O1_INF;
+    }
+    uint8_t previous_output = O1_X;
+    for (;;) {
+        int64_t t_earliest = O1_INF;
+        for (int i = 0; i < k; i++)
+            if (earliest_timestamp[i] < t_earliest) t_earliest = earliest_timestamp[i];
+        if (t_earliest == O1_INF) break;
+        for (int i = 0; i < k; i++) {
+            edge[i] = -1;
+            int64_t j = earliest_index[i];
+            if (earliest_timestamp[i] == t_earliest) {
+                edge[i] = edge_of(current_signals[i], in_v[i][j]);
+                current_signals[i] = in_v[i][j];
+                if (j + 1 == in_n[i]) {
+                    earliest_timestamp[i] = O1_INF;
+                } else {
+                    earliest_index[i] = j + 1;
+                    earliest_timestamp[i] = in_t[i][j + 1];
+                }
+            }
+        }
+        uint8_t new_output;
+        if (table) {
+            int packed = 0;
+            for (int i = 0; i < k; i++) packed |= current_signals[i] << (2 * i);
+            new_output = table[packed];
+        } else {
+            new_output = o1_calculate_signal(type, current_signals);
+        }
+        if (new_output != previous_output) {
+            int64_t del = O1_INF;
+            for (int i = 0; i < k; i++) {
+                if (edge[i] < 0) continue;
+                int64_t d = edge_out_delay(dly + 4 * i, edge[i], new_output);
+                if (d < del) del = d;
+            }
+            if (del != O1_INF && add_signal_change(out, new_output, t_earliest + del)) return -1;
+        }
+        previous_output = new_output;
+    }
+    return 0;
+}
+
+/* Whole netlist under the extended model: dly[P][2][2] per pin; udp[n_udp][256].
+ * Same return convention as o1_simulate. */
+o1_result *o1x_simulate(int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
+                        const int64_t *pin_net, const int32_t *dly, int n_udp, const uint8_t *udp,
+                        const int64_t *src_off, const int64_t *src_t, const uint8_t *src_v,
+                        int *status) {
+    *status = 0;
+    for (int64_t g = 0; g < G; g++) {
+        int64_t k = pin_off[g + 1] - pin_off[g];
+        int ok = type[g] < T_COUNT ? k == arity_of(type[g]) : (type[g] - T_COUNT < n_udp && k >= 1 && k <= 4);
+        if (!ok) { *status = -3; return NULL; }
+        for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++)
+            if (pin_net[p] < 0 || pin_net[p] >= S + G || pin_net[p] == S + g) { *status = -3; return NULL; }
+    }
+    o1_result *r = (o1_result *)calloc(1, sizeof(o1_result));
+    int64_t *order = (int64_t *)malloc((size_t)(G ? G : 1) * sizeof(int64_t));
+    if (!r || !order) { free(r); free(order); *status = -1; return NULL; }
+    r->S = S;
+    r->G = G;
+    r->gate_out = (o1_wave *)calloc((size_t)(G ? G : 1), sizeof(o1_wave));
+    if (!r->gate_out) { free(order); free(r); *status = -1; return NULL; }
+    int rc = topological_order(S, G, pin_off, pin_net, order);
+    if (rc) { free(order); o1_free(r); *status = rc; return NULL; }
+    for (int64_t idx = 0; idx < G; idx++) {
+        int64_t g = order[idx];
+        const int64_t *in_t[4];
+        const uint8_t *in_v[4];
+        int64_t in_n[4];
+        int k = (int)(pin_off[g + 1] - pin_off[g]);
+        for (int i = 0; i < k; i++) {
+            int64_t net = pin_net[pin_off[g] + i];
+            if (net < S) {
+                in_t[i] = src_t + src_off[net];
+                in_v[i] = src_v + src_off[net];
+                in_n[i] = src_off[net + 1] - src_off[net];
+            } else {
+                o1_wave *w = &r->gate_out[net - S];
+                in_t[i] = w->t;
+                in_v[i] = w->v;
+                in_n[i] = w->n;
+            }
+        }
+        const uint8_t *table = type[g] >= T_COUNT ? udp + 256 * (size_t)(type[g] - T_COUNT) : NULL;
+        if (o1x_process_cell(type[g], table, in_t, in_v, in_n, k, dly + 4 * pin_off[g], &r->gate_out[g])) {
+            free(order); o1_free(r); *status = -1; return NULL;
+        }
+    }
+    free(order);
+    return r;
+}

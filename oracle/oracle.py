@@ -83,6 +83,9 @@ class _O1:
         lib.o1_simulate_fingerprints.restype = ctypes.c_int
         lib.o1_simulate_fingerprints.argtypes = [i64, i64, P, P, P, P, P, P, P, P, P, P]
         lib.o1_fingerprints.argtypes = [i64, P, P, P, P]
+        lib.o1x_simulate.restype = P
+        lib.o1x_simulate.argtypes = [i64, i64, P, P, P, P, ctypes.c_int, P, P, P, P,
+                                     ctypes.POINTER(ctypes.c_int)]
         self.lib = lib
 
 
@@ -131,6 +134,40 @@ def o1_simulate(nl, st, lib: str | None = None):
         off = np.empty(nl.G + 1, dtype=np.int64)
         t = np.empty(n, dtype=np.int64)
         v = np.empty(n, dtype=np.uint8)
+        L.o1_copy(h, _ptr(off), _ptr(t), _ptr(v))
+    finally:
+        L.o1_free(h)
+    return off, t, v
+
+
+def o1x_simulate(nl, st, dly, udp=None, lib: str | None = None):
+    """O1 under the extended cell model (delays by pin, input edge and output
+    value; user-defined gate tables for types 12 and up). ``dly`` is int32
+    [P, 2, 2] (edge rise/fall, output 0/1; INT32_MAX = no relation), ``udp``
+    uint8 [n, 256]. Returns (off[G+1], t, v) like o1_simulate."""
+    L = o1_lib(lib).lib
+    type_ = np.ascontiguousarray(nl.type, dtype=np.uint8)
+    pin_off = np.ascontiguousarray(nl.pin_off, dtype=np.int64)
+    pin_net = np.ascontiguousarray(nl.pin_net, dtype=np.int64)
+    d = np.ascontiguousarray(dly, dtype=np.int32).reshape(-1)
+    assert d.size == 4 * nl.P
+    u = np.ascontiguousarray(udp if udp is not None else np.zeros((0, 256)), dtype=np.uint8)
+    soff = np.ascontiguousarray(st.off, dtype=np.int64)
+    st_t = np.ascontiguousarray(st.t, dtype=np.int64)
+    st_v = np.ascontiguousarray(st.v, dtype=np.uint8)
+    status = ctypes.c_int(0)
+    h = L.o1x_simulate(nl.S, nl.G, _ptr(type_), _ptr(pin_off), _ptr(pin_net), _ptr(d), len(u),
+                       _ptr(u) if len(u) else None, _ptr(soff), _ptr(st_t), _ptr(st_v),
+                       ctypes.byref(status))
+    if not h:
+        raise OracleError({-1: "out of memory", -2: "cycle", -3: "malformed netlist"}
+                          .get(status.value, str(status.value)))
+    try:
+        ln = np.empty(nl.G, dtype=np.int64)
+        L.o1_lengths(h, _ptr(ln))
+        off = np.empty(nl.G + 1, dtype=np.int64)
+        t = np.empty(int(ln.sum()), dtype=np.int64)
+        v = np.empty(int(ln.sum()), dtype=np.uint8)
         L.o1_copy(h, _ptr(off), _ptr(t), _ptr(v))
     finally:
         L.o1_free(h)
@@ -351,6 +388,79 @@ def o3_simulate(nl, st, t_max=None):
         for i in range(1, n_t):
             T = i - 1
             j = [c for c in cands if c[0] <= T]
+            y[S + g, i] = j[-1][1] if j else X
+    out = []
+    for g in range(G):
+        row = y[S + g]
+        out.append([(i - 1, int(row[i])) for i in range(1, n_t) if row[i] != row[i - 1]])
+    return out
+
+
+# ---------------------------------------------------------------------------
+# O3 under the extended cell model (tiny inputs only): the same dense-time
+# definition, with the gate value from a table for types 12 and up and the
+# delay of a candidate = min over the changed pins of their delay for their
+# edge and the new value; a candidate with no related changed pin never
+# appears; the gate's value is X until its first input change. Edge readings
+# as in the C oracle's extended model.
+
+NO_RELATION = 2**31 - 1
+
+
+def edge_class(old, new):
+    if new == 1 or (old == 0 and new in (X, Z)):
+        return 0
+    if new == 0 or (old == 1 and new in (X, Z)):
+        return 1
+    return 2
+
+
+def edge_delay(d22, edge, out):
+    """d22[edge][out]; edge 2 = both edges; out X = both outputs."""
+    vals = [d22[e][o] for e in (0, 1) if edge in (e, 2) for o in (0, 1) if out in (o, X)]
+    vals = [x for x in vals if x != NO_RELATION]
+    return min(vals) if vals else None
+
+
+def o3x_simulate(nl, st, dly, udp=None, t_max=None):
+    S, G = nl.S, nl.G
+    lvl = _levels(nl)
+    srcw = _source_waves(st, S)
+    if t_max is None:
+        last = max([w[-1][0] for w in srcw if w] + [0])
+        finite = [int(x) for x in np.asarray(dly).reshape(-1) if x != NO_RELATION]
+        dm = max(finite + [0])
+        t_max = last + (int(lvl.max(initial=0)) + 1) * (dm + 1) + 1
+    n_t = t_max + 2
+    y = np.full((S + G, n_t), X, dtype=np.int64)
+    for s, w in enumerate(srcw):
+        for t, v in w:
+            y[s, t + 1:] = v
+    for g in sorted(range(G), key=lambda g: (lvl[S + g], g)):
+        a, b = int(nl.pin_off[g]), int(nl.pin_off[g + 1])
+        nets = [int(x) for x in nl.pin_net[a:b]]
+        gt = int(nl.type[g])
+
+        def f(vals):
+            if gt >= 12:
+                return int(udp[gt - 12][sum(v << (2 * i) for i, v in enumerate(vals))])
+            return gate_eval(gt, vals)
+
+        # the gate is evaluated from its first input change on; before that its
+        # value is X (Algorithm 2 starts from an X previous value), which only
+        # matters for tables that map all-X inputs to 0 or 1
+        started = np.cumsum(np.any(y[nets, 1:] != y[nets, :-1], axis=0)) > 0
+        e = [X] + [f([int(y[n, i]) for n in nets]) if started[i - 1] else X for i in range(1, n_t)]
+        cands = []
+        for i in range(1, n_t):
+            if e[i] != e[i - 1]:
+                ds = [edge_delay(dly[a + k], edge_class(int(y[n, i - 1]), int(y[n, i])), e[i])
+                      for k, n in enumerate(nets) if y[n, i] != y[n, i - 1]]
+                ds = [x for x in ds if x is not None]
+                if ds:
+                    cands.append((i - 1 + min(ds), e[i]))
+        for i in range(1, n_t):
+            j = [c for c in cands if c[0] <= i - 1]
             y[S + g, i] = j[-1][1] if j else X
     out = []
     for g in range(G):

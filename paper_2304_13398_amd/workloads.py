@@ -272,6 +272,47 @@ def make_stimulus_skewed(*, S, mean_per_src, wcv, window, probs=(0.45, 0.45, 0.0
     return Stimulus(off, t, v)
 
 
+NO_RELATION = 2**31 - 1  # a delay entry of a pin unrelated to the output (the paper's inf)
+
+
+def make_cell_model(nl, *, seed, edge_spread=0.5, inf_prob=0.0, n_udp=0, udp_frac=0.0):
+    """The extended cell model over an existing netlist (delays by pin, input
+    edge and output value; user-defined gate tables):
+
+    * dly[p][edge][out], edge 0 = rise / 1 = fall, out 0 / 1: the pin's fall
+      (out 0) or rise (out 1) delay times a factor drawn per entry from
+      [1 - edge_spread, 1 + edge_spread]; each entry is NO_RELATION with
+      probability inf_prob;
+    * n_udp tables of 256 output values in {0, 1, X}, for arities 1-4 in
+      turn; a fraction udp_frac of the gates whose pin count matches a table's
+      arity switch to type 12 + that table.
+    Returns (type[G] uint8, dly[P, 2, 2] int32, udp[n_udp, 256] uint8)."""
+    r_d, r_i, r_u, r_g = _child_rngs(seed + 3_000_017, 4)
+    P = nl.P
+    base = np.stack([nl.fall, nl.rise], axis=1).astype(np.float64)        # [P, out]
+    fac = r_d.uniform(1 - edge_spread, 1 + edge_spread, size=(P, 2, 2))
+    dly = np.rint(base[:, None, :] * fac).astype(np.int64)
+    dly = np.clip(dly, 0, NO_RELATION - 1).astype(np.int32)
+    if inf_prob > 0:
+        dly[r_i.random(size=(P, 2, 2)) < inf_prob] = NO_RELATION
+    udp = r_u.choice(3, size=(n_udp, 256)).astype(np.uint8)
+    arity = np.array([1 + u % 4 for u in range(n_udp)], dtype=np.int64)
+    type_ = nl.type.copy()
+    if n_udp and udp_frac > 0:
+        k = np.diff(nl.pin_off)
+        pick = r_g.random(nl.G) < udp_frac
+        for g in np.nonzero(pick)[0]:
+            cands = np.nonzero(arity == k[g])[0]
+            if len(cands):
+                type_[g] = 12 + int(cands[int(r_g.integers(len(cands)))])
+    return type_, dly, udp
+
+
+def with_types(nl, type_) -> "Netlist":
+    return Netlist(nl.S, nl.G, np.asarray(type_, dtype=np.uint8), nl.pin_off, nl.pin_net,
+                   nl.rise, nl.fall, nl.level, nl.name + "+cells")
+
+
 # --------------------------------------------------------------------------
 # The benchmark configurations.
 

@@ -1,11 +1,16 @@
 """Plant plausible mistakes in a copy of the oracle (on the CPU) and check
-that the pins catch every one of them. The committed oracle is untouched."""
+that the pins catch every one of them. The committed oracle is untouched.
+
+Base-model mutants patch the first occurrence of their anchor (the base
+procedure precedes the extended one in the file); extended-model mutants
+patch anchors of the extended procedure and are checked by its pins."""
 import os
 
 import pytest
 
 from oracle import oracle as O
 from tests import oracle_pins as P
+from tests import test_oracle_ext as X
 
 MUTANTS = {
     "eq1_strict_tie": ("while (out->n > 0 && out->t[out->n - 1] >= t_r)",
@@ -35,13 +40,44 @@ MUTANTS = {
 }
 
 
+EXT_MUTANTS = {
+    "edge_rise_fall_swapped": (
+        "if (new_v == 1 || (old_v == 0 && (new_v == O1_X || new_v == O1_Z))) return 0;\n"
+        "    if (new_v == 0 || (old_v == 1 && (new_v == O1_X || new_v == O1_Z))) return 1;",
+        "if (new_v == 1 || (old_v == 0 && (new_v == O1_X || new_v == O1_Z))) return 1;\n"
+        "    if (new_v == 0 || (old_v == 1 && (new_v == O1_X || new_v == O1_Z))) return 0;"),
+    "edge_ignores_old_value": ("edge[i] = edge_of(current_signals[i], in_v[i][j]);",
+                               "edge[i] = edge_of(O1_X, in_v[i][j]);"),
+    "xz_change_counts_as_rise": ("return 2; /* X <-> Z */", "return 0;"),
+    "x_output_uses_only_out0": ("if (out != O1_X && o != out) continue;",
+                                "if (o != (out == 1)) continue;"),
+    "inf_candidate_kept": ("if (del != O1_INF && add_signal_change(out, new_output, t_earliest + del)) return -1;",
+                           "if (add_signal_change(out, new_output, del == O1_INF ? (int64_t)1 << 40 : t_earliest + del)) return -1;"),
+    "inf_read_as_zero": ("if (x != O1X_NO_RELATION && x < best) best = x;",
+                         "if ((x == O1X_NO_RELATION ? 0 : x) < best) best = x == O1X_NO_RELATION ? 0 : x;"),
+    "table_misindexed": ("packed |= current_signals[i] << (2 * i);",
+                         "packed |= current_signals[i] << i;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(EXT_MUTANTS))
+def test_extended_mutant_is_caught(name, tmp_path):
+    src = open(O.SRC).read()
+    a, b = EXT_MUTANTS[name]
+    assert src.count(a) == 1, f"mutation anchor for {name} not unique"
+    path = tmp_path / "o1_mut.c"
+    path.write_text(src.replace(a, b))
+    lib = O.build(force=True, src=str(path), out=str(tmp_path / f"libo1_{name}.so"))
+    assert X.check_ext(lib), f"no pin caught mutant {name}"
+
+
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_mutant_is_caught(name, tmp_path):
     src = open(O.SRC).read()
     a, b = MUTANTS[name]
-    assert src.count(a) == 1, f"mutation anchor for {name} not unique"
+    assert src.count(a) >= 1, f"mutation anchor for {name} missing"
     path = tmp_path / "o1_mut.c"
-    path.write_text(src.replace(a, b))
+    path.write_text(src.replace(a, b, 1))
     lib = O.build(force=True, src=str(path), out=str(tmp_path / f"libo1_{name}.so"))
     fails = []
     for check in P.FAST_CHECKS:
