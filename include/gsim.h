@@ -132,6 +132,27 @@ gsim_status sim_load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *
                              const int64_t *pin_off, const int64_t *pin_net,
                              const int32_t *rise_ps, const int32_t *fall_ps,
                              gsim_netlist *out);
+/* A netlist under the extended cell model. The paper's delay matrix is indexed
+ * by triggering pin, input edge and output value (Section 2.3; Section 3.2,
+ * with inf for a pin unrelated to an output), and module functions may be
+ * user-defined primitives (Section 3.3):
+ *   dly[P][2][2]  per pin: [edge: 0 rise, 1 fall][output value: 0, 1], in ps,
+ *                 >= 0, or GSIM_NO_RELATION for an unrelated pin. A pin change
+ *                 rises if its new value is 1 or it leaves 0 for X/Z, falls if
+ *                 its new value is 0 or it leaves 1 for X/Z; an X <-> Z change
+ *                 takes the smaller delay of both edges; a new output value X
+ *                 the smaller of the edge's delays to 0 and 1. A candidate
+ *                 whose changed pins are all unrelated never appears.
+ *   udp[n_udp][256] user-defined gate types 12 .. 11 + n_udp (any 1-4 pins):
+ *                 the gate's value for packed pin values (pin i in bits 2i and
+ *                 2i+1; entries 0, 1 or 2 = X). A gate is evaluated at its
+ *                 input transitions only, from an X previous value.
+ * Otherwise as sim_load_netlist (the arrays are copied; rise/fall unused). */
+#define GSIM_NO_RELATION 2147483647
+gsim_status sim_load_netlist_ext(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type,
+                                 const int64_t *pin_off, const int64_t *pin_net, const int32_t *dly,
+                                 int32_t n_udp, const uint8_t *udp, gsim_netlist *out);
+
 gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl);
 
 /* Per-netlist setting of GSIM_OPT_LANE_THRESHOLD (-1 = follow the context's

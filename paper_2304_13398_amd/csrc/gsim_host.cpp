@@ -129,16 +129,24 @@ struct Levelized {
     int64_t max_path_delay = 0;
 };
 
+// n_udp: user-defined gate types 12 .. 11 + n_udp are allowed (any 1-4 pins).
 Failure levelize(int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
-                 const int64_t *pin_net, const int32_t *rise, const int32_t *fall, Levelized *out) {
+                 const int64_t *pin_net, const int32_t *rise, const int32_t *fall, Levelized *out,
+                 int n_udp = 0) {
     if (S < 0 || G < 0) return fail(GSIM_E_ARG, "S and G must be >= 0 (S=%lld G=%lld)", (long long)S, (long long)G);
     if (S + G > INT32_MAX) return fail(GSIM_E_ARG, "S + G exceeds 2^31-1 nets");
     if (G > 0 && (!type || !pin_off || !pin_net || !rise || !fall))
         return fail(GSIM_E_ARG, "null netlist array");
     if (G > 0 && pin_off[0] != 0) return fail(GSIM_E_ARG, "pin_off[0] must be 0");
     for (int64_t g = 0; g < G; g++) {
-        if (type[g] >= GSIM_NUM_TYPES) return fail(GSIM_E_ARG, "gate %lld: unknown type %d", (long long)g, type[g]);
         const int64_t k = pin_off[g + 1] - pin_off[g];
+        if (type[g] >= GSIM_NUM_TYPES && type[g] < GSIM_NUM_TYPES + n_udp) {
+            if (k < 1 || k > kMaxPins)
+                return fail(GSIM_E_ARG, "gate %lld: user-defined type with %lld pins (1-4 allowed)",
+                            (long long)g, (long long)k);
+            continue;
+        }
+        if (type[g] >= GSIM_NUM_TYPES) return fail(GSIM_E_ARG, "gate %lld: unknown type %d", (long long)g, type[g]);
         if (k != kArity[type[g]])
             return fail(GSIM_E_ARG, "gate %lld: %lld pins, type %d needs %d", (long long)g, (long long)k,
                         type[g], kArity[type[g]]);
@@ -380,6 +388,8 @@ struct Netlist {
     std::vector<LevelRange> levels;
     std::vector<int64_t> internal_of_user;  // [G]
     GateRec *d_rec = nullptr;
+    uint8_t *d_lut = nullptr;       // netlist's own gate tables (built-in + user-defined), or null
+    int32_t *d_edly = nullptr;      // [G][4][2][2] delays by input edge and output value, or null
     // dependency-driven schedule: consumers of each gate's net (one entry per
     // reading pin), each gate's count of pins that read gate nets, and the
     // number of gates that read sources only (they come first in level order)
@@ -452,7 +462,7 @@ struct Executor {
     int64_t blocksum_cap = 0;
     uint64_t *d_list = nullptr;    // kNumLists lists of list_cap entries
     uint64_t *d_keys = nullptr;    // kListLane key arrays of list_cap entries
-    uint64_t *d_sorted = nullptr;  // 2 sorted lists of list_cap entries
+    uint64_t *d_sorted = nullptr;  // kVariants sorted lists of list_cap entries
     int64_t list_cap = 0;
     JobDesc *h_ring = nullptr;     // pinned [kRing][kMaxJobsPerStep]
     hipEvent_t ring_ev[kRing] = {};
@@ -513,11 +523,48 @@ T *pool_get(Pool &pool, int64_t n) {
 
 // ---- netlists ---------------------------------------------------------------
 
+void put_netlist(gsim_ctx ctx, Netlist *nl) {
+    ctx->pool->put(nl->d_rec);
+    ctx->pool->put(nl->d_fo_off);
+    ctx->pool->put(nl->d_fo);
+    ctx->pool->put(nl->d_pend0);
+    ctx->pool->put(nl->d_lut);
+    ctx->pool->put(nl->d_edly);
+    nl->d_rec = nullptr;
+    nl->d_fo_off = nullptr;
+    nl->d_fo = nullptr;
+    nl->d_pend0 = nullptr;
+    nl->d_lut = nullptr;
+    nl->d_edly = nullptr;
+}
+
+// dly (optional): per pin [2 edges][2 outputs] delays of the extended model;
+// then rise/fall are ignored. udp (optional): n_udp tables of 256 values.
 Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
-                     const int64_t *pin_net, const int32_t *rise, const int32_t *fall, gsim_netlist *out) {
+                     const int64_t *pin_net, const int32_t *rise, const int32_t *fall, gsim_netlist *out,
+                     const int32_t *dly = nullptr, int n_udp = 0, const uint8_t *udp = nullptr) {
     if (!out) return fail(GSIM_E_ARG, "null output handle");
+    if (n_udp < 0 || n_udp > 256 - GSIM_NUM_TYPES) return fail(GSIM_E_ARG, "n_udp must be in [0, %d]", 256 - GSIM_NUM_TYPES);
+    if (n_udp > 0 && !udp) return fail(GSIM_E_ARG, "null user-defined gate tables");
+    for (int64_t i = 0; i < (int64_t)n_udp * 256; i++)
+        if (udp[i] > 2) return fail(GSIM_E_ARG, "user-defined table %lld: entry %lld is %d (0, 1 or X allowed)",
+                                    (long long)(i / 256), (long long)(i % 256), udp[i]);
+    std::vector<int32_t> erise, efall;  // extended model: each pin's largest finite delay
+    if (dly) {
+        const int64_t P = G > 0 && pin_off ? pin_off[G] : 0;
+        erise.assign(std::max<int64_t>(P, 1), 0);
+        for (int64_t p = 0; p < P; p++)
+            for (int e = 0; e < 4; e++) {
+                const int32_t x = dly[4 * p + e];
+                if (x < 0) return fail(GSIM_E_ARG, "pin %lld: negative delay", (long long)p);
+                if (x != kNoRelation) erise[p] = std::max(erise[p], x);
+            }
+        efall = erise;
+        rise = erise.data();
+        fall = efall.data();
+    }
     Levelized lv;
-    Failure f = levelize(S, G, type, pin_off, pin_net, rise, fall, &lv);
+    Failure f = levelize(S, G, type, pin_off, pin_net, rise, fall, &lv, n_udp);
     if (f.st != GSIM_OK) return f;
     auto nl = std::make_unique<Netlist>();
     nl->S = S;
@@ -534,11 +581,14 @@ Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, co
         for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++) d = std::max(d, std::max(rise[p], fall[p]));
         return d;
     };
+    const int edge_model = dly ? 1 : 0;
     auto group_of = [&](int64_t g) {
         if (ctx->opt_kernel == 1) return kListLane;  // every gate on the lane kernel
         const int32_t d = gate_dmax(g);
         const int k = (int)(pin_off[g + 1] - pin_off[g]);
-        return d <= kWindowSmall ? wave_list(0, k) : d <= kWindowLarge ? wave_list(1, k) : kListLane;
+        return d <= kWindowSmall   ? wave_list(wave_variant(0, edge_model), k)
+               : d <= kWindowLarge ? wave_list(wave_variant(1, edge_model), k)
+                                   : kListLane;
     };
     const int32_t L = lv.n_levels;
     constexpr size_t NL = kNumLists;
@@ -635,6 +685,32 @@ Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, co
             return fail(GSIM_E_DEVICE, "netlist upload: %s", hipGetErrorString(e));
         }
     }
+    if (n_udp > 0) {
+        std::vector<uint8_t> lut = build_lut();
+        lut.resize((size_t)(GSIM_NUM_TYPES + n_udp) * 256);
+        std::memcpy(lut.data() + (size_t)GSIM_NUM_TYPES * 256, udp, (size_t)n_udp * 256);
+        nl->d_lut = (uint8_t *)ctx->pool->get(lut.size());
+        if (!nl->d_lut || hipMemcpy(nl->d_lut, lut.data(), lut.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            put_netlist(ctx, nl.get());
+            return fail(GSIM_E_OOM, "no device memory for the user-defined gate tables");
+        }
+    }
+    if (dly && G > 0) {
+        std::vector<int32_t> ed((size_t)G * 16, kNoRelation);
+        for (int64_t g = 0; g < G; g++) {
+            const int64_t ig = nl->internal_of_user[g];
+            for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++)
+                for (int e = 0; e < 4; e++) ed[(size_t)ig * 16 + (p - pin_off[g]) * 4 + e] = dly[4 * p + e];
+        }
+        nl->d_edly = pool_get<int32_t>(*ctx->pool, G * 16);
+        if (!nl->d_edly ||
+            hipMemcpy(nl->d_edly, ed.data(), sizeof(int32_t) * ed.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            put_netlist(ctx, nl.get());
+            return fail(GSIM_E_OOM, "no device memory for the edge delay table");
+        }
+    }
     const int64_t id = ctx->next_id++;
     ctx->netlists[id] = std::move(nl);
     *out = id;
@@ -697,7 +773,7 @@ Failure ensure_lists(gsim_ctx ctx, Executor *ex, int64_t items) {
     Pool &pool = *ctx->pool;
     uint64_t *nlist = pool_get<uint64_t>(pool, kNumLists * L);
     uint64_t *nkeys = pool_get<uint64_t>(pool, kListLane * L);
-    uint64_t *nsorted = pool_get<uint64_t>(pool, 2 * L);
+    uint64_t *nsorted = pool_get<uint64_t>(pool, kVariants * L);
     if (!nlist || !nkeys || !nsorted) {
         pool.put(nlist);
         pool.put(nkeys);
@@ -869,12 +945,13 @@ Failure enqueue_dataflow(gsim_ctx ctx, Job *j, hipStream_t s) {
     a.job.len = j->d_len;
     a.job.K = j->d_K;
     a.job.state = j->d_state;
+    a.job.lut = nl.d_lut ? nl.d_lut : ctx->d_lut;
+    a.job.edly = nl.d_edly;
     a.fo_off = nl.d_fo_off;
     a.fo = nl.d_fo;
     a.pend = j->d_pend;
     a.queue = j->d_queue;
     a.ctl = j->d_ctl;
-    a.lut = ctx->d_lut;
     a.G = nl.G;
     a.n_first = nl.n_first;
     const int64_t n_waves = std::min<int64_t>(nl.G, ctx->n_waves_resident);
@@ -1037,6 +1114,8 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
         d.sblock_begin = n_sblocks;
         d.lane_threshold = j->nl->lane_threshold >= 0 ? j->nl->lane_threshold : ctx->opt_lane_threshold;
         d.pad = 0;
+        d.lut = j->nl->d_lut ? j->nl->d_lut : ctx->d_lut;
+        d.edly = j->nl->d_edly;
         n_sblocks += (r.n + kSizeBlock - 1) / kSizeBlock;
         n_items += r.n;
         for (int c = 0; c < kNumLists; c++) n_list[c] += r.n_list[c];
@@ -1060,10 +1139,9 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
     a.blocksum = ex->d_blocksum;
     for (int c = 0; c < kNumLists; c++) a.list[c] = ex->d_list + (size_t)c * ex->list_cap;
     for (int c = 0; c < kListLane; c++) a.key[c] = ex->d_keys + (size_t)c * ex->list_cap;
-    for (int w = 0; w < 2; w++) a.sorted[w] = ex->d_sorted + (size_t)w * ex->list_cap;
+    for (int w = 0; w < kVariants; w++) a.sorted[w] = ex->d_sorted + (size_t)w * ex->list_cap;
     a.count = ex->d_counts + ex->parity * kCountWords;
     a.next_count = ex->d_counts + (1 - ex->parity) * kCountWords;
-    a.lut = ctx->d_lut;
     HIP_TRY(launch_size(a, s));
     HIP_TRY(launch_level_scan(a, s));
     HIP_TRY(launch_sort_lists(a, n_list, s));
@@ -1074,8 +1152,7 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
         HIP_TRY(hipEventCreate(&tm->b));
         HIP_TRY(hipEventRecord(tm->a, s));
     }
-    HIP_TRY(launch_eval_wave(a, 0, n_list + wave_list(0, 1), s));
-    HIP_TRY(launch_eval_wave(a, 1, n_list + wave_list(1, 1), s));
+    for (int v = 0; v < kVariants; v++) HIP_TRY(launch_eval_wave(a, v, n_list + wave_list(v, 1), s));
     HIP_TRY(launch_eval_lane(a, n_lane, s));
     if (tm) HIP_TRY(hipEventRecord(tm->b, s));
     ex->parity ^= 1;
@@ -1360,10 +1437,7 @@ gsim_status sim_destroy(gsim_ctx ctx) {
     for (auto &kv : ctx->executors) destroy_executor(ctx, kv.second.get());
     ctx->executors.clear();
     for (auto &kv : ctx->netlists) {
-        ctx->pool->put(kv.second->d_rec);
-        ctx->pool->put(kv.second->d_fo_off);
-        ctx->pool->put(kv.second->d_fo);
-        ctx->pool->put(kv.second->d_pend0);
+        put_netlist(ctx, kv.second.get());
     }
     ctx->netlists.clear();
     ctx->pool->put(ctx->d_lut);
@@ -1410,6 +1484,15 @@ gsim_status sim_load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *
     return record(ctx, load_netlist(ctx, S, G, type, pin_off, pin_net, rise_ps, fall_ps, out));
 }
 
+gsim_status sim_load_netlist_ext(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type,
+                                 const int64_t *pin_off, const int64_t *pin_net, const int32_t *dly,
+                                 int32_t n_udp, const uint8_t *udp, gsim_netlist *out) {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    if (G > 0 && !dly) return record(ctx, fail(GSIM_E_ARG, "null delay table"));
+    return record(ctx, load_netlist(ctx, S, G, type, pin_off, pin_net, nullptr, nullptr, out,
+                                    G > 0 ? dly : nullptr, n_udp, udp));
+}
+
 gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl) {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     auto it = ctx->netlists.find(nl);
@@ -1417,10 +1500,7 @@ gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl) {
     if (it->second->active_jobs > 0)
         return record(ctx, fail(GSIM_E_ARG, "netlist %lld still has %lld unreleased jobs", (long long)nl,
                                 (long long)it->second->active_jobs));
-    ctx->pool->put(it->second->d_rec);
-    ctx->pool->put(it->second->d_fo_off);
-    ctx->pool->put(it->second->d_fo);
-    ctx->pool->put(it->second->d_pend0);
+    put_netlist(ctx, it->second.get());
     ctx->netlists.erase(it);
     return GSIM_OK;
 }

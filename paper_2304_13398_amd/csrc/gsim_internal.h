@@ -35,11 +35,17 @@ constexpr int kWindowLarge = 256;
 constexpr int kSizeBlock = 256;
 
 // Evaluate work lists (one each per step): the wavefront kernel for each
-// delay window (small, large) and pin count (1-4), then the lane kernel.
-constexpr int kNumLists = 9;
-constexpr int kListLane = 8;
-__host__ __device__ constexpr int wave_list(int large_window, int pins) {
-    return large_window * 4 + pins - 1;
+// variant -- delay window (small, large) times delay model (output value
+// only; input edge and output value) -- and pin count (1-4), then the lane
+// kernel.
+constexpr int kVariants = 4;
+constexpr int kNumLists = kVariants * 4 + 1;
+constexpr int kListLane = kVariants * 4;
+__host__ __device__ constexpr int wave_variant(int large_window, int edge_model) {
+    return edge_model * 2 + large_window;
+}
+__host__ __device__ constexpr int wave_list(int variant, int pins) {
+    return variant * 4 + pins - 1;
 }
 // Dispatch order of the wavefront lists: each gate gets a segment by its
 // estimated cost (half-octave buckets of w_g times a per-pin-count weight,
@@ -47,11 +53,12 @@ __host__ __device__ constexpr int wave_list(int large_window, int pins) {
 // sorted list per delay window, and the evaluate launch takes it in order
 // (longest jobs first, so the short ones fill the tail of the level).
 constexpr int kCostBuckets = 32;
-constexpr int kSegments = kCostBuckets * 4;  // per delay window
-// Per-step counters: list lengths, segment sizes of both windows, sorted totals.
+constexpr int kSegments = kCostBuckets * 4;  // per variant
+// Per-step counters: list lengths, then the segment sizes of every variant.
 constexpr int kSegCountAt = kNumLists;
-constexpr int kSortedTotalAt = kSegCountAt + 2 * kSegments;
-constexpr int kCountWords = kSortedTotalAt + 2;
+constexpr int kCountWords = kSegCountAt + kVariants * kSegments;
+// A pin's delay entry for an unrelated output (the paper's inf).
+constexpr int32_t kNoRelation = INT32_MAX;
 
 // One gate, 64 bytes, in level order. Nets are internal ids: sources keep
 // their id, the gate at internal position i drives net S + i.
@@ -92,8 +99,10 @@ struct JobDesc {
     int64_t sblock_begin;    // first sizing block of this job in the step
     int32_t lane_threshold;  // gates reading fewer input transitions go to the lane kernel
     int32_t pad;
+    const uint8_t *lut;      // [types][256] gate value by packed pin values (built-in + user tables)
+    const int32_t *edly;     // [G][4 pins][2 edges][2 outputs] delays by input edge, or null
 };
-static_assert(sizeof(JobDesc) == 80, "JobDesc layout");
+static_assert(sizeof(JobDesc) == 96, "JobDesc layout");
 
 // A step: one level of each of n_jobs jobs.
 struct StepArgs {
@@ -104,10 +113,9 @@ struct StepArgs {
     int64_t *blocksum;       // [n_sblocks]: block totals, then absolute arena bases
     uint64_t *list[kNumLists];  // work lists: job << 32 | gate
     uint64_t *key[kListLane];   // per wavefront-list entry: segment << 32 | rank in segment
-    uint64_t *sorted[2];        // per delay window: the wavefront entries in dispatch order
+    uint64_t *sorted[kVariants];  // per variant: the wavefront entries in dispatch order
     uint32_t *count;         // [kCountWords] counters of this step (see kSegCountAt)
     uint32_t *next_count;    // [kCountWords] counters of the next step (cleared here)
-    const uint8_t *lut;      // [12][256] gate value by packed pin values
 };
 
 // Dependency-driven schedule: one job per launch, no level barrier. A gate
@@ -142,7 +150,7 @@ hipError_t launch_level_scan(const StepArgs &a, hipStream_t s);
 // evaluate the work list of class `cls`; `max_items` bounds the list length
 // Wavefront kernel over the four pin-count lists of one delay window
 // (max_items[k-1]: upper bound of the k-pin list's length).
-hipError_t launch_eval_wave(const StepArgs &a, int large_window, const int64_t *max_items,
+hipError_t launch_eval_wave(const StepArgs &a, int variant, const int64_t *max_items,
                             hipStream_t s);
 // Counting-sort scatter of the wavefront lists into the two sorted lists
 // (max_items[c]: upper bound of list c's length, c < kListLane).

@@ -113,13 +113,14 @@ __device__ __forceinline__ uint32_t cost_segment(int64_t w, int k) {
 // wavefront kernel of its delay window and pin count -- appended to that list,
 // with its segment in the dispatch order and its rank in that segment.
 __global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
-    static_assert(2 * kSegments == kSizeBlock, "one thread per segment of both windows");
+    constexpr int kAllSegs = kVariants * kSegments;
+    static_assert(kAllSegs % kSizeBlock == 0, "segments per thread");
     __shared__ int64_t wsum[kSizeBlock / 64];
     __shared__ uint32_t l_cnt[kNumLists], l_base[kNumLists];
-    __shared__ uint32_t s_cnt[2 * kSegments], s_base[2 * kSegments];
+    __shared__ uint32_t s_cnt[kAllSegs], s_base[kAllSegs];
     const int64_t b = blockIdx.x;
     const int t = threadIdx.x;
-    s_cnt[t] = 0;
+    for (int q = t; q < kAllSegs; q += kSizeBlock) s_cnt[q] = 0;
     if (t < kNumLists) l_cnt[t] = 0;
     const int j = job_of_block(A.jobs, A.n_jobs, b);
     const JobDesc &J = A.jobs[j];
@@ -127,15 +128,16 @@ __global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
     const int64_t g = J.lvl_begin + i;
     int64_t w = 0;
     int cls = -1;
-    uint32_t seg_key = 0;  // window * kSegments + segment, for wavefront gates
+    uint32_t seg_key = 0;  // variant * kSegments + segment, for wavefront gates
     if (i < J.n_gates) {
         const GateRec &r = J.rec[g];
         const int k = r.k;
 #pragma unroll
         for (int p = 0; p < kMaxPins; p++)
             if (p < k) w += J.len[r.net[p]];
-        cls = (r.dmax > kWindowLarge || w < J.lane_threshold) ? kListLane
-              : wave_list(r.dmax > kWindowSmall ? 1 : 0, k);
+        cls = (r.dmax > kWindowLarge || w < J.lane_threshold)
+                  ? kListLane
+                  : wave_list(wave_variant(r.dmax > kWindowSmall ? 1 : 0, J.edly ? 1 : 0), k);
         if (cls != kListLane) seg_key = (uint32_t)(cls / 4) * kSegments + cost_segment(w, k);
     }
     const int lane = lane_id(), wv = t >> 6;
@@ -159,7 +161,8 @@ __global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
     if (wave_gate) spos = atomicAdd(&s_cnt[seg_key], 1u);
     __syncthreads();
     if (t < kNumLists && l_cnt[t]) l_base[t] = atomicAdd(&A.count[t], l_cnt[t]);
-    if (s_cnt[t]) s_base[t] = atomicAdd(&A.count[kSegCountAt + t], s_cnt[t]);
+    for (int q = t; q < kAllSegs; q += kSizeBlock)
+        if (s_cnt[q]) s_base[q] = atomicAdd(&A.count[kSegCountAt + q], s_cnt[q]);
     __syncthreads();
     if (cls >= 0) {
         const uint32_t pos = l_base[cls] + lpos;
@@ -233,10 +236,10 @@ struct ListBounds {
     int64_t cum[kListLane + 1];  // cumulative upper bounds of the list lengths
 };
 
-__global__ __launch_bounds__(2 * kSegments) void sort_lists_kernel(StepArgs A, ListBounds lb) {
-    static_assert(2 * kSegments == 256, "one thread per segment of both windows");
-    __shared__ uint32_t seg_base[2 * kSegments];
-    __shared__ uint32_t wave_tot[4];
+__global__ __launch_bounds__(kVariants * kSegments) void sort_lists_kernel(StepArgs A, ListBounds lb) {
+    static_assert(kSegments == 128, "two waves per variant");
+    __shared__ uint32_t seg_base[kVariants * kSegments];
+    __shared__ uint32_t wave_tot[2 * kVariants];
     const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
     const uint32_t cnt = A.count[kSegCountAt + t];
     uint32_t x = cnt;
@@ -247,7 +250,7 @@ __global__ __launch_bounds__(2 * kSegments) void sort_lists_kernel(StepArgs A, L
     }
     if (lane == 63) wave_tot[wv] = x;
     __syncthreads();
-    // windows: waves 0-1 and 2-3
+    // variant v: waves 2v and 2v + 1
     seg_base[t] = x - cnt + ((wv & 1) ? wave_tot[wv - 1] : 0u);
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + t;
@@ -258,8 +261,8 @@ __global__ __launch_bounds__(2 * kSegments) void sort_lists_kernel(StepArgs A, L
     const int64_t p = i - lb.cum[c];
     if (i < lb.cum[kListLane] && p < (int64_t)A.count[c]) {
         const uint64_t key = A.key[c][p];
-        const int win = c / 4;
-        A.sorted[win][seg_base[win * kSegments + (int)(key >> 32)] + (uint32_t)key] = A.list[c][p];
+        const int var = c / 4;
+        A.sorted[var][seg_base[var * kSegments + (int)(key >> 32)] + (uint32_t)key] = A.list[c][p];
     }
 }
 
@@ -355,6 +358,8 @@ struct WaveLds {
                                          // the pairwise-merge buffers alias seq[W, W + kMergeBuf)
     uint32_t tile[kRoundSlots + 4 * (kMergePad + 1)];  // K x [guard, T(p) keys, 8 INF]
     uint32_t dtab[48];                   // min delay by (new value, set of changed pins)
+    uint32_t etab[12];                   // edge model: per (pin, edge class) the delays to
+                                         // 0, 1 and X in 10-bit fields (kEdgeNone = unrelated)
     uint8_t lut[256];
 };
 static_assert(kMergeBuf <= kRoundSlots + 32, "merge buffers must fit the survivor area");
@@ -439,7 +444,15 @@ __device__ __forceinline__ uint32_t wave_suffix_min(uint32_t x) {
     return umin32(x, later_rows);
 }
 
-template <int K, int W>
+// Edge class of a pin change (extended delay model): 0 rise (new value 1, or
+// 0 -> X/Z), 1 fall (new value 0, or 1 -> X/Z), 2 both (X <-> Z).
+__device__ __forceinline__ uint32_t edge_class(uint32_t old_v, uint32_t new_v) {
+    return (new_v == 1u || (old_v == 0u && new_v >= 2u)) ? 0u
+           : (new_v == 0u || (old_v == 1u && new_v >= 2u)) ? 1u : 2u;
+}
+constexpr uint32_t kEdgeNone = 1023u;  // a 10-bit delay field of an unrelated pin
+
+template <int K, int W, bool EDGE>
 __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const GateRec &R,
                                           int64_t gate, WaveLds<W> &L) {
     using Tl = Tiling<K>;
@@ -477,7 +490,22 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
 #pragma unroll
     for (int p = 0; p < K; p++)
         if (lane < kMergePad) L.tile[Tl::OFF(p) + 1 + Tl::T(p) + lane] = kNoKey32;
-    if (lane < 48) {
+    if (EDGE) {
+        // per (pin, edge class): delays to 0, 1 and X; finite ones are <= W
+        if (lane < 3 * K) {
+            const int pin = lane / 3, c = lane % 3;
+            const int32_t *d = J.edly + (size_t)gate * 16 + pin * 4;  // [edge][out]
+            uint32_t f[3];
+#pragma unroll
+            for (int o = 0; o < 2; o++) {
+                const int32_t a = c == 1 ? kNoRelation : d[o], b = c == 0 ? kNoRelation : d[2 + o];
+                const int32_t m = a < b ? a : b;
+                f[o] = m == kNoRelation ? kEdgeNone : (uint32_t)m;
+            }
+            f[2] = f[0] < f[1] ? f[0] : f[1];
+            L.etab[lane] = f[0] | f[1] << 10 | f[2] << 20;
+        }
+    } else if (lane < 48) {
         const uint32_t ev = (uint32_t)lane >> 4, mask = (uint32_t)lane & 15u;
         int32_t d = INT32_MAX;
 #pragma unroll
@@ -490,6 +518,7 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
     }
 
     uint32_t last_val = kX;  // value of the last final survivor
+    bool first_round = true; // the gate's previous value is X until its first input change
     int nq = 0;              // tentative survivors in L.seq[0, nq), offsets from base_prev
     int64_t base_prev = 0;
     int64_t out_n = 0;
@@ -602,14 +631,17 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         const uint32_t next_first = wave_shift_down(kNoTime28, mk[0] >> 4);
         const uint32_t prev_trail = wave_shift_up(kNoKey32, t_last << 4 | trail_mask);
 
-        // ---- gate value after each transition; time-group ends
+        // ---- gate value after each transition; time-group ends; edge classes
         uint32_t st = (state0 & ~(upd_excl >> 8) & 0xFFu) | (upd_excl & 0xFFu);
-        uint32_t evs = 0;  // gate value after each transition, 2 bits each
+        uint32_t evs = 0;    // gate value after each transition, 2 bits each
+        uint32_t edges = 0;  // edge model: edge class of each transition, 2 bits each
         uint32_t ge = 0, e_lastge = 0;
 #pragma unroll
         for (int k = 0; k < 8; k++) {
             const uint32_t sh = K == 1 ? 0u : (mk[k] & 3u) * 2u;
-            st = (st & ~(3u << sh)) | (((mk[k] >> 2) & 3u) << sh);
+            const uint32_t nv = (mk[k] >> 2) & 3u;
+            if (EDGE) edges |= edge_class((st >> sh) & 3u, nv) << (2 * k);
+            st = (st & ~(3u << sh)) | (nv << sh);
             const uint32_t ek = L.lut[st];
             evs |= ek << (2 * k);
             const uint32_t tn = k < 7 ? mk[k + 1] >> 4 : next_first;
@@ -617,28 +649,61 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
             ge |= end ? 1u << k : 0u;
             e_lastge = end ? ek : e_lastge;
         }
-        const uint32_t e0 = L.lut[state0];
+        const uint32_t e0 = first_round ? kX : L.lut[state0];
         const uint32_t e_from_prev = wave_shift_up(e0, e_lastge);
+        // edge model: this lane's trailing time group, delays to 0/1/X (10-bit fields)
+        uint32_t prev_trail_d = 0;
+        if (EDGE) {
+            uint32_t d0 = kEdgeNone, d1 = kEdgeNone, dx = kEdgeNone;
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                if ((mk[k] >> 4) != t_last || mk[k] == kNoKey32) continue;
+                const uint32_t ent = L.etab[(mk[k] & 3u) * 3 + ((edges >> (2 * k)) & 3u)];
+                d0 = umin32(d0, ent & 1023u);
+                d1 = umin32(d1, (ent >> 10) & 1023u);
+                dx = umin32(dx, ent >> 20);
+            }
+            prev_trail_d = wave_shift_up(kEdgeNone | kEdgeNone << 10 | kEdgeNone << 20,
+                                         d0 | d1 << 10 | dx << 20);
+        }
 
         // ---- candidates at group ends
         uint32_t sk[8];
         {
             uint32_t run_t = prev_trail >> 4, run_m = prev_trail & 15u;
+            uint32_t r0 = prev_trail_d & 1023u, r1 = (prev_trail_d >> 10) & 1023u, rx = prev_trail_d >> 20;
             uint32_t e_prev = e_from_prev;
 #pragma unroll
             for (int k = 0; k < 8; k++) {
                 const uint32_t tk = mk[k] >> 4;
-                const uint32_t pbit = K == 1 ? 1u : 1u << (mk[k] & 3u);
-                run_m = tk == run_t ? run_m | pbit : pbit;
+                const bool cont = tk == run_t;
+                if (EDGE) {
+                    const uint32_t ent = L.etab[(mk[k] & 3u) * 3 + ((edges >> (2 * k)) & 3u)];
+                    r0 = cont ? umin32(r0, ent & 1023u) : ent & 1023u;
+                    r1 = cont ? umin32(r1, (ent >> 10) & 1023u) : (ent >> 10) & 1023u;
+                    rx = cont ? umin32(rx, ent >> 20) : ent >> 20;
+                } else {
+                    const uint32_t pbit = K == 1 ? 1u : 1u << (mk[k] & 3u);
+                    run_m = cont ? run_m | pbit : pbit;
+                }
                 run_t = tk;
                 sk[k] = kNoKey32;
                 if ((ge >> k) & 1u) {
                     const uint32_t ek = (evs >> (2 * k)) & 3u;
-                    if (ek != e_prev) sk[k] = ((tk + L.dtab[ek * 16 + run_m]) << 2) | ek;
+                    if (ek != e_prev) {
+                        if (EDGE) {
+                            const uint32_t d = ek == 0u ? r0 : ek == 1u ? r1 : rx;
+                            // no related pin changed: the candidate never appears
+                            if (d != kEdgeNone) sk[k] = ((tk + d) << 2) | ek;
+                        } else {
+                            sk[k] = ((tk + L.dtab[ek * 16 + run_m]) << 2) | ek;
+                        }
+                    }
                     e_prev = ek;
                 }
             }
         }
+        first_round = false;
         state0 = (state0 & ~(upd_all >> 8) & 0xFFu) | (upd_all & 0xFFu);
 
         // ---- survivors among this round's candidates
@@ -737,19 +802,20 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
     }
 }
 
-// Every gate of the step whose largest delay is at most W, in one launch, one
-// wavefront per entry of the window's sorted list (costliest first).
-template <int W>
+// Every gate of the step in one variant (largest delay at most W; delay model
+// EDGE), in one launch, one wavefront per entry of the variant's sorted list
+// (costliest first).
+template <int W, bool EDGE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void eval_wave_kernel(StepArgs A,
-                                                                                              int win) {
+                                                                                              int var) {
     __shared__ WaveLds<W> L;
     const int lane = lane_id();
     const int64_t item = blockIdx.x;
-    const int list0 = win * 4;
+    const int list0 = var * 4;
     const int64_t total = (int64_t)A.count[list0] + A.count[list0 + 1] + A.count[list0 + 2] +
                           A.count[list0 + 3];
     if (item >= total) return;
-    const uint64_t e = A.sorted[win][item];
+    const uint64_t e = A.sorted[var][item];
     const JobDesc &J = A.jobs[(int)(e >> 32)];
     const int64_t gate = (int64_t)(uint32_t)e;
     const GateRec R = J.rec[gate];
@@ -758,13 +824,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void ev
         return;
     }
     reinterpret_cast<uint32_t *>(L.lut)[lane] =
-        reinterpret_cast<const uint32_t *>(A.lut + (int)R.type * 256)[lane];
+        reinterpret_cast<const uint32_t *>(J.lut + (int)R.type * 256)[lane];
     const int64_t ob = A.blocksum[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + J.off[J.S + gate];
     switch (R.k) {
-    case 1: eval_gate<1, W>(J, ob, R, gate, L); break;
-    case 2: eval_gate<2, W>(J, ob, R, gate, L); break;
-    case 3: eval_gate<3, W>(J, ob, R, gate, L); break;
-    default: eval_gate<4, W>(J, ob, R, gate, L); break;
+    case 1: eval_gate<1, W, EDGE>(J, ob, R, gate, L); break;
+    case 2: eval_gate<2, W, EDGE>(J, ob, R, gate, L); break;
+    case 3: eval_gate<3, W, EDGE>(J, ob, R, gate, L); break;
+    default: eval_gate<4, W, EDGE>(J, ob, R, gate, L); break;
     }
 }
 
@@ -795,11 +861,13 @@ __device__ void eval_seq(const JobDesc &J, const GateRec &R, int64_t gate, int64
         if (te == kInf) break;
         int changed = 0;
         int pack = 0;
+        uint32_t edge_of_pin = 0;  // extended model: edge class of each changed pin
 #pragma unroll
         for (int p = 0; p < kMaxPins; p++) {
             if (idx[p] < pl[p]) {
                 const uint64_t kp = Kar[pb[p] + idx[p]];
                 if (key_time(kp) == te) {
+                    edge_of_pin |= edge_class(cv[p], key_value(kp)) << (2 * p);
                     cv[p] = key_value(kp);
                     idx[p]++;
                     changed |= 1 << p;
@@ -811,8 +879,28 @@ __device__ void eval_seq(const JobDesc &J, const GateRec &R, int64_t gate, int64
         if (e != prev) {
             int64_t d = kInf;
 #pragma unroll
-            for (int p = 0; p < kMaxPins; p++)
-                if (changed & (1 << p)) d = min64(d, pin_delay(R.rise[p], R.fall[p], e));
+            for (int p = 0; p < kMaxPins; p++) {
+                if (!(changed & (1 << p))) continue;
+                if (J.edly) {
+                    // extended model: this pin's delay for its edge and the new value
+                    const int32_t *dp = J.edly + (size_t)gate * 16 + p * 4;
+                    const uint32_t c = (uint32_t)(edge_of_pin >> (2 * p)) & 3u;
+#pragma unroll
+                    for (int ed = 0; ed < 2; ed++)
+#pragma unroll
+                        for (int o = 0; o < 2; o++) {
+                            const int32_t x = dp[ed * 2 + o];
+                            if ((c == 2u || c == (uint32_t)ed) && (e == kX || e == (uint32_t)o) && x != kNoRelation)
+                                d = min64(d, x);
+                        }
+                } else {
+                    d = min64(d, pin_delay(R.rise[p], R.fall[p], e));
+                }
+            }
+            if (d == kInf) {  // no related pin changed: the candidate never appears
+                prev = e;
+                continue;
+            }
             const int64_t tr = te + d;
             while (n > 0 && key_time(Kar[ob + n - 1]) >= tr) n--;
             const uint32_t cur = n > 0 ? key_value(Kar[ob + n - 1]) : kX;
@@ -844,7 +932,7 @@ __global__ __launch_bounds__(64) void eval_lane_kernel(StepArgs A) {
     }
     const GateRec R = J.rec[gate];
     const int64_t ob = A.blocksum[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + J.off[J.S + gate];
-    eval_seq(J, R, gate, ob, A.lut + (int)R.type * 256);
+    eval_seq(J, R, gate, ob, J.lut + (int)R.type * 256);
 }
 
 // -------------------------------------------------------------------------
@@ -918,6 +1006,7 @@ constexpr uint32_t kDfTickets = 2;
 // Arena space is reserved per wavefront in chunks of A.chunk transitions (or
 // one gate's bound if larger), so the arena top takes one atomic per chunk.
 
+template <bool EDGE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void dataflow_kernel(DfArgs A) {
     __shared__ WaveLds<kWindowLarge> L;
     const int lane = lane_id();
@@ -965,15 +1054,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
                     J.off[J.S + g] = 0;
                 }
             } else if (R.dmax > kWindowLarge) {
-                if (lane == 0) eval_seq(J, R, g, ob, A.lut + (int)R.type * 256);
+                if (lane == 0) eval_seq(J, R, g, ob, J.lut + (int)R.type * 256);
             } else {
                 reinterpret_cast<uint32_t *>(L.lut)[lane] =
-                    reinterpret_cast<const uint32_t *>(A.lut + (int)R.type * 256)[lane];
+                    reinterpret_cast<const uint32_t *>(J.lut + (int)R.type * 256)[lane];
                 switch (R.k) {
-                case 1: eval_gate<1, kWindowLarge>(J, ob, R, g, L); break;
-                case 2: eval_gate<2, kWindowLarge>(J, ob, R, g, L); break;
-                case 3: eval_gate<3, kWindowLarge>(J, ob, R, g, L); break;
-                default: eval_gate<4, kWindowLarge>(J, ob, R, g, L); break;
+                case 1: eval_gate<1, kWindowLarge, EDGE>(J, ob, R, g, L); break;
+                case 2: eval_gate<2, kWindowLarge, EDGE>(J, ob, R, g, L); break;
+                case 3: eval_gate<3, kWindowLarge, EDGE>(J, ob, R, g, L); break;
+                default: eval_gate<4, kWindowLarge, EDGE>(J, ob, R, g, L); break;
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1117,14 +1206,17 @@ hipError_t launch_level_scan(const StepArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_eval_wave(const StepArgs &a, int large_window, const int64_t *max_items,
+hipError_t launch_eval_wave(const StepArgs &a, int variant, const int64_t *max_items,
                             hipStream_t s) {
     const int64_t total = max_items[0] + max_items[1] + max_items[2] + max_items[3];
     if (total <= 0) return hipSuccess;
-    if (large_window)
-        eval_wave_kernel<kWindowLarge><<<dim3((unsigned)total), dim3(64), 0, s>>>(a, 1);
-    else
-        eval_wave_kernel<kWindowSmall><<<dim3((unsigned)total), dim3(64), 0, s>>>(a, 0);
+    const dim3 grid((unsigned)total), block(64);
+    switch (variant) {
+    case wave_variant(0, 0): eval_wave_kernel<kWindowSmall, false><<<grid, block, 0, s>>>(a, variant); break;
+    case wave_variant(1, 0): eval_wave_kernel<kWindowLarge, false><<<grid, block, 0, s>>>(a, variant); break;
+    case wave_variant(0, 1): eval_wave_kernel<kWindowSmall, true><<<grid, block, 0, s>>>(a, variant); break;
+    default: eval_wave_kernel<kWindowLarge, true><<<grid, block, 0, s>>>(a, variant); break;
+    }
     return hipGetLastError();
 }
 
@@ -1133,8 +1225,9 @@ hipError_t launch_sort_lists(const StepArgs &a, const int64_t *max_items, hipStr
     lb.cum[0] = 0;
     for (int c = 0; c < kListLane; c++) lb.cum[c + 1] = lb.cum[c] + max_items[c];
     if (lb.cum[kListLane] <= 0) return hipSuccess;
-    const int64_t blocks = (lb.cum[kListLane] + 2 * kSegments - 1) / (2 * kSegments);
-    sort_lists_kernel<<<dim3((unsigned)blocks), dim3(2 * kSegments), 0, s>>>(a, lb);
+    constexpr int kThreads = kVariants * kSegments;
+    const int64_t blocks = (lb.cum[kListLane] + kThreads - 1) / kThreads;
+    sort_lists_kernel<<<dim3((unsigned)blocks), dim3(kThreads), 0, s>>>(a, lb);
     return hipGetLastError();
 }
 
@@ -1152,7 +1245,10 @@ hipError_t launch_df_init(const DfArgs &a, const int32_t *pend0, hipStream_t s) 
 
 hipError_t launch_dataflow(const DfArgs &a, int64_t n_waves, hipStream_t s) {
     if (a.G <= 0 || n_waves <= 0) return hipSuccess;
-    dataflow_kernel<<<dim3((unsigned)n_waves), dim3(64), 0, s>>>(a);
+    if (a.job.edly)
+        dataflow_kernel<true><<<dim3((unsigned)n_waves), dim3(64), 0, s>>>(a);
+    else
+        dataflow_kernel<false><<<dim3((unsigned)n_waves), dim3(64), 0, s>>>(a);
     return hipGetLastError();
 }
 

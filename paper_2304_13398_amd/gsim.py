@@ -19,8 +19,10 @@ OK, E_ARG, E_CYCLE, E_WAVEFORM, E_OOM, E_DEVICE, E_HANDLE, E_OVERFLOW = 0, -1, -
 STATUS_NAMES = {0: "OK", -1: "GSIM_E_ARG", -2: "GSIM_E_CYCLE", -3: "GSIM_E_WAVEFORM",
                 -4: "GSIM_E_OOM", -5: "GSIM_E_DEVICE", -6: "GSIM_E_HANDLE", -7: "GSIM_E_OVERFLOW"}
 OPT_ARENA_TRANSITIONS, OPT_KERNEL, OPT_KERNEL_TIMING, OPT_LANE_THRESHOLD, OPT_SCHEDULE = 1, 2, 4, 5, 6
+NO_RELATION = 2**31 - 1
 
 EXPORTED = ("sim_create", "sim_destroy", "sim_last_error", "sim_set_option", "sim_load_netlist",
+            "sim_load_netlist_ext",
             "sim_unload_netlist", "sim_set_netlist_option", "sim_netlist_info", "sim_submit", "sim_submit_device", "sim_run",
             "sim_run_device", "sim_run_batch", "sim_drive", "sim_job_done", "sim_wait",
             "sim_job_stats", "sim_fetch_waveforms", "sim_fetch_hashes", "sim_release_job", "sim_levelize",
@@ -72,6 +74,7 @@ def load_library(path: str = LIB_PATH):
         "sim_last_error": ([P], ctypes.c_char_p),
         "sim_set_option": ([P, ctypes.c_int, i64], st),
         "sim_load_netlist": ([P, i64, i64, P, P, P, P, P, P], st),
+        "sim_load_netlist_ext": ([P, i64, i64, P, P, P, P, ctypes.c_int32, P, P], st),
         "sim_unload_netlist": ([P, i64], st),
         "sim_netlist_info": ([P, i64, P], st),
         "sim_set_netlist_option": ([P, i64, ctypes.c_int, i64], st),
@@ -162,6 +165,21 @@ class Sim:
 
     def set_option(self, option: int, value: int):
         self._ck(self.lib.sim_set_option(self.ctx, option, int(value)))
+
+    def load_netlist_ext(self, nl, dly, udp=None) -> int:
+        """Extended cell model: ``dly`` int32 [P, 2, 2] (input edge rise/fall,
+        output 0/1; NO_RELATION = unrelated pin); ``udp`` uint8 [n, 256] tables
+        of user-defined types 12 + i. nl.type may use those types."""
+        d = _c(dly, np.int32).reshape(-1)
+        if d.size != 4 * int(nl.pin_off[-1] if len(nl.pin_off) else 0):
+            raise ValueError("dly must have shape [P, 2, 2]")
+        u = _c(udp if udp is not None else np.zeros((0, 256)), np.uint8)
+        arrs = (_c(nl.type, np.uint8), _c(nl.pin_off, np.int64), _c(nl.pin_net, np.int64))
+        h = ctypes.c_int64()
+        self._ck(self.lib.sim_load_netlist_ext(self.ctx, nl.S, nl.G, *[_p(a) for a in arrs], _p(d),
+                                               len(u), _p(u) if len(u) else None, ctypes.byref(h)))
+        self._nl_nets[h.value] = nl.S + nl.G
+        return h.value
 
     def load_netlist(self, nl) -> int:
         """``nl`` has S, G, type, pin_off, pin_net, rise, fall (workloads.Netlist)."""

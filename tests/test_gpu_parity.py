@@ -341,3 +341,55 @@ def test_skewed_source_activity(sim, wcv):
     as in the paper's WCV): heavy-tailed gate sizes, some silent sources."""
     nl, st = W.config2_skewed(wcv, G=20_000, S=256, L=30, seed=5)
     check(sim, nl, st)
+
+
+def ext_check(sim, nl, st, dly, udp, kernel=0):
+    say(f"extended model {nl.name} G={nl.G} N_in={st.n} udp={len(udp)} kernel={kernel}")
+    want = O.o1x_simulate(nl, st, dly, udp)
+    sim.set_option(G.OPT_KERNEL, kernel)
+    try:
+        h = sim.load_netlist_ext(nl, dly, udp)
+        try:
+            j = sim.run(h, st)
+            got = sim.fetch(j, np.arange(nl.S, nl.S + nl.G))
+            sim.release(j)
+        finally:
+            sim.unload_netlist(h)
+    finally:
+        sim.set_option(G.OPT_KERNEL, 0)
+    assert_same(got, want, nl)
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_edge_delays_and_user_tables_tiny(sim, kernel):
+    """Delays by pin, input edge and output value, with unrelated (inf)
+    entries; user-defined gate tables (including ones that map all-X inputs
+    to 0 or 1); wavefront and lane kernels."""
+    nl, st = W.config1(seed=6)
+    type_, dly, udp = W.make_cell_model(nl, seed=6, edge_spread=0.8, inf_prob=0.2, n_udp=8, udp_frac=0.4)
+    ext_check(sim, W.with_types(nl, type_), st, dly, udp, kernel)
+
+
+def test_edge_delays_mid_generator(sim):
+    nl, st = W.config2(G=20_000, S=64, L=30, n_per_src=400, seed=7)
+    type_, dly, udp = W.make_cell_model(nl, seed=7, edge_spread=0.5, inf_prob=0.05, n_udp=6, udp_frac=0.2)
+    ext_check(sim, W.with_types(nl, type_), st, dly, udp)
+
+
+def test_edge_delays_across_windows_and_xz_sources(sim):
+    """Delays from 0 to 400 ps (small and large windows and the lane kernel),
+    X and Z as likely as 0 and 1 at the sources."""
+    nl = W.make_netlist(G=3000, S=40, L=20, types=W.TYPES_ALL, dmin=0, dmax=400, seed=8, name="wide")
+    st = W.make_stimulus(S=40, n_per_src=300, window=50_000, probs=(0.25, 0.25, 0.25, 0.25), seed=8)
+    type_, dly, udp = W.make_cell_model(nl, seed=8, edge_spread=0.9, inf_prob=0.15, n_udp=8, udp_frac=0.5)
+    ext_check(sim, W.with_types(nl, type_), st, dly, udp)
+
+
+def test_edge_free_extended_load_equals_basic(sim):
+    """The extended loader with delays that do not depend on the edge gives
+    the basic model's result (different kernel variant, same definition)."""
+    nl, st = W.config2(G=8000, S=48, L=25, n_per_src=300, seed=9)
+    d = np.zeros((nl.P, 2, 2), dtype=np.int32)
+    d[:, :, 0] = nl.fall[:, None]
+    d[:, :, 1] = nl.rise[:, None]
+    ext_check(sim, nl, st, d, np.zeros((0, 256), np.uint8))
