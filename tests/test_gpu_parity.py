@@ -393,3 +393,12 @@ def test_edge_free_extended_load_equals_basic(sim):
     d[:, :, 0] = nl.fall[:, None]
     d[:, :, 1] = nl.rise[:, None]
     ext_check(sim, nl, st, d, np.zeros((0, 256), np.uint8))
+
+
+def test_standard_cell_netlist(sim):
+    """Multi-output library cells (adders, AOI, decoder, gated mux) expanded
+    into table gates with per-output delay matrices."""
+    from paper_2304_13398_amd import cells as CL
+    nl, dly, udp = CL.random_cell_netlist(3000, S=48, seed=10)
+    st = W.make_stimulus(S=48, n_per_src=200, window=100_000, seed=10)
+    ext_check(sim, nl, st, dly, udp)
