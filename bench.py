@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--cpu-levels", type=int, default=25,
                     help="levels of the workload the oracle runs for the CPU baseline")
     ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-configuration latency")
+    ap.add_argument("--no-industrial", action="store_true",
+                    help="skip the 10M-gate industrial-shaped configuration")
     ap.add_argument("--no-windows", action="store_true",
                     help="skip the exact time-window chunking measurement")
     ap.add_argument("--no-skewed", action="store_true",
@@ -88,7 +90,7 @@ def parse():
     ap.add_argument("--no-served", action="store_true",
                     help="skip the served section (Poisson requests over 8 resident netlists)")
     ap.add_argument("--served-jobs", type=int, default=300)
-    ap.add_argument("--served-rates", default="50,200", help="request rates (jobs/s), comma separated")
+    ap.add_argument("--served-rates", default="25,100,500", help="request rates (jobs/s), comma separated")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="instead of the workload, time a plain device-to-device copy of BYTES "
                          "(the practical HBM ceiling, and the reference for the profiler's "
@@ -350,6 +352,41 @@ def bench_windows(G, sim, nl, h, st, n_out_whole, ms_whole, n_windows=4):
             "overhead": dev_ms / ms_whole - 1.0}
 
 
+def bench_industrial(G, sim, seed, steps=3):
+    """The industrial-shaped configuration: 10M gates, 8,192 PIs + 50,000
+    pseudo-PIs, 150 levels, fan-in 1-4, fanout cap 5,000, 1-200 ps delays, 200
+    transitions per source (2 % X/Z); stimuli resident in HBM, one job at a
+    time, wall time per job."""
+    import torch
+    from paper_2304_13398_amd import workloads as W
+    t = time.perf_counter()
+    nl, st = W.config3(seed=seed)
+    gen_s = time.perf_counter() - t
+    h = sim.load_netlist(nl)
+    dev = torch.device("cuda:0")
+    d = [torch.from_numpy(a).to(dev) for a in (st.off, st.t, st.v)]
+    stream = torch.cuda.current_stream()
+    times, n_out, dev_ms = [], 0, []
+    for i in range(steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        j = sim.run_device(h, d[0].data_ptr(), d[1].data_ptr(), d[2].data_ptr(), st.n,
+                           stream=stream.cuda_stream)
+        sim.wait(j)
+        if i > 0:
+            times.append(time.perf_counter() - t0)
+            dev_ms.append(sim.stats(j).device_ms)
+        n_out = sim.stats(j).n_out
+        sim.release(j)
+    sim.unload_netlist(h)
+    ms = statistics.median(times) * 1000.0
+    print(f"[bench] industrial: {ms:.1f} ms per job ({gen_s:.0f}s to generate)", file=sys.stderr, flush=True)
+    return {"workload": "industrial-shaped: 10M gates, 8,192 PIs + 50,000 pseudo-PIs, 150 levels, "
+                        "fan-in 1-4, fanout cap 5,000, rise/fall 1-200 ps, 200 transitions per source",
+            "gates": nl.G, "sources": nl.S, "n_in": st.n, "n_out": int(n_out), "ms_per_job": ms,
+            "device_ms": statistics.median(dev_ms), "transitions_per_s": n_out / (ms / 1000.0)}
+
+
 def workload_stats(nl, lengths):
     """The paper's workload statistics (Table 2 columns and Eq. 5): coefficient
     of variation of the given (source) waveform lengths and of the generated
@@ -593,6 +630,8 @@ def main():
     if not args.no_batched:
         out["batched"] = bench_batched(G, sim, nl, h, args.batched_sets, args.seed)
     sim.unload_netlist(h)
+    if not args.no_industrial:
+        out["industrial"] = bench_industrial(G, sim, args.seed)
     if not args.no_served:
         rates = [float(x) for x in args.served_rates.split(",") if x]
         out["served"] = bench_served(G, sim, args.served_jobs, rates, args.seed)
