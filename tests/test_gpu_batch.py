@@ -208,3 +208,38 @@ def test_time_windows_on_the_gpu_equal_the_oracle(sim, n_windows):
         close()
     say(f"windows: {n_windows}, halo {WN.window_halo(nl)} ps")
     assert same(got, O.o1_simulate(nl, st))
+
+
+def test_mixed_delay_models_share_steps(sim):
+    """Jobs of a basic netlist, an extended one (edge delays, user tables) and
+    a cell netlist advance in the same steps: every evaluate variant and each
+    job's own gate tables in shared launches; each equals its oracle."""
+    from paper_2304_13398_amd import cells as CL
+    nl_a = W.config2_netlist(G=4000, S=40, L=25, seed=21)
+    nl_b = W.config2_netlist(G=3000, S=32, L=20, seed=22)
+    type_b, dly_b, udp_b = W.make_cell_model(nl_b, seed=22, edge_spread=0.7, inf_prob=0.1, n_udp=6, udp_frac=0.3)
+    ext_b = W.with_types(nl_b, type_b)
+    nl_c, dly_c, udp_c = CL.random_cell_netlist(1500, S=24, seed=23, dmax=120)
+    h_a, h_b = sim.load_netlist(nl_a), sim.load_netlist_ext(ext_b, dly_b, udp_b)
+    h_c = sim.load_netlist_ext(nl_c, dly_c, udp_c)
+    jobs = []
+    for k in range(6):
+        which = k % 3
+        nl, h = ((nl_a, h_a), (ext_b, h_b), (nl_c, h_c))[which]
+        st = W.make_stimulus(S=nl.S, n_per_src=60 + 40 * k, window=200_000, seed=400 + k)
+        jobs.append((sim.submit(h, st), which, nl, st))
+        sim.drive()
+    while any(not sim.done(j) for j, _, _, _ in jobs):
+        sim.drive(max_ahead=2)
+    for j, which, nl, st in jobs:
+        sim.wait(j)
+        if which == 0:
+            want = O.o1_simulate(nl, st)
+        elif which == 1:
+            want = O.o1x_simulate(nl, st, dly_b, udp_b)
+        else:
+            want = O.o1x_simulate(nl, st, dly_c, udp_c)
+        assert same(fetch_gates(sim, j, nl), want), f"job {j} (netlist {which})"
+        sim.release(j)
+    for h in (h_a, h_b, h_c):
+        sim.unload_netlist(h)
