@@ -439,6 +439,10 @@ struct Job {
     std::vector<std::shared_ptr<StepTiming>> timing;
     int64_t n_partial = 0;
     bool dataflow = false;        // dependency-driven schedule (one launch for every gate)
+    // the job's step descriptor of every level, for steps it has alone
+    // (uploaded once at admission instead of once per step)
+    JobDesc *h_desc = nullptr;    // pinned
+    JobDesc *d_desc = nullptr;
     int32_t *d_pend = nullptr, *d_queue = nullptr;
     DfCtl *d_ctl = nullptr;
     int32_t retries = 0;          // automatic re-runs after an arena overflow
@@ -805,6 +809,8 @@ void free_job_buffers(gsim_ctx ctx, Job *j) {
     pool.put(j->d_pend);
     pool.put(j->d_queue);
     pool.put(j->d_ctl);
+    pool.put(j->d_desc);
+    j->d_desc = nullptr;
     j->d_off = j->d_len = j->d_partial = j->d_src_off = nullptr;
     j->d_K = nullptr;
     j->d_state = nullptr;
@@ -824,6 +830,8 @@ void destroy_job(gsim_ctx ctx, Job *j) {
     if (j->nl) j->nl->active_jobs--;
     free_job_buffers(ctx, j);
     ctx->pinned.put(j->h_state);
+    ctx->pinned.put(j->h_desc);
+    j->h_desc = nullptr;
     ctx->pinned.put(j->h_src_off);
     ctx->pinned.put(j->h_t);
     ctx->pinned.put(j->h_v);
@@ -932,6 +940,24 @@ Failure finish_job(Job *j, hipStream_t s) {
     HIP_TRY(hipEventRecord(j->ev_done, s));
     j->phase = kEnqueued;
     return kOk;
+}
+
+// A job's step descriptor for one level, its sizing blocks starting at sblock_begin.
+void fill_desc(gsim_ctx ctx, Job *j, int32_t level, int64_t sblock_begin, JobDesc &d) {
+    const LevelRange &r = j->nl->levels[level];
+    d.rec = j->nl->d_rec;
+    d.S = j->nl->S;
+    d.off = j->d_off;
+    d.len = j->d_len;
+    d.K = j->d_K;
+    d.state = j->d_state;
+    d.lvl_begin = r.begin;
+    d.n_gates = r.n;
+    d.sblock_begin = sblock_begin;
+    d.lane_threshold = j->nl->lane_threshold >= 0 ? j->nl->lane_threshold : ctx->opt_lane_threshold;
+    d.pad = 0;
+    d.lut = j->nl->d_lut ? j->nl->d_lut : ctx->d_lut;
+    d.edly = j->nl->d_edly;
 }
 
 // Every gate of an admitted job in one dependency-driven launch.
@@ -1066,6 +1092,18 @@ Failure admit(gsim_ctx ctx, Executor *ex, Job *j) {
     j->next_level = 0;
     if (nl.n_levels == 0) return finish_job(j, s);
     if (j->dataflow) return enqueue_dataflow(ctx, j, s);
+    // descriptors for the steps this job has alone (optional: skipped if no memory)
+    const size_t desc_bytes = sizeof(JobDesc) * (size_t)nl.n_levels;
+    if (!j->h_desc) j->h_desc = (JobDesc *)ctx->pinned.get(desc_bytes);
+    j->d_desc = j->h_desc ? pool_get<JobDesc>(pool, nl.n_levels) : nullptr;
+    if (j->d_desc) {
+        for (int32_t l = 0; l < nl.n_levels; l++) {
+            JobDesc &d = j->h_desc[l];
+            std::memset(&d, 0, sizeof d);
+            fill_desc(ctx, j, l, 0, d);
+        }
+        HIP_TRY(hipMemcpyAsync(j->d_desc, j->h_desc, desc_bytes, hipMemcpyHostToDevice, s));
+    }
     ex->active.push_back(j);
     return kOk;
 }
@@ -1103,19 +1141,7 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
         Job *j = act[i];
         const LevelRange &r = j->nl->levels[j->next_level];
         JobDesc &d = desc[i];
-        d.rec = j->nl->d_rec;
-        d.S = j->nl->S;
-        d.off = j->d_off;
-        d.len = j->d_len;
-        d.K = j->d_K;
-        d.state = j->d_state;
-        d.lvl_begin = r.begin;
-        d.n_gates = r.n;
-        d.sblock_begin = n_sblocks;
-        d.lane_threshold = j->nl->lane_threshold >= 0 ? j->nl->lane_threshold : ctx->opt_lane_threshold;
-        d.pad = 0;
-        d.lut = j->nl->d_lut ? j->nl->d_lut : ctx->d_lut;
-        d.edly = j->nl->d_edly;
+        fill_desc(ctx, j, j->next_level, n_sblocks, d);
         n_sblocks += (r.n + kSizeBlock - 1) / kSizeBlock;
         n_items += r.n;
         for (int c = 0; c < kNumLists; c++) n_list[c] += r.n_list[c];
@@ -1128,11 +1154,18 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
     if (f.st == GSIM_OK) f = ensure_lists(ctx, ex, n_items);
     if (f.st != GSIM_OK) return f;
     hipStream_t s = ex->stream;
-    HIP_TRY(hipMemcpyAsync(ex->d_jobs, desc, sizeof(JobDesc) * (size_t)n, hipMemcpyHostToDevice, s));
+    // a job alone in the step uses its descriptor table from admission (the
+    // lane threshold is the one in force at admission)
+    const JobDesc *step_jobs = ex->d_jobs;
+    if (n == 1 && act[0]->d_desc) {
+        step_jobs = act[0]->d_desc + act[0]->next_level;
+    } else {
+        HIP_TRY(hipMemcpyAsync(ex->d_jobs, desc, sizeof(JobDesc) * (size_t)n, hipMemcpyHostToDevice, s));
+    }
     HIP_TRY(hipEventRecord(ex->ring_ev[slot], s));
     ex->ring_used[slot] = true;
     StepArgs a;
-    a.jobs = ex->d_jobs;
+    a.jobs = step_jobs;
     a.n_jobs = n;
     a.pad = 0;
     a.n_sblocks = n_sblocks;
@@ -1143,7 +1176,6 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
     a.count = ex->d_counts + ex->parity * kCountWords;
     a.next_count = ex->d_counts + (1 - ex->parity) * kCountWords;
     HIP_TRY(launch_size(a, s));
-    HIP_TRY(launch_level_scan(a, s));
     HIP_TRY(launch_sort_lists(a, n_list, s));
     std::shared_ptr<StepTiming> tm;
     if (ctx->opt_timing) {

@@ -146,13 +146,14 @@ hipError_t launch_init_sources(const int64_t *d_src_off, const int64_t *d_t, con
                                DevState *state, int64_t capacity, hipStream_t s);
 // size + classify (grid: n_sblocks), then per-job scan (grid: n_jobs)
 hipError_t launch_size(const StepArgs &a, hipStream_t s);
-hipError_t launch_level_scan(const StepArgs &a, hipStream_t s);
 // evaluate the work list of class `cls`; `max_items` bounds the list length
 // Wavefront kernel over the four pin-count lists of one delay window
 // (max_items[k-1]: upper bound of the k-pin list's length).
 hipError_t launch_eval_wave(const StepArgs &a, int variant, const int64_t *max_items,
                             hipStream_t s);
-// Counting-sort scatter of the wavefront lists into the two sorted lists
+// Per job of the step: its level's arena bases (exclusive scan of the sizing
+// blocks' totals, arena top bumped, overflow flagged); then the counting-sort
+// scatter of the wavefront lists into one sorted list per variant
 // (max_items[c]: upper bound of list c's length, c < kListLane).
 hipError_t launch_sort_lists(const StepArgs &a, const int64_t *max_items, hipStream_t s);
 hipError_t launch_eval_lane(const StepArgs &a, int64_t max_items, hipStream_t s);

@@ -180,19 +180,20 @@ __global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
     if (t == 0) A.blocksum[b] = total;
 }
 
-// One block per job: the job's block totals -> absolute arena bases; bump the
-// job's arena top (a device bump allocator); flag overflow.
-__global__ __launch_bounds__(1024) void level_scan_kernel(StepArgs A) {
+// One block per job (any block size up to 1024): the job's block totals ->
+// absolute arena bases; bump the job's arena top (a device bump allocator);
+// flag overflow.
+__device__ void job_scan(const StepArgs &A, int job) {
     __shared__ int64_t wsum[16];
     __shared__ int64_t carry_s;
-    const JobDesc &J = A.jobs[blockIdx.x];
+    const JobDesc &J = A.jobs[job];
     DevState *state = J.state;
     int64_t *blocksum = A.blocksum + J.sblock_begin;
     const int64_t nb = (J.n_gates + kSizeBlock - 1) / kSizeBlock;
-    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int lane = lane_id(), wv = threadIdx.x >> 6, n_waves = (int)blockDim.x >> 6;
     if (threadIdx.x == 0) carry_s = state->arena_top;
     __syncthreads();
-    for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
+    for (int64_t c0 = 0; c0 < nb; c0 += blockDim.x) {
         const int64_t i = c0 + threadIdx.x;
         const int64_t w = i < nb ? blocksum[i] : 0;
         int64_t x = w;
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(1024) void level_scan_kernel(StepArgs A) {
         if (lane == 63) wsum[wv] = x;
         __syncthreads();
         int64_t before = 0, total = 0;
-        for (int q = 0; q < 16; q++) {
+        for (int q = 0; q < n_waves; q++) {
             if (q < wv) before += wsum[q];
             total += wsum[q];
         }
@@ -230,8 +231,8 @@ __global__ __launch_bounds__(1024) void level_scan_kernel(StepArgs A) {
 
 // -------------------------------------------------------------------------
 // Counting-sort scatter of the wavefront lists: entry (c, pos) goes to
-// sorted[window][base of its segment + its rank]. The segment bases are an
-// exclusive scan of the segment sizes per window, redone by every block.
+// sorted[variant][base of its segment + its rank]. The segment bases are an
+// exclusive scan of the segment sizes per variant, redone by every block.
 struct ListBounds {
     int64_t cum[kListLane + 1];  // cumulative upper bounds of the list lengths
 };
@@ -240,6 +241,8 @@ __global__ __launch_bounds__(kVariants * kSegments) void sort_lists_kernel(StepA
     static_assert(kSegments == 128, "two waves per variant");
     __shared__ uint32_t seg_base[kVariants * kSegments];
     __shared__ uint32_t wave_tot[2 * kVariants];
+    // the first n_jobs blocks also place their job's level in the arena
+    if ((int)blockIdx.x < A.n_jobs) job_scan(A, (int)blockIdx.x);
     const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
     const uint32_t cnt = A.count[kSegCountAt + t];
     uint32_t x = cnt;
@@ -1200,11 +1203,6 @@ hipError_t launch_size(const StepArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_level_scan(const StepArgs &a, hipStream_t s) {
-    if (a.n_jobs == 0) return hipSuccess;
-    level_scan_kernel<<<dim3((unsigned)a.n_jobs), dim3(1024), 0, s>>>(a);
-    return hipGetLastError();
-}
 
 hipError_t launch_eval_wave(const StepArgs &a, int variant, const int64_t *max_items,
                             hipStream_t s) {
@@ -1224,9 +1222,10 @@ hipError_t launch_sort_lists(const StepArgs &a, const int64_t *max_items, hipStr
     ListBounds lb;
     lb.cum[0] = 0;
     for (int c = 0; c < kListLane; c++) lb.cum[c + 1] = lb.cum[c] + max_items[c];
-    if (lb.cum[kListLane] <= 0) return hipSuccess;
+    if (lb.cum[kListLane] <= 0 && a.n_jobs <= 0) return hipSuccess;
     constexpr int kThreads = kVariants * kSegments;
-    const int64_t blocks = (lb.cum[kListLane] + kThreads - 1) / kThreads;
+    int64_t blocks = (lb.cum[kListLane] + kThreads - 1) / kThreads;
+    blocks = blocks > a.n_jobs ? blocks : a.n_jobs;
     sort_lists_kernel<<<dim3((unsigned)blocks), dim3(kThreads), 0, s>>>(a, lb);
     return hipGetLastError();
 }
