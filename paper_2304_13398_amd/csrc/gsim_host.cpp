@@ -983,6 +983,9 @@ Failure enqueue_dataflow(gsim_ctx ctx, Job *j, hipStream_t s) {
     const int64_t n_waves = std::min<int64_t>(nl.G, ctx->n_waves_resident);
     // reservation granule: at most 1/16 of the arena left idle over all wavefronts
     a.chunk = std::min<int64_t>(int64_t(1) << 15, (j->capacity - j->n_in) / (16 * std::max<int64_t>(n_waves, 1)));
+    // small jobs are latency-bound: one ticket per claim keeps every ready gate
+    // on a wavefront of its own; large ones are bound by the claim counter
+    a.tickets = nl.G < 16 * ctx->n_waves_resident ? 1u : 2u;
     HIP_TRY(launch_df_init(a, nl.d_pend0, s));
     std::shared_ptr<StepTiming> tm;
     if (ctx->opt_timing) {

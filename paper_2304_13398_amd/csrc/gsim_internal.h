@@ -138,6 +138,7 @@ struct DfArgs {
     int64_t G;
     int64_t n_first;        // gates reading sources only (the first level): ready at the start
     int64_t chunk;          // arena reservation granule per wavefront, in transitions
+    uint32_t tickets;       // queue slots a wavefront claims per atomic (1..4)
 };
 
 // Kernel launchers (kernels.hip). All are asynchronous on `s`.

@@ -1001,11 +1001,13 @@ __device__ int32_t df_wait_slot(const DfArgs &A, uint32_t t, DevState *st) {
     }
 }
 
-// Tickets taken per atomic: a wavefront works through its tickets in order.
-// Queue slots are allocated in the order gates become ready, so while a
-// wavefront waits on its next slot no later slot holds a ready gate that
-// only it could run (the deadlock-freedom argument is unchanged).
-constexpr uint32_t kDfTickets = 2;
+// A wavefront takes A.tickets (1..kDfMaxTickets) consecutive tickets per
+// atomic and works through them in order. Queue slots are allocated in the
+// order gates become ready, so while a wavefront waits on its next slot no
+// later slot holds a ready gate that only it could run (the deadlock-freedom
+// argument is unchanged). More tickets per atomic relieve the one contended
+// counter; fewer keep gates near the critical path on wavefronts of their own.
+constexpr uint32_t kDfMaxTickets = 4;
 // Arena space is reserved per wavefront in chunks of A.chunk transitions (or
 // one gate's bound if larger), so the arena top takes one atomic per chunk.
 
@@ -1020,71 +1022,95 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
     bool stop = false;
     while (!stop) {
         uint32_t t0 = 0;
-        if (lane == 0) t0 = atomicAdd(&A.ctl->head, kDfTickets);
+        if (lane == 0) t0 = atomicAdd(&A.ctl->head, A.tickets);
         t0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)t0);
         if ((int64_t)t0 >= A.G) break;
-        const uint32_t t1 = (uint32_t)min64((int64_t)t0 + kDfTickets, A.G);
-        for (uint32_t t = t0; t < t1; t++) {
-            const int32_t g = df_wait_slot(A, t, st);
-            if (g < 0) {
+        const uint32_t t1 = (uint32_t)min64((int64_t)t0 + A.tickets, A.G);
+        uint32_t t = t0;
+        while (t < t1) {
+            // the next gate, and the one after if its slot is already filled:
+            // both run between one acquire and one release fence
+            const int32_t g0 = df_wait_slot(A, t, st);
+            if (g0 < 0) {
                 stop = true;
                 break;
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-
-            const GateRec R = J.rec[g];
-            int64_t w = 0;
-#pragma unroll
-            for (int p = 0; p < kMaxPins; p++)
-                if (p < R.k) w += J.len[R.net[p]];
-            reads += w;
-            if (chunk_end - chunk_at < w) {
-                const int64_t want = w > A.chunk ? w : A.chunk;
-                int64_t at = 0;
-                if (lane == 0)
-                    at = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&st->arena_top),
-                                            (unsigned long long)want);
-                chunk_at = (int64_t)readlane_u64((uint64_t)at, 0);
-                chunk_end = chunk_at + want;
-            }
-            const int64_t ob = chunk_at;
-            chunk_at += w;
-            const bool full = ob + w > st->capacity;
-            if (full || load_agent(reinterpret_cast<const uint32_t *>(&st->overflow))) {
+            // later tickets whose slots are already filled join the batch
+            int32_t g1 = -1, g2 = -1, g3 = -1;
+            int nb = 1;
+            if (t + 1 < t1) {
+                uint32_t q[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
                 if (lane == 0) {
-                    if (full) atomicOr(&st->overflow, 1);
-                    J.len[J.S + g] = 0;
-                    J.off[J.S + g] = 0;
+#pragma unroll
+                    for (int x = 0; x < 3; x++)
+                        if (t + 1 + x < t1) q[x] = load_agent(reinterpret_cast<const uint32_t *>(A.queue + t + 1 + x));
                 }
-            } else if (R.dmax > kWindowLarge) {
-                if (lane == 0) eval_seq(J, R, g, ob, J.lut + (int)R.type * 256);
-            } else {
-                reinterpret_cast<uint32_t *>(L.lut)[lane] =
-                    reinterpret_cast<const uint32_t *>(J.lut + (int)R.type * 256)[lane];
-                switch (R.k) {
-                case 1: eval_gate<1, kWindowLarge, EDGE>(J, ob, R, g, L); break;
-                case 2: eval_gate<2, kWindowLarge, EDGE>(J, ob, R, g, L); break;
-                case 3: eval_gate<3, kWindowLarge, EDGE>(J, ob, R, g, L); break;
-                default: eval_gate<4, kWindowLarge, EDGE>(J, ob, R, g, L); break;
+                g1 = __builtin_amdgcn_readfirstlane((int)q[0]);
+                g2 = __builtin_amdgcn_readfirstlane((int)q[1]);
+                g3 = __builtin_amdgcn_readfirstlane((int)q[2]);
+                nb = g1 < 0 ? 1 : g2 < 0 ? 2 : g3 < 0 ? 3 : 4;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            for (int b = 0; b < nb; b++) {
+                const int32_t g = b == 0 ? g0 : b == 1 ? g1 : b == 2 ? g2 : g3;
+                const GateRec R = J.rec[g];
+                int64_t w = 0;
+#pragma unroll
+                for (int p = 0; p < kMaxPins; p++)
+                    if (p < R.k) w += J.len[R.net[p]];
+                reads += w;
+                if (chunk_end - chunk_at < w) {
+                    const int64_t want = w > A.chunk ? w : A.chunk;
+                    int64_t at = 0;
+                    if (lane == 0)
+                        at = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&st->arena_top),
+                                                (unsigned long long)want);
+                    chunk_at = (int64_t)readlane_u64((uint64_t)at, 0);
+                    chunk_end = chunk_at + want;
+                }
+                const int64_t ob = chunk_at;
+                chunk_at += w;
+                const bool full = ob + w > st->capacity;
+                if (full || load_agent(reinterpret_cast<const uint32_t *>(&st->overflow))) {
+                    if (lane == 0) {
+                        if (full) atomicOr(&st->overflow, 1);
+                        J.len[J.S + g] = 0;
+                        J.off[J.S + g] = 0;
+                    }
+                } else if (R.dmax > kWindowLarge) {
+                    if (lane == 0) eval_seq(J, R, g, ob, J.lut + (int)R.type * 256);
+                } else {
+                    reinterpret_cast<uint32_t *>(L.lut)[lane] =
+                        reinterpret_cast<const uint32_t *>(J.lut + (int)R.type * 256)[lane];
+                    switch (R.k) {
+                    case 1: eval_gate<1, kWindowLarge, EDGE>(J, ob, R, g, L); break;
+                    case 2: eval_gate<2, kWindowLarge, EDGE>(J, ob, R, g, L); break;
+                    case 3: eval_gate<3, kWindowLarge, EDGE>(J, ob, R, g, L); break;
+                    default: eval_gate<4, kWindowLarge, EDGE>(J, ob, R, g, L); break;
+                    }
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             // consumers whose last pending pin this was: queued with one atomic per batch
-            const int64_t f1 = A.fo_off[g + 1];
-            for (int64_t i0 = A.fo_off[g]; i0 < f1; i0 += 64) {
-                const int64_t i = i0 + lane;
-                const int32_t c = i < f1 ? A.fo[i] : -1;
-                const bool ready = c >= 0 && atomicSub(&A.pend[c], 1) == 1;
-                const uint64_t mask = __ballot(ready);
-                if (mask == 0) continue;
-                const int leader = __ffsll((unsigned long long)mask) - 1;
-                uint32_t base = 0;
-                if (lane == leader) base = atomicAdd(&A.ctl->tail, (uint32_t)__popcll(mask));
-                base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
-                if (ready)
-                    __hip_atomic_store(A.queue + base + lanes_below(mask), c, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+            for (int b = 0; b < nb; b++) {
+                const int32_t g = b == 0 ? g0 : b == 1 ? g1 : b == 2 ? g2 : g3;
+                const int64_t f1 = A.fo_off[g + 1];
+                for (int64_t i0 = A.fo_off[g]; i0 < f1; i0 += 64) {
+                    const int64_t i = i0 + lane;
+                    const int32_t c = i < f1 ? A.fo[i] : -1;
+                    const bool ready = c >= 0 && atomicSub(&A.pend[c], 1) == 1;
+                    const uint64_t mask = __ballot(ready);
+                    if (mask == 0) continue;
+                    const int leader = __ffsll((unsigned long long)mask) - 1;
+                    uint32_t base = 0;
+                    if (lane == leader) base = atomicAdd(&A.ctl->tail, (uint32_t)__popcll(mask));
+                    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+                    if (ready)
+                        __hip_atomic_store(A.queue + base + lanes_below(mask), c, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
+            t += nb;
         }
     }
     if (lane == 0 && reads > 0)
