@@ -14,6 +14,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -490,7 +491,7 @@ struct gsim_ctx_s {
     std::map<int64_t, std::unique_ptr<Job>> jobs;
     std::map<hipStream_t, std::unique_ptr<Executor>> executors;
     int64_t arenas_held = 0;  // jobs that hold an output arena (admitted, not yet released)
-    int64_t *d_stage_t = nullptr;  // fetch staging buffers, kStage transitions
+    int64_t *d_stage_t = nullptr;  // fetch staging buffers, 2 x kStage transitions
     uint8_t *d_stage_v = nullptr;
     int64_t *d_stage_meta = nullptr;
     int64_t opt_arena = 0;
@@ -1331,6 +1332,68 @@ Failure net_meta(gsim_ctx ctx, Job *j, const std::vector<int64_t> &ids, std::vec
     return kOk;
 }
 
+// True for memory from hipHostMalloc (or registered with HIP); pageable
+// memory reads as unregistered (or the query fails, and its error is cleared).
+bool is_pinned_host(const void *ptr) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeHost;
+}
+
+// memcpy split over up to 16 threads for large copies out of pinned staging.
+void parallel_copy(void *dst, const void *src, size_t bytes) {
+    constexpr size_t kMinPerThread = size_t(4) << 20;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>({16, hw, std::max<size_t>(1, bytes / kMinPerThread)});
+    if (nt <= 1) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    const size_t part = (bytes + nt - 1) / nt;
+    std::vector<std::thread> pool;
+    for (size_t k = 1; k < nt; k++) {
+        const size_t a = k * part, e = std::min(bytes, a + part);
+        if (a >= e) break;
+        pool.emplace_back([=] { std::memcpy((char *)dst + a, (const char *)src + a, e - a); });
+    }
+    std::memcpy(dst, src, std::min(bytes, part));
+    for (auto &t : pool) t.join();
+}
+
+// Pinned host staging (two batches) and the events of one fetch call.
+struct FetchStaging {
+    gsim_ctx ctx;
+    int64_t *h_t[2] = {nullptr, nullptr};
+    uint8_t *h_v[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool good = true;
+    FetchStaging(gsim_ctx c, bool direct) : ctx(c) {
+        for (int p = 0; p < 2; p++) {
+            if (hipEventCreateWithFlags(&ev[p], hipEventDisableTiming) != hipSuccess) {
+                ev[p] = nullptr;
+                good = false;
+            }
+            if (direct) continue;
+            h_t[p] = (int64_t *)ctx->pinned.get(sizeof(int64_t) * (size_t)kStage);
+            h_v[p] = (uint8_t *)ctx->pinned.get((size_t)kStage);
+            if (!h_t[p] || !h_v[p]) good = false;
+        }
+    }
+    ~FetchStaging() {
+        // the stream may still copy into the staging buffers after an error
+        if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+        for (int p = 0; p < 2; p++) {
+            ctx->pinned.put(h_t[p]);
+            ctx->pinned.put(h_v[p]);
+            if (ev[p]) (void)hipEventDestroy(ev[p]);
+        }
+    }
+    bool ok() const { return good; }
+};
+
 Failure fetch(gsim_ctx ctx, Job *j, const int64_t *nets, int64_t n, int64_t *out_off, int64_t *out_t,
               uint8_t *out_v, int64_t cap) {
     Failure f = wait_job(ctx, j);
@@ -1347,25 +1410,42 @@ Failure fetch(gsim_ctx ctx, Job *j, const int64_t *nets, int64_t n, int64_t *out
     if (!out_t) return kOk;
     if (!out_v) return fail(GSIM_E_ARG, "null out_v");
     if (cap < out_off[n]) return fail(GSIM_E_ARG, "capacity %lld < %lld transitions", (long long)cap, (long long)out_off[n]);
-    // Gather in batches through the staging buffers; a net that does not fit
-    // in what is left of a batch is split across batches.
-    const int64_t stage = kStage;
-    int64_t *d_st = ctx->d_stage_t;
-    uint8_t *d_sv = ctx->d_stage_v;
-    const int64_t max_batch = kStageBatch;
-    int64_t *d_meta = ctx->d_stage_meta;
+    // Gather in batches through two device staging buffers; a net that does
+    // not fit in what is left of a batch is split across batches. Batch b is
+    // gathered and copied to the host while the host copies batch b-1 out of
+    // its pinned staging buffer into the caller's memory (several threads);
+    // if the caller's buffers are pinned themselves, they are copied to
+    // directly.
+    const bool direct = is_pinned_host(out_t) && is_pinned_host(out_v);
+    FetchStaging fs(ctx, direct);
+    if (!fs.ok()) return fail(GSIM_E_OOM, "no pinned host memory for the fetch staging buffers");
+    const int64_t stage = kStage, max_batch = kStageBatch;
     hipStream_t s = ctx->stream;
-    std::vector<int64_t> meta(3 * max_batch);
+    std::vector<int64_t> meta[2] = {std::vector<int64_t>(3 * max_batch), std::vector<int64_t>(3 * max_batch)};
+    int64_t pend_dst[2] = {0, 0}, pend_n[2] = {0, 0};
+    bool pending[2] = {false, false};
+    auto drain = [&](int p) -> Failure {
+        if (!pending[p]) return kOk;
+        pending[p] = false;
+        HIP_TRY(hipEventSynchronize(fs.ev[p]));
+        if (!direct && pend_n[p] > 0) {
+            parallel_copy(out_t + pend_dst[p], fs.h_t[p], sizeof(int64_t) * (size_t)pend_n[p]);
+            parallel_copy(out_v + pend_dst[p], fs.h_v[p], (size_t)pend_n[p]);
+        }
+        return kOk;
+    };
     int64_t i = 0, done_in_net = 0;  // next net, transitions of it already copied
-    while (i < n) {
+    for (int b = 0; i < n; b++) {
+        const int p = b & 1;
         int64_t nb = 0, acc = 0;
         const int64_t dst0 = out_off[i] + done_in_net;
+        int64_t *m = meta[p].data();
         while (i < n && nb < max_batch && acc < stage) {
             const int64_t li = len[i] - done_in_net;
             const int64_t take = std::min(li, stage - acc);
-            meta[nb] = off[i] + done_in_net;
-            meta[max_batch + nb] = take;
-            meta[2 * max_batch + nb] = acc;
+            m[nb] = off[i] + done_in_net;
+            m[max_batch + nb] = take;
+            m[2 * max_batch + nb] = acc;
             nb++;
             acc += take;
             if (take == li) {
@@ -1375,15 +1455,27 @@ Failure fetch(gsim_ctx ctx, Job *j, const int64_t *nets, int64_t n, int64_t *out
                 done_in_net += take;
             }
         }
-        HIP_TRY(hipMemcpyAsync(d_meta, meta.data(), sizeof(int64_t) * 3 * (size_t)max_batch, hipMemcpyHostToDevice, s));
+        int64_t *d_meta = ctx->d_stage_meta + p * 3 * max_batch;
+        int64_t *d_st = ctx->d_stage_t + p * stage;
+        uint8_t *d_sv = ctx->d_stage_v + p * stage;
+        HIP_TRY(hipMemcpyAsync(d_meta, m, sizeof(int64_t) * 3 * (size_t)max_batch, hipMemcpyHostToDevice, s));
         HIP_TRY(launch_gather(d_meta, d_meta + max_batch, d_meta + 2 * max_batch, nb, j->d_K, d_st, d_sv, s));
         if (acc > 0) {
-            HIP_TRY(hipMemcpyAsync(out_t + dst0, d_st, sizeof(int64_t) * (size_t)acc, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(out_v + dst0, d_sv, (size_t)acc, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(direct ? (void *)(out_t + dst0) : (void *)fs.h_t[p], d_st,
+                                   sizeof(int64_t) * (size_t)acc, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(direct ? (void *)(out_v + dst0) : (void *)fs.h_v[p], d_sv, (size_t)acc,
+                                   hipMemcpyDeviceToHost, s));
         }
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipEventRecord(fs.ev[p], s));
+        pend_dst[p] = dst0;
+        pend_n[p] = acc;
+        pending[p] = true;
+        f = drain(p ^ 1);  // the previous batch, while this one is copied
+        if (f.st != GSIM_OK) return f;
     }
-    return kOk;
+    f = drain(0);
+    if (f.st == GSIM_OK) f = drain(1);
+    return f;
 }
 
 Failure fetch_hashes(gsim_ctx ctx, Job *j, const int64_t *nets, int64_t n, uint64_t *out) {
@@ -1449,9 +1541,9 @@ gsim_status sim_create(int device, uint64_t hbm_budget_bytes, gsim_ctx *out) {
     }
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess)
         return record(nullptr, fail(GSIM_E_DEVICE, "stream creation failed"));
-    ctx->d_stage_t = (int64_t *)ctx->pool->get(sizeof(int64_t) * kStage);
-    ctx->d_stage_v = (uint8_t *)ctx->pool->get(kStage);
-    ctx->d_stage_meta = (int64_t *)ctx->pool->get(sizeof(int64_t) * 3 * kStageBatch);
+    ctx->d_stage_t = (int64_t *)ctx->pool->get(sizeof(int64_t) * 2 * kStage);
+    ctx->d_stage_v = (uint8_t *)ctx->pool->get(2 * kStage);
+    ctx->d_stage_meta = (int64_t *)ctx->pool->get(sizeof(int64_t) * 2 * 3 * kStageBatch);
     if (!ctx->d_stage_t || !ctx->d_stage_v || !ctx->d_stage_meta)
         return record(nullptr, fail(GSIM_E_OOM, "no device memory for the fetch staging buffers"));
     std::vector<uint8_t> lut = build_lut();

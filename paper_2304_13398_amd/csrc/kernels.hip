@@ -1021,11 +1021,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
     int64_t reads = 0;                    // sum of w_g over this wavefront's gates
     bool stop = false;
     while (!stop) {
+        const uint32_t n_t = A.tickets < 1u ? 1u : A.tickets > kDfMaxTickets ? kDfMaxTickets : A.tickets;
         uint32_t t0 = 0;
-        if (lane == 0) t0 = atomicAdd(&A.ctl->head, A.tickets);
+        if (lane == 0) t0 = atomicAdd(&A.ctl->head, n_t);
         t0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)t0);
         if ((int64_t)t0 >= A.G) break;
-        const uint32_t t1 = (uint32_t)min64((int64_t)t0 + A.tickets, A.G);
+        const uint32_t t1 = (uint32_t)min64((int64_t)t0 + n_t, A.G);
         uint32_t t = t0;
         while (t < t1) {
             // the next gate, and the one after if its slot is already filled:
