@@ -40,7 +40,12 @@
  *  - The whole circuit: gates are evaluated in a topological order that this
  *    file computes itself (Kahn's algorithm), so each gate's inputs are
  *    complete when it is evaluated (the dependency rule of Section 4.1).
+ *    o1_simulate_parallel evaluates the same gates level by level on several
+ *    threads (for timing the oracle on a multi-core host); its result is the
+ *    same.
  */
+#define _POSIX_C_SOURCE 200809L
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -305,6 +310,139 @@ o1_result *o1_simulate(int64_t S, int64_t G, const uint8_t *type, const int64_t 
         }
     }
     free(order);
+    return r;
+}
+
+/* ---- Level-parallel driver (for timing the oracle on several cores). ----
+ * The same per-gate procedure as o1_simulate. A gate's level is one more
+ * than the highest level among the gates it reads (sources are level 0), so
+ * the gates of one level read only finished waveforms of lower levels; each
+ * level is split into contiguous ranges, one per thread, and the threads are
+ * joined before the next level starts. The result is identical to
+ * o1_simulate's: every gate sees the same complete input waveforms. */
+typedef struct {
+    int64_t S;
+    const uint8_t *type;
+    const int64_t *pin_off, *pin_net;
+    const int32_t *rise, *fall;
+    const int64_t *src_off, *src_t;
+    const uint8_t *src_v;
+    o1_result *r;
+    const int64_t *gates; /* this thread's gates */
+    int64_t n;
+    int failed;
+} o1_level_part;
+
+static int eval_gate_into(const o1_level_part *a, int64_t g) {
+    const int64_t *in_t[4];
+    const uint8_t *in_v[4];
+    int64_t in_n[4];
+    int k = arity_of(a->type[g]);
+    for (int i = 0; i < k; i++) {
+        int64_t net = a->pin_net[a->pin_off[g] + i];
+        if (net < a->S) {
+            in_t[i] = a->src_t + a->src_off[net];
+            in_v[i] = a->src_v + a->src_off[net];
+            in_n[i] = a->src_off[net + 1] - a->src_off[net];
+        } else {
+            const o1_wave *w = &a->r->gate_out[net - a->S];
+            in_t[i] = w->t;
+            in_v[i] = w->v;
+            in_n[i] = w->n;
+        }
+    }
+    return o1_process_cell(a->type[g], in_t, in_v, in_n, a->rise + a->pin_off[g],
+                           a->fall + a->pin_off[g], &a->r->gate_out[g]);
+}
+
+static void *level_part_run(void *arg) {
+    o1_level_part *a = (o1_level_part *)arg;
+    for (int64_t i = 0; i < a->n && !a->failed; i++)
+        if (eval_gate_into(a, a->gates[i])) a->failed = 1;
+    return NULL;
+}
+
+o1_result *o1_simulate_parallel(int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
+                                const int64_t *pin_net, const int32_t *rise, const int32_t *fall,
+                                const int64_t *src_off, const int64_t *src_t, const uint8_t *src_v,
+                                int n_threads, int *status) {
+    *status = 0;
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > 256) n_threads = 256;
+    for (int64_t g = 0; g < G; g++) {
+        if (type[g] >= T_COUNT || pin_off[g + 1] - pin_off[g] != arity_of(type[g])) {
+            *status = -3;
+            return NULL;
+        }
+        for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++)
+            if (pin_net[p] < 0 || pin_net[p] >= S + G || pin_net[p] == S + g) {
+                *status = -3;
+                return NULL;
+            }
+    }
+    size_t gn = (size_t)(G ? G : 1);
+    o1_result *r = (o1_result *)calloc(1, sizeof(o1_result));
+    int64_t *order = (int64_t *)malloc(gn * sizeof(int64_t));
+    int64_t *level = (int64_t *)calloc(gn, sizeof(int64_t));
+    int64_t *by_level = (int64_t *)malloc(gn * sizeof(int64_t));
+    if (!r || !order || !level || !by_level) {
+        free(r); free(order); free(level); free(by_level);
+        *status = -1;
+        return NULL;
+    }
+    r->S = S;
+    r->G = G;
+    r->gate_out = (o1_wave *)calloc(gn, sizeof(o1_wave));
+    int rc = r->gate_out ? topological_order(S, G, pin_off, pin_net, order) : -1;
+    int64_t n_levels = 0, *level_start = NULL;
+    if (!rc) {
+        for (int64_t idx = 0; idx < G; idx++) { /* inputs precede their readers */
+            int64_t g = order[idx], lv = 0;
+            for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++)
+                if (pin_net[p] >= S && level[pin_net[p] - S] > lv) lv = level[pin_net[p] - S];
+            level[g] = lv + 1;
+            if (lv + 1 > n_levels) n_levels = lv + 1;
+        }
+        level_start = (int64_t *)calloc((size_t)n_levels + 2, sizeof(int64_t));
+        if (!level_start) rc = -1;
+    }
+    if (!rc) { /* counting sort of the gates by level */
+        for (int64_t g = 0; g < G; g++) level_start[level[g] + 1]++;
+        for (int64_t l = 1; l <= n_levels + 1; l++) level_start[l] += level_start[l - 1];
+        for (int64_t g = 0; g < G; g++) by_level[level_start[level[g]]++] = g;
+        for (int64_t l = n_levels + 1; l > 0; l--) level_start[l] = level_start[l - 1];
+        level_start[0] = 0;
+    }
+    for (int64_t l = 1; !rc && l <= n_levels; l++) {
+        const int64_t a0 = level_start[l], a1 = level_start[l + 1], n = a1 - a0;
+        int nt = n < n_threads ? (int)(n ? n : 1) : n_threads;
+        o1_level_part parts[256];
+        pthread_t th[256];
+        int started[256];
+        for (int k = 0; k < nt; k++) {
+            o1_level_part *pa = &parts[k];
+            pa->S = S; pa->type = type; pa->pin_off = pin_off; pa->pin_net = pin_net;
+            pa->rise = rise; pa->fall = fall; pa->src_off = src_off; pa->src_t = src_t;
+            pa->src_v = src_v; pa->r = r; pa->failed = 0;
+            const int64_t lo = a0 + n * k / nt, hi = a0 + n * (k + 1) / nt;
+            pa->gates = by_level + lo;
+            pa->n = hi - lo;
+            started[k] = k > 0 && pthread_create(&th[k], NULL, level_part_run, pa) == 0;
+        }
+        level_part_run(&parts[0]);
+        for (int k = 1; k < nt; k++) {
+            if (started[k]) pthread_join(th[k], NULL);
+            else level_part_run(&parts[k]); /* no thread: run it here */
+        }
+        for (int k = 0; k < nt; k++)
+            if (parts[k].failed) rc = -1;
+    }
+    free(order); free(level); free(by_level); free(level_start);
+    if (rc) {
+        o1_free(r);
+        *status = rc;
+        return NULL;
+    }
     return r;
 }
 

@@ -61,7 +61,7 @@ def build(force: bool = True, src: str = SRC, out: str = LIB, extra=()) -> str:
     """Compile ``o1.c`` with gcc into a shared library (plain -O2)."""
     if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
         tmp = out + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", *extra, "-o", tmp, src])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-pthread", *extra, "-o", tmp, src])
         os.replace(tmp, out)
     return out
 
@@ -73,6 +73,9 @@ class _O1:
         i64 = ctypes.c_int64
         lib.o1_simulate.restype = P
         lib.o1_simulate.argtypes = [i64, i64, P, P, P, P, P, P, P, P, ctypes.POINTER(ctypes.c_int)]
+        lib.o1_simulate_parallel.restype = P
+        lib.o1_simulate_parallel.argtypes = [i64, i64, P, P, P, P, P, P, P, P, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_int)]
         lib.o1_lengths.argtypes = [P, P]
         lib.o1_copy.argtypes = [P, P, P, P]
         lib.o1_free.argtypes = [P]
@@ -109,9 +112,10 @@ class OracleError(RuntimeError):
     pass
 
 
-def o1_simulate(nl, st, lib: str | None = None):
+def o1_simulate(nl, st, lib: str | None = None, threads: int = 0):
     """O1 on a whole netlist. Returns (off[G+1], t, v): gate g's waveform is
-    t[off[g]:off[g+1]], v[off[g]:off[g+1]]."""
+    t[off[g]:off[g+1]], v[off[g]:off[g+1]]. With ``threads`` > 0 the gates of
+    each level are split over that many threads (same result)."""
     L = o1_lib(lib).lib
     type_ = np.ascontiguousarray(nl.type, dtype=np.uint8)
     pin_off = np.ascontiguousarray(nl.pin_off, dtype=np.int64)
@@ -122,8 +126,13 @@ def o1_simulate(nl, st, lib: str | None = None):
     st_t = np.ascontiguousarray(st.t, dtype=np.int64)
     st_v = np.ascontiguousarray(st.v, dtype=np.uint8)
     status = ctypes.c_int(0)
-    h = L.o1_simulate(nl.S, nl.G, _ptr(type_), _ptr(pin_off), _ptr(pin_net), _ptr(rise),
-                      _ptr(fall), _ptr(soff), _ptr(st_t), _ptr(st_v), ctypes.byref(status))
+    if threads > 0:
+        h = L.o1_simulate_parallel(nl.S, nl.G, _ptr(type_), _ptr(pin_off), _ptr(pin_net), _ptr(rise),
+                                   _ptr(fall), _ptr(soff), _ptr(st_t), _ptr(st_v), threads,
+                                   ctypes.byref(status))
+    else:
+        h = L.o1_simulate(nl.S, nl.G, _ptr(type_), _ptr(pin_off), _ptr(pin_net), _ptr(rise),
+                          _ptr(fall), _ptr(soff), _ptr(st_t), _ptr(st_v), ctypes.byref(status))
     if not h:
         raise OracleError({-1: "out of memory", -2: "cycle", -3: "malformed netlist"}
                           .get(status.value, str(status.value)))
