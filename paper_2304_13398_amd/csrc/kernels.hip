@@ -329,19 +329,26 @@ __device__ __forceinline__ uint32_t wave_shift_down(uint32_t identity, uint32_t 
 // same as keeping, among the survivors, those whose value differs from the
 // previous survivor's (X before the first).
 //
-// The wave walks the inputs in rounds of up to 512 transitions (T = 512/K
-// per pin; 192, 192 and 128 for three pins). The round's horizon H is the smallest
-// last-loaded time over pins that have more transitions beyond their tile,
-// capped so the round spans less than 2^28 ps; every input transition at or
-// before H is in the round. In-round inputs are 32-bit keys
-// offset << 4 | value << 2 | pin (offset from the round's base), so the
-// merged order of the round is plain key order (by time; the order inside a
-// time group does not matter). The merge is done per lane:
-// lane l owns merged positions [8l, 8l + 8), finds where they start in the
-// two sorted lists it merges by a merge-path search, and takes the 8
-// smallest of the next 8 of each list with a bitonic network (three pins:
-// the first two merged through LDS, then with the third; four pins: two
-// pairwise merges through LDS, then one more). Pin values after each
+// The wave walks the inputs in rounds of up to 512 transitions. Each pin
+// loads a tile of its next transitions (512 for one pin; 384, 256 and 192
+// each for two, three and four pins: more than a round takes, so that one
+// pin whose tile ends early does not cut the round short). The round's
+// horizon H is the smallest last-loaded time over pins that have more
+// transitions beyond their tile, capped so the round spans less than 2^28
+// ps, and lowered to just before the time of the 513th merged transition
+// (four pins: of the 257th of either pairwise merge) when there are more;
+// every input transition at or before H is in the round. In-round inputs are
+// 32-bit keys offset << 4 | value << 2 | pin (offset from the round's base),
+// so the merged order of the round is plain key order (by time; the order
+// inside a time group does not matter). The merge is done per lane: lane l
+// owns merged positions [8l, 8l + 8), finds where they start in the two
+// sorted lists it merges by a merge-path search, and takes the 8 smallest of
+// the next 8 of each list with a bitonic network (three pins: the first 512
+// of the first two through LDS, then with the third; four pins: the first
+// 256 of each pair through LDS, then one more merge). Tiles are held as the
+// low 32 bits of the packed transitions; a tile keeps only transitions whose
+// high word equals its first one's (the rest wait for a later round), so
+// one uniform word completes every key of the tile. Pin values after each
 // merged transition come from a wave scan of "set pin p to v" updates; a
 // transition ends a time group when the next one has another time; the
 // group's candidate takes its delay from a per-gate table indexed by new
@@ -353,13 +360,20 @@ __device__ __forceinline__ uint32_t wave_shift_down(uint32_t identity, uint32_t 
 // pin delay is at most W (see kWindowSmall). The next round's tiles are
 // prefetched into registers while the current one runs.
 constexpr int kMergePad = 8;                       // INF keys after each sorted list
-constexpr int kMergeBuf = 2 * (256 + kMergePad + 1);  // two pairwise-merge outputs with guards
+// pairwise-merge outputs with guards: two of 256 (four pins) or one of 512 (three)
+constexpr int kMergeBuf = 2 * (256 + kMergePad + 1);
+static_assert(kMergeBuf >= 512 + kMergePad + 1, "the three-pin merge buffer fits");
+
+constexpr int kTileWords = 4 * (192 + 1 + kMergePad);  // the largest of the K x tile layouts
+static_assert(kTileWords >= 512 + 1 + kMergePad && kTileWords >= 2 * (384 + 1 + kMergePad) &&
+                  kTileWords >= 3 * (256 + 1 + kMergePad),
+              "every pin count's tiles fit");
 
 template <int W>
 struct WaveLds {
     uint32_t seq[W + kRoundSlots + 32];  // tentative survivors [0, nq), then this round's;
                                          // the pairwise-merge buffers alias seq[W, W + kMergeBuf)
-    uint32_t tile[kRoundSlots + 4 * (kMergePad + 1)];  // K x [guard, T(p) keys, 8 INF]
+    uint32_t tile[kTileWords];           // K x [guard, T keys, 8 INF]
     uint32_t dtab[48];                   // min delay by (new value, set of changed pins)
     uint32_t etab[12];                   // edge model: per (pin, edge class) the delays to
                                          // 0, 1 and X in 10-bit fields (kEdgeNone = unrelated)
@@ -369,11 +383,11 @@ static_assert(kMergeBuf <= kRoundSlots + 32, "merge buffers must fit the survivo
 
 template <int K>
 struct Tiling {
-    // transitions per pin per round; tile p of LDS is [guard, T(p) keys, 8 INF]
-    static constexpr int T(int p) { return K == 1 ? 512 : K == 2 ? 256 : K == 3 ? (p < 2 ? 192 : 128) : 128; }
-    static constexpr int E(int p) { return T(p) / 64; }  // per lane
-    static constexpr int EMAX = T(0) / 64;
-    static constexpr int OFF(int p) { return p == 0 ? 0 : OFF(p - 1) + T(p - 1) + 1 + kMergePad; }
+    // transitions loaded per pin; tile p of LDS is [guard, T keys, 8 INF]
+    static constexpr int T = K == 1 ? 512 : K == 2 ? 384 : K == 3 ? 256 : 192;
+    static constexpr int E = T / 64;  // per lane
+    static constexpr int OFF(int p) { return p * (T + 1 + kMergePad); }
+    static constexpr int WORDS = K * (T + 1 + kMergePad);
 };
 static_assert(kRoundSlots == 512, "tiling assumes 512-transition rounds");
 
@@ -455,11 +469,75 @@ __device__ __forceinline__ uint32_t edge_class(uint32_t old_v, uint32_t new_v) {
 }
 constexpr uint32_t kEdgeNone = 1023u;  // a 10-bit delay field of an unrelated pin
 
-template <int K, int W, bool EDGE>
+// One pin's tile: the low words of up to T of its next packed transitions
+// (one per lane and register); lane 0 of aux holds the high word of the
+// first, lane 1 that of the last.
+template <int T>
+struct PinTile {
+    uint32_t lo[T / 64];
+    uint32_t aux;
+    int n;  // transitions loaded
+};
+
+// Start loading the tile at src (r transitions left there); nothing waits.
+template <int T>
+__device__ __forceinline__ void tile_fetch(const uint64_t *src, int64_t r, PinTile<T> &t) {
+    const int lane = lane_id();
+    t.n = (int)min64(r, (int64_t)T);
+    const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src);  // low word first
+#pragma unroll
+    for (int e = 0; e < T / 64; e++) t.lo[e] = lane + 64 * e < t.n ? s32[2 * (lane + 64 * e)] : 0u;
+    t.aux = lane < 2 && t.n > 0 ? s32[lane == 0 ? 1 : 2 * (t.n - 1) + 1] : 0u;
+}
+
+// A loaded tile as the round uses it: the transitions [0, lim) that share the
+// first one's high word hi; the time of its first transition; and the pin's
+// horizon hp -- every transition of the pin up to hp is in [0, lim) (kInf if
+// the tile holds all r that are left).
+template <int T>
+__device__ __forceinline__ void tile_settle(const uint64_t *src, int64_t r, const PinTile<T> &t, int &lim,
+                                            uint32_t &hi, int64_t &t0, int64_t &hp) {
+    lim = t.n;
+    hi = 0xFFFFFFFFu;
+    t0 = kInf;
+    hp = kInf;
+    if (t.n == 0) return;
+    hi = (uint32_t)__builtin_amdgcn_readlane((int)t.aux, 0);
+    const uint32_t hi_last = (uint32_t)__builtin_amdgcn_readlane((int)t.aux, 1);
+    const uint32_t lo_first = (uint32_t)__builtin_amdgcn_readlane((int)t.lo[0], 0);
+    t0 = key_time(((uint64_t)hi << 32) | lo_first);
+    if (r > t.n) {
+        const int e_last = (t.n - 1) >> 6;
+        uint32_t v = t.lo[0];
+#pragma unroll
+        for (int e = 1; e < T / 64; e++) v = e == e_last ? t.lo[e] : v;
+        const uint32_t lo_last = (uint32_t)__builtin_amdgcn_readlane((int)v, (t.n - 1) & 63);
+        hp = key_time(((uint64_t)hi_last << 32) | lo_last);
+    }
+    if (hi_last != hi) {
+        // rare: the tile reaches a later high word; keep the transitions before
+        // it (a prefix, the tile being sorted)
+        const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src);
+        const int lane = lane_id();
+        int c = 0;
+#pragma unroll
+        for (int e = 0; e < T / 64; e++) {
+            const int i = lane + 64 * e;
+            c += __popcll(__ballot(i < t.n && s32[2 * i + 1] == hi));
+        }
+        lim = c;
+        hp = (((int64_t)hi + 1) << 30) - 1;  // the last time with high word hi
+    }
+}
+
+// PREFETCH: the next round's tiles load while the round runs (more
+// registers); otherwise at the end of the round.
+template <int K, int W, bool EDGE, bool PREFETCH>
 __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const GateRec &R,
                                           int64_t gate, WaveLds<W> &L) {
     using Tl = Tiling<K>;
-    constexpr int EM = Tl::EMAX;
+    constexpr int TT = Tl::T;
+    constexpr int E = Tl::E;
     const int lane = lane_id();
     const int64_t S = J.S;
     int64_t *len = J.len;
@@ -479,20 +557,13 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
 #pragma unroll
     for (int p = 0; p < K; p++) state0 |= (uint32_t)kX << (2 * p);
 
-    // tiles are loaded from a uniform base with 32-bit lane offsets
-    uint64_t pre[K][EM];
+    PinTile<TT> tl[K];  // this round's tiles
 #pragma unroll
-    for (int p = 0; p < K; p++) {
-        const uint64_t *src = Kar + pb[p];
-        const int lim = (int)min64(pl[p], (int64_t)Tl::T(p));
-#pragma unroll
-        for (int e = 0; e < EM; e++)
-            if (e < Tl::E(p)) pre[p][e] = lane + 64 * e < lim ? src[lane + 64 * e] : kNoKey;
-    }
+    for (int p = 0; p < K; p++) tile_fetch<TT>(Kar + pb[p], pl[p], tl[p]);
     // INF keys after each tile; the delay table
 #pragma unroll
     for (int p = 0; p < K; p++)
-        if (lane < kMergePad) L.tile[Tl::OFF(p) + 1 + Tl::T(p) + lane] = kNoKey32;
+        if (lane < kMergePad) L.tile[Tl::OFF(p) + 1 + TT + lane] = kNoKey32;
     if (EDGE) {
         // per (pin, edge class): delays to 0, 1 and X; finite ones are <= W
         if (lane < 3 * K) {
@@ -538,12 +609,16 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         }
         if (!more) break;
 
-        // ---- base (earliest pending time), horizon, in-round counts
+        // ---- base (earliest pending time), horizon from the tiles
+        int lim[K];
+        uint32_t thi[K];
         int64_t H = kInf, base = kInf;
 #pragma unroll
         for (int p = 0; p < K; p++) {
-            if (rem[p] > Tl::T(p)) H = min64(H, key_time(readlane_u64(pre[p][Tl::E(p) - 1], 63)));
-            if (rem[p] > 0) base = min64(base, key_time(readlane_u64(pre[p][0], 0)));
+            int64_t t0, hp;
+            tile_settle<TT>(Kar + pb[p] + cur[p], rem[p], tl[p], lim[p], thi[p], t0, hp);
+            H = min64(H, hp);
+            base = min64(base, t0);
         }
         if (nq > 0) {
             base = min64(base, base_prev + (int64_t)(L.seq[0] >> 2));
@@ -551,58 +626,52 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
             for (int c = lane; c < nq; c += 64) L.seq[c] -= shift;
         }
         H = min64(H, base + kSpan);
-        int m[K];
-        bool all_in = true;
         const uint64_t hkey = H < kTimeLimit ? pack_key(H, 3u) : ~uint64_t(0);  // last key of the round
         const uint32_t base4 = (uint32_t)pack_key(base, 0u);  // low word of base << 2
+        const uint32_t hk_hi = (uint32_t)(hkey >> 32);
+        int m[K];
 #pragma unroll
         for (int p = 0; p < K; p++) {
+            // a tile key is at or before H by its (uniform) high word, else by its low word
+            const uint32_t lo_max = thi[p] < hk_hi ? 0xFFFFFFFFu : (uint32_t)hkey;
+            const int lim_in = thi[p] > hk_hi ? 0 : lim[p];
             m[p] = 0;
-            const int lim = (int)min64(rem[p], (int64_t)Tl::T(p));
 #pragma unroll
-            for (int e = 0; e < EM; e++) {
-                if (e >= Tl::E(p)) continue;
-                const uint64_t key = pre[p][e];
-                const bool in = lane + 64 * e < lim && key <= hkey;
+            for (int e = 0; e < E; e++) {
+                const uint32_t lo = tl[p].lo[e];
+                const bool in = lane + 64 * e < lim_in && lo <= lo_max;
                 m[p] += __popcll(__ballot(in));
                 // (t - base) << 2 | v < 2^30 equals the low word of key - (base << 2)
-                L.tile[Tl::OFF(p) + 1 + 64 * e + lane] = in ? (((uint32_t)key - base4) << 2) | (uint32_t)p : kNoKey32;
+                L.tile[Tl::OFF(p) + 1 + 64 * e + lane] = in ? ((lo - base4) << 2) | (uint32_t)p : kNoKey32;
             }
-            all_in = all_in && m[p] == rem[p];
-        }
-        // split horizon: with every remaining input in this round, all survivors are final
-        const uint32_t hsplit = all_in ? kNoKey32 : (uint32_t)(H - base) << 2 | 3u;
-        uint64_t nxt[K][EM];
-#pragma unroll
-        for (int p = 0; p < K; p++) {
-            const uint64_t *src = Kar + pb[p] + cur[p] + m[p];
-            const int lim = (int)min64(rem[p] - m[p], (int64_t)Tl::T(p));
-#pragma unroll
-            for (int e = 0; e < EM; e++)
-                if (e < Tl::E(p)) nxt[p][e] = lane + 64 * e < lim ? src[lane + 64 * e] : kNoKey;
         }
         __syncthreads();
 
-        // ---- merged positions [8 lane, 8 lane + 8) of the round
+        // ---- merged positions [8 lane, 8 lane + 8) of the round; the time
+        // of a merged key past the round's 512 (pairs: 256) slots
         uint32_t mk[8];
+        uint32_t cut = kNoTime28;
         if constexpr (K == 1) {
 #pragma unroll
             for (int k = 0; k < 8; k++) mk[k] = L.tile[1 + 8 * lane + k];
         } else if constexpr (K == 2) {
             merge8<9>(L.tile + Tl::OFF(0) + 1, m[0], L.tile + Tl::OFF(1) + 1, m[1], 8 * lane, mk);
+            if (m[0] + m[1] > 512) cut = (uint32_t)__builtin_amdgcn_readlane((int)mk[7], 63) >> 4;
         } else if constexpr (K == 3) {
-            // pins 0 and 1 (192 each) into AB by lanes 0-47, then AB with pin 2's tile
-            if (lane < 48) {
+            // the first 512 of pins 0 and 1 into AB, then AB with pin 2's tile
+            {
                 uint32_t h[8];
-                merge8<8>(L.tile + Tl::OFF(0) + 1, m[0], L.tile + Tl::OFF(1) + 1, m[1], 8 * lane, h);
+                merge8<9>(L.tile + Tl::OFF(0) + 1, m[0], L.tile + Tl::OFF(1) + 1, m[1], 8 * lane, h);
 #pragma unroll
                 for (int k = 0; k < 8; k++) AB[8 * lane + k] = h[k];
-            } else if (lane < 48 + kMergePad) {
-                AB[384 + lane - 48] = kNoKey32;
+                if (lane < kMergePad) AB[512 + lane] = kNoKey32;
             }
             __syncthreads();
-            merge8<8>(AB, m[0] + m[1], L.tile + Tl::OFF(2) + 1, m[2], 8 * lane, mk);
+            const int ab = m[0] + m[1] < 512 ? m[0] + m[1] : 512;
+            merge8<9>(AB, ab, L.tile + Tl::OFF(2) + 1, m[2], 8 * lane, mk);
+            if (m[0] + m[1] + m[2] > 512) cut = (uint32_t)__builtin_amdgcn_readlane((int)mk[7], 63) >> 4;
         } else {
+            // the first 256 of pins 0 and 1 (lanes 0-31) and of pins 2 and 3 (lanes 32-63)
             const bool hi_half = lane >= 32;
             const uint32_t *A = L.tile + (hi_half ? Tl::OFF(2) : Tl::OFF(0)) + 1;
             const uint32_t *B = L.tile + (hi_half ? Tl::OFF(3) : Tl::OFF(1)) + 1;
@@ -614,8 +683,50 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
 #pragma unroll
             for (int k = 0; k < 8; k++) dst[k] = h[k];
             if (lane < 2 * kMergePad) (lane < kMergePad ? AB : CD)[256 + (lane % kMergePad)] = kNoKey32;
+            const uint32_t c_ab = (uint32_t)__builtin_amdgcn_readlane((int)h[7], 31) >> 4;
+            const uint32_t c_cd = (uint32_t)__builtin_amdgcn_readlane((int)h[7], 63) >> 4;
+            if (m[0] + m[1] > 256) cut = c_ab;
+            if (m[2] + m[K - 1] > 256) cut = umin32(cut, c_cd);
             __syncthreads();
-            merge8<9>(AB, m[0] + m[1], CD, m[2] + m[K - 1], 8 * lane, mk);
+            merge8<9>(AB, m[0] + m[1] < 256 ? m[0] + m[1] : 256, CD,
+                      m[2] + m[K - 1] < 256 ? m[2] + m[K - 1] : 256, 8 * lane, mk);
+        }
+        if (cut != kNoTime28 && (int64_t)cut - 1 < H - base) {
+            // the round ends before the cut key's time: fewer keys of each pin are in
+            H = base + (int64_t)cut - 1;
+            const uint32_t hoff = cut - 1;
+            const uint32_t hk32 = hoff << 4 | 15u;
+#pragma unroll
+            for (int k = 0; k < 8; k++) mk[k] = mk[k] <= hk32 ? mk[k] : kNoKey32;
+            // in-round keys per pin: 8-bit counts per lane, summed over each
+            // row of 16 lanes (at most 128 per field), then over the rows
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int k = 0; k < 8; k++) cnt += mk[k] != kNoKey32 ? 1u << (8 * (mk[k] & 3u)) : 0u;
+            cnt += dpp_u32<kDppRowShr1>(0u, cnt);
+            cnt += dpp_u32<kDppRowShr2>(0u, cnt);
+            cnt += dpp_u32<kDppRowShr4>(0u, cnt);
+            cnt += dpp_u32<kDppRowShr8>(0u, cnt);
+            uint32_t rows[4];
+#pragma unroll
+            for (int r = 0; r < 4; r++) rows[r] = (uint32_t)__builtin_amdgcn_readlane((int)cnt, 16 * r + 15);
+#pragma unroll
+            for (int p = 0; p < K; p++) {
+                m[p] = 0;
+#pragma unroll
+                for (int r = 0; r < 4; r++) m[p] += (int)((rows[r] >> (8 * p)) & 0xFFu);
+            }
+        }
+        bool all_in = true;
+#pragma unroll
+        for (int p = 0; p < K; p++) all_in = all_in && m[p] == rem[p];
+        // split horizon: with every remaining input in this round, all survivors are final
+        const uint32_t hsplit = all_in ? kNoKey32 : (uint32_t)(H - base) << 2 | 3u;
+        constexpr bool kPrefetch = PREFETCH;
+        PinTile<TT> nx[K];
+        if constexpr (kPrefetch) {
+#pragma unroll
+            for (int p = 0; p < K; p++) tile_fetch<TT>(Kar + pb[p] + cur[p] + m[p], rem[p] - m[p], nx[p]);
         }
 
         // ---- pin states: this lane's composed update, scanned over the wave
@@ -789,9 +900,8 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
 #pragma unroll
         for (int p = 0; p < K; p++) {
             cur[p] += m[p];
-#pragma unroll
-            for (int e = 0; e < EM; e++)
-                if (e < Tl::E(p)) pre[p][e] = nxt[p][e];
+            if constexpr (kPrefetch) tl[p] = nx[p];
+            else tile_fetch<TT>(Kar + pb[p] + cur[p], rem[p] - m[p], tl[p]);
         }
         __syncthreads();
     }
@@ -830,10 +940,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void ev
         reinterpret_cast<const uint32_t *>(J.lut + (int)R.type * 256)[lane];
     const int64_t ob = A.blocksum[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + J.off[J.S + gate];
     switch (R.k) {
-    case 1: eval_gate<1, W, EDGE>(J, ob, R, gate, L); break;
-    case 2: eval_gate<2, W, EDGE>(J, ob, R, gate, L); break;
-    case 3: eval_gate<3, W, EDGE>(J, ob, R, gate, L); break;
-    default: eval_gate<4, W, EDGE>(J, ob, R, gate, L); break;
+    // four pins load their next tiles at the end of each round (registers)
+    case 1: eval_gate<1, W, EDGE, true>(J, ob, R, gate, L); break;
+    case 2: eval_gate<2, W, EDGE, true>(J, ob, R, gate, L); break;
+    case 3: eval_gate<3, W, EDGE, true>(J, ob, R, gate, L); break;
+    default: eval_gate<4, W, EDGE, false>(J, ob, R, gate, L); break;
     }
 }
 
@@ -1084,10 +1195,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
                     reinterpret_cast<uint32_t *>(L.lut)[lane] =
                         reinterpret_cast<const uint32_t *>(J.lut + (int)R.type * 256)[lane];
                     switch (R.k) {
-                    case 1: eval_gate<1, kWindowLarge, EDGE>(J, ob, R, g, L); break;
-                    case 2: eval_gate<2, kWindowLarge, EDGE>(J, ob, R, g, L); break;
-                    case 3: eval_gate<3, kWindowLarge, EDGE>(J, ob, R, g, L); break;
-                    default: eval_gate<4, kWindowLarge, EDGE>(J, ob, R, g, L); break;
+                    case 1: eval_gate<1, kWindowLarge, EDGE, false>(J, ob, R, g, L); break;
+                    case 2: eval_gate<2, kWindowLarge, EDGE, false>(J, ob, R, g, L); break;
+                    case 3: eval_gate<3, kWindowLarge, EDGE, false>(J, ob, R, g, L); break;
+                    default: eval_gate<4, kWindowLarge, EDGE, false>(J, ob, R, g, L); break;
                     }
                 }
             }
