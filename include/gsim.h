@@ -99,8 +99,13 @@ enum gsim_option {
     /* Schedule of later jobs: 0 = level by level (one launch chain per level,
      * shared by every admitted job); 1 = dependency-driven (Section 3.3,
      * Algorithm 1): one persistent launch per job in which a gate starts as
-     * soon as its last fan-in gate has finished, with no level barrier.
-     * Results are identical. */
+     * soon as its last fan-in gate has finished, with no level barrier;
+     * 2 = chosen per job: dependency-driven when the netlist has fewer than
+     * 800 gates per level on average (launch overhead dominates the level
+     * chain) or, for stimuli given in host memory, when the per-source
+     * transition counts vary with a coefficient of variation (the paper's
+     * workload WCV, Eq. 5) of at least 2.5; level by level otherwise.
+     * Results are identical under every setting. */
     GSIM_OPT_SCHEDULE = 6
 };
 
@@ -252,6 +257,7 @@ typedef struct {
                                 evaluate launches, else 0 */
     int64_t eval_launches;   /* levels timed for eval_ms */
     int64_t retries;         /* automatic re-runs after an output-storage overflow */
+    int64_t schedule;        /* the job's schedule: 0 level by level, 1 dependency-driven */
 } gsim_job_stats;
 /* Statistics of a finished job (waits for it). */
 gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out);

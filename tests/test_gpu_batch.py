@@ -243,3 +243,36 @@ def test_mixed_delay_models_share_steps(sim):
         sim.release(j)
     for h in (h_a, h_b, h_c):
         sim.unload_netlist(h)
+
+
+def test_automatic_schedule_choice():
+    """GSIM_OPT_SCHEDULE = 2 picks the dependency-driven launch for a small
+    netlist and for uneven source activity, level by level for a large
+    netlist with even activity; results equal the explicit schedules'."""
+    sim = G.Sim(0)
+    try:
+        cases = []
+        nl_t, st_t = W.config1(seed=1)
+        cases.append(("tiny", nl_t, st_t, 1))
+        nl_u, st_u = W.config2(seed=3, G=100_000, S=205)
+        cases.append(("uniform 100k", nl_u, st_u, 0))
+        st_s = W.make_stimulus_skewed(S=nl_u.S, mean_per_src=1000, wcv=5.0, window=1_000_000, seed=3)
+        cases.append(("skewed 100k", nl_u, st_s, 1))
+        for name, nl, st, want_sched in cases:
+            h = sim.load_netlist(nl)
+            hashes = {}
+            for sched in (2, 0, 1):
+                sim.set_option(G.OPT_SCHEDULE, sched)
+                j = sim.run(h, st)
+                sim.wait(j)
+                if sched == 2:
+                    got = sim.stats(j).schedule
+                    say(f"auto schedule on {name}: {got}")
+                    assert got == want_sched, name
+                hashes[sched] = sim.hashes(j)
+                sim.release(j)
+            sim.set_option(G.OPT_SCHEDULE, 0)
+            assert np.array_equal(hashes[2], hashes[0]) and np.array_equal(hashes[2], hashes[1]), name
+            sim.unload_netlist(h)
+    finally:
+        sim.close()
