@@ -471,7 +471,7 @@ constexpr uint32_t kEdgeNone = 1023u;  // a 10-bit delay field of an unrelated p
 
 // One pin's tile: the low words of up to T of its next packed transitions
 // (one per lane and register); lane 0 of aux holds the high word of the
-// first, lane 1 that of the last.
+// first, lane 1 that of the last (LEAN: lane 2 the low word of the last).
 template <int T>
 struct PinTile {
     uint32_t lo[T / 64];
@@ -480,21 +480,26 @@ struct PinTile {
 };
 
 // Start loading the tile at src (r transitions left there); nothing waits.
-template <int T>
+template <int T, bool LEAN>
 __device__ __forceinline__ void tile_fetch(const uint64_t *src, int64_t r, PinTile<T> &t) {
     const int lane = lane_id();
     t.n = (int)min64(r, (int64_t)T);
     const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src);  // low word first
 #pragma unroll
     for (int e = 0; e < T / 64; e++) t.lo[e] = lane + 64 * e < t.n ? s32[2 * (lane + 64 * e)] : 0u;
-    t.aux = lane < 2 && t.n > 0 ? s32[lane == 0 ? 1 : 2 * (t.n - 1) + 1] : 0u;
+    if constexpr (LEAN) {
+        const int last = 2 * (t.n - 1);
+        t.aux = lane < 3 && t.n > 0 ? s32[lane == 0 ? 1 : lane == 1 ? last + 1 : last] : 0u;
+    } else {
+        t.aux = lane < 2 && t.n > 0 ? s32[lane == 0 ? 1 : 2 * (t.n - 1) + 1] : 0u;
+    }
 }
 
 // A loaded tile as the round uses it: the transitions [0, lim) that share the
 // first one's high word hi; the time of its first transition; and the pin's
 // horizon hp -- every transition of the pin up to hp is in [0, lim) (kInf if
 // the tile holds all r that are left).
-template <int T>
+template <int T, bool LEAN>
 __device__ __forceinline__ void tile_settle(const uint64_t *src, int64_t r, const PinTile<T> &t, int &lim,
                                             uint32_t &hi, int64_t &t0, int64_t &hp) {
     lim = t.n;
@@ -507,11 +512,16 @@ __device__ __forceinline__ void tile_settle(const uint64_t *src, int64_t r, cons
     const uint32_t lo_first = (uint32_t)__builtin_amdgcn_readlane((int)t.lo[0], 0);
     t0 = key_time(((uint64_t)hi << 32) | lo_first);
     if (r > t.n) {
-        const int e_last = (t.n - 1) >> 6;
-        uint32_t v = t.lo[0];
+        uint32_t lo_last;
+        if constexpr (LEAN) {
+            lo_last = (uint32_t)__builtin_amdgcn_readlane((int)t.aux, 2);
+        } else {
+            const int e_last = (t.n - 1) >> 6;
+            uint32_t v = t.lo[0];
 #pragma unroll
-        for (int e = 1; e < T / 64; e++) v = e == e_last ? t.lo[e] : v;
-        const uint32_t lo_last = (uint32_t)__builtin_amdgcn_readlane((int)v, (t.n - 1) & 63);
+            for (int e = 1; e < T / 64; e++) v = e == e_last ? t.lo[e] : v;
+            lo_last = (uint32_t)__builtin_amdgcn_readlane((int)v, (t.n - 1) & 63);
+        }
         hp = key_time(((uint64_t)hi_last << 32) | lo_last);
     }
     if (hi_last != hi) {
@@ -531,8 +541,13 @@ __device__ __forceinline__ void tile_settle(const uint64_t *src, int64_t r, cons
 }
 
 // PREFETCH: the next round's tiles load while the round runs (more
-// registers); otherwise at the end of the round.
-template <int K, int W, bool EDGE, bool PREFETCH>
+// registers); otherwise at the end of the round. LEAN (level kernel): the
+// last loaded transition comes from an extra lane of the tile's auxiliary
+// register, and the lane's trailing time group is looked for among its last
+// K positions only (at most one transition per pin shares a time). The
+// dependency-driven kernel keeps the longer form of both: one of its runs
+// with the shorter form did not finish, and the cause is not known.
+template <int K, int W, bool EDGE, bool PREFETCH, bool LEAN>
 __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const GateRec &R,
                                           int64_t gate, WaveLds<W> &L) {
     using Tl = Tiling<K>;
@@ -559,7 +574,7 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
 
     PinTile<TT> tl[K];  // this round's tiles
 #pragma unroll
-    for (int p = 0; p < K; p++) tile_fetch<TT>(Kar + pb[p], pl[p], tl[p]);
+    for (int p = 0; p < K; p++) tile_fetch<TT, LEAN>(Kar + pb[p], pl[p], tl[p]);
     // INF keys after each tile; the delay table
 #pragma unroll
     for (int p = 0; p < K; p++)
@@ -616,7 +631,7 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
 #pragma unroll
         for (int p = 0; p < K; p++) {
             int64_t t0, hp;
-            tile_settle<TT>(Kar + pb[p] + cur[p], rem[p], tl[p], lim[p], thi[p], t0, hp);
+            tile_settle<TT, LEAN>(Kar + pb[p] + cur[p], rem[p], tl[p], lim[p], thi[p], t0, hp);
             H = min64(H, hp);
             base = min64(base, t0);
         }
@@ -726,7 +741,7 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         PinTile<TT> nx[K];
         if constexpr (kPrefetch) {
 #pragma unroll
-            for (int p = 0; p < K; p++) tile_fetch<TT>(Kar + pb[p] + cur[p] + m[p], rem[p] - m[p], nx[p]);
+            for (int p = 0; p < K; p++) tile_fetch<TT, LEAN>(Kar + pb[p] + cur[p] + m[p], rem[p] - m[p], nx[p]);
         }
 
         // ---- pin states: this lane's composed update, scanned over the wave
@@ -737,7 +752,14 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
             const uint32_t sh = K == 1 ? 0u : (mk[k] & 3u) * 2u;
             const bool valid = mk[k] != kNoKey32;
             if (valid) upd = (upd & ~(3u << sh)) | (((mk[k] >> 2) & 3u) << sh) | (0x300u << sh);
-            trail_mask |= (mk[k] >> 4) == t_last ? 1u << (sh >> 1) : 0u;
+            if (!LEAN) trail_mask |= (mk[k] >> 4) == t_last ? 1u << (sh >> 1) : 0u;
+        }
+        if constexpr (LEAN) {
+#pragma unroll
+            for (int k = 8 - K; k < 8; k++) {
+                const uint32_t sh = K == 1 ? 0u : (mk[k] & 3u) * 2u;
+                trail_mask |= (mk[k] >> 4) == t_last ? 1u << (sh >> 1) : 0u;
+            }
         }
         const uint32_t upd_incl = wave_prefix_compose(upd);
         const uint32_t upd_excl = wave_shift_up(0u, upd_incl);
@@ -770,7 +792,7 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         if (EDGE) {
             uint32_t d0 = kEdgeNone, d1 = kEdgeNone, dx = kEdgeNone;
 #pragma unroll
-            for (int k = 0; k < 8; k++) {
+            for (int k = LEAN ? 8 - K : 0; k < 8; k++) {
                 if ((mk[k] >> 4) != t_last || mk[k] == kNoKey32) continue;
                 const uint32_t ent = L.etab[(mk[k] & 3u) * 3 + ((edges >> (2 * k)) & 3u)];
                 d0 = umin32(d0, ent & 1023u);
@@ -901,7 +923,7 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         for (int p = 0; p < K; p++) {
             cur[p] += m[p];
             if constexpr (kPrefetch) tl[p] = nx[p];
-            else tile_fetch<TT>(Kar + pb[p] + cur[p], rem[p] - m[p], tl[p]);
+            else tile_fetch<TT, LEAN>(Kar + pb[p] + cur[p], rem[p] - m[p], tl[p]);
         }
         __syncthreads();
     }
@@ -941,10 +963,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void ev
     const int64_t ob = A.blocksum[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + J.off[J.S + gate];
     switch (R.k) {
     // four pins load their next tiles at the end of each round (registers)
-    case 1: eval_gate<1, W, EDGE, true>(J, ob, R, gate, L); break;
-    case 2: eval_gate<2, W, EDGE, true>(J, ob, R, gate, L); break;
-    case 3: eval_gate<3, W, EDGE, true>(J, ob, R, gate, L); break;
-    default: eval_gate<4, W, EDGE, false>(J, ob, R, gate, L); break;
+    case 1: eval_gate<1, W, EDGE, true, true>(J, ob, R, gate, L); break;
+    case 2: eval_gate<2, W, EDGE, true, true>(J, ob, R, gate, L); break;
+    case 3: eval_gate<3, W, EDGE, true, true>(J, ob, R, gate, L); break;
+    default: eval_gate<4, W, EDGE, false, true>(J, ob, R, gate, L); break;
     }
 }
 
@@ -1195,10 +1217,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
                     reinterpret_cast<uint32_t *>(L.lut)[lane] =
                         reinterpret_cast<const uint32_t *>(J.lut + (int)R.type * 256)[lane];
                     switch (R.k) {
-                    case 1: eval_gate<1, kWindowLarge, EDGE, false>(J, ob, R, g, L); break;
-                    case 2: eval_gate<2, kWindowLarge, EDGE, false>(J, ob, R, g, L); break;
-                    case 3: eval_gate<3, kWindowLarge, EDGE, false>(J, ob, R, g, L); break;
-                    default: eval_gate<4, kWindowLarge, EDGE, false>(J, ob, R, g, L); break;
+                    case 1: eval_gate<1, kWindowLarge, EDGE, false, false>(J, ob, R, g, L); break;
+                    case 2: eval_gate<2, kWindowLarge, EDGE, false, false>(J, ob, R, g, L); break;
+                    case 3: eval_gate<3, kWindowLarge, EDGE, false, false>(J, ob, R, g, L); break;
+                    default: eval_gate<4, kWindowLarge, EDGE, false, false>(J, ob, R, g, L); break;
                     }
                 }
             }
