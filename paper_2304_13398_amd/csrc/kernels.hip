@@ -484,13 +484,30 @@ template <int T, bool LEAN>
 __device__ __forceinline__ void tile_fetch(const uint64_t *src, int64_t r, PinTile<T> &t) {
     const int lane = lane_id();
     t.n = (int)min64(r, (int64_t)T);
-    const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src);  // low word first
-#pragma unroll
-    for (int e = 0; e < T / 64; e++) t.lo[e] = lane + 64 * e < t.n ? s32[2 * (lane + 64 * e)] : 0u;
     if constexpr (LEAN) {
-        const int last = 2 * (t.n - 1);
-        t.aux = lane < 3 && t.n > 0 ? s32[lane == 0 ? 1 : lane == 1 ? last + 1 : last] : 0u;
+        // straight-line loads from one scalar base; lanes past the tile load
+        // its last transition again (entries past n are never used)
+        if (t.n > 0) {
+            const uint64_t a = (uint64_t)src;
+            const uint32_t a_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+            const uint32_t a_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+            const uint32_t *s32 = reinterpret_cast<const uint32_t *>(((uint64_t)a_hi << 32) | a_lo);
+            const int last = t.n - 1;
+#pragma unroll
+            for (int e = 0; e < T / 64; e++) {
+                const int i = lane + 64 * e < last ? lane + 64 * e : last;
+                t.lo[e] = s32[2 * i];  // low word first
+            }
+            t.aux = s32[lane == 0 ? 1 : lane == 1 ? 2 * last + 1 : 2 * last];
+        } else {
+#pragma unroll
+            for (int e = 0; e < T / 64; e++) t.lo[e] = 0u;
+            t.aux = 0u;
+        }
     } else {
+        const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src);  // low word first
+#pragma unroll
+        for (int e = 0; e < T / 64; e++) t.lo[e] = lane + 64 * e < t.n ? s32[2 * (lane + 64 * e)] : 0u;
         t.aux = lane < 2 && t.n > 0 ? s32[lane == 0 ? 1 : 2 * (t.n - 1) + 1] : 0u;
     }
 }
