@@ -266,7 +266,11 @@ gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out);
  *   nets  [n] net ids to fetch (sources included); NULL = all S+G nets in id order
  *   out_off [n+1] receives offsets into out_t/out_v (out_off[0] = 0)
  *   out_t, out_v: capacity `cap` transitions; if out_t is NULL only out_off is
- *   filled (size query). GSIM_E_ARG if cap < out_off[n]. */
+ *   filled (size query). GSIM_E_ARG if cap < out_off[n].
+ * Buffers from hipHostMalloc (page-locked) are written by DMA directly; other
+ * host memory is filled from page-locked staging by up to 16 host threads,
+ * overlapped with the next batch's transfer. Returns when every byte is in
+ * place; the caller keeps ownership of all arrays. */
 gsim_status sim_fetch_waveforms(gsim_ctx ctx, gsim_job job, const int64_t *nets, int64_t n,
                                 int64_t *out_off, int64_t *out_t, uint8_t *out_v, int64_t cap);
 
