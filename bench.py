@@ -139,6 +139,18 @@ def pool_map(fn, items):
         return list(ex.map(fn, items))
 
 
+# Unfinished steps the request loop lets the executor enqueue ahead of it (a
+# request that arrives waits at most this many steps, well under a
+# millisecond here, to join). Measured with 300 requests: at 100 jobs/s p50/p99
+# 18/120 ms with two, 16/98 ms with eight; at 500 jobs/s 538/1626 and 338/1520.
+SERVE_LOOKAHEAD = 8
+
+# Unfinished steps the batched loop lets the executor enqueue ahead of it: with
+# two, the host loop could not keep the device busy (1.01 s for the 64 sets);
+# from eight on the device never waits (0.75 s).
+BATCH_LOOKAHEAD = 8
+
+
 def bench_batched(G, sim, nl, h, n_sets, seed):
     """Batched: n_sets stimulus sets over the resident netlist, per-set
     transitions per PI log-uniform in [50, 5000]; all sets through the
@@ -176,8 +188,10 @@ def bench_batched(G, sim, nl, h, n_sets, seed):
         pending = sim.run_batch(h, sorted(sets, key=lambda x: -x.n))
         diag["run_batch_return_s"] = time.perf_counter() - t0
         n_out, retries, drives = 0, 0, 0
+        # every set is submitted up front, so steps may run far ahead of the
+        # host loop (a request loop keeps this short so late arrivals join soon)
         while pending:
-            sim.drive(max_ahead=2)         # admit sets as memory frees, advance all
+            sim.drive(max_ahead=BATCH_LOOKAHEAD)  # admit sets as memory frees, advance all
             drives += 1
             for j in [j for j in pending if sim.done(j)]:
                 st = sim.stats(j)
@@ -200,11 +214,12 @@ def bench_batched(G, sim, nl, h, n_sets, seed):
         "one_per_launch_transitions_per_s": n1 / t1, "one_per_launch_s": t1,
         "speedup": t1 / t2,
         "tuned_lane_threshold": thr, "tuning_ms": tms, "batched_diagnostics": diag,
+        "lookahead_steps": BATCH_LOOKAHEAD,
         "includes": "stimulus upload (pageable H2D), all levels, per-set completion wait",
     }
 
 
-def bench_served(G, sim, n_jobs, rates, seed):
+def bench_served(G, sim, n_jobs, rates, seed, lookahead=None):
     """Served: Poisson requests over 8 resident netlists (10k-2M gates), each
     request log-uniform 20-2,000 transitions per PI and asking for its
     netlist's primary outputs; continuous batching vs one job at a time."""
@@ -235,7 +250,8 @@ def bench_served(G, sim, n_jobs, rates, seed):
            "jobs_per_rate": n_jobs, "tuned_lane_thresholds": tuned, "rates": {}}
     for rate in rates:
         reqs = serve.served_workload(n_jobs, rate, nls, pool, seed=seed + int(rate))
-        rc, mc = serve.serve_continuous(sim, hs, reqs, max_ahead=2)
+        rc, mc = serve.serve_continuous(sim, hs, reqs,
+                                        max_ahead=SERVE_LOOKAHEAD if lookahead is None else lookahead)
         rs, ms = serve.serve_sequential(sim, hs, reqs)
         out["rates"][str(rate)] = {"continuous": serve.summarize(rc, mc),
                                    "sequential": serve.summarize(rs, ms)}

@@ -67,7 +67,7 @@ def _finish(sim, j, req, t0):
     return Result(lat, int(n_out), int(off[-1]), fp, req)
 
 
-def serve_continuous(sim: G.Sim, handles, requests, max_ahead: int = 2):
+def serve_continuous(sim: G.Sim, handles, requests, max_ahead: int = 8):
     reqs = sorted(requests, key=lambda r: r.arrival)
     results = []
     running = {}
