@@ -198,7 +198,10 @@ gsim_status sim_submit(gsim_ctx ctx, gsim_netlist nl, const int64_t *src_off, co
  * PyTorch) holding N_in = src_off[S] transitions; the caller keeps them alive
  * and unmodified until the job completes. They are validated on the host only
  * if `validate` is non-zero (one device-to-host copy); otherwise the caller
- * guarantees the waveform conventions. */
+ * guarantees the waveform conventions. Stimuli that break them give
+ * unspecified waveforms, but every gate still ends: a gate whose evaluation
+ * stops making progress (an input out of time order) makes sim_wait return
+ * GSIM_E_DEVICE. */
 gsim_status sim_submit_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_off,
                               const int64_t *d_t, const uint8_t *d_v, int64_t n_in, int validate,
                               void *hip_stream, gsim_job *out);

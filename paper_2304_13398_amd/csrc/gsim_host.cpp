@@ -1318,6 +1318,8 @@ Failure wait_job(gsim_ctx ctx, Job *j) {
                     (long long)j->capacity, (int)j->retries);
     if (j->h_state->check_error == 3)
         return fail(GSIM_E_DEVICE, "the dependency-driven schedule made no progress and stopped");
+    if (j->h_state->check_error == 4)
+        return fail(GSIM_E_DEVICE, "a gate's evaluation made no progress (an input waveform out of order)");
     if (j->h_state->check_error)
         return fail(GSIM_E_DEVICE, "internal consistency check failed (code %d)", j->h_state->check_error);
     return kOk;

@@ -83,7 +83,9 @@ struct DevState {
     int64_t n_out;           // output transitions (filled by the final reduction)
     int32_t overflow;        // arena exhausted: later levels are skipped
     int32_t check_error;     // an internal consistency check failed (never expected); 3: the
-                             // dependency-driven schedule made no progress for too long
+                             // dependency-driven schedule made no progress for too long;
+                             // 4: a gate's round took no input and finalised nothing (an
+                             // input waveform out of order)
 };
 
 // One job's share of a step: the gates of its current level.

@@ -642,13 +642,14 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
     uint32_t *const AB = L.seq + W + 1;                    // pairwise merges (K >= 3)
     uint32_t *const CD = AB + 256 + kMergePad + 1;         // (K == 4)
 
+    bool stalled = false;  // the last round made no progress (see below)
     for (;;) {
         int64_t rem[K];
-        bool more = nq > 0;
+        bool more = nq > 0 && !stalled;
 #pragma unroll
         for (int p = 0; p < K; p++) {
             rem[p] = pl[p] - cur[p];
-            more |= rem[p] > 0;
+            more |= rem[p] > 0 && !stalled;
         }
         if (!more) break;
 
@@ -909,6 +910,17 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         for (int c0 = 0; c0 < nseq; c0 += 64) {
             const int c = c0 + lane;
             nf += __popcll(__ballot(c < nseq && L.seq[c] <= hsplit));
+        }
+        // every round takes an input transition (the pin whose next one is at
+        // the base is in) or makes a survivor final (one at the base); neither
+        // means an input waveform is out of order: stop the gate with an error
+        // instead of looping
+        {
+            int taken = 0;
+#pragma unroll
+            for (int p = 0; p < K; p++) taken += m[p];
+            stalled = taken == 0 && nf == 0;
+            if (stalled && lane == 0) J.state->check_error = 4;
         }
         for (int c0 = 0; c0 < nf; c0 += 64) {
             const int j = c0 + lane;
