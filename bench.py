@@ -395,25 +395,55 @@ def bench_skewed(G, sim, nl, h, seed, wcvs=(5.0, 20.0), steps=3):
 def bench_windows(G, sim, nl, h, st, n_out_whole, ms_whole, n_windows=4):
     """Exact time-window chunking of the mid job: device time and output
     volume of the windows (each with its halo) against the whole job; the
-    windows' outputs inside their own ranges add up to the whole job's."""
+    windows' outputs inside their own ranges add up to the whole job's. Also
+    wall time from host stimuli to finished jobs: the whole job, the windows
+    one after another, and the windows submitted together (shared launches)."""
     from paper_2304_13398_amd import windows as WN
     H = WN.window_halo(nl)
-    inner = WN.window_bounds(st, n_windows)
-    edges = [None] + inner + [None]
+    wins = WN.window_stimuli(nl, st, n_windows, halo=H)
     dev_ms, n_out = 0.0, 0
-    for k in range(len(edges) - 1):
-        lo, hi = edges[k], edges[k + 1]
-        sub = WN.window_stimulus(st, nl.S, 0 if lo is None else max(0, lo - H),
-                                 np.iinfo(np.int64).max if hi is None else hi)
+    for _, _, sub in wins:
         j = sim.run(h, sub)
         sim.wait(j)
         s = sim.stats(j)
         dev_ms += s.device_ms
         n_out += s.n_out
         sim.release(j)
-    return {"windows": len(edges) - 1, "halo_ps": H, "device_ms_sum": dev_ms,
+
+    def whole():
+        t0 = time.perf_counter()
+        j = sim.run(h, st)
+        sim.wait(j)
+        sim.release(j)
+        return time.perf_counter() - t0
+
+    def one_by_one():
+        t0 = time.perf_counter()
+        for _, _, sub in wins:
+            j = sim.run(h, sub)
+            sim.wait(j)
+            sim.release(j)
+        return time.perf_counter() - t0
+
+    def together():
+        t0 = time.perf_counter()
+        pending = [sim.submit(h, sub) for _, _, sub in wins]
+        while pending:
+            sim.drive(max_ahead=BATCH_LOOKAHEAD)
+            for j in [j for j in pending if sim.done(j)]:
+                sim.release(j)
+                pending.remove(j)
+        return time.perf_counter() - t0
+
+    for f in (whole, one_by_one, together):  # untimed pass: staging allocation
+        f()
+    w_s, seq_s, tog_s = (min(f() for _ in range(2)) for f in (whole, one_by_one, together))
+    return {"windows": len(wins), "halo_ps": H, "device_ms_sum": dev_ms,
             "device_ms_whole": ms_whole, "n_out_sum": int(n_out), "n_out_whole": int(n_out_whole),
-            "overhead": dev_ms / ms_whole - 1.0}
+            "overhead": dev_ms / ms_whole - 1.0,
+            "wall_ms": {"whole_job": w_s * 1e3, "windows_one_by_one": seq_s * 1e3,
+                        "windows_together": tog_s * 1e3},
+            "wall_includes": "stimulus copy and upload from host memory, all levels, completion"}
 
 
 def bench_industrial(G, sim, seed, steps=3):

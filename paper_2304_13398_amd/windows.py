@@ -94,13 +94,12 @@ def window_bounds(st, n_windows: int) -> list[int]:
     return sorted(set(q for q in qs if q > 0))
 
 
-def simulate_windowed(nl, st, run, n_windows: int, halo: int | None = None):
-    """The job's gate waveforms assembled from ``n_windows`` independent runs.
-    Returns (off[G+1], t, v) in gate order, like one run of the whole job."""
+def window_stimuli(nl, st, n_windows: int, halo: int | None = None):
+    """The windows' ranges [lo, hi) (None: open) and their stimuli."""
     H = window_halo(nl) if halo is None else halo
     inner = window_bounds(st, n_windows)
     edges = [None] + inner + [None]
-    gid_parts, t_parts, v_parts = [], [], []
+    out = []
     for k in range(len(edges) - 1):
         lo, hi = edges[k], edges[k + 1]
         if lo is None and hi is None:
@@ -109,7 +108,20 @@ def simulate_windowed(nl, st, run, n_windows: int, halo: int | None = None):
             t_lo = 0 if lo is None else max(0, lo - H)
             t_hi = np.iinfo(np.int64).max if hi is None else hi
             sub = window_stimulus(st, nl.S, t_lo, t_hi)
-        off, t, v = run(sub)
+        out.append((lo, hi, sub))
+    return out
+
+
+def simulate_windowed(nl, st, run, n_windows: int, halo: int | None = None, run_many=None):
+    """The job's gate waveforms assembled from ``n_windows`` independent runs.
+    Returns (off[G+1], t, v) in gate order, like one run of the whole job.
+    ``run`` maps one window's stimulus to its gate waveforms; ``run_many``,
+    if given, maps the list of all windows' stimuli to the list of results
+    (so the windows can run together)."""
+    wins = window_stimuli(nl, st, n_windows, halo)
+    results = run_many([w[2] for w in wins]) if run_many is not None else [run(w[2]) for w in wins]
+    gid_parts, t_parts, v_parts = [], [], []
+    for (lo, hi, _), (off, t, v) in zip(wins, results):
         gid = np.repeat(np.arange(nl.G, dtype=np.int64), np.diff(off))
         keep = np.ones(len(t), dtype=bool)
         if lo is not None:
@@ -129,7 +141,9 @@ def simulate_windowed(nl, st, run, n_windows: int, halo: int | None = None):
 
 
 def gpu_engine(sim, nl):
-    """Engine for ``simulate_windowed``: the library on one resident netlist."""
+    """Engine for ``simulate_windowed``: the library on one resident netlist.
+    Returns (run, run_many, close): run_many submits every window at once and
+    lets the executor advance them in shared launches."""
     h = sim.load_netlist(nl)
     gates = np.arange(nl.S, nl.S + nl.G)
 
@@ -141,7 +155,17 @@ def gpu_engine(sim, nl):
         finally:
             sim.release(j)
 
+    def run_many(subs):
+        jobs = [sim.submit(h, sub) for sub in subs]
+        try:
+            for j in jobs:
+                sim.wait(j)
+            return [sim.fetch(j, gates) for j in jobs]
+        finally:
+            for j in jobs:
+                sim.release(j)
+
     def close():
         sim.unload_netlist(h)
 
-    return run, close
+    return run, run_many, close

@@ -201,13 +201,16 @@ def test_time_windows_on_the_gpu_equal_the_oracle(sim, n_windows):
     of the whole job."""
     from paper_2304_13398_amd import windows as WN
     nl, st = W.config3(G=6000, S=150, L=30, n_per_src=120, seed=13)
-    run, close = WN.gpu_engine(sim, nl)
+    run, run_many, close = WN.gpu_engine(sim, nl)
     try:
         got = WN.simulate_windowed(nl, st, run, n_windows)
+        together = WN.simulate_windowed(nl, st, None, n_windows, run_many=run_many)
     finally:
         close()
     say(f"windows: {n_windows}, halo {WN.window_halo(nl)} ps")
-    assert same(got, O.o1_simulate(nl, st))
+    want = O.o1_simulate(nl, st)
+    assert same(got, want)
+    assert same(together, want)
 
 
 def test_mixed_delay_models_share_steps(sim):
