@@ -307,6 +307,29 @@ def test_time_gaps_beyond_32_bits(sim, kernel):
     check(sim, nl, P.stimulus_of(waves), kernel)
 
 
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_times_near_the_limit(sim, kernel):
+    """Source times just below 2^61 and just below 2^62 minus the longest path
+    delay (the largest the library accepts): tiles whose keys' high words sit
+    at the top of their range and change inside a tile, dense bursts across
+    several 2^30 ps boundaries, through 12 levels of gates."""
+    rng = np.random.default_rng(31)
+    S = 8
+    nl = W.make_netlist(G=600, S=S, L=12, types=W.TYPES_ALL, dmin=0, dmax=60, seed=31, name="near-limit")
+    top = (1 << 62) - 1 - 12 * 61 - 1_000  # every output stays below 2^62
+    waves = []
+    for s in range(S):
+        starts = [(1 << 61) - 5_000, (1 << 61) + (1 << 30) - 700, top - 600_000, top - 3_000]
+        ts = np.unique(np.concatenate([b + np.sort(rng.choice(2_500, size=90, replace=False)) for b in starts]))
+        vals, prev = [], 2
+        for _ in ts:
+            v = int(rng.choice([c for c in range(4) if c != prev]))
+            vals.append(v)
+            prev = v
+        waves.append(list(zip(ts.tolist(), vals)))
+    check(sim, nl, P.stimulus_of(waves), kernel)
+
+
 def test_one_huge_gap_at_round_edge(sim):
     """A burst, a gap of 2^31 ps, then a second burst, through a chain of gates."""
     a = [(t, 1 if i % 2 == 0 else 0) for i, t in enumerate(range(0, 300, 3))]
