@@ -100,7 +100,9 @@ def parse():
     return ap.parse_args()
 
 
-def copy_probe(nbytes, reps=5):
+def copy_rate(nbytes, reps=5):
+    """Read-plus-write GB/s of a plain device copy of nbytes (the practical
+    HBM ceiling; both events on torch's current stream, where the copy runs)."""
     import torch
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
     a.fill_(1)
@@ -114,7 +116,12 @@ def copy_probe(nbytes, reps=5):
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / reps
-    gbps = 2 * nbytes / (ms / 1000.0) / 1e9
+    del a, b
+    return ms, 2 * nbytes / (ms / 1000.0) / 1e9
+
+
+def copy_probe(nbytes, reps=5):
+    ms, gbps = copy_rate(nbytes, reps)
     print(json.dumps({"copy_probe_bytes": nbytes, "ms_per_copy": ms,
                       "read_plus_write_gbps": gbps}), flush=True)
     return 0
@@ -650,6 +657,11 @@ def main():
             "valu_busy_frac": valu / (CU_COUNT * CLOCK_HZ) / avg_launch_s,
             "note": "the evaluate kernel is bound by VALU issue, not by HBM bandwidth",
     }
+
+    # the practical ceiling: a plain 1 GiB device copy on the same GPU
+    _, copy_gbps = copy_rate(1 << 30)
+    out["roofline"]["copy_ceiling_gbps"] = copy_gbps
+    out["roofline"]["frac_of_copy_ceiling"] = achieved / copy_gbps
 
     out["workload_stats"] = workload_stats(nl, lengths)
 
