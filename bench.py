@@ -528,8 +528,9 @@ def algorithmic_bytes(nl, lengths):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
-              "multi-GPU path.", file=sys.stderr, flush=True)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no "
+              "multi-GPU path (one job splits across GPUs by time windows, each window a "
+              "single-GPU job).", file=sys.stderr, flush=True)
         return 2
     if args.copy_probe:
         return copy_probe(args.copy_probe)
