@@ -6,6 +6,8 @@
 #include "gsim_internal.h"
 
 #include <algorithm>
+#include <exception>
+#include <new>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1379,12 +1381,21 @@ void parallel_copy(void *dst, const void *src, size_t bytes) {
     }
     const size_t part = (bytes + nt - 1) / nt;
     std::vector<std::thread> pool;
-    for (size_t k = 1; k < nt; k++) {
-        const size_t a = k * part, e = std::min(bytes, a + part);
-        if (a >= e) break;
-        pool.emplace_back([=] { std::memcpy((char *)dst + a, (const char *)src + a, e - a); });
+    size_t started = 1;  // parts [1, started) have a thread; the rest are copied here
+    try {
+        pool.reserve(nt - 1);
+        for (size_t k = 1; k < nt; k++, started++) {
+            const size_t a = k * part, e = std::min(bytes, a + part);
+            if (a >= e) break;
+            pool.emplace_back([=] { std::memcpy((char *)dst + a, (const char *)src + a, e - a); });
+        }
+    } catch (...) {  // no more threads: fewer helpers
     }
     std::memcpy(dst, src, std::min(bytes, part));
+    for (size_t k = started; k < nt; k++) {
+        const size_t a = k * part, e = std::min(bytes, a + part);
+        if (a < e) std::memcpy((char *)dst + a, (const char *)src + a, e - a);
+    }
     for (auto &t : pool) t.join();
 }
 
@@ -1530,6 +1541,30 @@ Failure fetch_hashes(gsim_ctx ctx, Job *j, const int64_t *nets, int64_t n, uint6
 // ===========================================================================
 // C ABI.
 
+namespace {
+// The C entry points never throw: an exception from the host runtime (out of
+// host memory, a thread that could not start) becomes a status, recorded on
+// the context when there is one.
+gsim_status exception_status(gsim_ctx ctx) noexcept {
+    gsim_status st = GSIM_E_DEVICE;
+    const char *what = "unexpected host error";
+    try {
+        throw;
+    } catch (const std::bad_alloc &) {
+        st = GSIM_E_OOM;
+        what = "host memory exhausted";
+    } catch (const std::exception &e) {
+        what = e.what();
+    } catch (...) {
+    }
+    try {
+        return record(ctx, fail(st, "%s", what));
+    } catch (...) {
+        return st;
+    }
+}
+}  // namespace
+
 extern "C" {
 
 const char *sim_version(void) { return "gsim 0.2 (gfx950)"; }
@@ -1542,7 +1577,7 @@ const char *sim_last_error(gsim_ctx ctx) {
     return copy.c_str();
 }
 
-gsim_status sim_create(int device, uint64_t hbm_budget_bytes, gsim_ctx *out) {
+gsim_status sim_create(int device, uint64_t hbm_budget_bytes, gsim_ctx *out) try {
     if (!out) return record(nullptr, fail(GSIM_E_ARG, "null output"));
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
@@ -1579,9 +1614,11 @@ gsim_status sim_create(int device, uint64_t hbm_budget_bytes, gsim_ctx *out) {
     }
     *out = ctx.release();
     return GSIM_OK;
+} catch (...) {
+    return exception_status(nullptr);
 }
 
-gsim_status sim_destroy(gsim_ctx ctx) {
+gsim_status sim_destroy(gsim_ctx ctx) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     (void)hipSetDevice(ctx->device);
     for (auto &kv : ctx->jobs) destroy_job(ctx, kv.second.get());
@@ -1600,9 +1637,11 @@ gsim_status sim_destroy(gsim_ctx ctx) {
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return GSIM_OK;
+} catch (...) {
+    return exception_status(ctx);
 }
 
-gsim_status sim_set_option(gsim_ctx ctx, int option, int64_t value) {
+gsim_status sim_set_option(gsim_ctx ctx, int option, int64_t value) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     switch (option) {
     case GSIM_OPT_ARENA_TRANSITIONS:
@@ -1627,25 +1666,31 @@ gsim_status sim_set_option(gsim_ctx ctx, int option, int64_t value) {
         return GSIM_OK;
     }
     return record(ctx, fail(GSIM_E_ARG, "unknown option %d", option));
+} catch (...) {
+    return exception_status(ctx);
 }
 
 gsim_status sim_load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type,
                              const int64_t *pin_off, const int64_t *pin_net,
-                             const int32_t *rise_ps, const int32_t *fall_ps, gsim_netlist *out) {
+                             const int32_t *rise_ps, const int32_t *fall_ps, gsim_netlist *out) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     return record(ctx, load_netlist(ctx, S, G, type, pin_off, pin_net, rise_ps, fall_ps, out));
+} catch (...) {
+    return exception_status(ctx);
 }
 
 gsim_status sim_load_netlist_ext(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type,
                                  const int64_t *pin_off, const int64_t *pin_net, const int32_t *dly,
-                                 int32_t n_udp, const uint8_t *udp, gsim_netlist *out) {
+                                 int32_t n_udp, const uint8_t *udp, gsim_netlist *out) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     if (G > 0 && !dly) return record(ctx, fail(GSIM_E_ARG, "null delay table"));
     return record(ctx, load_netlist(ctx, S, G, type, pin_off, pin_net, nullptr, nullptr, out,
                                     G > 0 ? dly : nullptr, n_udp, udp));
+} catch (...) {
+    return exception_status(ctx);
 }
 
-gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl) {
+gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     auto it = ctx->netlists.find(nl);
     if (it == ctx->netlists.end()) return record(ctx, fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nl));
@@ -1655,9 +1700,11 @@ gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl) {
     put_netlist(ctx, it->second.get());
     ctx->netlists.erase(it);
     return GSIM_OK;
+} catch (...) {
+    return exception_status(ctx);
 }
 
-gsim_status sim_set_netlist_option(gsim_ctx ctx, gsim_netlist nl, int option, int64_t value) {
+gsim_status sim_set_netlist_option(gsim_ctx ctx, gsim_netlist nl, int option, int64_t value) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     auto it = ctx->netlists.find(nl);
     if (it == ctx->netlists.end()) return record(ctx, fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nl));
@@ -1665,9 +1712,11 @@ gsim_status sim_set_netlist_option(gsim_ctx ctx, gsim_netlist nl, int option, in
     if (value < -1 || value > INT32_MAX) return record(ctx, fail(GSIM_E_ARG, "lane threshold out of range"));
     it->second->lane_threshold = (int32_t)value;
     return GSIM_OK;
+} catch (...) {
+    return exception_status(ctx);
 }
 
-gsim_status sim_netlist_info(gsim_ctx ctx, gsim_netlist nl, gsim_netlist_info *out) {
+gsim_status sim_netlist_info(gsim_ctx ctx, gsim_netlist nl, gsim_netlist_info *out) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     auto it = ctx->netlists.find(nl);
     if (it == ctx->netlists.end()) return record(ctx, fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nl));
@@ -1681,53 +1730,63 @@ gsim_status sim_netlist_info(gsim_ctx ctx, gsim_netlist nl, gsim_netlist_info *o
     out->max_path_delay = n.max_path_delay;
     out->lane_gates = n.lane_gates;
     return GSIM_OK;
+} catch (...) {
+    return exception_status(ctx);
 }
 
 gsim_status sim_submit(gsim_ctx ctx, gsim_netlist nl, const int64_t *src_off, const int64_t *t,
-                       const uint8_t *v, void *hip_stream, gsim_job *out) {
+                       const uint8_t *v, void *hip_stream, gsim_job *out) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     if (!out) return record(ctx, fail(GSIM_E_ARG, "null output"));
     Job *j = nullptr;
     Failure f = submit(ctx, nl, src_off, t, v, false, 0, 0, (hipStream_t)hip_stream, &j);
     if (f.st == GSIM_OK) *out = j->id;
     return record(ctx, f);
+} catch (...) {
+    return exception_status(ctx);
 }
 
 gsim_status sim_submit_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_off, const int64_t *d_t,
                               const uint8_t *d_v, int64_t n_in, int validate, void *hip_stream,
-                              gsim_job *out) {
+                              gsim_job *out) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     if (!out) return record(ctx, fail(GSIM_E_ARG, "null output"));
     Job *j = nullptr;
     Failure f = submit(ctx, nl, d_src_off, d_t, d_v, true, n_in, validate, (hipStream_t)hip_stream, &j);
     if (f.st == GSIM_OK) *out = j->id;
     return record(ctx, f);
+} catch (...) {
+    return exception_status(ctx);
 }
 
 gsim_status sim_run(gsim_ctx ctx, gsim_netlist nl, const int64_t *src_off, const int64_t *t,
-                    const uint8_t *v, void *hip_stream, gsim_job *out) {
+                    const uint8_t *v, void *hip_stream, gsim_job *out) try {
     gsim_status st = sim_submit(ctx, nl, src_off, t, v, hip_stream, out);
     if (st != GSIM_OK) return st;
     Job *j = nullptr;
     Failure f = find_job(ctx, *out, &j);
     if (f.st == GSIM_OK) f = drive_until_enqueued(ctx, j);
     return record(ctx, f);
+} catch (...) {
+    return exception_status(ctx);
 }
 
 gsim_status sim_run_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_off,
                            const int64_t *d_t, const uint8_t *d_v, int64_t n_in, int validate,
-                           void *hip_stream, gsim_job *out) {
+                           void *hip_stream, gsim_job *out) try {
     gsim_status st = sim_submit_device(ctx, nl, d_src_off, d_t, d_v, n_in, validate, hip_stream, out);
     if (st != GSIM_OK) return st;
     Job *j = nullptr;
     Failure f = find_job(ctx, *out, &j);
     if (f.st == GSIM_OK) f = drive_until_enqueued(ctx, j);
     return record(ctx, f);
+} catch (...) {
+    return exception_status(ctx);
 }
 
 gsim_status sim_run_batch(gsim_ctx ctx, gsim_netlist nl, int32_t n_sets, const int64_t *const *src_off,
                           const int64_t *const *t, const uint8_t *const *v, void *hip_stream,
-                          gsim_job *out) {
+                          gsim_job *out) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     if (n_sets < 0 || (n_sets > 0 && (!src_off || !t || !v || !out)))
         return record(ctx, fail(GSIM_E_ARG, "bad batch arguments"));
@@ -1757,10 +1816,12 @@ gsim_status sim_run_batch(gsim_ctx ctx, gsim_netlist nl, int32_t n_sets, const i
         }
     }
     return GSIM_OK;
+} catch (...) {
+    return exception_status(ctx);
 }
 
 gsim_status sim_drive(gsim_ctx ctx, void *hip_stream, int32_t max_ahead, int32_t *n_active,
-                      int32_t *n_queued) {
+                      int32_t *n_queued) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     if (max_ahead < 0 || max_ahead >= kRing) return record(ctx, fail(GSIM_E_ARG, "max_ahead must be in [0, %d)", kRing));
     Failure f = set_device(ctx);
@@ -1772,9 +1833,11 @@ gsim_status sim_drive(gsim_ctx ctx, void *hip_stream, int32_t max_ahead, int32_t
         if (n_queued) *n_queued = (int32_t)ex->queue.size();
     }
     return record(ctx, f);
+} catch (...) {
+    return exception_status(ctx);
 }
 
-gsim_status sim_job_done(gsim_ctx ctx, gsim_job job, int32_t *done) {
+gsim_status sim_job_done(gsim_ctx ctx, gsim_job job, int32_t *done) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     if (!done) return record(ctx, fail(GSIM_E_ARG, "null output"));
     Job *j = nullptr;
@@ -1792,17 +1855,21 @@ gsim_status sim_job_done(gsim_ctx ctx, gsim_job job, int32_t *done) {
         }
     }
     return GSIM_OK;
+} catch (...) {
+    return exception_status(ctx);
 }
 
-gsim_status sim_wait(gsim_ctx ctx, gsim_job job) {
+gsim_status sim_wait(gsim_ctx ctx, gsim_job job) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     Job *j = nullptr;
     Failure f = find_job(ctx, job, &j);
     if (f.st == GSIM_OK) f = wait_job(ctx, j);
     return record(ctx, f);
+} catch (...) {
+    return exception_status(ctx);
 }
 
-gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out) {
+gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     if (!out) return record(ctx, fail(GSIM_E_ARG, "null output"));
     Job *j = nullptr;
@@ -1830,28 +1897,34 @@ gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out) {
         out->eval_launches++;
     }
     return GSIM_OK;
+} catch (...) {
+    return exception_status(ctx);
 }
 
 gsim_status sim_fetch_waveforms(gsim_ctx ctx, gsim_job job, const int64_t *nets, int64_t n,
-                                int64_t *out_off, int64_t *out_t, uint8_t *out_v, int64_t cap) {
+                                int64_t *out_off, int64_t *out_t, uint8_t *out_v, int64_t cap) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     Job *j = nullptr;
     Failure f = find_job(ctx, job, &j);
     if (f.st == GSIM_OK) f = set_device(ctx);
     if (f.st == GSIM_OK) f = fetch(ctx, j, nets, n, out_off, out_t, out_v, cap);
     return record(ctx, f);
+} catch (...) {
+    return exception_status(ctx);
 }
 
-gsim_status sim_fetch_hashes(gsim_ctx ctx, gsim_job job, const int64_t *nets, int64_t n, uint64_t *out) {
+gsim_status sim_fetch_hashes(gsim_ctx ctx, gsim_job job, const int64_t *nets, int64_t n, uint64_t *out) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     Job *j = nullptr;
     Failure f = find_job(ctx, job, &j);
     if (f.st == GSIM_OK) f = set_device(ctx);
     if (f.st == GSIM_OK) f = fetch_hashes(ctx, j, nets, n, out);
     return record(ctx, f);
+} catch (...) {
+    return exception_status(ctx);
 }
 
-gsim_status sim_release_job(gsim_ctx ctx, gsim_job job) {
+gsim_status sim_release_job(gsim_ctx ctx, gsim_job job) try {
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     auto it = ctx->jobs.find(job);
     if (it == ctx->jobs.end()) return record(ctx, fail(GSIM_E_HANDLE, "unknown job handle %lld", (long long)job));
@@ -1859,23 +1932,29 @@ gsim_status sim_release_job(gsim_ctx ctx, gsim_job job) {
     destroy_job(ctx, it->second.get());
     ctx->jobs.erase(it);
     return GSIM_OK;
+} catch (...) {
+    return exception_status(ctx);
 }
 
 gsim_status sim_levelize(int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
                          const int64_t *pin_net, const int32_t *rise_ps, const int32_t *fall_ps,
-                         int32_t *level_out, int32_t *n_levels_out) {
+                         int32_t *level_out, int32_t *n_levels_out) try {
     Levelized lv;
     Failure f = levelize(S, G, type, pin_off, pin_net, rise_ps, fall_ps, &lv);
     if (f.st != GSIM_OK) return record(nullptr, f);
     if (level_out) std::copy(lv.level.begin(), lv.level.end(), level_out);
     if (n_levels_out) *n_levels_out = lv.n_levels;
     return GSIM_OK;
+} catch (...) {
+    return exception_status(nullptr);
 }
 
 gsim_status sim_validate_stimulus(int64_t S, const int64_t *src_off, const int64_t *t,
-                                  const uint8_t *v, int64_t max_path_delay) {
+                                  const uint8_t *v, int64_t max_path_delay) try {
     if (S < 0 || max_path_delay < 0) return record(nullptr, fail(GSIM_E_ARG, "negative S or path delay"));
     return record(nullptr, validate_stimulus(S, src_off, t, v, max_path_delay));
+} catch (...) {
+    return exception_status(nullptr);
 }
 
 }  // extern "C"
