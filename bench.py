@@ -276,6 +276,27 @@ def bench_served(G, sim, n_jobs, rates, seed, lookahead=None):
     return out
 
 
+def oracle_times(O, nl, st, n_threads):
+    """The oracle on a netlist: output transitions, single-thread seconds,
+    level-parallel seconds (the two results must agree)."""
+    t1 = time.perf_counter()
+    off, _, _ = O.o1_simulate(nl, st)
+    single_s = time.perf_counter() - t1
+    n_o = int(off[-1])
+    del off
+    t1 = time.perf_counter()
+    p_off, _, _ = O.o1_simulate(nl, st, threads=n_threads)
+    par_s = time.perf_counter() - t1
+    assert int(p_off[-1]) == n_o, "level-parallel oracle disagrees with the sequential one"
+    return n_o, single_s, par_s
+
+
+def oracle_threads():
+    """Host threads for the level-parallel oracle: the cores this process may
+    use, at most 16 (the CPU share of one GPU)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
 def bench_end_to_end(G, sim, nl, h, st, reps=2):
     """The headline job from host stimuli to every net's waveform in host
     memory: stimulus upload, validation and the run (sim_run + sim_wait), then
@@ -453,7 +474,7 @@ def bench_windows(G, sim, nl, h, st, n_out_whole, ms_whole, n_windows=4):
             "wall_includes": "stimulus copy and upload from host memory, all levels, completion"}
 
 
-def bench_industrial(G, sim, seed, steps=3):
+def bench_industrial(G, sim, seed, steps=3, oracle_levels=0):
     """The industrial-shaped configuration: 10M gates, 8,192 PIs + 50,000
     pseudo-PIs, 150 levels, fan-in 1-4, fanout cap 5,000, 1-200 ps delays, 200
     transitions per source (2 % X/Z); stimuli resident in HBM, one job at a
@@ -482,10 +503,18 @@ def bench_industrial(G, sim, seed, steps=3):
     sim.unload_netlist(h)
     ms = statistics.median(times) * 1000.0
     print(f"[bench] industrial: {ms:.1f} ms per job ({gen_s:.0f}s to generate)", file=sys.stderr, flush=True)
-    return {"workload": "industrial-shaped: 10M gates, 8,192 PIs + 50,000 pseudo-PIs, 150 levels, "
-                        "fan-in 1-4, fanout cap 5,000, rise/fall 1-200 ps, 200 transitions per source",
-            "gates": nl.G, "sources": nl.S, "n_in": st.n, "n_out": int(n_out), "ms_per_job": ms,
-            "device_ms": statistics.median(dev_ms), "transitions_per_s": n_out / (ms / 1000.0)}
+    res = {"workload": "industrial-shaped: 10M gates, 8,192 PIs + 50,000 pseudo-PIs, 150 levels, "
+                       "fan-in 1-4, fanout cap 5,000, rise/fall 1-200 ps, 200 transitions per source",
+           "gates": nl.G, "sources": nl.S, "n_in": st.n, "n_out": int(n_out), "ms_per_job": ms,
+           "device_ms": statistics.median(dev_ms), "transitions_per_s": n_out / (ms / 1000.0)}
+    if oracle_levels > 0:
+        from oracle import oracle as O
+        n_gates = int(np.searchsorted(nl.level, oracle_levels, side="right"))
+        n_t = oracle_threads()
+        n_o, single_s, par_s = oracle_times(O, nl.prefix(n_gates), st, n_t)
+        res["oracle_sample"] = {"levels": f"1-{oracle_levels}", "gates": n_gates, "n_out": n_o,
+                                "single_thread_s": single_s, "parallel_s": par_s, "threads": n_t}
+    return res
 
 
 def workload_stats(nl, lengths):
@@ -717,8 +746,7 @@ def main():
         n_o = int(o_off[-1])
         del o_off, o_v, gate_of, lvl
         # the same sample with each level's gates split over the host's cores
-        # (at most 16: the CPU share of one GPU)
-        n_threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        n_threads = oracle_threads()
         t1 = time.perf_counter()
         p_off, _, _ = O.o1_simulate(sub, st, threads=n_threads)
         par_s = time.perf_counter() - t1
@@ -758,13 +786,55 @@ def main():
         out["batched"] = bench_batched(G, sim, nl, h, args.batched_sets, args.seed)
     sim.unload_netlist(h)
     if not args.no_industrial:
-        out["industrial"] = bench_industrial(G, sim, args.seed)
+        out["industrial"] = bench_industrial(G, sim, args.seed,
+                                             oracle_levels=0 if args.no_cpu_baseline else 10)
     if not args.no_served:
         rates = [float(x) for x in args.served_rates.split(",") if x]
         out["served"] = bench_served(G, sim, args.served_jobs, rates, args.seed)
+    if "cpu_baseline" in out:
+        out["cpu_baseline"].update(eq6_speedups(out, nl_tiny_oracle(args) if "tiny_latency" in out else None))
     print(json.dumps(out), flush=True)
     sim.close()
     return 0
+
+
+def nl_tiny_oracle(args):
+    """The oracle on the whole tiny job: (n_out, single-thread s, parallel s)."""
+    from oracle import oracle as O
+    from paper_2304_13398_amd import workloads as W
+    nl, st = W.config1(seed=args.seed)
+    return oracle_times(O, nl, st, oracle_threads())
+
+
+def eq6_speedups(out, tiny):
+    """GPU over oracle per configuration (the paper's Eq. 6 speedup, here as a
+    ratio of output-transition rates on the same work) and their geometric
+    mean, against the level-parallel and the single-thread oracle."""
+    cb = out["cpu_baseline"]
+    per = {"mid": {"gpu_transitions_per_s": out["value"], "oracle_parallel_per_s": cb["value"],
+                   "oracle_single_per_s": cb["single_thread_value"]}}
+    if tiny is not None:
+        n_o, single_s, par_s = tiny
+        # the tiny job's latency under the schedule the automatic choice picks
+        # (dependency-driven for a netlist this small), resident stimuli
+        key = "tiny_latency_dataflow" if "tiny_latency_dataflow" in out else "tiny_latency"
+        gpu_s = out[key]["resident_p50_us"] / 1e6
+        per["tiny"] = {"gpu_transitions_per_s": n_o / gpu_s, "oracle_parallel_per_s": n_o / par_s,
+                       "oracle_single_per_s": n_o / single_s, "gpu_schedule": key}
+    ind = out.get("industrial", {}).get("oracle_sample")
+    if ind is not None:
+        per["industrial"] = {"gpu_transitions_per_s": out["industrial"]["transitions_per_s"],
+                             "oracle_parallel_per_s": ind["n_out"] / ind["parallel_s"],
+                             "oracle_single_per_s": ind["n_out"] / ind["single_thread_s"],
+                             "oracle_sample": f"levels {ind['levels']}"}
+    for v in per.values():
+        v["speedup"] = v["gpu_transitions_per_s"] / v["oracle_parallel_per_s"]
+        v["speedup_single_thread"] = v["gpu_transitions_per_s"] / v["oracle_single_per_s"]
+        # the faster CPU form (threads cost more than they give on a tiny job)
+        v["speedup_best_cpu"] = min(v["speedup"], v["speedup_single_thread"])
+    g = lambda key: float(np.exp(np.mean([np.log(v[key]) for v in per.values()])))
+    return {"per_config": per, "geomean_speedup_best_cpu": g("speedup_best_cpu"),
+            "geomean_speedup": g("speedup"), "geomean_speedup_single_thread": g("speedup_single_thread")}
 
 
 if __name__ == "__main__":
