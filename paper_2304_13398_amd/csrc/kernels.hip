@@ -35,7 +35,6 @@ __device__ __forceinline__ int64_t shfl_down64(int64_t x, int d) {
     return (int64_t)shfl_down_u64((uint64_t)x, d);
 }
 
-__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
@@ -284,15 +283,6 @@ __device__ __forceinline__ uint32_t dpp_u32(uint32_t identity, uint32_t x) {
 
 __device__ __forceinline__ uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
 
-__device__ __forceinline__ uint32_t wave_prefix_min(uint32_t x) {
-    x = umin32(x, dpp_u32<kDppRowShr1>(~0u, x));
-    x = umin32(x, dpp_u32<kDppRowShr2>(~0u, x));
-    x = umin32(x, dpp_u32<kDppRowShr4>(~0u, x));
-    x = umin32(x, dpp_u32<kDppRowShr8>(~0u, x));
-    x = umin32(x, dpp_u32<kDppRowBcast15, 0xa>(~0u, x));
-    x = umin32(x, dpp_u32<kDppRowBcast31, 0xc>(~0u, x));
-    return x;
-}
 
 __device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t x) {
     x += dpp_u32<kDppRowShr1>(0u, x);
