@@ -104,3 +104,29 @@ def test_context_without_device_fails_cleanly():
     if torch.cuda.is_available():
         pytest.skip("a device is present")
     _expect(G.E_DEVICE, G.Sim)
+
+
+def header_struct(name):
+    """(field, C type) pairs of `typedef struct { ... } name;` in gsim.h."""
+    src = open(os.path.join(ROOT, "include", "gsim.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r"\s*;", src).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        fields += [(n.strip(), ctype) for n in names.split(",")]
+    return fields
+
+
+@pytest.mark.parametrize("c_name,py_cls", [("gsim_job_stats", "JobStats"),
+                                           ("gsim_netlist_info", "NetlistInfo")])
+def test_binding_structs_match_the_header(c_name, py_cls):
+    import ctypes
+    ctype_of = {"int64_t": ctypes.c_int64, "int32_t": ctypes.c_int32, "double": ctypes.c_double,
+                "uint64_t": ctypes.c_uint64}
+    want = [(n, ctype_of[t]) for n, t in header_struct(c_name)]
+    got = list(getattr(G, py_cls)._fields_)
+    assert got == want
