@@ -7,10 +7,11 @@ _U = np.uint64
 
 
 def mix(x):
-    x = np.asarray(x, dtype=np.uint64) + _U(0x9E3779B97F4A7C15)
-    x = (x ^ (x >> _U(30))) * _U(0xBF58476D1CE4E5B9)
-    x = (x ^ (x >> _U(27))) * _U(0x94D049BB133111EB)
-    return x ^ (x >> _U(31))
+    with np.errstate(over="ignore"):  # arithmetic mod 2^64 by definition
+        x = np.asarray(x, dtype=np.uint64) + _U(0x9E3779B97F4A7C15)
+        x = (x ^ (x >> _U(30))) * _U(0xBF58476D1CE4E5B9)
+        x = (x ^ (x >> _U(27))) * _U(0x94D049BB133111EB)
+        return x ^ (x >> _U(31))
 
 
 def fingerprints(off, t, v):
