@@ -1601,17 +1601,21 @@ gsim_status sim_create(int device, uint64_t hbm_budget_bytes, gsim_ctx *out) try
     }
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess)
         return record(nullptr, fail(GSIM_E_DEVICE, "stream creation failed"));
+    // from here a failure also destroys the stream (the pool frees its slab itself)
+    auto give_up = [&](gsim_status st, const char *msg) {
+        (void)hipStreamDestroy(ctx->stream);
+        return record(nullptr, fail(st, "%s", msg));
+    };
     ctx->d_stage_t = (int64_t *)ctx->pool->get(sizeof(int64_t) * 2 * kStage);
     ctx->d_stage_v = (uint8_t *)ctx->pool->get(2 * kStage);
     ctx->d_stage_meta = (int64_t *)ctx->pool->get(sizeof(int64_t) * 2 * 3 * kStageBatch);
     if (!ctx->d_stage_t || !ctx->d_stage_v || !ctx->d_stage_meta)
-        return record(nullptr, fail(GSIM_E_OOM, "no device memory for the fetch staging buffers"));
+        return give_up(GSIM_E_OOM, "no device memory for the fetch staging buffers");
     std::vector<uint8_t> lut = build_lut();
     ctx->d_lut = (uint8_t *)ctx->pool->get(lut.size());
-    if (!ctx->d_lut || hipMemcpy(ctx->d_lut, lut.data(), lut.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipStreamDestroy(ctx->stream);
-        return record(nullptr, fail(GSIM_E_DEVICE, "gate table upload failed"));
-    }
+    if (!ctx->d_lut) return give_up(GSIM_E_OOM, "no device memory for the gate table");
+    if (hipMemcpy(ctx->d_lut, lut.data(), lut.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return give_up(GSIM_E_DEVICE, "gate table upload failed");
     *out = ctx.release();
     return GSIM_OK;
 } catch (...) {
