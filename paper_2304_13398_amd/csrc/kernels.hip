@@ -666,15 +666,21 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         int m[K];
 #pragma unroll
         for (int p = 0; p < K; p++) {
-            // a tile key is at or before H by its (uniform) high word, else by its low word
-            const uint32_t lo_max = thi[p] < hk_hi ? 0xFFFFFFFFu : (uint32_t)hkey;
-            const int lim_in = thi[p] > hk_hi ? 0 : lim[p];
+            // a tile key is at or before H by its (uniform) high word, else by
+            // its low word. Both bounds go through scalar registers, so each
+            // test below is one compare, and the count is the AND of two
+            // ballots (a ballot of the conjunction would cost two vector
+            // instructions more per key)
+            const uint32_t lo_max =
+                (uint32_t)__builtin_amdgcn_readfirstlane((int)(thi[p] < hk_hi ? 0xFFFFFFFFu : (uint32_t)hkey));
+            const int lim_in = __builtin_amdgcn_readfirstlane(thi[p] > hk_hi ? 0 : lim[p]);
             m[p] = 0;
 #pragma unroll
             for (int e = 0; e < E; e++) {
                 const uint32_t lo = tl[p].lo[e];
-                const bool in = lane + 64 * e < lim_in && lo <= lo_max;
-                m[p] += __popcll(__ballot(in));
+                const bool in_lane = lane + 64 * e < lim_in, in_time = lo <= lo_max;
+                const bool in = in_lane && in_time;
+                m[p] += __popcll(__ballot(in_lane) & __ballot(in_time));
                 // (t - base) << 2 | v < 2^30 equals the low word of key - (base << 2)
                 L.tile[Tl::OFF(p) + 1 + 64 * e + lane] = in ? ((lo - base4) << 2) | (uint32_t)p : kNoKey32;
             }
