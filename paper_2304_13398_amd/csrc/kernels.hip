@@ -37,6 +37,14 @@ __device__ __forceinline__ int64_t shfl_down64(int64_t x, int d) {
 
 __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 
+// A value every lane holds alike, moved to scalar registers, so that what is
+// computed from it (and branches on it) stays off the vector unit.
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uint64_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
 // Number of set bits of `mask` below this lane.
@@ -634,6 +642,13 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
 
     bool stalled = false;  // the last round made no progress (see below)
     for (;;) {
+        // the loop-carried counts are the same on every lane; restating that
+        // here lets the compiler keep the loop's control and the pins'
+        // bookkeeping on the scalar unit (otherwise it treats the loop as
+        // divergent and carries them in vector registers)
+        nq = __builtin_amdgcn_readfirstlane(nq);
+#pragma unroll
+        for (int p = 0; p < K; p++) cur[p] = uniform64(cur[p]);
         int64_t rem[K];
         bool more = nq > 0 && !stalled;
 #pragma unroll
