@@ -992,7 +992,7 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
 // EDGE), in one launch, one wavefront per entry of the variant's sorted list
 // (costliest first).
 template <int W, bool EDGE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void eval_wave_kernel(StepArgs A,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W == 64 ? 6 : 5))) void eval_wave_kernel(StepArgs A,
                                                                                               int var) {
     __shared__ WaveLds<W> L;
     const int lane = lane_id();
@@ -1017,7 +1017,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void ev
     case 1: eval_gate<1, W, EDGE, true, true, false>(J, ob, R, gate, L); break;
     case 2: eval_gate<2, W, EDGE, true, true, false>(J, ob, R, gate, L); break;
     case 3: eval_gate<3, W, EDGE, true, true, false>(J, ob, R, gate, L); break;
-    default: eval_gate<4, W, EDGE, false, true, false>(J, ob, R, gate, L); break;
+    default: eval_gate<4, W, EDGE, true, true, false>(J, ob, R, gate, L); break;
     }
 }
 
