@@ -990,7 +990,10 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
 
 // Every gate of the step in one variant (largest delay at most W; delay model
 // EDGE), in one launch, one wavefront per entry of the variant's sorted list
-// (costliest first).
+// (costliest first). Occupancy: six wavefronts per SIMD for the 64 ps window
+// (6 KB of LDS each; a seventh would need 168 KB of the CU's 160 KB), five
+// for 256 (6.75 KB each). Six cost a few spilled registers and measured 3 %
+// faster than five.
 template <int W, bool EDGE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W == 64 ? 6 : 5))) void eval_wave_kernel(StepArgs A,
                                                                                               int var) {
@@ -1013,7 +1016,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W == 64 ? 6 
         reinterpret_cast<const uint32_t *>(J.lut + (int)R.type * 256)[lane];
     const int64_t ob = A.blocksum[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + J.off[J.S + gate];
     switch (R.k) {
-    // four pins load their next tiles at the end of each round (registers)
+    // every pin count prefetches its next tiles during the round
     case 1: eval_gate<1, W, EDGE, true, true, false>(J, ob, R, gate, L); break;
     case 2: eval_gate<2, W, EDGE, true, true, false>(J, ob, R, gate, L); break;
     case 3: eval_gate<3, W, EDGE, true, true, false>(J, ob, R, gate, L); break;
