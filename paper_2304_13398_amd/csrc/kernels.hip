@@ -403,10 +403,13 @@ __device__ __forceinline__ void cswap(uint32_t &a, uint32_t &b) {
 }
 
 // Merged positions [d, d + 8) of the sorted lists A[0, a) and B[0, b) (keys
-// distinct, each list followed by kMergePad kNoKey32 and preceded by one
-// readable guard word); positions past a + b come out as kNoKey32. NIT
-// search steps cover split ranges up to 2^NIT - 1.
-template <int NIT>
+// distinct, each list followed by kMergePad kNoKey32, B preceded by a zero
+// guard word); positions past a + b come out as kNoKey32. NIT search steps
+// cover split ranges up to 2^NIT - 1. Once the search has converged, its
+// test is false by itself (A's pad or B's guard decides it), so the steps
+// need no check that the range is still open; CHECKED keeps that check (the
+// dependency-driven kernel: without it, its register allocation spills).
+template <int NIT, bool CHECKED>
 __device__ __forceinline__ void merge8(const uint32_t *A, int a, const uint32_t *B, int b, int d,
                                        uint32_t (&c)[8]) {
     d = d < a + b ? d : a + b;
@@ -416,7 +419,7 @@ __device__ __forceinline__ void merge8(const uint32_t *A, int a, const uint32_t 
     for (int it = 0; it < NIT; it++) {
         const int mid = (lo + hi) >> 1;
         const bool less = A[mid] < B[d - 1 - mid];
-        const bool go = lo < hi;
+        const bool go = !CHECKED || lo < hi;
         lo = go && less ? mid + 1 : lo;
         hi = go && !less ? mid : hi;
     }
@@ -601,10 +604,12 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
     PinTile<TT> tl[K];  // this round's tiles
 #pragma unroll
     for (int p = 0; p < K; p++) tile_fetch<TT, LEAN>(Kar + pb[p], pl[p], tl[p]);
-    // INF keys after each tile; the delay table
+    // INF keys after each tile, a zero guard before it (merge8); the delay table
 #pragma unroll
-    for (int p = 0; p < K; p++)
+    for (int p = 0; p < K; p++) {
         if (lane < kMergePad) L.tile[Tl::OFF(p) + 1 + TT + lane] = kNoKey32;
+        if (!AGENT && lane == kMergePad) L.tile[Tl::OFF(p)] = 0u;  // (the checked search needs none)
+    }
     if (EDGE) {
         // per (pin, edge class): delays to 0, 1 and X; finite ones are <= W
         if (lane < 3 * K) {
@@ -710,20 +715,20 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
 #pragma unroll
             for (int k = 0; k < 8; k++) mk[k] = L.tile[1 + 8 * lane + k];
         } else if constexpr (K == 2) {
-            merge8<9>(L.tile + Tl::OFF(0) + 1, m[0], L.tile + Tl::OFF(1) + 1, m[1], 8 * lane, mk);
+            merge8<9, AGENT>(L.tile + Tl::OFF(0) + 1, m[0], L.tile + Tl::OFF(1) + 1, m[1], 8 * lane, mk);
             if (m[0] + m[1] > 512) cut = (uint32_t)__builtin_amdgcn_readlane((int)mk[7], 63) >> 4;
         } else if constexpr (K == 3) {
             // the first 512 of pins 0 and 1 into AB, then AB with pin 2's tile
             {
                 uint32_t h[8];
-                merge8<9>(L.tile + Tl::OFF(0) + 1, m[0], L.tile + Tl::OFF(1) + 1, m[1], 8 * lane, h);
+                merge8<9, AGENT>(L.tile + Tl::OFF(0) + 1, m[0], L.tile + Tl::OFF(1) + 1, m[1], 8 * lane, h);
 #pragma unroll
                 for (int k = 0; k < 8; k++) AB[8 * lane + k] = h[k];
                 if (lane < kMergePad) AB[512 + lane] = kNoKey32;
             }
             __syncthreads();
             const int ab = m[0] + m[1] < 512 ? m[0] + m[1] : 512;
-            merge8<9>(AB, ab, L.tile + Tl::OFF(2) + 1, m[2], 8 * lane, mk);
+            merge8<9, AGENT>(AB, ab, L.tile + Tl::OFF(2) + 1, m[2], 8 * lane, mk);
             if (m[0] + m[1] + m[2] > 512) cut = (uint32_t)__builtin_amdgcn_readlane((int)mk[7], 63) >> 4;
         } else {
             // the first 256 of pins 0 and 1 (lanes 0-31) and of pins 2 and 3 (lanes 32-63)
@@ -733,17 +738,18 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
             const int a = hi_half ? m[2] : m[0];
             const int b = hi_half ? m[K - 1] : m[1];
             uint32_t h[8];
-            merge8<8>(A, a, B, b, 8 * (lane & 31), h);
+            merge8<8, AGENT>(A, a, B, b, 8 * (lane & 31), h);
             uint32_t *dst = (hi_half ? CD : AB) + 8 * (lane & 31);
 #pragma unroll
             for (int k = 0; k < 8; k++) dst[k] = h[k];
             if (lane < 2 * kMergePad) (lane < kMergePad ? AB : CD)[256 + (lane % kMergePad)] = kNoKey32;
+            if (!AGENT && lane == 2 * kMergePad) CD[-1] = 0u;  // the second list's guard (after AB's pads)
             const uint32_t c_ab = (uint32_t)__builtin_amdgcn_readlane((int)h[7], 31) >> 4;
             const uint32_t c_cd = (uint32_t)__builtin_amdgcn_readlane((int)h[7], 63) >> 4;
             if (m[0] + m[1] > 256) cut = c_ab;
             if (m[2] + m[K - 1] > 256) cut = umin32(cut, c_cd);
             __syncthreads();
-            merge8<9>(AB, m[0] + m[1] < 256 ? m[0] + m[1] : 256, CD,
+            merge8<9, AGENT>(AB, m[0] + m[1] < 256 ? m[0] + m[1] : 256, CD,
                       m[2] + m[K - 1] < 256 ? m[2] + m[K - 1] : 256, 8 * lane, mk);
         }
         if (cut != kNoTime28 && (int64_t)cut - 1 < H - base) {
