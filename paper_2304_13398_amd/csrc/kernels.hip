@@ -824,7 +824,9 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
             const uint32_t nv = (mk[k] >> 2) & 3u;
             if (EDGE) edges |= edge_class((st >> sh) & 3u, nv) << (2 * k);
             st = (st & ~(3u << sh)) | (nv << sh);
-            const uint32_t ek = L.lut[st];
+            // table entries are 0, 1 or X (2); the 2-bit extract replaces the
+            // byte mask the compiler adds after each byte load
+            const uint32_t ek = __builtin_amdgcn_ubfe(L.lut[st], 0, 2);
             evs |= ek << (2 * k);
             const uint32_t tn = k < 7 ? mk[k + 1] >> 4 : next_first;
             const bool end = mk[k] != kNoKey32 && (mk[k] >> 4) != tn;
