@@ -112,19 +112,28 @@ enum gsim_option {
 /* ---- context ------------------------------------------------------------ */
 
 /* Open a context on HIP device `device`. `hbm_budget_bytes` caps the device
- * memory the context allocates (0 = 90% of the device's free memory). */
+ * memory the context allocates (0 = 90% of the device's free memory).
+ * Passage: the device memory that holds every waveform of a job at once is
+ * the premise of one-pass parallelism (Section 1, Motivation; Section 3). */
 gsim_status sim_create(int device, uint64_t hbm_budget_bytes, gsim_ctx *out);
-/* Release every netlist, job and buffer of the context. */
+/* Release every netlist, job and buffer of the context. No passage of the
+ * paper (plumbing). */
 gsim_status sim_destroy(gsim_ctx ctx);
 /* Message of the last failed call on `ctx` (or of the last failed
  * context-free call when ctx is NULL); owned by the library, valid until the
- * next call on the same context. Never NULL. */
+ * next call on the same context. Never NULL. No passage (plumbing). */
 const char *sim_last_error(gsim_ctx ctx);
+/* Set one of enum gsim_option on the context; each option cites its own
+ * passage above. GSIM_E_ARG for an unknown option or a value out of range. */
 gsim_status sim_set_option(gsim_ctx ctx, int option, int64_t value);
 
 /* ---- netlists ------------------------------------------------------------ */
 
 /* Validate, levelize and upload a netlist (host levelizer and CSR builder).
+ * Passage: the netlist, module functions and delays given to the problem
+ * (Section 2.1, Objective Statement), kept on the device for the whole run
+ * with each output net stored once on its hyperedge (Section 3, the
+ * figure on distributing an output waveform).
  *   S, G     number of source nets and gates (S >= 1, G >= 0)
  *   type     [G] gate types (enum gsim_gate_type)
  *   pin_off  [G+1] gate g's pins are pin_off[g] .. pin_off[g+1]-1; pin_off[0]=0,
@@ -158,10 +167,15 @@ gsim_status sim_load_netlist_ext(gsim_ctx ctx, int64_t S, int64_t G, const uint8
                                  const int64_t *pin_off, const int64_t *pin_net, const int32_t *dly,
                                  int32_t n_udp, const uint8_t *udp, gsim_netlist *out);
 
+/* Free a netlist's device copy. GSIM_E_HANDLE if unknown; jobs of the
+ * netlist must be released first (GSIM_E_ARG otherwise). No passage
+ * (plumbing). */
 gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl);
 
 /* Per-netlist setting of GSIM_OPT_LANE_THRESHOLD (-1 = follow the context's
- * option); other options are per context. Applies to jobs stepped afterwards. */
+ * option); other options are per context. Applies to jobs stepped afterwards.
+ * Passage: a task's cost grows with its input waveforms' length (Section 5,
+ * the WCV discussion), which the threshold bins on. */
 gsim_status sim_set_netlist_option(gsim_ctx ctx, gsim_netlist nl, int option, int64_t value);
 
 typedef struct {
@@ -171,7 +185,23 @@ typedef struct {
     int64_t max_path_delay;  /* largest sum of per-gate largest delays along a path */
     int64_t lane_gates;      /* gates routed to the lane-per-gate kernel */
 } gsim_netlist_info;
+/* Sizes of a loaded netlist. `levels` is the number of parallel layers a
+ * level-by-level schedule needs (Section 4.1). */
 gsim_status sim_netlist_info(gsim_ctx ctx, gsim_netlist nl, gsim_netlist_info *out);
+
+/* Device memory of the context (no passage of the paper: plumbing). The
+ * context carves every device buffer out of one slab of `budget_bytes`;
+ * `live_bytes` is what netlists, jobs and fetch staging hold now, and
+ * `largest_free_bytes` the largest buffer that can still be allocated.
+ * `jobs_holding_storage` counts jobs that hold output storage (admitted and
+ * not yet released). */
+typedef struct {
+    uint64_t budget_bytes;
+    uint64_t live_bytes;
+    uint64_t largest_free_bytes;
+    int64_t jobs_holding_storage;
+} gsim_memory_info;
+gsim_status sim_memory_info(gsim_ctx ctx, gsim_memory_info *out);
 
 /* ---- runs ----------------------------------------------------------------- */
 
@@ -182,7 +212,9 @@ gsim_status sim_netlist_info(gsim_ctx ctx, gsim_netlist nl, gsim_netlist_info *o
  * admitted when its device storage fits the context's HBM budget; until then
  * it waits in the executor's queue. */
 
-/* Queue one re-simulation of `nl` over host-resident source waveforms:
+/* Queue one re-simulation of `nl` over host-resident source waveforms
+ * (passage: the given waveforms of primary and pseudo-primary inputs,
+ * Section 2.1; transferred to the device in one round, Section 1.4):
  *   src_off [S+1] source s's transitions are t/v[src_off[s] .. src_off[s+1]-1]
  *   t [N_in], v [N_in] with N_in = src_off[S]
  * The stimuli are validated and copied to the device (one transfer) before the
@@ -194,7 +226,9 @@ gsim_status sim_netlist_info(gsim_ctx ctx, gsim_netlist nl, gsim_netlist_info *o
 gsim_status sim_submit(gsim_ctx ctx, gsim_netlist nl, const int64_t *src_off, const int64_t *t,
                        const uint8_t *v, void *hip_stream, gsim_job *out);
 
-/* As sim_submit, but the three arrays are device pointers (e.g. owned by
+/* Passage as sim_submit (Section 2.1), with the given waveforms already in
+ * device memory.
+ * As sim_submit, but the three arrays are device pointers (e.g. owned by
  * PyTorch) holding N_in = src_off[S] transitions; the caller keeps them alive
  * and unmodified until the job completes. They are validated on the host only
  * if `validate` is non-zero (one device-to-host copy); otherwise the caller
@@ -208,16 +242,20 @@ gsim_status sim_submit_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_sr
 
 /* sim_submit, then drive the executor until every level of the job is
  * enqueued; returns without waiting for the device. GSIM_E_OOM if the job
- * cannot be admitted because unreleased jobs hold the budget. */
+ * cannot be admitted because unreleased jobs hold the budget. Passage: the
+ * whole computation on the device with no host synchronisation in between
+ * (Section 1.4, Algorithmic Flow; Section 4.1; Algorithm 2 per gate). */
 gsim_status sim_run(gsim_ctx ctx, gsim_netlist nl, const int64_t *src_off, const int64_t *t,
                     const uint8_t *v, void *hip_stream, gsim_job *out);
 
-/* sim_submit_device, then as sim_run. */
+/* sim_submit_device, then as sim_run (passage as sim_run). */
 gsim_status sim_run_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_off,
                            const int64_t *d_t, const uint8_t *d_v, int64_t n_in, int validate,
                            void *hip_stream, gsim_job *out);
 
-/* Batched execution of `n_sets` stimulus sets over one resident netlist:
+/* No passage of the paper: several independent re-simulations of one
+ * netlist share launches (the paper runs one task at a time).
+ * Batched execution of `n_sets` stimulus sets over one resident netlist:
  * src_off[i], t[i], v[i] are set i's host arrays (as sim_submit); out[n_sets]
  * receives the job handles. All sets that fit the budget run together, level
  * by level, in shared launches; the others are admitted as released jobs free
@@ -229,7 +267,8 @@ gsim_status sim_run_batch(gsim_ctx ctx, gsim_netlist nl, int32_t n_sets,
                           const int64_t *const *src_off, const int64_t *const *t,
                           const uint8_t *const *v, void *hip_stream, gsim_job *out);
 
-/* One scheduling pass of the executor on `hip_stream`: admit queued jobs that
+/* No passage of the paper (serving: continuous batching across jobs).
+ * One scheduling pass of the executor on `hip_stream`: admit queued jobs that
  * fit, enqueue the next level of every admitted job, then block until at most
  * `max_ahead` steps are unfinished on the device (0 = do not block; at most
  * 31). Reports the number of admitted jobs with levels left and of queued jobs.
@@ -237,12 +276,16 @@ gsim_status sim_run_batch(gsim_ctx ctx, gsim_netlist nl, int32_t n_sets,
 gsim_status sim_drive(gsim_ctx ctx, void *hip_stream, int32_t max_ahead, int32_t *n_active,
                       int32_t *n_queued);
 
-/* Non-blocking: *done = 1 if the job's results are ready (or it failed). A job
+/* No passage (plumbing for request loops).
+ * Non-blocking: *done = 1 if the job's results are ready (or it failed). A job
  * found to have overflowed automatically sized storage is queued again with
  * twice the storage and reports 0. */
 gsim_status sim_job_done(gsim_ctx ctx, gsim_job job, int32_t *done);
 
-/* Drive the job's executor until the job is enqueued, then block until its
+/* Passage: the end of the parallel computation, after which the results
+ * are complete on the device (Section 1.4; Algorithm 1 ends when every
+ * thread's cells are done).
+ * Drive the job's executor until the job is enqueued, then block until its
  * device work is done. A job whose automatically sized output storage
  * overflowed is re-run with twice the storage (up to 6 times) before this
  * returns. GSIM_E_OOM if storage set with GSIM_OPT_ARENA_TRANSITIONS overflowed,
@@ -262,10 +305,13 @@ typedef struct {
     int64_t retries;         /* automatic re-runs after an output-storage overflow */
     int64_t schedule;        /* the job's schedule: 0 level by level, 1 dependency-driven */
 } gsim_job_stats;
-/* Statistics of a finished job (waits for it). */
+/* Statistics of a finished job (waits for it). Passage: `pin_reads` is the
+ * per-gate Eq. 2 bound summed over the job; n_out the output lengths. */
 gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out);
 
-/* Copy waveforms of a finished job to host memory.
+/* Copy waveforms of a finished job to host memory. Passage: the results are
+ * transferred back to the CPU as the output, the second and last transfer of
+ * the one-pass flow (Section 1.4; Section 4.2).
  *   nets  [n] net ids to fetch (sources included); NULL = all S+G nets in id order
  *   out_off [n+1] receives offsets into out_t/out_v (out_off[0] = 0)
  *   out_t, out_v: capacity `cap` transitions; if out_t is NULL only out_off is
@@ -277,7 +323,8 @@ gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out);
 gsim_status sim_fetch_waveforms(gsim_ctx ctx, gsim_job job, const int64_t *nets, int64_t n,
                                 int64_t *out_off, int64_t *out_t, uint8_t *out_v, int64_t cap);
 
-/* Fingerprint of each requested net's waveform (nets as sim_fetch_waveforms;
+/* No passage of the paper (a check on results too large to copy).
+ * Fingerprint of each requested net's waveform (nets as sim_fetch_waveforms;
  * NULL = all S+G nets in id order), computed on the device: with
  * mix(x) the SplitMix64 finaliser (x += 0x9E3779B97F4A7C15;
  * x = (x ^ x>>30) * 0xBF58476D1CE4E5B9; x = (x ^ x>>27) * 0x94D049BB133111EB;
@@ -288,13 +335,14 @@ gsim_status sim_fetch_waveforms(gsim_ctx ctx, gsim_job job, const int64_t *nets,
 gsim_status sim_fetch_hashes(gsim_ctx ctx, gsim_job job, const int64_t *nets, int64_t n,
                              uint64_t *out);
 
-/* Free a job's device storage. */
+/* Free a job's device storage. No passage (plumbing). */
 gsim_status sim_release_job(gsim_ctx ctx, gsim_job job);
 
 /* ---- host-only helpers (no device needed) ----------------------------------- */
 
 /* The levelizer of sim_load_netlist: level[g] = 1 + max level of its input
- * nets (sources are level 0). Same validation and errors as sim_load_netlist
+ * nets (sources are level 0). Passage: the parallel layers of a DAG netlist
+ * (Section 4.1, the partitioning that Algorithm 1 avoids). Same validation and errors as sim_load_netlist
  * (ctx-free: read the message with sim_last_error(NULL)). */
 gsim_status sim_levelize(int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
                          const int64_t *pin_net, const int32_t *rise_ps, const int32_t *fall_ps,
@@ -302,12 +350,14 @@ gsim_status sim_levelize(int64_t S, int64_t G, const uint8_t *type, const int64_
 
 /* Check source waveforms against the conventions above and the time range
  * needed by a netlist whose longest path delay is `max_path_delay`.
+ * Passage: a waveform as consecutive (value, time) transitions (Section 2.1)
+ * with every signal X before its first one (Algorithm 2's initial values).
  * GSIM_E_WAVEFORM or GSIM_E_OVERFLOW with the first offending source named in
  * sim_last_error(NULL). */
 gsim_status sim_validate_stimulus(int64_t S, const int64_t *src_off, const int64_t *t,
                                   const uint8_t *v, int64_t max_path_delay);
 
-/* Library version string. */
+/* Library version string. No passage (plumbing). */
 const char *sim_version(void);
 
 #ifdef __cplusplus

@@ -1280,12 +1280,9 @@ bool requeue_if_overflowed(gsim_ctx ctx, Job *j) {
     if (j->retries >= kMaxRetries) return false;
     j->retries++;
     j->capacity_request = 2 * j->capacity;
-    Pool &pool = *ctx->pool;
-    if (j->d_K) ctx->arenas_held--;
-    pool.put(j->d_off); pool.put(j->d_len); pool.put(j->d_partial); pool.put(j->d_state); pool.put(j->d_K);
-    j->d_off = j->d_len = j->d_partial = nullptr;
-    j->d_state = nullptr;
-    j->d_K = nullptr;
+    // every device buffer of the run goes back to the pool: admission
+    // allocates them all again (sources, descriptors, dependency-driven state)
+    free_job_buffers(ctx, j);
     j->timing.clear();
     j->phase = kQueued;
     j->ex->queue.push_front(j);
@@ -1733,6 +1730,18 @@ gsim_status sim_netlist_info(gsim_ctx ctx, gsim_netlist nl, gsim_netlist_info *o
     out->max_delay_ps = n.max_delay;
     out->max_path_delay = n.max_path_delay;
     out->lane_gates = n.lane_gates;
+    return GSIM_OK;
+} catch (...) {
+    return exception_status(ctx);
+}
+
+gsim_status sim_memory_info(gsim_ctx ctx, gsim_memory_info *out) try {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    if (!out) return record(ctx, fail(GSIM_E_ARG, "null output"));
+    out->budget_bytes = ctx->pool->budget();
+    out->live_bytes = ctx->pool->live();
+    out->largest_free_bytes = ctx->pool->largest_free();
+    out->jobs_holding_storage = ctx->arenas_held;
     return GSIM_OK;
 } catch (...) {
     return exception_status(ctx);

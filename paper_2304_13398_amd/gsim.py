@@ -25,7 +25,7 @@ NO_RELATION = 2**31 - 1
 
 EXPORTED = ("sim_create", "sim_destroy", "sim_last_error", "sim_set_option", "sim_load_netlist",
             "sim_load_netlist_ext",
-            "sim_unload_netlist", "sim_set_netlist_option", "sim_netlist_info", "sim_submit", "sim_submit_device", "sim_run",
+            "sim_unload_netlist", "sim_set_netlist_option", "sim_netlist_info", "sim_memory_info", "sim_submit", "sim_submit_device", "sim_run",
             "sim_run_device", "sim_run_batch", "sim_drive", "sim_job_done", "sim_wait",
             "sim_job_stats", "sim_fetch_waveforms", "sim_fetch_hashes", "sim_release_job", "sim_levelize",
             "sim_validate_stimulus", "sim_version")
@@ -41,6 +41,11 @@ class NetlistInfo(ctypes.Structure):
     _fields_ = [("S", ctypes.c_int64), ("G", ctypes.c_int64), ("P", ctypes.c_int64),
                 ("levels", ctypes.c_int32), ("max_delay_ps", ctypes.c_int32),
                 ("max_path_delay", ctypes.c_int64), ("lane_gates", ctypes.c_int64)]
+
+
+class MemoryInfo(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("live_bytes", ctypes.c_uint64),
+                ("largest_free_bytes", ctypes.c_uint64), ("jobs_holding_storage", ctypes.c_int64)]
 
 
 class JobStats(ctypes.Structure):
@@ -79,6 +84,7 @@ def load_library(path: str = LIB_PATH):
         "sim_load_netlist_ext": ([P, i64, i64, P, P, P, P, ctypes.c_int32, P, P], st),
         "sim_unload_netlist": ([P, i64], st),
         "sim_netlist_info": ([P, i64, P], st),
+        "sim_memory_info": ([P, P], st),
         "sim_set_netlist_option": ([P, i64, ctypes.c_int, i64], st),
         "sim_submit": ([P, i64, P, P, P, P, P], st),
         "sim_submit_device": ([P, i64, P, P, P, i64, ctypes.c_int, P, P], st),
@@ -204,6 +210,12 @@ class Sim:
         info = NetlistInfo()
         self._ck(self.lib.sim_netlist_info(self.ctx, h, ctypes.byref(info)))
         return info
+
+    def memory_info(self) -> MemoryInfo:
+        """Device memory of the context (budget, held, largest free)."""
+        m = MemoryInfo()
+        self._ck(self.lib.sim_memory_info(self.ctx, ctypes.byref(m)))
+        return m
 
     def run(self, h: int, st, stream: int | None = None) -> int:
         """Start a job over host-resident stimuli (st: off, t, v)."""

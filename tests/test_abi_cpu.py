@@ -122,7 +122,8 @@ def header_struct(name):
 
 
 @pytest.mark.parametrize("c_name,py_cls", [("gsim_job_stats", "JobStats"),
-                                           ("gsim_netlist_info", "NetlistInfo")])
+                                           ("gsim_netlist_info", "NetlistInfo"),
+                                           ("gsim_memory_info", "MemoryInfo")])
 def test_binding_structs_match_the_header(c_name, py_cls):
     import ctypes
     ctype_of = {"int64_t": ctypes.c_int64, "int32_t": ctypes.c_int32, "double": ctypes.c_double,

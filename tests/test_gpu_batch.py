@@ -126,6 +126,7 @@ def test_learned_arena_size_and_automatic_retry(sim):
     j = sim.run(h, dense)
     sim.wait(j)
     sim.release(j)
+    held = sim.memory_info()
     retries = []
     for n in (40, 15, 5):
         st = W.make_stimulus(S=nl.S, n_per_src=n, window=1_000_000, seed=32 + n)
@@ -135,6 +136,12 @@ def test_learned_arena_size_and_automatic_retry(sim):
         assert same(fetch_gates(sim, j, nl), O.o1_simulate(nl, st))
         sim.release(j)
     say(f"retries per sparse job: {retries}")
+    assert sum(retries) > 0, "the sparse jobs were meant to overflow their first arena"
+    # every buffer of an overflowed run went back to the pool: after the
+    # retried jobs are released the context holds what it held before them
+    after = sim.memory_info()
+    assert after.jobs_holding_storage == held.jobs_holding_storage == 0
+    assert after.live_bytes == held.live_bytes, (held.live_bytes, after.live_bytes)
     sim.unload_netlist(h)
 
 
