@@ -1144,7 +1144,10 @@ __global__ __launch_bounds__(64) void eval_lane_kernel(StepArgs A) {
 // gate enters the queue exactly once, so the G tickets are all filled and a
 // wavefront leaves when its ticket is past the end. Ordering across the
 // XCDs' L2 caches: outputs are published with an agent-scope release fence
-// before the decrements, and read after an agent-scope acquire fence.
+// before the decrements; the wavefront whose decrement makes a gate ready
+// acquires (so the other producers' outputs are ordered before it) and
+// queues the gate with a release store; the wavefront that takes the gate
+// reads its inputs after an agent-scope acquire fence.
 // Safety exit: a wavefront that sees no new queue entry for kDfSpinLimit
 // polls (each after a sleep of about 2k cycles: tens of seconds in all) flags
 // the job (check_error = 3) and leaves, and so does every wavefront that sees
@@ -1298,12 +1301,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
                     const bool ready = c >= 0 && atomicSub(&A.pend[c], 1) == 1;
                     const uint64_t mask = __ballot(ready);
                     if (mask == 0) continue;
+                    // A count that reached zero here carries the decrements of
+                    // the consumer's other producers, each made after their
+                    // release fence. The acquire fence takes their outputs in,
+                    // and the release store of the queue slot hands them on with
+                    // this wavefront's own: whoever reads the slot and then
+                    // fences with acquire sees every input of the gate. Nothing
+                    // is left dirty since the fence above, so the release costs
+                    // little, and only batches that make a gate ready pay it.
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     const int leader = __ffsll((unsigned long long)mask) - 1;
                     uint32_t base = 0;
                     if (lane == leader) base = atomicAdd(&A.ctl->tail, (uint32_t)__popcll(mask));
                     base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
                     if (ready)
-                        __hip_atomic_store(A.queue + base + lanes_below(mask), c, __ATOMIC_RELAXED,
+                        __hip_atomic_store(A.queue + base + lanes_below(mask), c, __ATOMIC_RELEASE,
                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
