@@ -252,7 +252,8 @@ static int topological_order(int64_t S, int64_t G, const int64_t *pin_off,
 
 void o1_free(o1_result *r) {
     if (!r) return;
-    for (int64_t g = 0; g < r->G; g++) { free(r->gate_out[g].t); free(r->gate_out[g].v); }
+    if (r->gate_out)
+        for (int64_t g = 0; g < r->G; g++) { free(r->gate_out[g].t); free(r->gate_out[g].v); }
     free(r->gate_out);
     free(r);
 }
@@ -331,7 +332,17 @@ typedef struct {
     const int64_t *gates; /* this thread's gates */
     int64_t n;
     int failed;
+    /* memory-light mode (o1_simulate_fingerprints_parallel), else NULL:
+     * each gate's length and fingerprint; its copy into `kept` if keep_at[g]
+     * >= 0; its waveform freed at once if no gate reads it */
+    int64_t *len;
+    uint64_t *fp;
+    const int64_t *keep_at;
+    o1_result *kept;
+    const int64_t *last_reader_level;
 } o1_level_part;
+
+static uint64_t fingerprint(const int64_t *t, const uint8_t *v, int64_t n);
 
 static int eval_gate_into(const o1_level_part *a, int64_t g) {
     const int64_t *in_t[4];
@@ -355,45 +366,60 @@ static int eval_gate_into(const o1_level_part *a, int64_t g) {
                            a->fall + a->pin_off[g], &a->r->gate_out[g]);
 }
 
+static int copy_wave(const o1_wave *from, o1_wave *to) {
+    size_t n = (size_t)(from->n ? from->n : 1);
+    to->t = (int64_t *)malloc(n * sizeof(int64_t));
+    to->v = (uint8_t *)malloc(n);
+    if (!to->t || !to->v) return -1;
+    if (from->n) {
+        memcpy(to->t, from->t, (size_t)from->n * sizeof(int64_t));
+        memcpy(to->v, from->v, (size_t)from->n);
+    }
+    to->n = to->cap = from->n;
+    return 0;
+}
+
 static void *level_part_run(void *arg) {
     o1_level_part *a = (o1_level_part *)arg;
-    for (int64_t i = 0; i < a->n && !a->failed; i++)
-        if (eval_gate_into(a, a->gates[i])) a->failed = 1;
+    for (int64_t i = 0; i < a->n && !a->failed; i++) {
+        const int64_t g = a->gates[i];
+        if (eval_gate_into(a, g)) {
+            a->failed = 1;
+            break;
+        }
+        if (!a->len) continue;
+        o1_wave *w = &a->r->gate_out[g];
+        a->len[g] = w->n;
+        a->fp[g] = fingerprint(w->t, w->v, w->n);
+        if (a->keep_at[g] >= 0 && copy_wave(w, &a->kept->gate_out[a->keep_at[g]])) a->failed = 1;
+        if (a->last_reader_level[g] == 0) { /* nothing reads it */
+            free(w->t); free(w->v);
+            w->t = NULL; w->v = NULL;
+        }
+    }
     return NULL;
 }
 
-o1_result *o1_simulate_parallel(int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
-                                const int64_t *pin_net, const int32_t *rise, const int32_t *fall,
-                                const int64_t *src_off, const int64_t *src_t, const uint8_t *src_v,
-                                int n_threads, int *status) {
-    *status = 0;
-    if (n_threads < 1) n_threads = 1;
-    if (n_threads > 256) n_threads = 256;
+static int check_netlist(int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
+                         const int64_t *pin_net) {
     for (int64_t g = 0; g < G; g++) {
-        if (type[g] >= T_COUNT || pin_off[g + 1] - pin_off[g] != arity_of(type[g])) {
-            *status = -3;
-            return NULL;
-        }
+        if (type[g] >= T_COUNT || pin_off[g + 1] - pin_off[g] != arity_of(type[g])) return -3;
         for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++)
-            if (pin_net[p] < 0 || pin_net[p] >= S + G || pin_net[p] == S + g) {
-                *status = -3;
-                return NULL;
-            }
+            if (pin_net[p] < 0 || pin_net[p] >= S + G || pin_net[p] == S + g) return -3;
     }
-    size_t gn = (size_t)(G ? G : 1);
-    o1_result *r = (o1_result *)calloc(1, sizeof(o1_result));
-    int64_t *order = (int64_t *)malloc(gn * sizeof(int64_t));
-    int64_t *level = (int64_t *)calloc(gn, sizeof(int64_t));
-    int64_t *by_level = (int64_t *)malloc(gn * sizeof(int64_t));
-    if (!r || !order || !level || !by_level) {
-        free(r); free(order); free(level); free(by_level);
-        *status = -1;
-        return NULL;
-    }
-    r->S = S;
-    r->G = G;
-    r->gate_out = (o1_wave *)calloc(gn, sizeof(o1_wave));
-    int rc = r->gate_out ? topological_order(S, G, pin_off, pin_net, order) : -1;
+    return 0;
+}
+
+/* Level of every gate (1 + the highest level among the gates it reads;
+ * sources are level 0) and the gates sorted by level: level l holds
+ * by_level[level_start[l] .. level_start[l + 1]). level_start has n_levels + 2
+ * entries and is the caller's to free. */
+static int sort_by_level(int64_t S, int64_t G, const int64_t *pin_off, const int64_t *pin_net,
+                         int64_t *level, int64_t *by_level, int64_t **level_start_out,
+                         int64_t *n_levels_out) {
+    int64_t *order = (int64_t *)malloc((size_t)(G ? G : 1) * sizeof(int64_t));
+    if (!order) return -1;
+    int rc = topological_order(S, G, pin_off, pin_net, order);
     int64_t n_levels = 0, *level_start = NULL;
     if (!rc) {
         for (int64_t idx = 0; idx < G; idx++) { /* inputs precede their readers */
@@ -413,37 +439,166 @@ o1_result *o1_simulate_parallel(int64_t S, int64_t G, const uint8_t *type, const
         for (int64_t l = n_levels + 1; l > 0; l--) level_start[l] = level_start[l - 1];
         level_start[0] = 0;
     }
-    for (int64_t l = 1; !rc && l <= n_levels; l++) {
-        const int64_t a0 = level_start[l], a1 = level_start[l + 1], n = a1 - a0;
-        int nt = n < n_threads ? (int)(n ? n : 1) : n_threads;
-        o1_level_part parts[256];
-        pthread_t th[256];
-        int started[256];
-        for (int k = 0; k < nt; k++) {
-            o1_level_part *pa = &parts[k];
-            pa->S = S; pa->type = type; pa->pin_off = pin_off; pa->pin_net = pin_net;
-            pa->rise = rise; pa->fall = fall; pa->src_off = src_off; pa->src_t = src_t;
-            pa->src_v = src_v; pa->r = r; pa->failed = 0;
-            const int64_t lo = a0 + n * k / nt, hi = a0 + n * (k + 1) / nt;
-            pa->gates = by_level + lo;
-            pa->n = hi - lo;
-            started[k] = k > 0 && pthread_create(&th[k], NULL, level_part_run, pa) == 0;
-        }
-        level_part_run(&parts[0]);
-        for (int k = 1; k < nt; k++) {
-            if (started[k]) pthread_join(th[k], NULL);
-            else level_part_run(&parts[k]); /* no thread: run it here */
-        }
-        for (int k = 0; k < nt; k++)
-            if (parts[k].failed) rc = -1;
+    free(order);
+    *level_start_out = level_start;
+    *n_levels_out = n_levels;
+    return rc;
+}
+
+/* One level's gates split into contiguous ranges, one per thread; every
+ * thread is joined before this returns. `proto` holds the fields common to
+ * all parts. Returns -1 if a gate failed (out of memory). */
+static int run_level(const o1_level_part *proto, const int64_t *gates, int64_t n, int n_threads) {
+    int nt = n < n_threads ? (int)(n ? n : 1) : n_threads;
+    o1_level_part parts[256];
+    pthread_t th[256];
+    int started[256];
+    for (int k = 0; k < nt; k++) {
+        o1_level_part *pa = &parts[k];
+        *pa = *proto;
+        pa->failed = 0;
+        const int64_t lo = n * k / nt, hi = n * (k + 1) / nt;
+        pa->gates = gates + lo;
+        pa->n = hi - lo;
+        started[k] = k > 0 && pthread_create(&th[k], NULL, level_part_run, pa) == 0;
     }
-    free(order); free(level); free(by_level); free(level_start);
+    level_part_run(&parts[0]);
+    for (int k = 1; k < nt; k++) {
+        if (started[k]) pthread_join(th[k], NULL);
+        else level_part_run(&parts[k]); /* no thread: run it here */
+    }
+    for (int k = 0; k < nt; k++)
+        if (parts[k].failed) return -1;
+    return 0;
+}
+
+o1_result *o1_simulate_parallel(int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_off,
+                                const int64_t *pin_net, const int32_t *rise, const int32_t *fall,
+                                const int64_t *src_off, const int64_t *src_t, const uint8_t *src_v,
+                                int n_threads, int *status) {
+    *status = 0;
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > 256) n_threads = 256;
+    if ((*status = check_netlist(S, G, type, pin_off, pin_net)) != 0) return NULL;
+    size_t gn = (size_t)(G ? G : 1);
+    o1_result *r = (o1_result *)calloc(1, sizeof(o1_result));
+    int64_t *level = (int64_t *)calloc(gn, sizeof(int64_t));
+    int64_t *by_level = (int64_t *)malloc(gn * sizeof(int64_t));
+    if (!r || !level || !by_level) {
+        free(r); free(level); free(by_level);
+        *status = -1;
+        return NULL;
+    }
+    r->S = S;
+    r->G = G;
+    r->gate_out = (o1_wave *)calloc(gn, sizeof(o1_wave));
+    int64_t n_levels = 0, *level_start = NULL;
+    int rc = r->gate_out ? sort_by_level(S, G, pin_off, pin_net, level, by_level, &level_start, &n_levels) : -1;
+    o1_level_part proto;
+    memset(&proto, 0, sizeof proto);
+    proto.S = S; proto.type = type; proto.pin_off = pin_off; proto.pin_net = pin_net;
+    proto.rise = rise; proto.fall = fall; proto.src_off = src_off; proto.src_t = src_t;
+    proto.src_v = src_v; proto.r = r;
+    for (int64_t l = 1; !rc && l <= n_levels; l++)
+        rc = run_level(&proto, by_level + level_start[l], level_start[l + 1] - level_start[l], n_threads);
+    free(level); free(by_level); free(level_start);
     if (rc) {
         o1_free(r);
         *status = rc;
         return NULL;
     }
     return r;
+}
+
+/* Level-parallel memory-light driver for full-size parity checks: the gates
+ * of o1_simulate, level by level on n_threads threads as o1_simulate_parallel,
+ * each waveform reduced to len[g] and fp[g] (the fingerprint defined below
+ * o1_fingerprints) and freed once the level of its last reader is done. The
+ * n_keep gates listed in `keep` (distinct gate indices) are also returned
+ * whole, in that order, as an o1_result of n_keep entries (free with
+ * o1_free). Returns NULL with *status as o1_simulate on failure. */
+o1_result *o1_simulate_fingerprints_parallel(int64_t S, int64_t G, const uint8_t *type,
+                                             const int64_t *pin_off, const int64_t *pin_net,
+                                             const int32_t *rise, const int32_t *fall,
+                                             const int64_t *src_off, const int64_t *src_t,
+                                             const uint8_t *src_v, int n_threads, int64_t *len,
+                                             uint64_t *fp, int64_t n_keep, const int64_t *keep,
+                                             int *status) {
+    *status = 0;
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > 256) n_threads = 256;
+    if ((*status = check_netlist(S, G, type, pin_off, pin_net)) != 0) return NULL;
+    for (int64_t i = 0; i < n_keep; i++)
+        if (keep[i] < 0 || keep[i] >= G) {
+            *status = -3;
+            return NULL;
+        }
+    size_t gn = (size_t)(G ? G : 1);
+    o1_result *work = (o1_result *)calloc(1, sizeof(o1_result));
+    o1_result *kept = (o1_result *)calloc(1, sizeof(o1_result));
+    int64_t *level = (int64_t *)calloc(gn, sizeof(int64_t));
+    int64_t *by_level = (int64_t *)malloc(gn * sizeof(int64_t));
+    int64_t *keep_at = (int64_t *)malloc(gn * sizeof(int64_t));
+    int64_t *last_reader = (int64_t *)calloc(gn, sizeof(int64_t));
+    int64_t *free_at = (int64_t *)malloc(gn * sizeof(int64_t));
+    int rc = (work && kept && level && by_level && keep_at && last_reader && free_at) ? 0 : -1;
+    if (!rc) {
+        work->S = kept->S = S;
+        work->G = G;
+        kept->G = n_keep;
+        work->gate_out = (o1_wave *)calloc(gn, sizeof(o1_wave));
+        kept->gate_out = (o1_wave *)calloc((size_t)(n_keep ? n_keep : 1), sizeof(o1_wave));
+        if (!work->gate_out || !kept->gate_out) rc = -1;
+    }
+    int64_t n_levels = 0, *level_start = NULL, *free_start = NULL;
+    if (!rc) rc = sort_by_level(S, G, pin_off, pin_net, level, by_level, &level_start, &n_levels);
+    if (!rc) {
+        for (int64_t g = 0; g < G; g++) keep_at[g] = -1;
+        for (int64_t i = 0; i < n_keep; i++) keep_at[keep[i]] = i;
+        /* the level after which each gate's waveform is no longer read */
+        for (int64_t g = 0; g < G; g++)
+            for (int64_t p = pin_off[g]; p < pin_off[g + 1]; p++)
+                if (pin_net[p] >= S && last_reader[pin_net[p] - S] < level[g])
+                    last_reader[pin_net[p] - S] = level[g];
+        free_start = (int64_t *)calloc((size_t)n_levels + 2, sizeof(int64_t));
+        if (!free_start) rc = -1;
+    }
+    if (!rc) { /* gates grouped by the level that frees them */
+        for (int64_t g = 0; g < G; g++) free_start[last_reader[g] + 1]++;
+        for (int64_t l = 1; l <= n_levels + 1; l++) free_start[l] += free_start[l - 1];
+        for (int64_t g = 0; g < G; g++) free_at[free_start[last_reader[g]]++] = g;
+        for (int64_t l = n_levels + 1; l > 0; l--) free_start[l] = free_start[l - 1];
+        free_start[0] = 0;
+    }
+    o1_level_part proto;
+    memset(&proto, 0, sizeof proto);
+    proto.S = S; proto.type = type; proto.pin_off = pin_off; proto.pin_net = pin_net;
+    proto.rise = rise; proto.fall = fall; proto.src_off = src_off; proto.src_t = src_t;
+    proto.src_v = src_v; proto.r = work;
+    proto.len = len; proto.fp = fp; proto.keep_at = keep_at; proto.kept = kept;
+    proto.last_reader_level = last_reader;
+    for (int64_t l = 1; !rc && l <= n_levels; l++) {
+        rc = run_level(&proto, by_level + level_start[l], level_start[l + 1] - level_start[l], n_threads);
+        for (int64_t i = free_start[l]; !rc && i < free_start[l + 1]; i++) {
+            o1_wave *w = &work->gate_out[free_at[i]];
+            free(w->t); free(w->v);
+            w->t = NULL; w->v = NULL;
+        }
+    }
+    free(level); free(by_level); free(keep_at); free(last_reader); free(free_at);
+    free(level_start); free(free_start);
+    if (work) {
+        if (work->gate_out)
+            for (int64_t g = 0; g < G; g++) { free(work->gate_out[g].t); free(work->gate_out[g].v); }
+        free(work->gate_out);
+        free(work);
+    }
+    if (rc) {
+        o1_free(kept);
+        *status = rc;
+        return NULL;
+    }
+    return kept;
 }
 
 /* Per-gate output lengths. */

@@ -86,6 +86,10 @@ class _O1:
         lib.o1_simulate_fingerprints.restype = ctypes.c_int
         lib.o1_simulate_fingerprints.argtypes = [i64, i64, P, P, P, P, P, P, P, P, P, P]
         lib.o1_fingerprints.argtypes = [i64, P, P, P, P]
+        lib.o1_simulate_fingerprints_parallel.restype = P
+        lib.o1_simulate_fingerprints_parallel.argtypes = [i64, i64, P, P, P, P, P, P, P, P,
+                                                          ctypes.c_int, P, P, i64, P,
+                                                          ctypes.POINTER(ctypes.c_int)]
         lib.o1x_simulate.restype = P
         lib.o1x_simulate.argtypes = [i64, i64, P, P, P, P, ctypes.c_int, P, P, P, P,
                                      ctypes.POINTER(ctypes.c_int)]
@@ -207,6 +211,38 @@ def o1_simulate_fingerprints(nl, st, lib: str | None = None):
     if rc:
         raise OracleError({-1: "out of memory", -2: "cycle", -3: "malformed netlist"}.get(rc, str(rc)))
     return ln[:nl.G], fp[:nl.G]
+
+
+def o1_simulate_fingerprints_parallel(nl, st, threads: int, keep=None, lib: str | None = None):
+    """O1 on a whole netlist, level by level on ``threads`` threads, keeping
+    each gate's output length and fingerprint (waveforms freed after the level
+    of their last reader) and the whole waveforms of the gates in ``keep``:
+    (len[G], fp[G], (off, t, v) of the kept gates in the order given)."""
+    L = o1_lib(lib).lib
+    arrs = [np.ascontiguousarray(a, dtype=d) for a, d in (
+        (nl.type, np.uint8), (nl.pin_off, np.int64), (nl.pin_net, np.int64), (nl.rise, np.int32),
+        (nl.fall, np.int32), (st.off, np.int64), (st.t, np.int64), (st.v, np.uint8))]
+    keep = np.ascontiguousarray(np.zeros(0) if keep is None else keep, dtype=np.int64)
+    ln = np.zeros(max(nl.G, 1), dtype=np.int64)
+    fp = np.zeros(max(nl.G, 1), dtype=np.uint64)
+    status = ctypes.c_int(0)
+    h = L.o1_simulate_fingerprints_parallel(nl.S, nl.G, *[_ptr(a) for a in arrs], int(threads),
+                                            _ptr(ln), _ptr(fp), len(keep),
+                                            _ptr(keep) if len(keep) else None, ctypes.byref(status))
+    if not h:
+        raise OracleError({-1: "out of memory", -2: "cycle", -3: "malformed netlist"}.get(
+            status.value, str(status.value)))
+    try:
+        n = np.zeros(max(len(keep), 1), dtype=np.int64)
+        L.o1_lengths(h, _ptr(n))
+        off = np.zeros(len(keep) + 1, dtype=np.int64)
+        off[1:] = np.cumsum(n[:len(keep)])
+        t = np.zeros(max(int(off[-1]), 1), dtype=np.int64)
+        v = np.zeros(max(int(off[-1]), 1), dtype=np.uint8)
+        L.o1_copy(h, _ptr(off), _ptr(t), _ptr(v))
+    finally:
+        L.o1_free(h)
+    return ln[:nl.G], fp[:nl.G], (off, t[:off[-1]], v[:off[-1]])
 
 
 def o1_gate(gtype, waves, rise, fall, lib: str | None = None):
