@@ -1,17 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the re-simulation hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--seed S] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--seed S] [--headline-only]
+                    [--no-cpu-baseline] [--served-full] ...
 
-A step is one whole job: every level of the 1M-gate mid-size workload (1M
-gates, 2,048 PIs, 60 levels, fan-in 1-4, power-law fanout, 1-50 ps delays,
-1,000 transitions per PI over 1 us) simulated from stimuli already resident
-in HBM, through the C ABI (sim_run_device), on one stream, with jobs
-enqueued two deep so host enqueue overlaps device work. Prints one JSON line.
+A step is one whole job of the industrial-shaped workload: every level of a
+10M-gate netlist (8,192 PIs + 50,000 pseudo-PIs, 150 levels, fan-in 1-4,
+power-law fanout up to 5,000, 1-200 ps rise/fall delays, 200 transitions per
+source) simulated from stimuli already resident in HBM, through the C ABI
+(sim_run_device), on one stream, with jobs enqueued two deep so host enqueue
+overlaps device work. The evaluate launches are bracketed with HIP events on
+that stream. The same measurement on the 1M-gate mid-size workload, the
+dependency-driven schedule, latency of the 1,000-gate job, batching, serving,
+time windows and the end-to-end rate follow as nested sections. Prints one
+JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import statistics
@@ -21,65 +28,59 @@ import time
 import numpy as np
 
 HBM_PEAK_GBPS = 8000.0
+CU_COUNT, CLOCK_HZ = 256, 2.4e9   # MI355X: 256 CUs at 2.4 GHz; one wave64 VALU instruction per CU per cycle
 ROOT = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "eval_wave_cfg2_hbm_traffic.txt")
+PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2304_13398_amd", "csrc", "kernels.hip")
 
+# Committed counter profiles of each workload's dominant evaluate kernel; a
+# figure is used only while the kernel source hash recorded there matches.
+PROFILE_FILES = {
+    "industrial": ("eval_wave256_industrial_hbm_traffic.txt", "eval_wave256_industrial_sq_counters.txt"),
+    "mid": ("eval_wave64_mid_hbm_traffic.txt", "eval_wave64_mid_sq_counters.txt"),
+}
 
-def measured_traffic_bytes_per_launch():
-    """HBM bytes per evaluate launch from the committed FETCH_SIZE/WRITE_SIZE
-    profile (already scaled by the copy calibration), or None if the profile is
-    missing or was taken on other kernel source than the one built now."""
-    import hashlib
+
+def kernel_source_hash():
     try:
-        text = open(TRAFFIC_PROFILE).read()
-        src_hash = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+        return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    if f"sha256 prefix: {src_hash}" not in text:
-        return None
-    for line in text.splitlines():
-        if line.startswith("traffic_bytes_per_launch:"):
-            return float(line.split(":")[1])
-    return None
 
 
-SQ_PROFILE = os.path.join(ROOT, "profiles", "eval_wave_cfg2_sq_counters.txt")
-CU_COUNT, CLOCK_HZ = 256, 2.4e9   # MI355X: 256 CUs; one wave64 VALU instruction per CU per cycle
-
-
-def measured_valu_per_launch():
-    """VALU wave instructions per evaluate launch from the committed SQ
-    profile, or None if it was taken on other kernel source."""
-    import hashlib
+def profile_value(fname, key):
+    """A figure from a committed profile summary ("key: value" or "key value"
+    line), or None if the file is missing or was taken on other kernel source."""
     try:
-        text = open(SQ_PROFILE).read()
-        src_hash = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+        text = open(os.path.join(PROFILES, fname)).read()
     except OSError:
         return None
-    if f"sha256 prefix: {src_hash}" not in text:
+    h = kernel_source_hash()
+    if not h or f"sha256 prefix: {h}" not in text:
         return None
     for line in text.splitlines():
-        if line.startswith("SQ_INSTS_VALU"):
-            return float(line.split()[1])
+        if line.startswith(key):
+            rest = line[len(key):].lstrip(": \t").split()
+            if rest:
+                return float(rest[0])
     return None
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--gates", type=int, default=1_000_000)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed industrial steps (for profiler runs)")
+    ap.add_argument("--mid-only", action="store_true",
+                    help="only the timed mid-size steps (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-levels", type=int, default=25,
-                    help="levels of the workload the oracle runs for the CPU baseline")
+    ap.add_argument("--no-mid", action="store_true", help="skip the 1M-gate mid-size sections")
     ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-configuration latency")
-    ap.add_argument("--no-industrial", action="store_true",
-                    help="skip the 10M-gate industrial-shaped configuration")
     ap.add_argument("--no-e2e", action="store_true",
-                    help="skip the host-to-host run of the headline job (all waveforms fetched)")
+                    help="skip the host-to-host run of the mid job (all waveforms fetched)")
     ap.add_argument("--no-windows", action="store_true",
                     help="skip the exact time-window chunking measurement")
     ap.add_argument("--no-skewed", action="store_true",
@@ -91,13 +92,191 @@ def parse():
     ap.add_argument("--batched-sets", type=int, default=64)
     ap.add_argument("--no-served", action="store_true",
                     help="skip the served section (Poisson requests over 8 resident netlists)")
-    ap.add_argument("--served-jobs", type=int, default=300)
-    ap.add_argument("--served-rates", default="25,100,500", help="request rates (jobs/s), comma separated")
+    ap.add_argument("--served-rates", default="10,25,50,100,250,500",
+                    help="request rates (jobs/s), comma separated")
+    ap.add_argument("--served-seconds", type=float, default=8.0,
+                    help="arrival span per rate (jobs = rate x span, at least 100 and at most 1,000)")
+    ap.add_argument("--served-full", action="store_true",
+                    help="1,000 requests at every rate (about six minutes of arrivals)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="instead of the workload, time a plain device-to-device copy of BYTES "
                          "(the practical HBM ceiling, and the reference for the profiler's "
                          "FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def say(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---- bytes the method must move ---------------------------------------------
+
+def b_min_bytes(nl, lengths):
+    """Bytes a job must move at least: every waveform that some gate reads is
+    read once and every output written once, at 9 bytes a transition (int64
+    time + int8 value, the paper's element), plus each gate's output offset
+    (8 B) and the netlist (type and pin offset, 1 + 8 B per gate; pin net and
+    rise/fall, 4 + 8 B per pin)."""
+    read = np.zeros(nl.S + nl.G, dtype=bool)
+    read[nl.pin_net] = True
+    consumed = int(lengths[read].sum())
+    n_out = int(lengths[nl.S:].sum())
+    return 9 * consumed + 9 * n_out + 8 * nl.G + 9 * nl.G + 12 * nl.P
+
+
+def b_pin_bytes(nl, lengths):
+    """As b_min_bytes, but every pin reads its waveform itself (no reuse
+    across a net's readers)."""
+    pin_reads = int(lengths[nl.pin_net].sum())
+    n_out = int(lengths[nl.S:].sum())
+    return 9 * pin_reads + 9 * n_out + 8 * nl.G + 9 * nl.G + 12 * nl.P
+
+
+def per_level_bytes(nl, lengths):
+    """Bytes the level-by-level evaluate launches touch: per level, every net
+    the level reads once (8 B a packed transition), every output written once,
+    the 64-byte gate record and 16 B of offset and length per pin read and per
+    output."""
+    S = nl.S
+    total = 0
+    pin_gate = np.repeat(np.arange(nl.G), np.diff(nl.pin_off))
+    order = np.argsort(nl.level[pin_gate], kind="stable")
+    lv_pin = nl.level[pin_gate][order]
+    nets_sorted = nl.pin_net[order]
+    bounds = np.searchsorted(lv_pin, np.arange(1, int(nl.level.max()) + 2))
+    gates_per_level = np.bincount(nl.level, minlength=int(nl.level.max()) + 1)
+    out_len = np.bincount(nl.level, weights=lengths[S:S + nl.G].astype(np.float64),
+                          minlength=int(nl.level.max()) + 1)
+    for lv in range(1, int(nl.level.max()) + 1):
+        nets = np.unique(nets_sorted[bounds[lv - 1]:bounds[lv]])
+        pins = bounds[lv] - bounds[lv - 1]
+        total += 8 * int(lengths[nets].sum()) + 8 * int(out_len[lv]) + 64 * int(gates_per_level[lv])
+        total += 16 * int(pins) + 16 * int(gates_per_level[lv])
+    return total
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+# ---- one workload, timed -------------------------------------------------------
+
+def timed_job(G, sim, nl, st, steps, warmup, name, profile_key):
+    """Jobs of one workload from stimuli resident in HBM, two deep on torch's
+    current stream: wall time per job over `steps` after `warmup`, the device
+    time of the evaluate launches (HIP events on that stream), and the
+    roofline of the evaluate kernel against HBM bandwidth."""
+    import torch
+    dev = torch.device("cuda:0")
+    d = [torch.from_numpy(a).to(dev) for a in (st.off, st.t, st.v)]
+    stream = torch.cuda.current_stream()
+    sim.set_option(G.OPT_KERNEL_TIMING, 1)
+    h = sim.load_netlist(nl)
+    info = sim.netlist_info(h)
+
+    def launch(validate=False):
+        return sim.run_device(h, d[0].data_ptr(), d[1].data_ptr(), d[2].data_ptr(), st.n,
+                              stream=stream.cuda_stream, validate=validate)
+
+    stats = []
+
+    def finish(j, keep):
+        sim.wait(j)
+        if keep:
+            stats.append(sim.stats(j))
+        sim.release(j)
+
+    finish(launch(validate=True), False)  # also validates the stimuli once on the device copy
+    for _ in range(max(0, warmup - 1)):
+        finish(launch(), False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prev = None
+    for _ in range(steps):
+        j = launch()
+        if prev is not None:
+            finish(prev, True)
+        prev = j
+    if prev is not None:
+        finish(prev, True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n_out = stats[-1].n_out
+    assert all(s.n_out == n_out for s in stats), "steps disagree on the output size"
+    ms = wall / steps * 1000.0
+    eval_ms = statistics.median(s.eval_ms for s in stats)
+    launches = stats[-1].eval_launches
+    say(f"{name}: {steps} steps in {wall:.3f}s, {ms:.2f} ms per job, evaluate {eval_ms:.2f} ms "
+        f"over {launches} launches")
+
+    # every net's length from one more run: the bytes the method must move
+    j = launch()
+    sim.wait(j)
+    lengths = sim.lengths(j)
+    pin_reads = sim.stats(j).pin_reads
+    sim.release(j)
+    sim.set_option(G.OPT_KERNEL_TIMING, 0)
+    b_min = b_min_bytes(nl, lengths)
+    avg_launch_s = eval_ms / launches / 1000.0
+    achieved = b_min / launches / avg_launch_s / 1e9
+    traffic_file, sq_file = PROFILE_FILES[profile_key]
+    traffic_per_launch = profile_value(traffic_file, "traffic_bytes_per_launch")
+    valu = profile_value(sq_file, "SQ_INSTS_VALU")
+    roof = {
+        "kernel": "eval_wave_kernel (one wavefront per gate; the level's launches bracketed together)",
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBPS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBPS,
+        "traffic": (traffic_per_launch / avg_launch_s / 1e9) if traffic_per_launch else None,
+        "traffic_bytes_per_launch": traffic_per_launch,
+        "algorithmic_bytes_per_launch": b_min / launches,
+        "algorithmic_bytes_per_output_transition": b_min / n_out,
+        "output_transitions_per_launch": n_out / launches,
+        "avg_launch_ms": eval_ms / launches,
+        "launches_per_step": launches,
+        "b_min_bytes_per_job": b_min,
+        "b_pin_gbps": b_pin_bytes(nl, lengths) / launches / avg_launch_s / 1e9,
+        "per_level_reads_gbps": per_level_bytes(nl, lengths) / launches / avg_launch_s / 1e9,
+        "profiles": {"traffic": f"profiles/{traffic_file}", "sq": f"profiles/{sq_file}"},
+    }
+    if valu:
+        # issue bound: the VALU stream's time at one wave64 instruction per CU per cycle
+        busy = valu / (CU_COUNT * CLOCK_HZ) / avg_launch_s
+        roof["alu"] = {"valu_instr_per_launch": valu, "issue_busy_frac": busy,
+                       "lane_ops_per_s": valu * 64 / avg_launch_s,
+                       "peak_lane_ops_per_s": CU_COUNT * 64 * CLOCK_HZ}
+        roof["binds"] = "alu (VALU issue)" if busy > 0.8 else "neither fully (latency)"
+    res = {"ms_per_step": ms, "value": n_out / (ms / 1000.0), "n_out": int(n_out),
+           "device_ms_per_step": statistics.median(s.device_ms for s in stats),
+           "eval_ms_per_step": eval_ms, "pin_reads": int(pin_reads), "roofline": roof,
+           "levels": info.levels}
+    return h, d, res, lengths
+
+
+def oracle_whole_job(O, nl, st, n_threads, single=True):
+    """The oracle (plain C; each waveform freed after its last reader) on the
+    whole job: output transitions and seconds level-parallel on n_threads, and
+    on one thread. Both runs must give the same lengths and fingerprints."""
+    t = time.perf_counter()
+    ln_p, fp_p, _ = O.o1_simulate_fingerprints_parallel(nl, st, n_threads)
+    par_s = time.perf_counter() - t
+    n_o = int(ln_p.sum())
+    single_s = None
+    if single:
+        t = time.perf_counter()
+        ln_s, fp_s = O.o1_simulate_fingerprints(nl, st)
+        single_s = time.perf_counter() - t
+        assert np.array_equal(ln_s, ln_p) and np.array_equal(fp_s, fp_p), \
+            "level-parallel oracle disagrees with the sequential one"
+    return n_o, par_s, single_s
 
 
 def copy_rate(nbytes, reps=5):
@@ -156,139 +335,6 @@ SERVE_LOOKAHEAD = 8
 # two, the host loop could not keep the device busy (1.01 s for the 64 sets);
 # from eight on the device never waits (0.75 s).
 BATCH_LOOKAHEAD = 8
-
-
-def bench_batched(G, sim, nl, h, n_sets, seed):
-    """Batched: n_sets stimulus sets over the resident netlist, per-set
-    transitions per PI log-uniform in [50, 5000]; all sets through the
-    executor (shared launches, admitted as HBM allows, largest sets first) vs
-    one set per launch chain. The lane threshold is autotuned on a sample set
-    first."""
-    from paper_2304_13398_amd import autotune
-    from paper_2304_13398_amd import workloads as W
-    rng = np.random.default_rng(seed + 7_000_001)
-    ns = W.loguniform_int(rng, 50, 5000, size=n_sets)
-    t = time.perf_counter()
-    sets = pool_map(_gen_stimulus, [(nl.S, int(n), 1_000_000, seed * 1000 + i)
-                                    for i, n in enumerate(ns)])
-    print(f"[bench] batched: {n_sets} sets generated in {time.perf_counter() - t:.1f}s "
-          f"({sum(x.n for x in sets)} transitions)", file=sys.stderr, flush=True)
-    tuner = autotune.Autotuner(sim, candidates=(0, 64, 192, 512), reps=1)
-    median = sets[int(np.argsort(ns)[len(ns) // 2])]
-    thr, tms = tuner.tune(nl, h, median)
-
-    def one_per_launch():
-        t0 = time.perf_counter()
-        n_out = 0
-        for st in sets:
-            j = sim.run(h, st)
-            sim.wait(j)
-            n_out += sim.stats(j).n_out
-            sim.release(j)
-        return n_out, time.perf_counter() - t0
-
-    diag = {}
-
-    def batched():
-        t0 = time.perf_counter()
-        # largest first (first-fit decreasing): jobs are released as they finish
-        pending = sim.run_batch(h, sorted(sets, key=lambda x: -x.n))
-        diag["run_batch_return_s"] = time.perf_counter() - t0
-        n_out, retries, drives = 0, 0, 0
-        # every set is submitted up front, so steps may run far ahead of the
-        # host loop (a request loop keeps this short so late arrivals join soon)
-        while pending:
-            sim.drive(max_ahead=BATCH_LOOKAHEAD)  # admit sets as memory frees, advance all
-            drives += 1
-            for j in [j for j in pending if sim.done(j)]:
-                st = sim.stats(j)
-                n_out += st.n_out
-                retries += st.retries
-                sim.release(j)
-                pending.remove(j)
-        diag["retries"], diag["drive_calls"] = retries, drives
-        return n_out, time.perf_counter() - t0
-
-    # one untimed pass of each first: the first batch allocates page-locked
-    # staging for all its sets at once (the one-per-launch loop reuses one set)
-    one_per_launch()
-    batched()
-    n1, t1 = one_per_launch()
-    n2, t2 = batched()
-    assert n1 == n2, "batched and one-per-launch runs disagree on the output size"
-    print(f"[bench] batched: one-per-launch {t1:.2f}s, batched {t2:.2f}s", file=sys.stderr, flush=True)
-    return {
-        "workload": f"{n_sets} stimulus sets over the 1M-gate netlist, transitions per PI "
-                    f"log-uniform 50-5,000 (mean {float(ns.mean()):.0f})",
-        "sets": n_sets, "n_in": int(sum(x.n for x in sets)), "n_out": int(n2),
-        "batched_transitions_per_s": n2 / t2, "batched_s": t2,
-        "one_per_launch_transitions_per_s": n1 / t1, "one_per_launch_s": t1,
-        "speedup": t1 / t2,
-        "tuned_lane_threshold": thr, "tuning_ms": tms, "batched_diagnostics": diag,
-        "lookahead_steps": BATCH_LOOKAHEAD,
-        "includes": "stimulus upload (pageable H2D), all levels, per-set completion wait",
-    }
-
-
-def bench_served(G, sim, n_jobs, rates, seed, lookahead=None):
-    """Served: Poisson requests over 8 resident netlists (10k-2M gates), each
-    request log-uniform 20-2,000 transitions per PI and asking for its
-    netlist's primary outputs; continuous batching vs one job at a time."""
-    from paper_2304_13398_amd import autotune, serve
-    t = time.perf_counter()
-    nls = serve.served_netlists(seed=seed)
-    rng = np.random.default_rng(seed + 5_000_011)
-    items = []
-    for k, nl in enumerate(nls):
-        for i, n in enumerate(W_loguniform(rng, 20, 2000, 6)):
-            items.append((nl.S, int(n), 1_000_000, seed * 100_000 + k * 1000 + i))
-    stims = pool_map(_gen_stimulus, items)
-    pool = [stims[6 * k:6 * k + 6] for k in range(len(nls))]
-    hs = [sim.load_netlist(nl) for nl in nls]
-    print(f"[bench] served: netlists and stimuli ready in {time.perf_counter() - t:.1f}s",
-          file=sys.stderr, flush=True)
-    tuner = autotune.Autotuner(sim, candidates=(0, 64, 192, 512), reps=1)
-    tuned = []
-    for nl, h, p in zip(nls, hs, pool):
-        tuned.append(tuner.tune(nl, h, sorted(p, key=lambda x: x.n)[len(p) // 2])[0])
-        big = max(p, key=lambda x: x.n)
-        j = sim.run(h, big)          # learn the arena use of the largest request
-        sim.wait(j)
-        sim.release(j)
-    out = {"workload": "8 resident netlists of 10k-2M gates (mid-size generator, 60 levels); "
-                       "requests uniform over netlists, 20-2,000 transitions per PI (log-uniform), "
-                       "Poisson arrivals; each request fetches its primary outputs",
-           "jobs_per_rate": n_jobs, "tuned_lane_thresholds": tuned, "rates": {}}
-    for rate in rates:
-        reqs = serve.served_workload(n_jobs, rate, nls, pool, seed=seed + int(rate))
-        rc, mc = serve.serve_continuous(sim, hs, reqs,
-                                        max_ahead=SERVE_LOOKAHEAD if lookahead is None else lookahead)
-        rs, ms = serve.serve_sequential(sim, hs, reqs)
-        out["rates"][str(rate)] = {"continuous": serve.summarize(rc, mc),
-                                   "sequential": serve.summarize(rs, ms)}
-        print(f"[bench] served rate {rate}: continuous p50/p99 "
-              f"{out['rates'][str(rate)]['continuous']['p50_ms']:.1f}/"
-              f"{out['rates'][str(rate)]['continuous']['p99_ms']:.1f} ms, sequential "
-              f"{out['rates'][str(rate)]['sequential']['p50_ms']:.1f}/"
-              f"{out['rates'][str(rate)]['sequential']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
-    for h in hs:
-        sim.unload_netlist(h)
-    return out
-
-
-def oracle_times(O, nl, st, n_threads):
-    """The oracle on a netlist: output transitions, single-thread seconds,
-    level-parallel seconds (the two results must agree)."""
-    t1 = time.perf_counter()
-    off, _, _ = O.o1_simulate(nl, st)
-    single_s = time.perf_counter() - t1
-    n_o = int(off[-1])
-    del off
-    t1 = time.perf_counter()
-    p_off, _, _ = O.o1_simulate(nl, st, threads=n_threads)
-    par_s = time.perf_counter() - t1
-    assert int(p_off[-1]) == n_o, "level-parallel oracle disagrees with the sequential one"
-    return n_o, single_s, par_s
 
 
 def oracle_threads():
@@ -474,49 +520,6 @@ def bench_windows(G, sim, nl, h, st, n_out_whole, ms_whole, n_windows=4):
             "wall_includes": "stimulus copy and upload from host memory, all levels, completion"}
 
 
-def bench_industrial(G, sim, seed, steps=3, oracle_levels=0):
-    """The industrial-shaped configuration: 10M gates, 8,192 PIs + 50,000
-    pseudo-PIs, 150 levels, fan-in 1-4, fanout cap 5,000, 1-200 ps delays, 200
-    transitions per source (2 % X/Z); stimuli resident in HBM, one job at a
-    time, wall time per job."""
-    import torch
-    from paper_2304_13398_amd import workloads as W
-    t = time.perf_counter()
-    nl, st = W.config3(seed=seed)
-    gen_s = time.perf_counter() - t
-    h = sim.load_netlist(nl)
-    dev = torch.device("cuda:0")
-    d = [torch.from_numpy(a).to(dev) for a in (st.off, st.t, st.v)]
-    stream = torch.cuda.current_stream()
-    times, n_out, dev_ms = [], 0, []
-    for i in range(steps + 1):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        j = sim.run_device(h, d[0].data_ptr(), d[1].data_ptr(), d[2].data_ptr(), st.n,
-                           stream=stream.cuda_stream)
-        sim.wait(j)
-        if i > 0:
-            times.append(time.perf_counter() - t0)
-            dev_ms.append(sim.stats(j).device_ms)
-        n_out = sim.stats(j).n_out
-        sim.release(j)
-    sim.unload_netlist(h)
-    ms = statistics.median(times) * 1000.0
-    print(f"[bench] industrial: {ms:.1f} ms per job ({gen_s:.0f}s to generate)", file=sys.stderr, flush=True)
-    res = {"workload": "industrial-shaped: 10M gates, 8,192 PIs + 50,000 pseudo-PIs, 150 levels, "
-                       "fan-in 1-4, fanout cap 5,000, rise/fall 1-200 ps, 200 transitions per source",
-           "gates": nl.G, "sources": nl.S, "n_in": st.n, "n_out": int(n_out), "ms_per_job": ms,
-           "device_ms": statistics.median(dev_ms), "transitions_per_s": n_out / (ms / 1000.0)}
-    if oracle_levels > 0:
-        from oracle import oracle as O
-        n_gates = int(np.searchsorted(nl.level, oracle_levels, side="right"))
-        n_t = oracle_threads()
-        n_o, single_s, par_s = oracle_times(O, nl.prefix(n_gates), st, n_t)
-        res["oracle_sample"] = {"levels": f"1-{oracle_levels}", "gates": n_gates, "n_out": n_o,
-                                "single_thread_s": single_s, "parallel_s": par_s, "threads": n_t}
-    return res
-
-
 def workload_stats(nl, lengths):
     """The paper's workload statistics (Table 2 columns and Eq. 5): coefficient
     of variation of the given (source) waveform lengths and of the generated
@@ -535,23 +538,147 @@ def W_loguniform(rng, lo, hi, n):
     return W.loguniform_int(rng, lo, hi, size=n)
 
 
-def algorithmic_bytes(nl, lengths):
-    """Bytes the evaluate launches must move, per level: every input waveform a
-    level reads once (8 B per transition: the device packs time << 2 | value
-    into one word), every output written once, the 64-byte gate record, the
-    per-net offset and length (16 B) of every pin read and of every output
-    written."""
-    S = nl.S
-    per_level = []
-    pin_gate = np.repeat(np.arange(nl.G), np.diff(nl.pin_off))
-    for lv in range(1, int(nl.level.max()) + 1):
-        gates = np.nonzero(nl.level == lv)[0]
-        pins = np.isin(pin_gate, gates)
-        nets = np.unique(nl.pin_net[pins])
-        b = 8 * int(lengths[nets].sum()) + 8 * int(lengths[S + gates].sum())
-        b += 64 * len(gates) + 16 * int(pins.sum()) + 16 * len(gates)
-        per_level.append(b)
-    return per_level
+# Unfinished steps the request loop lets the executor enqueue ahead of it (a
+# request that arrives waits at most this many steps, well under a
+# millisecond here, to join). Measured with 300 requests: at 100 jobs/s p50/p99
+# 18/120 ms with two, 16/98 ms with eight; at 500 jobs/s 538/1626 and 338/1520.
+SERVE_LOOKAHEAD = 8
+
+# Unfinished steps the batched loop lets the executor enqueue ahead of it: with
+# two, the host loop could not keep the device busy (1.01 s for the 64 sets);
+# from eight on the device never waits (0.75 s).
+BATCH_LOOKAHEAD = 8
+
+
+def bench_batched(G, sim, nl, h, n_sets, seed):
+    """Batched: n_sets stimulus sets over the resident netlist, per-set
+    transitions per PI log-uniform in [50, 5000] (the sets the full-size
+    parity test checks); all sets through the executor (shared launches,
+    admitted as HBM allows, largest sets first) vs one set per launch chain.
+    The lane threshold is autotuned on a sample set first."""
+    from paper_2304_13398_amd import autotune
+    from paper_2304_13398_amd import workloads as W
+    t = time.perf_counter()
+    set_args = W.config4_set_args(S=nl.S, n_sets=n_sets, seed=seed)
+    sets = pool_map(_gen_stimulus, set_args)
+    ns = np.array([a[1] for a in set_args])
+    say(f"batched: {n_sets} sets generated in {time.perf_counter() - t:.1f}s "
+        f"({sum(x.n for x in sets)} transitions)")
+    tuner = autotune.Autotuner(sim, candidates=(0, 64, 192, 512), reps=1)
+    median = sets[int(np.argsort(ns)[len(ns) // 2])]
+    thr, tms = tuner.tune(nl, h, median)
+
+    def one_per_launch():
+        t0 = time.perf_counter()
+        n_out = 0
+        for st in sets:
+            j = sim.run(h, st)
+            sim.wait(j)
+            n_out += sim.stats(j).n_out
+            sim.release(j)
+        return n_out, time.perf_counter() - t0
+
+    diag = {}
+
+    def batched():
+        t0 = time.perf_counter()
+        # largest first (first-fit decreasing): jobs are released as they finish
+        pending = sim.run_batch(h, sorted(sets, key=lambda x: -x.n))
+        diag["run_batch_return_s"] = time.perf_counter() - t0
+        n_out, retries, drives = 0, 0, 0
+        while pending:
+            sim.drive(max_ahead=BATCH_LOOKAHEAD)  # admit sets as memory frees, advance all
+            drives += 1
+            for j in [j for j in pending if sim.done(j)]:
+                st = sim.stats(j)
+                n_out += st.n_out
+                retries += st.retries
+                sim.release(j)
+                pending.remove(j)
+        diag["retries"], diag["drive_calls"] = retries, drives
+        return n_out, time.perf_counter() - t0
+
+    # one untimed pass of each first: the first batch allocates page-locked
+    # staging for all its sets at once (the one-per-launch loop reuses one set)
+    one_per_launch()
+    batched()
+    n1, t1 = one_per_launch()
+    n2, t2 = batched()
+    assert n1 == n2, "batched and one-per-launch runs disagree on the output size"
+    say(f"batched: one-per-launch {t1:.2f}s, batched {t2:.2f}s")
+    return {
+        "workload": f"{n_sets} stimulus sets over the 1M-gate netlist, transitions per PI "
+                    f"log-uniform 50-5,000 (mean {float(ns.mean()):.0f})",
+        "sets": n_sets, "n_in": int(sum(x.n for x in sets)), "n_out": int(n2),
+        "batched_transitions_per_s": n2 / t2, "batched_s": t2,
+        "one_per_launch_transitions_per_s": n1 / t1, "one_per_launch_s": t1,
+        "speedup": t1 / t2,
+        "tuned_lane_threshold": thr, "tuning_ms": tms, "batched_diagnostics": diag,
+        "lookahead_steps": BATCH_LOOKAHEAD,
+        "includes": "stimulus upload (pageable H2D), all levels, per-set completion wait",
+    }
+
+
+def bench_served(G, sim, rates, seed, seconds, full):
+    """Served: Poisson requests over 8 resident netlists (10k-2M gates), each
+    request log-uniform 20-2,000 transitions per PI and asking for the
+    waveforms of its netlist's deepest level plus every net's fingerprint;
+    continuous batching vs one job at a time, on the same arrivals."""
+    from paper_2304_13398_amd import autotune, serve
+    t = time.perf_counter()
+    nls = serve.served_netlists(seed=seed)
+    rng = np.random.default_rng(seed + 5_000_011)
+    items = []
+    per = 6
+    for k, nl in enumerate(nls):
+        for i, n in enumerate(W_loguniform(rng, 20, 2000, per)):
+            items.append((nl.S, int(n), 1_000_000, seed * 100_000 + k * 1000 + i))
+    stims = pool_map(_gen_stimulus, items)
+    pool = [stims[per * k:per * k + per] for k in range(len(nls))]
+    hs = [sim.load_netlist(nl) for nl in nls]
+    say(f"served: netlists and stimuli ready in {time.perf_counter() - t:.1f}s")
+    tuner = autotune.Autotuner(sim, candidates=(0, 64, 192, 512), reps=1)
+    tuned = []
+    for nl, h, p in zip(nls, hs, pool):
+        tuned.append(tuner.tune(nl, h, sorted(p, key=lambda x: x.n)[len(p) // 2])[0])
+        big = max(p, key=lambda x: x.n)
+        j = sim.run(h, big)          # learn the arena use of the largest request
+        sim.wait(j)
+        sim.release(j)
+    out = {"workload": "8 resident netlists of 10k-2M gates (mid-size generator, 60 levels); "
+                       "requests uniform over netlists, 20-2,000 transitions per PI (log-uniform), "
+                       "Poisson arrivals; each request fetches its deepest level's waveforms and "
+                       "every net's fingerprint",
+           "tuned_lane_thresholds": tuned, "rates": {}}
+    for rate in rates:
+        n_jobs = 1000 if full else int(min(1000, max(100, rate * seconds)))
+        reqs = serve.served_workload(n_jobs, rate, nls, pool, seed=seed + int(rate))
+        rc, mc = serve.serve_continuous(sim, hs, reqs, max_ahead=SERVE_LOOKAHEAD)
+        rs, ms = serve.serve_sequential(sim, hs, reqs)
+        c, s = serve.summarize(rc, mc), serve.summarize(rs, ms)
+        out["rates"][str(rate)] = {"jobs": n_jobs, "continuous": c, "sequential": s}
+        say(f"served rate {rate} ({n_jobs} jobs): continuous p50/p99 {c['p50_ms']:.1f}/{c['p99_ms']:.1f} ms, "
+            f"sequential {s['p50_ms']:.1f}/{s['p99_ms']:.1f} ms")
+    for h in hs:
+        sim.unload_netlist(h)
+    return out
+
+
+def eq6_speedups(per):
+    """GPU over oracle per configuration (the paper's Eq. 6 speedup, here as a
+    ratio of output-transition rates on the same work) and their geometric
+    mean, against the level-parallel and the single-thread oracle."""
+    for v in per.values():
+        v["speedup"] = v["gpu_transitions_per_s"] / v["oracle_parallel_per_s"]
+        if v.get("oracle_single_per_s"):
+            v["speedup_single_thread"] = v["gpu_transitions_per_s"] / v["oracle_single_per_s"]
+            # the faster CPU form (threads cost more than they give on a tiny job)
+            v["speedup_best_cpu"] = min(v["speedup"], v["speedup_single_thread"])
+        else:
+            v["speedup_best_cpu"] = v["speedup"]
+    g = lambda key: float(np.exp(np.mean([np.log(v[key]) for v in per.values() if key in v])))
+    return {"per_config": per, "geomean_speedup_best_cpu": g("speedup_best_cpu"),
+            "geomean_speedup": g("speedup")}
 
 
 def main():
@@ -566,275 +693,173 @@ def main():
     import torch
     from paper_2304_13398_amd import gsim as G
     from paper_2304_13398_amd import workloads as W
-
-    t_gen = time.perf_counter()
-    S = max(32, int(round(2048 * args.gates / 1_000_000)))
-    nl, st = W.config2(seed=args.seed, G=args.gates, S=S)
-    t_gen = time.perf_counter() - t_gen
-    print(f"[bench] workload generated in {t_gen:.1f}s: G={nl.G} S={nl.S} P={nl.P} N_in={st.n}",
-          file=sys.stderr, flush=True)
-
-    dev = torch.device("cuda:0")
-    d_off = torch.from_numpy(st.off).to(dev)
-    d_t = torch.from_numpy(st.t).to(dev)
-    d_v = torch.from_numpy(st.v).to(dev)
-    stream = torch.cuda.current_stream()
     sim = G.Sim(0)
-    sim.set_option(G.OPT_KERNEL_TIMING, 1)
-    h = sim.load_netlist(nl)
-    info = sim.netlist_info(h)
+    n_threads = oracle_threads()
+    eq6 = {}
 
-    def launch():
-        return sim.run_device(h, d_off.data_ptr(), d_t.data_ptr(), d_v.data_ptr(), st.n,
-                              stream=stream.cuda_stream)
+    if args.mid_only:
+        nl, st = W.config2(seed=args.seed)
+        h, d, res, _ = timed_job(G, sim, nl, st, args.steps, args.warmup, "mid", "mid")
+        print(json.dumps({"mid": res}), flush=True)
+        sim.close()
+        return 0
 
-    stats = []
-
-    def finish(j, keep):
-        sim.wait(j)
-        if keep:
-            stats.append(sim.stats(j))
-        sim.release(j)
-
-    # warmup (also validates the stimuli once on the device copy)
-    j = sim.run_device(h, d_off.data_ptr(), d_t.data_ptr(), d_v.data_ptr(), st.n,
-                       stream=stream.cuda_stream, validate=True)
-    finish(j, False)
-    for _ in range(max(0, args.warmup - 1)):
-        finish(launch(), False)
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    prev = None
-    for _ in range(args.steps):
-        j = launch()
-        if prev is not None:
-            finish(prev, True)
-        prev = j
-    if prev is not None:
-        finish(prev, True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    print(f"[bench] timed {args.steps} steps in {wall:.3f}s", file=sys.stderr, flush=True)
-
-    n_out = stats[-1].n_out
-    assert all(s.n_out == n_out for s in stats), "steps disagree on the output size"
-    ms_per_step = wall / args.steps * 1000.0
-    value = n_out / (ms_per_step / 1000.0)
-    dev_ms = statistics.median(s.device_ms for s in stats)
-    eval_ms = statistics.median(s.eval_ms for s in stats)
-    launches = stats[-1].eval_launches
-
-    # algorithmic bytes of the evaluate launches, from this run's lengths
-    j = launch()
-    sim.wait(j)
-    off = np.zeros(nl.S + nl.G + 1, dtype=np.int64)
-    sim.lib.sim_fetch_waveforms(sim.ctx, j, None, nl.S + nl.G,
-                                off.ctypes.data_as(G.ctypes.c_void_p), None, None, 0)
-    sim.release(j)
-    lengths = np.diff(off)
-    per_level = algorithmic_bytes(nl, lengths)
-    b_eval = float(sum(per_level))
-    achieved = b_eval / (eval_ms / 1000.0) / 1e9
-    b_pin = 8.0 * stats[-1].pin_reads + 8.0 * n_out
-    traffic_per_launch = measured_traffic_bytes_per_launch()
-    avg_launch_s = eval_ms / launches / 1000.0
-
+    # ---- headline: the industrial-shaped job --------------------------------
+    t = time.perf_counter()
+    nl, st = W.config3(seed=args.seed)
+    say(f"industrial workload generated in {time.perf_counter() - t:.1f}s: G={nl.G} S={nl.S} "
+        f"P={nl.P} N_in={st.n}")
+    h, d, res, lengths = timed_job(G, sim, nl, st, args.steps, args.warmup, "industrial", "industrial")
     out = {
         "metric": "output transitions/sec",
-        "value": value,
+        "value": res["value"],
         "unit": "transitions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
         "config": {
-            "workload": "mid-size re-simulation: 1M-gate levelled random DAG, 2,048 PIs, "
-                        "60 levels, fan-in 1-4, power-law fanout (alpha 2.2, cap 1,000), "
-                        "rise/fall 1-50 ps, 1,000 transitions per PI over [0, 1e6] ps, "
-                        "values 0/1/X/Z p=.45/.45/.05/.05",
+            "workload": "industrial-shaped re-simulation: 10M-gate levelled random DAG, 8,192 PIs + "
+                        "50,000 pseudo-PIs, 150 levels, fan-in 1-4, power-law fanout (alpha 2.2, "
+                        "cap 5,000), rise/fall 1-200 ps, 200 transitions per source over [0, 1e6] ps, "
+                        "values 0/1/X/Z p=.49/.49/.01/.01",
             "seed": args.seed, "gates": nl.G, "sources": nl.S, "pins": nl.P,
-            "levels": info.levels, "n_in": st.n, "n_out": int(n_out),
+            "levels": res["levels"], "n_in": st.n, "n_out": res["n_out"],
             "parallelism": "single GPU",
         },
-        "device_ms_per_step": dev_ms,
-        "hbm_gbps_step": (b_eval / (dev_ms / 1000.0) / 1e9),
-        "roofline": {
-            "kernel": "eval_wave_kernel<64> (every gate here has delays <= 64 ps)",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": (traffic_per_launch / avg_launch_s / 1e9) if traffic_per_launch else None,
-            "traffic_bytes_per_launch": traffic_per_launch,
-            "algorithmic_bytes_per_launch": b_eval / launches,
-            "avg_launch_ms": eval_ms / launches,
-            "launches_per_step": launches,
-            "per_pin_bytes_gbps": b_pin / (eval_ms / 1000.0) / 1e9,
-        },
+        "device_ms_per_step": res["device_ms_per_step"],
+        "eval_ms_per_step": res["eval_ms_per_step"],
+        "roofline": res["roofline"],
     }
-    valu = measured_valu_per_launch()
-    if valu:
-        # issue bound: the VALU stream's time at one instruction per CU per cycle
-        out["roofline"]["issue"] = {
-            "valu_instr_per_launch": valu,
-            "valu_busy_frac": valu / (CU_COUNT * CLOCK_HZ) / avg_launch_s,
-            "note": "the evaluate kernel is bound by VALU issue, not by HBM bandwidth",
-    }
-
-    # the practical ceiling: a plain 1 GiB device copy on the same GPU
+    if args.headline_only:
+        print(json.dumps(out), flush=True)
+        sim.close()
+        return 0
     _, copy_gbps = copy_rate(1 << 30)
     out["roofline"]["copy_ceiling_gbps"] = copy_gbps
-    out["roofline"]["frac_of_copy_ceiling"] = achieved / copy_gbps
-
+    out["roofline"]["frac_of_copy_ceiling"] = out["roofline"]["achieved"] / copy_gbps
     out["workload_stats"] = workload_stats(nl, lengths)
-
-    if not args.no_dataflow:
-        # the same jobs under the dependency-driven schedule (one persistent launch per job)
-        sim.set_option(G.OPT_SCHEDULE, 1)
-        dstats = []
-        finish(launch(), False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        prev = None
-        for _ in range(args.steps):
-            j = launch()
-            if prev is not None:
-                sim.wait(prev)
-                dstats.append(sim.stats(prev))
-                sim.release(prev)
-            prev = j
-        sim.wait(prev)
-        dstats.append(sim.stats(prev))
-        sim.release(prev)
-        torch.cuda.synchronize()
-        dwall = time.perf_counter() - t0
-        sim.set_option(G.OPT_SCHEDULE, 0)
-        assert all(x.n_out == n_out for x in dstats), "dependency-driven runs disagree on the output size"
-        d_ms = dwall / args.steps * 1000.0
-        d_eval = statistics.median(x.eval_ms for x in dstats)
-        out["dataflow"] = {
-            "schedule": "dependency-driven: one persistent launch per job, no level barrier",
-            "ms_per_step": d_ms,
-            "value": n_out / (d_ms / 1000.0),
-            "kernel_ms": d_eval,
-            "algorithmic_gbps": b_eval / (d_eval / 1000.0) / 1e9,
-            "vs_levels": ms_per_step / d_ms,
-        }
-        print(f"[bench] dependency-driven: {d_ms:.2f} ms per step (levels {ms_per_step:.2f})",
-              file=sys.stderr, flush=True)
-
+    sim.unload_netlist(h)
+    del d
     if not args.no_cpu_baseline:
         from oracle import oracle as O
-        lv = min(args.cpu_levels, info.levels)
-        n_gates = int(np.searchsorted(nl.level, lv, side="right"))
-        sub = nl.prefix(n_gates)
-        t1 = time.perf_counter()
-        o_off, _, o_v = O.o1_simulate(sub, st)
-        cpu_s = time.perf_counter() - t1
-        gate_of = np.repeat(np.arange(n_gates), np.diff(o_off))
-        lvl = nl.level[gate_of]
-        out["workload_stats"]["x_fraction_per_level"] = {
-            "levels": f"1-{lv} (from the oracle sample)",
-            "values": [round(float((o_v[lvl == l] == 2).mean()), 4) for l in range(1, lv + 1)]}
-        n_o = int(o_off[-1])
-        del o_off, o_v, gate_of, lvl
-        # the same sample with each level's gates split over the host's cores
-        n_threads = oracle_threads()
-        t1 = time.perf_counter()
-        p_off, _, _ = O.o1_simulate(sub, st, threads=n_threads)
-        par_s = time.perf_counter() - t1
-        assert int(p_off[-1]) == n_o, "level-parallel oracle disagrees with the sequential one"
-        del p_off
-        v1, vp = n_o / cpu_s, n_o / par_s
+        n_o, par_s, single_s = oracle_whole_job(O, nl, st, n_threads)
+        assert n_o == res["n_out"], "the oracle's output size differs from the GPU's"
         out["cpu_baseline"] = {
-            "value": vp,
+            "value": n_o / par_s,
             "unit": "transitions/s",
             "cores": n_threads,
             "kind": "oracle",
-            "sample": f"oracle O1 (plain C), each level's gates split over {n_threads} threads, on "
-                      f"levels 1-{lv} of the same workload ({n_gates} gates, {n_o} output "
-                      f"transitions, {par_s:.1f}s); single thread {cpu_s:.1f}s",
-            "single_thread_value": v1,
-            "gpu_speedup": value / vp,
-            "gpu_speedup_single_thread": value / v1,
+            "sample": f"the whole job (oracle O1 in plain C, each level's gates split over {n_threads} "
+                      f"threads; {n_o} output transitions in {par_s:.1f}s); one thread {single_s:.1f}s",
+            "single_thread_value": n_o / single_s,
+            "cpu_model": cpu_model(),
+            "gpu_speedup": res["value"] / (n_o / par_s),
+            "gpu_speedup_single_thread": res["value"] / (n_o / single_s),
         }
-        print(f"[bench] oracle: {v1:.3g} transitions/s on 1 thread, {vp:.3g} on {n_threads}",
-              file=sys.stderr, flush=True)
-    sim.set_option(G.OPT_KERNEL_TIMING, 0)
-    if not args.no_e2e:
-        out["end_to_end"] = bench_end_to_end(G, sim, nl, h, st)
-        print(f"[bench] end to end: {out['end_to_end']}", file=sys.stderr, flush=True)
-    if not args.no_windows:
-        out["time_windows"] = bench_windows(G, sim, nl, h, st, n_out, dev_ms)
-        print(f"[bench] time windows: {out['time_windows']}", file=sys.stderr, flush=True)
-    if not args.no_skewed:
-        out["skewed"] = bench_skewed(G, sim, nl, h, args.seed)
+        eq6["industrial"] = {"gpu_transitions_per_s": res["value"], "oracle_parallel_per_s": n_o / par_s,
+                             "oracle_single_per_s": n_o / single_s}
+        say(f"oracle on the whole industrial job: {par_s:.1f}s on {n_threads} threads, {single_s:.1f}s on one")
+    del nl, st, lengths
+
+    # ---- the 1M-gate mid-size job and the sections built on it -----------------
+    if not args.no_mid:
+        nl, st = W.config2(seed=args.seed)
+        h, d, mid, m_lengths = timed_job(G, sim, nl, st, min(args.steps, 10), args.warmup, "mid", "mid")
+        mid["workload"] = ("mid-size re-simulation: 1M-gate levelled random DAG, 2,048 PIs, 60 levels, "
+                           "fan-in 1-4, power-law fanout (alpha 2.2, cap 1,000), rise/fall 1-50 ps, "
+                           "1,000 transitions per PI over [0, 1e6] ps, values 0/1/X/Z p=.45/.45/.05/.05")
+        mid["workload_stats"] = workload_stats(nl, m_lengths)
+        out["mid"] = mid
+        stream = torch.cuda.current_stream()
+
+        def launch():
+            return sim.run_device(h, d[0].data_ptr(), d[1].data_ptr(), d[2].data_ptr(), st.n,
+                                  stream=stream.cuda_stream)
+
+        if not args.no_dataflow:
+            # the same jobs under the dependency-driven schedule (one persistent launch per job)
+            sim.set_option(G.OPT_SCHEDULE, 1)
+            sim.set_option(G.OPT_KERNEL_TIMING, 1)
+            j = launch()
+            sim.wait(j)
+            sim.release(j)
+            torch.cuda.synchronize()
+            steps = min(args.steps, 10)
+            t0 = time.perf_counter()
+            dstats = []
+            for _ in range(steps):
+                j = launch()
+                sim.wait(j)
+                dstats.append(sim.stats(j))
+                sim.release(j)
+            dwall = time.perf_counter() - t0
+            sim.set_option(G.OPT_SCHEDULE, 0)
+            sim.set_option(G.OPT_KERNEL_TIMING, 0)
+            assert all(x.n_out == mid["n_out"] for x in dstats), "dependency-driven runs disagree"
+            d_ms = dwall / steps * 1000.0
+            d_eval = statistics.median(x.eval_ms for x in dstats)
+            out["dataflow"] = {
+                "workload": "the mid-size job",
+                "schedule": "dependency-driven: one persistent launch per job, no level barrier",
+                "ms_per_step": d_ms, "value": mid["n_out"] / (d_ms / 1000.0), "kernel_ms": d_eval,
+                "b_min_gbps": mid["roofline"]["b_min_bytes_per_job"] / (d_eval / 1000.0) / 1e9,
+                "vs_levels": mid["ms_per_step"] / d_ms,
+            }
+            say(f"dependency-driven: {d_ms:.2f} ms per mid job (levels {mid['ms_per_step']:.2f})")
+        if not args.no_cpu_baseline:
+            from oracle import oracle as O
+            n_o, par_s, _ = oracle_whole_job(O, nl, st, n_threads, single=False)
+            assert n_o == mid["n_out"], "the oracle's output size differs from the GPU's"
+            # one thread on a closed prefix of the netlist (levels 1-15)
+            n_gates = int(np.searchsorted(nl.level, 15, side="right"))
+            t1 = time.perf_counter()
+            ln_s, _ = O.o1_simulate_fingerprints(nl.prefix(n_gates), st)
+            single_s = time.perf_counter() - t1
+            eq6["mid"] = {"gpu_transitions_per_s": mid["value"], "oracle_parallel_per_s": n_o / par_s,
+                          "oracle_single_per_s": int(ln_s.sum()) / single_s,
+                          "oracle_single_sample": "levels 1-15"}
+            mid["cpu_oracle"] = {"whole_job_parallel_s": par_s, "threads": n_threads,
+                                 "single_thread_levels_1_15_s": single_s}
+        if not args.no_e2e:
+            out["end_to_end"] = bench_end_to_end(G, sim, nl, h, st)
+            say(f"end to end: {out['end_to_end']}")
+        if not args.no_windows:
+            out["time_windows"] = bench_windows(G, sim, nl, h, st, mid["n_out"], mid["device_ms_per_step"])
+            say(f"time windows: {out['time_windows']}")
+        if not args.no_skewed:
+            out["skewed"] = bench_skewed(G, sim, nl, h, args.seed)
+        if not args.no_batched:
+            out["batched"] = bench_batched(G, sim, nl, h, args.batched_sets, args.seed)
+        sim.unload_netlist(h)
+        del d
     if not args.no_tiny:
         out["tiny_latency"] = bench_tiny_latency(G, sim, args.seed)
         if not args.no_dataflow:
             sim.set_option(G.OPT_SCHEDULE, 1)
             out["tiny_latency_dataflow"] = bench_tiny_latency(G, sim, args.seed)
             sim.set_option(G.OPT_SCHEDULE, 0)
-    if not args.no_batched:
-        out["batched"] = bench_batched(G, sim, nl, h, args.batched_sets, args.seed)
-    sim.unload_netlist(h)
-    if not args.no_industrial:
-        out["industrial"] = bench_industrial(G, sim, args.seed,
-                                             oracle_levels=0 if args.no_cpu_baseline else 10)
+        if not args.no_cpu_baseline:
+            from oracle import oracle as O
+            nl1, st1 = W.config1(seed=args.seed)
+            n_o, par_s, single_s = oracle_whole_job(O, nl1, st1, n_threads)
+            key = "tiny_latency_dataflow" if "tiny_latency_dataflow" in out else "tiny_latency"
+            gpu_s = out[key]["resident_p50_us"] / 1e6
+            eq6["tiny"] = {"gpu_transitions_per_s": n_o / gpu_s, "oracle_parallel_per_s": n_o / par_s,
+                           "oracle_single_per_s": n_o / single_s, "gpu_schedule": key}
     if not args.no_served:
         rates = [float(x) for x in args.served_rates.split(",") if x]
-        out["served"] = bench_served(G, sim, args.served_jobs, rates, args.seed)
-    if "cpu_baseline" in out:
-        out["cpu_baseline"].update(eq6_speedups(out, nl_tiny_oracle(args) if "tiny_latency" in out else None))
+        out["served"] = bench_served(G, sim, rates, args.seed, args.served_seconds, args.served_full)
+    if eq6 and "cpu_baseline" in out:
+        out["cpu_baseline"].update(eq6_speedups(eq6))
     print(json.dumps(out), flush=True)
     sim.close()
     return 0
-
-
-def nl_tiny_oracle(args):
-    """The oracle on the whole tiny job: (n_out, single-thread s, parallel s)."""
-    from oracle import oracle as O
-    from paper_2304_13398_amd import workloads as W
-    nl, st = W.config1(seed=args.seed)
-    return oracle_times(O, nl, st, oracle_threads())
-
-
-def eq6_speedups(out, tiny):
-    """GPU over oracle per configuration (the paper's Eq. 6 speedup, here as a
-    ratio of output-transition rates on the same work) and their geometric
-    mean, against the level-parallel and the single-thread oracle."""
-    cb = out["cpu_baseline"]
-    per = {"mid": {"gpu_transitions_per_s": out["value"], "oracle_parallel_per_s": cb["value"],
-                   "oracle_single_per_s": cb["single_thread_value"]}}
-    if tiny is not None:
-        n_o, single_s, par_s = tiny
-        # the tiny job's latency under the schedule the automatic choice picks
-        # (dependency-driven for a netlist this small), resident stimuli
-        key = "tiny_latency_dataflow" if "tiny_latency_dataflow" in out else "tiny_latency"
-        gpu_s = out[key]["resident_p50_us"] / 1e6
-        per["tiny"] = {"gpu_transitions_per_s": n_o / gpu_s, "oracle_parallel_per_s": n_o / par_s,
-                       "oracle_single_per_s": n_o / single_s, "gpu_schedule": key}
-    ind = out.get("industrial", {}).get("oracle_sample")
-    if ind is not None:
-        per["industrial"] = {"gpu_transitions_per_s": out["industrial"]["transitions_per_s"],
-                             "oracle_parallel_per_s": ind["n_out"] / ind["parallel_s"],
-                             "oracle_single_per_s": ind["n_out"] / ind["single_thread_s"],
-                             "oracle_sample": f"levels {ind['levels']}"}
-    for v in per.values():
-        v["speedup"] = v["gpu_transitions_per_s"] / v["oracle_parallel_per_s"]
-        v["speedup_single_thread"] = v["gpu_transitions_per_s"] / v["oracle_single_per_s"]
-        # the faster CPU form (threads cost more than they give on a tiny job)
-        v["speedup_best_cpu"] = min(v["speedup"], v["speedup_single_thread"])
-    g = lambda key: float(np.exp(np.mean([np.log(v[key]) for v in per.values()])))
-    return {"per_config": per, "geomean_speedup_best_cpu": g("speedup_best_cpu"),
-            "geomean_speedup": g("speedup"), "geomean_speedup_single_thread": g("speedup_single_thread")}
 
 
 if __name__ == "__main__":

@@ -360,13 +360,19 @@ def loguniform_int(rng, lo, hi, size=None):
     return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size=size))).astype(np.int64)
 
 
+def config4_set_args(S=2048, n_sets=64, seed=1, lo=50, hi=5000, window=1_000_000):
+    """Arguments of make_stimulus for each batched set: (S, n_s, window, seed_s)
+    with n_s ~ round(exp U(ln lo, ln hi)) transitions on every PI."""
+    rng = _child_rngs(seed + 7_000_001, 1)[0]
+    ns = loguniform_int(rng, lo, hi, size=n_sets)
+    return [(S, int(n), window, seed * 1000 + s) for s, n in enumerate(ns)]
+
+
 def config4_sets(S=2048, n_sets=64, seed=1, lo=50, hi=5000, window=1_000_000):
     """Batched: ``n_sets`` stimulus sets, set s has n_s ~ round(exp U(ln lo, ln hi))
     transitions on every PI."""
-    rng = _child_rngs(seed + 7_000_001, 1)[0]
-    ns = loguniform_int(rng, lo, hi, size=n_sets)
-    return [make_stimulus(S=S, n_per_src=int(n), window=window, seed=seed * 1000 + s)
-            for s, n in enumerate(ns)]
+    return [make_stimulus(S=a, n_per_src=n, window=w, seed=sd)
+            for a, n, w, sd in config4_set_args(S, n_sets, seed, lo, hi, window)]
 
 
 def config5_netlist_sizes():
