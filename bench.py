@@ -31,7 +31,9 @@ HBM_PEAK_GBPS = 8000.0
 CU_COUNT, CLOCK_HZ = 256, 2.4e9   # MI355X: 256 CUs at 2.4 GHz; one wave64 VALU instruction per CU per cycle
 ROOT = os.path.dirname(os.path.abspath(__file__))
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2304_13398_amd", "csrc", "kernels.hip")
+# device code: the kernels and the per-gate evaluation they share
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_13398_amd", "csrc", f)
+                  for f in ("kernels.hip", "eval_core.h", "gsim_internal.h")]
 
 # Committed counter profiles of each workload's dominant evaluate kernel; a
 # figure is used only while the kernel source hash recorded there matches.
@@ -43,7 +45,10 @@ PROFILE_FILES = {
 
 def kernel_source_hash():
     try:
-        return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            h.update(open(f, "rb").read())
+        return h.hexdigest()[:16]
     except OSError:
         return None
 
