@@ -116,13 +116,17 @@ def test_admission_waves_under_a_small_budget():
 
 
 def test_learned_arena_size_and_automatic_retry(sim):
-    """A dense stimulus teaches the netlist's arena use per input transition;
-    sparse stimuli then need more per input transition than 1.5x that, so
-    their first runs overflow and are re-run with twice the storage. Results
-    stay exact."""
+    """A dense stimulus teaches the netlist's arena use per input transition:
+    3,000 transitions per source packed into 6 ns, so that most of them are
+    eaten as glitches at the first gates and deeper levels reserve little
+    (about 46 slots per input transition, from the oracle's lengths). Sparse
+    stimuli spread over 1 us need about 500 per input transition, far more
+    than 1.5x that, so the first of them overflows and is re-run with twice
+    the storage until it fits. Results stay exact, and the overflowed runs
+    leave nothing allocated."""
     nl = W.config2_netlist(G=6000, S=32, L=40, seed=9)
     h = sim.load_netlist(nl)
-    dense = W.make_stimulus(S=nl.S, n_per_src=3000, window=1_000_000, seed=31)
+    dense = W.make_stimulus(S=nl.S, n_per_src=3000, window=6_000, seed=31)
     j = sim.run(h, dense)
     sim.wait(j)
     sim.release(j)
