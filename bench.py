@@ -81,6 +81,8 @@ def parse():
                     help="only the timed industrial steps (for profiler runs)")
     ap.add_argument("--mid-only", action="store_true",
                     help="only the timed mid-size steps (for profiler runs)")
+    ap.add_argument("--eval-form", choices=("segmented", "merged"), default="segmented",
+                    help="data-parallel form of the wavefront-per-gate kernel (same results)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mid", action="store_true", help="skip the 1M-gate mid-size sections")
     ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-configuration latency")
@@ -200,11 +202,34 @@ def timed_job(G, sim, nl, st, steps, warmup, name, profile_key):
     finish(launch(validate=True), False)  # also validates the stimuli once on the device copy
     for _ in range(max(0, warmup - 1)):
         finish(launch(), False)
+    # two jobs in flight when two fit the HBM budget, else one at a time
+    depth = 2
+    a = launch()
+    try:
+        finish(launch(), False)
+    except G.GsimError as e:
+        if e.status != G.E_OOM:
+            raise
+        depth = 1
+    finish(a, False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     prev = None
     for _ in range(steps):
-        j = launch()
+        if depth == 1 and prev is not None:
+            finish(prev, True)
+            prev = None
+        try:
+            j = launch()
+        except G.GsimError as e:
+            # the pool could not place a second arena next to the first
+            # (fragmentation): one at a time from here on
+            if e.status != G.E_OOM or prev is None:
+                raise
+            depth = 1
+            finish(prev, True)
+            prev = None
+            j = launch()
         if prev is not None:
             finish(prev, True)
         prev = j
@@ -217,8 +242,8 @@ def timed_job(G, sim, nl, st, steps, warmup, name, profile_key):
     ms = wall / steps * 1000.0
     eval_ms = statistics.median(s.eval_ms for s in stats)
     launches = stats[-1].eval_launches
-    say(f"{name}: {steps} steps in {wall:.3f}s, {ms:.2f} ms per job, evaluate {eval_ms:.2f} ms "
-        f"over {launches} launches")
+    say(f"{name}: {steps} steps in {wall:.3f}s, {ms:.2f} ms per job ({depth} in flight), evaluate "
+        f"{eval_ms:.2f} ms over {launches} launches")
 
     # every net's length from one more run: the bytes the method must move
     j = launch()
@@ -259,7 +284,7 @@ def timed_job(G, sim, nl, st, steps, warmup, name, profile_key):
                        "lane_ops_per_s": valu * 64 / avg_launch_s,
                        "peak_lane_ops_per_s": CU_COUNT * 64 * CLOCK_HZ}
         roof["binds"] = "alu (VALU issue)" if busy > 0.8 else "neither fully (latency)"
-    res = {"ms_per_step": ms, "value": n_out / (ms / 1000.0), "n_out": int(n_out),
+    res = {"ms_per_step": ms, "value": n_out / (ms / 1000.0), "n_out": int(n_out), "jobs_in_flight": depth,
            "device_ms_per_step": statistics.median(s.device_ms for s in stats),
            "eval_ms_per_step": eval_ms, "pin_reads": int(pin_reads), "roofline": roof,
            "levels": info.levels}
@@ -699,6 +724,7 @@ def main():
     from paper_2304_13398_amd import gsim as G
     from paper_2304_13398_amd import workloads as W
     sim = G.Sim(0)
+    sim.set_option(G.OPT_EVAL_FORM, G.FORM_SEGMENTED if args.eval_form == "segmented" else G.FORM_MERGED)
     n_threads = oracle_threads()
     eq6 = {}
 

@@ -106,7 +106,14 @@ enum gsim_option {
      * transition counts vary with a coefficient of variation (the paper's
      * workload WCV, Eq. 5) of at least 2.5; level by level otherwise.
      * Results are identical under every setting. */
-    GSIM_OPT_SCHEDULE = 6
+    GSIM_OPT_SCHEDULE = 6,
+    /* Data-parallel form of the level schedule's wavefront-per-gate kernel
+     * (Algorithm 2 per gate either way; identical results): 0 = segmented,
+     * each lane runs the procedure over a time segment of the gate's inputs
+     * and the lanes' candidates are reconciled by Eq. 1 across lanes;
+     * 1 = merged positions, the inputs merged in time across the wavefront
+     * and every step a wavefront scan. */
+    GSIM_OPT_EVAL_FORM = 7
 };
 
 /* ---- context ------------------------------------------------------------ */
@@ -242,7 +249,8 @@ gsim_status sim_submit_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_sr
 
 /* sim_submit, then drive the executor until every level of the job is
  * enqueued; returns without waiting for the device. GSIM_E_OOM if the job
- * cannot be admitted because unreleased jobs hold the budget. Passage: the
+ * cannot be admitted because unreleased jobs hold the budget; on any error
+ * the job is discarded and *out is 0. Passage: the
  * whole computation on the device with no host synchronisation in between
  * (Section 1.4, Algorithmic Flow; Section 4.1; Algorithm 2 per gate). */
 gsim_status sim_run(gsim_ctx ctx, gsim_netlist nl, const int64_t *src_off, const int64_t *t,

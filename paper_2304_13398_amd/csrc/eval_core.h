@@ -773,6 +773,434 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
 }
 
 // -------------------------------------------------------------------------
+// Segmented wavefront-per-gate evaluation.
+//
+// The same per-gate procedure in a second data-parallel form, with lanes in
+// time order instead of merged positions. Each round's input transitions (as
+// in eval_gate: every transition at or before the horizon H, tiles of 512,
+// 384, 256 or 192 per pin) are cut into 64 consecutive time segments, one per
+// lane, at equal-count points of the pin with the most transitions in the
+// round. Each lane finds where its segment starts in the other pins' tiles (a
+// binary search), takes each pin's last value before it, and then runs
+// Algorithm 2 itself over its segment: it merges its share of the tiles in
+// time, applies each time group, evaluates the gate, and keeps its candidates
+// on a stack, a new candidate first removing those that appear no earlier
+// than it (Eq. 1). Candidates of a later lane deny too: of a lane's stack only
+// the entries appearing before the earliest candidate of every later lane
+// survive (a suffix minimum over the lanes; a stack's bottom is its lane's
+// earliest candidate), and of the tentative survivors of earlier rounds those
+// appearing before the round's earliest candidate. Survivors are increasing
+// in appearance time; those at or before H are final (later rounds'
+// candidates appear after H), and the Fig. 3 drop keeps a final survivor
+// whose value differs from the previous survivor's, the previous lane's last
+// one carried by a wave scan. The rest stay tentative for the next round.
+// A lane's stack lives in LDS from its segment's first merged index, so the
+// stacks never overlap.
+template <int K>
+struct SegTiling {
+    static constexpr int T = K == 1 ? 512 : K == 2 ? 384 : K == 3 ? 256 : 192;
+    static constexpr int E = T / 64;
+    static constexpr int OFF(int p) { return p * T; }  // key 0 of pin p
+    static constexpr int KEYS = K * T;
+};
+constexpr int kSegKeys = 768;  // the largest round: K x T
+static_assert(SegTiling<1>::KEYS <= kSegKeys && SegTiling<2>::KEYS <= kSegKeys &&
+                  SegTiling<3>::KEYS <= kSegKeys && SegTiling<4>::KEYS <= kSegKeys,
+              "every pin count's tiles fit");
+
+template <int W>
+struct SegLds {
+    uint32_t tile[kSegKeys];   // K x T in-round keys; after the segments, the output staging
+    uint32_t stack[kSegKeys];  // lane stacks, each from its segment's first merged index
+    uint32_t seq[W];           // tentative survivors of earlier rounds
+    uint32_t dtab[48];         // min delay by (new value, set of changed pins)
+    uint32_t etab[12];         // edge model: per (pin, edge class) delays to 0, 1, X (10-bit fields)
+    uint8_t lut[256];
+};
+
+// The gate's delay tables in LDS: output-value model dtab[value * 16 + set of
+// changed pins] = the smallest delay over those pins; edge model etab[pin * 3
+// + edge class] = the pin's delays to 0, 1 and X for that input edge.
+template <int K, bool EDGE>
+__device__ __forceinline__ void delay_tables(const JobDesc &J, const GateRec &R, int64_t gate,
+                                             uint32_t *dtab, uint32_t *etab) {
+    const int lane = lane_id();
+    if (EDGE) {
+        if (lane < 3 * K) {
+            const int pin = lane / 3, c = lane % 3;
+            const int32_t *d = J.edly + (size_t)gate * 16 + pin * 4;  // [edge][out]
+            uint32_t f[3];
+#pragma unroll
+            for (int o = 0; o < 2; o++) {
+                const int32_t a = c == 1 ? kNoRelation : d[o], b = c == 0 ? kNoRelation : d[2 + o];
+                const int32_t m = a < b ? a : b;
+                f[o] = m == kNoRelation ? kEdgeNone : (uint32_t)m;
+            }
+            f[2] = f[0] < f[1] ? f[0] : f[1];
+            etab[lane] = f[0] | f[1] << 10 | f[2] << 20;
+        }
+    } else if (lane < 48) {
+        const uint32_t ev = (uint32_t)lane >> 4, mask = (uint32_t)lane & 15u;
+        int32_t d = INT32_MAX;
+#pragma unroll
+        for (int q = 0; q < K; q++)
+            if (mask & (1u << q)) {
+                const int32_t dq = pin_delay(R.rise[q], R.fall[q], ev);
+                d = dq < d ? dq : d;
+            }
+        dtab[lane] = (uint32_t)d;
+    }
+}
+
+// Index of the first of the n keys at t[0, n) whose time is >= s (keys sorted).
+template <int T>
+__device__ __forceinline__ int seg_lower_bound(const uint32_t *t, int n, uint32_t s) {
+    int idx = 0;
+#pragma unroll
+    for (int step = 512; step >= 1; step >>= 1) {
+        if (step > T) continue;
+        const int j = idx + step;
+        const int at = (j < n ? j : n) - 1;
+        const uint32_t k = t[at > 0 ? at : 0];
+        idx = j <= n && (k >> 4) < s ? j : idx;
+    }
+    return idx;
+}
+
+template <int K, int W, bool EDGE, bool AGENT>
+__device__ __forceinline__ void eval_gate_seg(const JobDesc &J, int64_t ob, const GateRec &R,
+                                              int64_t gate, SegLds<W> &L) {
+    using Tl = SegTiling<K>;
+    constexpr int TT = Tl::T;
+    constexpr int E = Tl::E;
+    const int lane = lane_id();
+    const int64_t S = J.S;
+    int64_t *len = J.len;
+    int64_t *off = J.off;
+    uint64_t *Kar = J.K;
+
+    int64_t pb[K], pl[K], cur[K];
+    int64_t reserved = 0;  // slots sized for this gate: the sum of its input lengths
+#pragma unroll
+    for (int p = 0; p < K; p++) {
+        pb[p] = off[R.net[p]];
+        pl[p] = len[R.net[p]];
+        cur[p] = 0;
+        reserved += pl[p];
+    }
+    uint32_t state0 = 0;  // pin values before the round, 2 bits per pin
+#pragma unroll
+    for (int p = 0; p < K; p++) state0 |= (uint32_t)kX << (2 * p);
+
+    PinTile<TT> tl[K];
+#pragma unroll
+    for (int p = 0; p < K; p++) tile_fetch<TT, true>(Kar + pb[p], pl[p], tl[p]);
+    delay_tables<K, EDGE>(J, R, gate, L.dtab, L.etab);
+
+    uint32_t last_val = kX;  // value of the last final survivor
+    bool first_round = true;
+    int nq = 0;              // tentative survivors in L.seq[0, nq), offsets from base_prev
+    int64_t base_prev = 0;
+    int64_t out_n = 0;
+    bool stalled = false;
+    for (;;) {
+        nq = __builtin_amdgcn_readfirstlane(nq);
+#pragma unroll
+        for (int p = 0; p < K; p++) cur[p] = uniform64(cur[p]);
+        int64_t rem[K];
+        bool more = nq > 0 && !stalled;
+#pragma unroll
+        for (int p = 0; p < K; p++) {
+            rem[p] = pl[p] - cur[p];
+            more |= rem[p] > 0 && !stalled;
+        }
+        if (!more) break;
+
+        // ---- base (earliest pending time) and horizon, as in eval_gate
+        int lim[K];
+        uint32_t thi[K];
+        int64_t H = kInf, base = kInf;
+#pragma unroll
+        for (int p = 0; p < K; p++) {
+            int64_t t0, hp;
+            tile_settle<TT, true>(Kar + pb[p] + cur[p], rem[p], tl[p], lim[p], thi[p], t0, hp);
+            H = min64(H, hp);
+            base = min64(base, t0);
+        }
+        if (nq > 0) {
+            const uint32_t q0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)L.seq[0]);
+            base = min64(base, base_prev + (int64_t)(q0 >> 2));
+            const uint32_t shift = (uint32_t)(base - base_prev) << 2;
+            for (int c = lane; c < nq; c += 64) L.seq[c] -= shift;
+        }
+        H = min64(H, base + kSpan);
+        const uint64_t hkey = H < kTimeLimit ? pack_key(H, 3u) : ~uint64_t(0);
+        const uint32_t base4 = (uint32_t)pack_key(base, 0u);
+        const uint32_t hk_hi = (uint32_t)(hkey >> 32);
+        int m[K];
+#pragma unroll
+        for (int p = 0; p < K; p++) {
+            const uint32_t lo_max =
+                (uint32_t)__builtin_amdgcn_readfirstlane((int)(thi[p] < hk_hi ? 0xFFFFFFFFu : (uint32_t)hkey));
+            const int lim_in = __builtin_amdgcn_readfirstlane(thi[p] > hk_hi ? 0 : lim[p]);
+            m[p] = 0;
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                const uint32_t lo = tl[p].lo[e];
+                const bool in_lane = lane + 64 * e < lim_in, in_time = lo <= lo_max;
+                m[p] += __popcll(__ballot(in_lane) & __ballot(in_time));
+                L.tile[Tl::OFF(p) + 64 * e + lane] =
+                    in_lane && in_time ? ((lo - base4) << 2) | (uint32_t)p : kNoKey32;
+            }
+        }
+        bool all_in = true;
+#pragma unroll
+        for (int p = 0; p < K; p++) all_in = all_in && m[p] == rem[p];
+        const uint32_t hsplit = all_in ? kNoKey32 : (uint32_t)(H - base) << 2 | 3u;
+        PinTile<TT> nx[K];
+#pragma unroll
+        for (int p = 0; p < K; p++) tile_fetch<TT, true>(Kar + pb[p] + cur[p] + m[p], rem[p] - m[p], nx[p]);
+        __syncthreads();
+
+        // ---- this lane's segment: [s, next lane's s) in time
+        int q = 0, mq = m[0];
+#pragma unroll
+        for (int p = 1; p < K; p++)
+            if (m[p] > mq) {
+                q = p;
+                mq = m[p];
+            }
+        const int iq = (lane * mq) >> 6;
+        const uint32_t s = lane == 0 ? 0u : L.tile[Tl::OFF(0) + q * TT + iq] >> 4;
+        int ip[K], endi[K];
+        int sb = 0;  // merged index of the segment's first transition
+#pragma unroll
+        for (int p = 0; p < K; p++) {
+            if (p == q) ip[p] = iq;
+            else ip[p] = seg_lower_bound<TT>(L.tile + Tl::OFF(p), m[p], s);
+            endi[p] = (int)wave_shift_down((uint32_t)m[p], (uint32_t)ip[p]);
+            sb += ip[p];
+        }
+        // pin values before the segment; the gate's value there (X before any input change)
+        uint32_t st = state0;
+#pragma unroll
+        for (int p = 0; p < K; p++)
+            if (ip[p] > 0) {
+                const uint32_t k = L.tile[Tl::OFF(p) + ip[p] - 1];
+                st = (st & ~(3u << (2 * p))) | (((k >> 2) & 3u) << (2 * p));
+            }
+        uint32_t e_prev = first_round && sb == 0 ? (uint32_t)kX : __builtin_amdgcn_ubfe(L.lut[st], 0, 2);
+        // pin values after the round (for the next one)
+        uint32_t state_next = state0;
+#pragma unroll
+        for (int p = 0; p < K; p++)
+            if (m[p] > 0) {
+                const uint32_t k = (uint32_t)__builtin_amdgcn_readfirstlane((int)L.tile[Tl::OFF(p) + m[p] - 1]);
+                state_next = (state_next & ~(3u << (2 * p))) | (((k >> 2) & 3u) << (2 * p));
+            }
+
+        // ---- Algorithm 2 over the segment; candidates on the lane's stack (Eq. 1)
+        uint32_t head[K];
+        int idx[K];
+#pragma unroll
+        for (int p = 0; p < K; p++) {
+            idx[p] = ip[p];
+            head[p] = idx[p] < endi[p] ? L.tile[Tl::OFF(p) + idx[p]] : kNoKey32;
+        }
+        int n = 0;         // the stack: L.stack[sb, sb + n)
+        uint32_t top = 0;  // L.stack[sb + n - 1] when n > 0
+        for (;;) {
+            uint32_t mn = head[0];
+#pragma unroll
+            for (int p = 1; p < K; p++) mn = umin32(mn, head[p]);
+            const bool act = mn != kNoKey32;
+            if (__ballot(act) == 0) break;
+            if (act) {
+                const uint32_t t = mn >> 4;
+                uint32_t mask = 0;
+                uint32_t r0 = kEdgeNone, r1 = kEdgeNone, rx = kEdgeNone;
+#pragma unroll
+                for (int p = 0; p < K; p++) {
+                    if ((head[p] >> 4) == t) {
+                        const uint32_t nv = (head[p] >> 2) & 3u;
+                        if (EDGE) {
+                            const uint32_t ent = L.etab[p * 3 + edge_class((st >> (2 * p)) & 3u, nv)];
+                            r0 = umin32(r0, ent & 1023u);
+                            r1 = umin32(r1, (ent >> 10) & 1023u);
+                            rx = umin32(rx, ent >> 20);
+                        }
+                        st = (st & ~(3u << (2 * p))) | (nv << (2 * p));
+                        mask |= 1u << p;
+                        idx[p]++;
+                        head[p] = idx[p] < endi[p] ? L.tile[Tl::OFF(p) + idx[p]] : kNoKey32;
+                    }
+                }
+                const uint32_t e = __builtin_amdgcn_ubfe(L.lut[st], 0, 2);
+                if (e != e_prev) {
+                    const uint32_t d = EDGE ? (e == 0u ? r0 : e == 1u ? r1 : rx) : L.dtab[e * 16 + mask];
+                    // (edge model: no related pin changed, the candidate never appears)
+                    if (!EDGE || d != kEdgeNone) {
+                        const uint32_t key = ((t + d) << 2) | e;
+                        while (n > 0 && (top >> 2) >= (key >> 2)) {
+                            n--;
+                            top = n > 0 ? L.stack[sb + n - 1] : 0u;
+                        }
+                        L.stack[sb + n] = key;
+                        n++;
+                        top = key;
+                    }
+                    e_prev = e;
+                }
+            }
+        }
+
+        // ---- survivors: before every later lane's earliest candidate
+        const uint32_t bottom = n > 0 ? L.stack[sb] : kNoKey32;
+        const uint32_t suf = wave_suffix_min(bottom);
+        const uint32_t round_min = (uint32_t)__builtin_amdgcn_readlane((int)suf, 0);
+        const uint32_t later = wave_shift_down(kNoKey32, suf);
+        while (n > 0 && (top >> 2) >= (later >> 2)) {
+            n--;
+            top = n > 0 ? L.stack[sb + n - 1] : 0u;
+        }
+        // tentative survivors of earlier rounds outlive this round iff they
+        // appear before every candidate of this round (they are increasing)
+        int ncs = 0;
+        for (int c0 = 0; c0 < nq; c0 += 64) {
+            const int c = c0 + lane;
+            ncs += __popcll(__ballot(c < nq && (L.seq[c] >> 2) < (round_min >> 2)));
+        }
+        // final: appearing at or before H (a prefix of every ordered list)
+        int nft = 0;
+        for (int c0 = 0; c0 < ncs; c0 += 64) {
+            const int c = c0 + lane;
+            nft += __popcll(__ballot(c < ncs && L.seq[c] <= hsplit));
+        }
+        int f = n;
+        {
+            uint32_t tp = top;
+            while (f > 0 && tp > hsplit) {
+                f--;
+                tp = f > 0 ? L.stack[sb + f - 1] : 0u;
+            }
+        }
+        // the value before this lane's first survivor: the previous lane's last
+        // one, else the last surviving tentative, else the last final value
+        const uint32_t mark = n > 0 ? 0x300u | (top & 3u) : 0u;
+        const uint32_t carried = wave_shift_up(0u, wave_prefix_compose(mark));
+        const uint32_t tent_last =
+            ncs > 0 ? (uint32_t)__builtin_amdgcn_readfirstlane((int)L.seq[ncs - 1]) & 3u : last_val;
+        const uint32_t vprev0 = (carried & 0x300u) ? (carried & 3u) : tent_last;
+
+        // ---- final survivors whose value differs from the previous one: the
+        // tentative ones first, then the lanes' in lane order
+        int kt = 0;
+        for (int c0 = 0; c0 < nft; c0 += 64) {
+            const int c = c0 + lane;
+            const bool in = c < nft;
+            const uint32_t kc = in ? L.seq[c] : 0u;
+            const uint32_t vp = c == 0 ? last_val : (in ? (L.seq[c - 1] & 3u) : 0u);
+            const bool keep = in && (kc & 3u) != vp;
+            const uint64_t mask = __ballot(keep);
+            const int64_t at = out_n + kt + lanes_below(mask);
+            if (keep && at < reserved) put<AGENT>(Kar + ob + at, pack_key(base + (int64_t)(kc >> 2), kc & 3u));
+            kt += __popcll(mask);
+        }
+        int kl = 0;
+        {
+            uint32_t vp = vprev0;
+            for (int j = 0; j < f; j++) {
+                const uint32_t k = L.stack[sb + j];
+                kl += (k & 3u) != vp ? 1 : 0;
+                vp = k & 3u;
+            }
+        }
+        const uint32_t kincl = wave_prefix_sum((uint32_t)kl);
+        const int ktot = __builtin_amdgcn_readlane((int)kincl, 63);
+        {
+            uint32_t vp = vprev0;
+            int at = (int)kincl - kl;
+            for (int j = 0; j < f; j++) {
+                const uint32_t k = L.stack[sb + j];
+                if ((k & 3u) != vp) L.tile[at++] = k;  // the tiles are read no more this round
+                vp = k & 3u;
+            }
+        }
+        __syncthreads();
+        for (int j0 = 0; j0 < ktot; j0 += 64) {
+            const int j = j0 + lane;
+            const int64_t at = out_n + kt + j;
+            if (j < ktot && at < reserved) {
+                const uint32_t k = L.tile[j];
+                put<AGENT>(Kar + ob + at, pack_key(base + (int64_t)(k >> 2), k & 3u));
+            }
+        }
+        out_n += kt + ktot;
+        {
+            // the value of the last final survivor
+            const uint32_t fmark = f > 0 ? 0x300u | (L.stack[sb + f - 1] & 3u) : 0u;
+            const uint32_t flast = (uint32_t)__builtin_amdgcn_readlane((int)wave_prefix_compose(fmark), 63);
+            if (flast & 0x300u) last_val = flast & 3u;
+            else if (nft > 0) last_val = (uint32_t)__builtin_amdgcn_readfirstlane((int)L.seq[nft - 1]) & 3u;
+        }
+        // every round takes an input transition or makes a survivor final;
+        // neither means an input waveform is out of order: stop with an error
+        {
+            int taken = 0;
+#pragma unroll
+            for (int p = 0; p < K; p++) taken += m[p];
+            stalled = taken == 0 && nft == 0 && __ballot(f > 0) == 0;
+            if (stalled && lane == 0) J.state->check_error = 4;
+        }
+
+        // ---- the tentative ones, in order, at the front of L.seq
+        const int keep_old = ncs - nft;
+        const int tn = n - f;
+        const uint32_t tincl = wave_prefix_sum((uint32_t)tn);
+        int ntent = keep_old + __builtin_amdgcn_readlane((int)tincl, 63);
+        if (ntent > W) {  // cannot happen when dmax <= W
+            if (lane == 0) J.state->check_error = 1;
+            ntent = W;
+        }
+        {
+            uint32_t rr[W / 64];
+#pragma unroll
+            for (int c = 0; c < W / 64; c++) {
+                const int j = c * 64 + lane;
+                if (j < keep_old) rr[c] = L.seq[nft + j];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < W / 64; c++) {
+                const int j = c * 64 + lane;
+                if (j < keep_old) L.seq[j] = rr[c];
+            }
+            const int d0 = keep_old + (int)tincl - tn;
+            for (int i = 0; i < tn; i++)
+                if (d0 + i < W) L.seq[d0 + i] = L.stack[sb + f + i];
+        }
+        nq = ntent;
+        base_prev = base;
+        first_round = false;
+        state0 = state_next;
+#pragma unroll
+        for (int p = 0; p < K; p++) {
+            cur[p] += m[p];
+            tl[p] = nx[p];
+        }
+        __syncthreads();
+    }
+    if (out_n > reserved) {  // cannot happen: at most one output per distinct input time
+        if (lane == 0) J.state->check_error = 2;
+        out_n = reserved;
+    }
+    if (lane == 0) {
+        put<AGENT>(len + S + gate, out_n);
+        put<AGENT>(off + S + gate, ob);
+    }
+}
+
+// -------------------------------------------------------------------------
 // Lane-per-gate evaluation: the sequential procedure on one lane, with the
 // gate's reserved output region used directly as the list of scheduled
 // transitions (denials pop its tail). Exact for any delay.

@@ -501,6 +501,7 @@ struct gsim_ctx_s {
     int opt_kernel = 0;
     int opt_timing = 0;
     int opt_schedule = 0;
+    int opt_form = kFormSegmented;
     int64_t n_waves_resident = 0;  // persistent wavefronts of the dependency-driven schedule
     int32_t opt_lane_threshold = 0;
 };
@@ -1213,7 +1214,7 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
         HIP_TRY(hipEventCreate(&tm->b));
         HIP_TRY(hipEventRecord(tm->a, s));
     }
-    for (int v = 0; v < kVariants; v++) HIP_TRY(launch_eval_wave(a, v, n_list + wave_list(v, 1), s));
+    for (int v = 0; v < kVariants; v++) HIP_TRY(launch_eval_wave(a, v, n_list + wave_list(v, 1), ctx->opt_form, s));
     HIP_TRY(launch_eval_lane(a, n_lane, s));
     if (tm) HIP_TRY(hipEventRecord(tm->b, s));
     ex->parity ^= 1;
@@ -1268,6 +1269,18 @@ Failure find_job(gsim_ctx ctx, gsim_job id, Job **out) {
     if (it == ctx->jobs.end()) return fail(GSIM_E_HANDLE, "unknown job handle %lld", (long long)id);
     *out = it->second.get();
     return kOk;
+}
+
+// A job a failed call created: freed, and the caller's handle cleared, so the
+// failure leaves nothing behind (a job that could not be admitted would
+// otherwise stay queued).
+void discard_job(gsim_ctx ctx, gsim_job *out) {
+    auto it = ctx->jobs.find(*out);
+    if (it != ctx->jobs.end()) {
+        destroy_job(ctx, it->second.get());
+        ctx->jobs.erase(it);
+    }
+    *out = 0;
 }
 
 constexpr int kMaxRetries = 6;
@@ -1665,6 +1678,10 @@ gsim_status sim_set_option(gsim_ctx ctx, int option, int64_t value) try {
         if (value < 0 || value > 2) return record(ctx, fail(GSIM_E_ARG, "schedule option must be 0, 1 or 2"));
         ctx->opt_schedule = (int)value;
         return GSIM_OK;
+    case GSIM_OPT_EVAL_FORM:
+        if (value < 0 || value > 1) return record(ctx, fail(GSIM_E_ARG, "evaluation form must be 0 or 1"));
+        ctx->opt_form = (int)value;
+        return GSIM_OK;
     }
     return record(ctx, fail(GSIM_E_ARG, "unknown option %d", option));
 } catch (...) {
@@ -1779,6 +1796,7 @@ gsim_status sim_run(gsim_ctx ctx, gsim_netlist nl, const int64_t *src_off, const
     Job *j = nullptr;
     Failure f = find_job(ctx, *out, &j);
     if (f.st == GSIM_OK) f = drive_until_enqueued(ctx, j);
+    if (f.st != GSIM_OK) discard_job(ctx, out);
     return record(ctx, f);
 } catch (...) {
     return exception_status(ctx);
@@ -1792,6 +1810,7 @@ gsim_status sim_run_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_o
     Job *j = nullptr;
     Failure f = find_job(ctx, *out, &j);
     if (f.st == GSIM_OK) f = drive_until_enqueued(ctx, j);
+    if (f.st != GSIM_OK) discard_job(ctx, out);
     return record(ctx, f);
 } catch (...) {
     return exception_status(ctx);

@@ -152,7 +152,9 @@ hipError_t launch_size(const StepArgs &a, hipStream_t s);
 // evaluate the work list of class `cls`; `max_items` bounds the list length
 // Wavefront kernel over the four pin-count lists of one delay window
 // (max_items[k-1]: upper bound of the k-pin list's length).
-hipError_t launch_eval_wave(const StepArgs &a, int variant, const int64_t *max_items,
+// form: kFormSegmented (eval_gate_seg) or kFormMerged (eval_gate).
+constexpr int kFormSegmented = 0, kFormMerged = 1;
+hipError_t launch_eval_wave(const StepArgs &a, int variant, const int64_t *max_items, int form,
                             hipStream_t s);
 // Per job of the step: its level's arena bases (exclusive scan of the sizing
 // blocks' totals, arena top bumped, overflow flagged); then the counting-sort

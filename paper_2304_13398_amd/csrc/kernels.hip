@@ -272,6 +272,38 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W == 64 ? 6 
     }
 }
 
+// The same lists with the segmented form (eval_gate_seg): five wavefronts per
+// SIMD (the LDS limit: 6.9 KB per wavefront for the 64 ps window, 7.7 KB for
+// 256).
+template <int W, bool EDGE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void eval_seg_kernel(StepArgs A,
+                                                                                             int var) {
+    __shared__ SegLds<W> L;
+    const int lane = lane_id();
+    const int64_t item = blockIdx.x;
+    const int list0 = var * 4;
+    const int64_t total = (int64_t)A.count[list0] + A.count[list0 + 1] + A.count[list0 + 2] +
+                          A.count[list0 + 3];
+    if (item >= total) return;
+    const uint64_t e = A.sorted[var][item];
+    const JobDesc &J = A.jobs[(int)(e >> 32)];
+    const int64_t gate = (int64_t)(uint32_t)e;
+    const GateRec R = J.rec[gate];
+    if (J.state->overflow) {
+        if (lane == 0) { J.len[J.S + gate] = 0; J.off[J.S + gate] = 0; }
+        return;
+    }
+    reinterpret_cast<uint32_t *>(L.lut)[lane] =
+        reinterpret_cast<const uint32_t *>(J.lut + (int)R.type * 256)[lane];
+    const int64_t ob = A.blocksum[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + J.off[J.S + gate];
+    switch (R.k) {
+    case 1: eval_gate_seg<1, W, EDGE, false>(J, ob, R, gate, L); break;
+    case 2: eval_gate_seg<2, W, EDGE, false>(J, ob, R, gate, L); break;
+    case 3: eval_gate_seg<3, W, EDGE, false>(J, ob, R, gate, L); break;
+    default: eval_gate_seg<4, W, EDGE, false>(J, ob, R, gate, L); break;
+    }
+}
+
 __global__ __launch_bounds__(64) void eval_lane_kernel(StepArgs A) {
     const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (item >= (int64_t)A.count[kListLane]) return;
@@ -593,11 +625,20 @@ hipError_t launch_size(const StepArgs &a, hipStream_t s) {
 }
 
 
-hipError_t launch_eval_wave(const StepArgs &a, int variant, const int64_t *max_items,
+hipError_t launch_eval_wave(const StepArgs &a, int variant, const int64_t *max_items, int form,
                             hipStream_t s) {
     const int64_t total = max_items[0] + max_items[1] + max_items[2] + max_items[3];
     if (total <= 0) return hipSuccess;
     const dim3 grid((unsigned)total), block(64);
+    if (form == kFormSegmented) {
+        switch (variant) {
+        case wave_variant(0, 0): eval_seg_kernel<kWindowSmall, false><<<grid, block, 0, s>>>(a, variant); break;
+        case wave_variant(1, 0): eval_seg_kernel<kWindowLarge, false><<<grid, block, 0, s>>>(a, variant); break;
+        case wave_variant(0, 1): eval_seg_kernel<kWindowSmall, true><<<grid, block, 0, s>>>(a, variant); break;
+        default: eval_seg_kernel<kWindowLarge, true><<<grid, block, 0, s>>>(a, variant); break;
+        }
+        return hipGetLastError();
+    }
     switch (variant) {
     case wave_variant(0, 0): eval_wave_kernel<kWindowSmall, false><<<grid, block, 0, s>>>(a, variant); break;
     case wave_variant(1, 0): eval_wave_kernel<kWindowLarge, false><<<grid, block, 0, s>>>(a, variant); break;

@@ -18,7 +18,9 @@
 // out.bin: int64 out_off[n_eval+1]; uint64 out_keys[]; int32 err[n_eval].
 // Modes: 0 level kernel's form; 1 dependency-driven kernel's form; 2 the
 // dependency-driven form with the level kernel's shorter tile and
-// trailing-group code; 3 the level kernel's form without that shorter code.
+// trailing-group code; 3 the level kernel's form without that shorter code;
+// 4 the segmented form (eval_gate_seg) as the level kernel runs it; 5 the
+// segmented form as the dependency-driven kernel runs it.
 #include <sys/mman.h>
 
 #include <cstdarg>
@@ -227,9 +229,29 @@ void (*pick(int k))(void *) {
     }
 }
 
+template <int K, int W, bool EDGE, bool AGENT>
+void seg_body(void *p) {
+    Task &t = *(Task *)p;
+    SegLds<W> &L = *(SegLds<W> *)t.L;
+    reinterpret_cast<uint32_t *>(L.lut)[lane_id()] = reinterpret_cast<const uint32_t *>(t.lut)[lane_id()];
+    eval_gate_seg<K, W, EDGE, AGENT>(*t.J, t.ob, *t.R, t.gate, L);
+}
+
+template <int W, bool EDGE, bool AGENT>
+void (*pick_seg(int k))(void *) {
+    switch (k) {
+    case 1: return seg_body<1, W, EDGE, AGENT>;
+    case 2: return seg_body<2, W, EDGE, AGENT>;
+    case 3: return seg_body<3, W, EDGE, AGENT>;
+    default: return seg_body<4, W, EDGE, AGENT>;
+    }
+}
+
 template <bool EDGE>
 void (*variant(int mode, int window, int k))(void *) {
     switch (mode) {
+    case 4: return window == 64 ? pick_seg<64, EDGE, false>(k) : pick_seg<256, EDGE, false>(k);
+    case 5: return pick_seg<256, EDGE, true>(k);
     case 0: return window == 64 ? pick<64, EDGE, true, true, false>(k) : pick<256, EDGE, true, true, false>(k);
     case 1: return pick<256, EDGE, false, false, true>(k);
     case 2: return pick<256, EDGE, false, true, true>(k);
@@ -306,8 +328,9 @@ int main(int argc, char **argv) {
     auto rel = [&](const uint64_t *p) { return (int64_t)(((intptr_t)p - (intptr_t)base) / 8); };
 
     std::mt19937_64 rng(12345);
-    std::vector<uint8_t> lds(sizeof(WaveLds<kWindowLarge>) > sizeof(WaveLds<kWindowSmall>)
-                                 ? sizeof(WaveLds<kWindowLarge>) : sizeof(WaveLds<kWindowSmall>));
+    size_t lds_bytes = sizeof(WaveLds<kWindowLarge>);
+    lds_bytes = std::max(lds_bytes, sizeof(SegLds<kWindowLarge>));
+    std::vector<uint8_t> lds(lds_bytes);
     std::vector<int64_t> out_off(1, 0);
     std::vector<uint64_t> out_keys;
     std::vector<int32_t> err((size_t)n_eval, 0);
@@ -353,7 +376,8 @@ int main(int argc, char **argv) {
         for (auto &x : lds) x = (uint8_t)rng();
         Task t{&J, ob, &R, g, lds.data(), lut.data() + (size_t)R.type * 256};
         const int window = dmax <= kWindowSmall ? 64 : 256;
-        const bool wave_gate = mode == 0 || mode == 3 ? dmax <= kWindowLarge : dmax <= kWindowLarge;
+        const bool wave_gate = dmax <= kWindowLarge;
+        const bool level_form = mode == 0 || mode == 3 || mode == 4;
         std::string msg;
         if (wave_gate) {
             void (*body)(void *) = has_edge ? variant<true>((int)mode, window, R.k)
@@ -362,7 +386,7 @@ int main(int argc, char **argv) {
             if (emu::wave().failed) msg = emu::wave().msg;
         } else {
             emu::wave().lane = 0;
-            if (mode == 0 || mode == 3)
+            if (level_form)
                 eval_seq<false>(J, R, g, ob, lut.data() + (size_t)R.type * 256);
             else
                 eval_seq<true>(J, R, g, ob, lut.data() + (size_t)R.type * 256);

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2304_13398_amd", "csrc")
 BUILD = os.path.join(HERE, "_build")
 
-MODES = {"levels": 0, "dataflow": 1, "dataflow_lean": 2, "levels_long": 3}
+MODES = {"levels": 0, "dataflow": 1, "dataflow_lean": 2, "levels_long": 3, "seg": 4, "seg_dataflow": 5}
 
 
 def build(asan: bool = False) -> str:

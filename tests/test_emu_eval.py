@@ -10,8 +10,11 @@ Each gate gets the oracle's waveforms of its input nets, so the comparison is
 of the per-gate procedure alone (Algorithm 2 with Eq. 1 and the Fig. 3 drop),
 independent of the schedule that feeds it.
 
-Forms: "levels" (the level kernel: tiles prefetched, shorter tile and
-trailing-group code), "dataflow" (the dependency-driven kernel), and
+Forms: "seg" and "seg_dataflow" (the segmented form, eval_gate_seg, as the
+level and the dependency-driven kernels run it), "levels" (the merged form
+of the level kernel: tiles prefetched, shorter tile and trailing-group code),
+"levels_long" (that form without the shorter code), "dataflow" (the merged
+form of the dependency-driven kernel), and
 "dataflow_lean" (the dependency-driven kernel with the level kernel's shorter
 code, a form withdrawn after one GPU run of the 20k-gate extended-model case
 did not finish). No GPU is used.
@@ -44,7 +47,7 @@ def tiny():
     return nl, st, O.o1_simulate(nl, st), E.builtin_lut(O.gate_eval)
 
 
-@pytest.mark.parametrize("mode", ["levels", "dataflow", "dataflow_lean", "levels_long"])
+@pytest.mark.parametrize("mode", ["seg", "seg_dataflow", "levels", "dataflow", "dataflow_lean", "levels_long"])
 def test_tiny_every_gate(tiny, mode):
     nl, st, want, lut = tiny
     gates = np.arange(nl.G)
@@ -57,9 +60,10 @@ def test_tiny_under_address_sanitizer(tiny):
     read or write outside them is reported."""
     nl, st, want, lut = tiny
     gates = np.arange(0, nl.G, 3)
-    got, err, log = E.run("levels", nl, st, want, lut, gates=gates, max_ops=MAX_OPS, asan=True)
-    assert "AddressSanitizer" not in log
-    compare(got, err, want, gates)
+    for mode in ("seg", "levels"):
+        got, err, log = E.run(mode, nl, st, want, lut, gates=gates, max_ops=MAX_OPS, asan=True)
+        assert "AddressSanitizer" not in log
+        compare(got, err, want, gates)
 
 
 def test_a_wrong_table_entry_is_seen(tiny):
@@ -86,12 +90,12 @@ def edge_mid():
     return nl, st, dly, want, lut
 
 
-@pytest.mark.parametrize("mode", ["dataflow_lean", "dataflow", "levels"])
+@pytest.mark.parametrize("mode", ["dataflow_lean", "seg", "dataflow", "levels"])
 def test_edge_model_mid_generator(edge_mid, mode):
-    """Every gate in the withdrawn form; a third of them in the two forms in
-    use."""
+    """Every gate in the withdrawn form and in the segmented form; a third of
+    them in the two merged forms in use."""
     nl, st, dly, want, lut = edge_mid
-    gates = np.arange(nl.G) if mode == "dataflow_lean" else np.arange(0, nl.G, 3)
+    gates = np.arange(nl.G) if mode in ("dataflow_lean", "seg") else np.arange(0, nl.G, 3)
     got, err, _ = E.run(mode, nl, st, want, lut, gates=gates, dly=dly, max_ops=MAX_OPS)
     compare(got, err, want, gates)
 
@@ -105,6 +109,6 @@ def test_wide_delays_xz_sources():
     nl = W.with_types(nl, type_)
     want = O.o1x_simulate(nl, st, dly, udp)
     lut = np.concatenate([E.builtin_lut(O.gate_eval), udp])
-    for mode in ("levels", "dataflow"):
+    for mode in ("seg", "seg_dataflow", "levels", "dataflow"):
         got, err, _ = E.run(mode, nl, st, want, lut, dly=dly, max_ops=MAX_OPS)
         compare(got, err, want, np.arange(nl.G))
