@@ -261,6 +261,42 @@ gsim_status sim_run_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_o
                            const int64_t *d_t, const uint8_t *d_v, int64_t n_in, int validate,
                            void *hip_stream, gsim_job *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the level
+ * schedule of sim_run_device over buffers the caller supplies, allocating
+ * nothing. Every step buffer (job state, step counters, work lists, level
+ * descriptors) lives in a static device array of 32 MiB per GPU that the
+ * library holds until the process ends; a netlist whose largest level needs
+ * more than that (about 30 bytes per gate of its largest level, plus 96 bytes
+ * per level) is refused with GSIM_E_ARG. Every call on a GPU shares that
+ * array, so calls that overlap on one GPU (several streams, several host
+ * threads) race and give undefined results; calls in one stream are ordered.
+ * Asynchronous on `hip_stream` (NULL = the context's stream): returns after
+ * enqueueing; the results are valid once the stream reaches them.
+ *   d_src_off, d_t, d_v, n_in  the source waveforms in device memory, as
+ *                   sim_run_device (not validated; the caller guarantees the
+ *                   waveform conventions)
+ *   d_off, d_len    [S+G] device int64: each net's offset into d_arena and
+ *                   transition count, indexed by the library's net order
+ *                   (sim_netlist_net_order gives the index of each net)
+ *   d_arena         [arena_cap] device uint64: every waveform, sources first,
+ *                   each transition packed as time << 2 | value
+ *   d_result        [4] device int64: output transitions over all gates, 1 if
+ *                   d_arena overflowed (results then incomplete: call again with
+ *                   more), the device check code (0 = none), and the arena
+ *                   transitions used
+ * All buffers stay the caller's. Errors (nothing is enqueued): GSIM_E_ARG,
+ * GSIM_E_HANDLE, GSIM_E_DEVICE. */
+gsim_status sim_run_device_noalloc(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_off,
+                                   const int64_t *d_t, const uint8_t *d_v, int64_t n_in, int64_t *d_off,
+                                   int64_t *d_len, uint64_t *d_arena, int64_t arena_cap, int64_t *d_result,
+                                   void *hip_stream);
+
+/* No passage (plumbing for sim_run_device_noalloc): net_index[S+G] receives,
+ * for every net id of the caller (sources, then gate g's net S + g), its index
+ * in the library's net order (gates are stored level by level). Host only. */
+gsim_status sim_netlist_net_order(gsim_ctx ctx, gsim_netlist nl, int64_t *net_index);
+
 /* No passage of the paper: several independent re-simulations of one
  * netlist share launches (the paper runs one task at a time).
  * Batched execution of `n_sets` stimulus sets over one resident netlist:

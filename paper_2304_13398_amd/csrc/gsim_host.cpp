@@ -1337,6 +1337,120 @@ Failure wait_job(gsim_ctx ctx, Job *j) {
     return kOk;
 }
 
+// ---- the no-allocation run ---------------------------------------------------------
+
+// Where each step buffer of a level-by-level run of `nl` sits in the static
+// scratch array (byte offsets): the job state, the two step-counter halves,
+// the partial sums of the output count, one descriptor per level, the sizing
+// block sums, and the work lists, keys and sorted lists, each sized for the
+// largest level (the lane list for every gate of a level when a lane
+// threshold may move gates there).
+struct NoAllocLayout {
+    size_t state = 0, counts = 0, partial = 0, desc = 0, blocksum = 0;
+    size_t list[kNumLists] = {}, key[kListLane] = {}, sorted[kVariants] = {};
+    size_t total = 0;
+    int64_t n_partial = 0;
+};
+
+NoAllocLayout noalloc_layout(const Netlist &nl, int32_t lane_threshold) {
+    int64_t cap[kNumLists] = {}, scap[kVariants] = {};
+    for (const LevelRange &r : nl.levels) {
+        for (int c = 0; c < kNumLists; c++) cap[c] = std::max(cap[c], r.n_list[c]);
+        for (int v = 0; v < kVariants; v++) {
+            int64_t n = 0;
+            for (int k = 1; k <= 4; k++) n += r.n_list[wave_list(v, k)];
+            scap[v] = std::max(scap[v], n);
+        }
+    }
+    if (lane_threshold > 0) cap[kListLane] = nl.max_level_n;
+    NoAllocLayout L;
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        const size_t here = at;
+        at += (bytes + 255) / 256 * 256;
+        return here;
+    };
+    L.n_partial = std::max<int64_t>(1, std::min<int64_t>(1024, (nl.G + 255) / 256));
+    L.state = take(sizeof(DevState));
+    L.counts = take(sizeof(uint32_t) * 2 * kCountWords);
+    L.partial = take(sizeof(int64_t) * (size_t)L.n_partial);
+    L.desc = take(sizeof(JobDesc) * (size_t)nl.n_levels);
+    L.blocksum = take(sizeof(int64_t) * (size_t)((nl.max_level_n + kSizeBlock - 1) / kSizeBlock));
+    for (int c = 0; c < kNumLists; c++) L.list[c] = take(sizeof(uint64_t) * (size_t)cap[c]);
+    for (int c = 0; c < kListLane; c++) L.key[c] = take(sizeof(uint64_t) * (size_t)cap[c]);
+    for (int v = 0; v < kVariants; v++) L.sorted[v] = take(sizeof(uint64_t) * (size_t)scap[v]);
+    L.total = at;
+    return L;
+}
+
+// Every level of `nl` over the caller's buffers and the scratch array, on
+// stream `s`, in the launches of the level schedule. Allocates nothing.
+Failure run_noalloc(gsim_ctx ctx, const Netlist &nl, const int64_t *d_src_off, const int64_t *d_t,
+                    const uint8_t *d_v, int64_t n_in, int64_t *d_off, int64_t *d_len, uint64_t *d_arena,
+                    int64_t arena_cap, int64_t *d_result, hipStream_t s) {
+    uint8_t *base = (uint8_t *)noalloc_scratch(ctx->device);
+    if (!base) return fail(GSIM_E_DEVICE, "the no-allocation scratch of device %d was not set up", ctx->device);
+    const int32_t thr = nl.lane_threshold >= 0 ? nl.lane_threshold : ctx->opt_lane_threshold;
+    const NoAllocLayout L = noalloc_layout(nl, thr);
+    if (L.total > kNoAllocScratchBytes)
+        return fail(GSIM_E_ARG,
+                    "the netlist needs %llu bytes of step scratch (largest level %lld gates, %d levels); "
+                    "the no-allocation entry point holds %llu: use sim_run_device",
+                    (unsigned long long)L.total, (long long)nl.max_level_n, (int)nl.n_levels,
+                    (unsigned long long)kNoAllocScratchBytes);
+    DevState *state = (DevState *)(base + L.state);
+    uint32_t *counts = (uint32_t *)(base + L.counts);
+    JobDesc *desc = (JobDesc *)(base + L.desc);
+    HIP_TRY(launch_clear_u32(counts, 2 * kCountWords, s));
+    HIP_TRY(launch_init_sources(d_src_off, d_t, d_v, nl.S, n_in, d_off, d_len, d_arena, state, arena_cap, s));
+    for (int32_t l0 = 0; l0 < nl.n_levels; l0 += kDescBatch) {
+        DescBatch b;
+        std::memset(&b, 0, sizeof b);
+        b.n = std::min<int32_t>(kDescBatch, nl.n_levels - l0);
+        b.dst = desc + l0;
+        for (int32_t i = 0; i < b.n; i++) {
+            const LevelRange &r = nl.levels[l0 + i];
+            JobDesc &d = b.d[i];
+            d.rec = nl.d_rec;
+            d.S = nl.S;
+            d.off = d_off;
+            d.len = d_len;
+            d.K = d_arena;
+            d.state = state;
+            d.lvl_begin = r.begin;
+            d.n_gates = r.n;
+            d.sblock_begin = 0;
+            d.lane_threshold = thr;
+            d.lut = nl.d_lut ? nl.d_lut : ctx->d_lut;
+            d.edly = nl.d_edly;
+        }
+        HIP_TRY(launch_write_descs(b, s));
+    }
+    for (int32_t l = 0; l < nl.n_levels; l++) {
+        const LevelRange &r = nl.levels[l];
+        StepArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.jobs = desc + l;
+        a.n_jobs = 1;
+        a.n_sblocks = (r.n + kSizeBlock - 1) / kSizeBlock;
+        a.blocksum = (int64_t *)(base + L.blocksum);
+        for (int c = 0; c < kNumLists; c++) a.list[c] = (uint64_t *)(base + L.list[c]);
+        for (int c = 0; c < kListLane; c++) a.key[c] = (uint64_t *)(base + L.key[c]);
+        for (int v = 0; v < kVariants; v++) a.sorted[v] = (uint64_t *)(base + L.sorted[v]);
+        a.count = counts + (l & 1) * kCountWords;
+        a.next_count = counts + (1 - (l & 1)) * kCountWords;
+        const int64_t n_lane = thr > 0 ? r.n : r.n_list[kListLane];
+        HIP_TRY(launch_size(a, s));
+        HIP_TRY(launch_sort_lists(a, r.n_list, s));
+        for (int v = 0; v < kVariants; v++)
+            HIP_TRY(launch_eval_wave(a, v, r.n_list + wave_list(v, 1), ctx->opt_form, s));
+        HIP_TRY(launch_eval_lane(a, n_lane, s));
+    }
+    HIP_TRY(launch_count_out(d_len, nl.S, nl.G, (int64_t *)(base + L.partial), L.n_partial, state, s));
+    HIP_TRY(launch_run_result(state, d_result, s));
+    return kOk;
+}
+
 // Internal ids of the requested nets (all nets in id order when nets is null).
 Failure internal_ids(const Netlist &nl, const int64_t *nets, int64_t n, std::vector<int64_t> &ids) {
     const int64_t N = nl.S + nl.G;
@@ -1626,6 +1740,9 @@ gsim_status sim_create(int device, uint64_t hbm_budget_bytes, gsim_ctx *out) try
     if (!ctx->d_lut) return give_up(GSIM_E_OOM, "no device memory for the gate table");
     if (hipMemcpy(ctx->d_lut, lut.data(), lut.size(), hipMemcpyHostToDevice) != hipSuccess)
         return give_up(GSIM_E_DEVICE, "gate table upload failed");
+    // the no-allocation entry point's scratch on this device: its address is
+    // looked up once here (sim_run_device_noalloc reports a failure)
+    if (noalloc_scratch_setup(device) != hipSuccess) (void)hipGetLastError();
     *out = ctx.release();
     return GSIM_OK;
 } catch (...) {
@@ -1812,6 +1929,41 @@ gsim_status sim_run_device(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_o
     if (f.st == GSIM_OK) f = drive_until_enqueued(ctx, j);
     if (f.st != GSIM_OK) discard_job(ctx, out);
     return record(ctx, f);
+} catch (...) {
+    return exception_status(ctx);
+}
+
+gsim_status sim_run_device_noalloc(gsim_ctx ctx, gsim_netlist nl, const int64_t *d_src_off,
+                                   const int64_t *d_t, const uint8_t *d_v, int64_t n_in, int64_t *d_off,
+                                   int64_t *d_len, uint64_t *d_arena, int64_t arena_cap, int64_t *d_result,
+                                   void *hip_stream) try {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    auto it = ctx->netlists.find(nl);
+    if (it == ctx->netlists.end()) return record(ctx, fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nl));
+    const Netlist &n = *it->second;
+    if (!d_src_off || !d_off || !d_len || !d_arena || !d_result || (n_in > 0 && (!d_t || !d_v)))
+        return record(ctx, fail(GSIM_E_ARG, "null device buffer"));
+    if (n_in < 0 || arena_cap < n_in)
+        return record(ctx, fail(GSIM_E_ARG, "n_in = %lld with arena_cap = %lld (need 0 <= n_in <= arena_cap)",
+                                (long long)n_in, (long long)arena_cap));
+    Failure f = set_device(ctx);
+    if (f.st == GSIM_OK)
+        f = run_noalloc(ctx, n, d_src_off, d_t, d_v, n_in, d_off, d_len, d_arena, arena_cap, d_result,
+                        hip_stream ? (hipStream_t)hip_stream : ctx->stream);
+    return record(ctx, f);
+} catch (...) {
+    return exception_status(ctx);
+}
+
+gsim_status sim_netlist_net_order(gsim_ctx ctx, gsim_netlist nl, int64_t *net_index) try {
+    if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
+    auto it = ctx->netlists.find(nl);
+    if (it == ctx->netlists.end()) return record(ctx, fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nl));
+    if (!net_index) return record(ctx, fail(GSIM_E_ARG, "null output"));
+    const Netlist &n = *it->second;
+    for (int64_t i = 0; i < n.S; i++) net_index[i] = i;
+    for (int64_t g = 0; g < n.G; g++) net_index[n.S + g] = n.S + n.internal_of_user[g];
+    return GSIM_OK;
 } catch (...) {
     return exception_status(ctx);
 }

@@ -178,4 +178,24 @@ hipError_t launch_hash(const int64_t *nets_off, const int64_t *nets_len, int64_t
 hipError_t launch_gather_meta(const int64_t *net, int64_t n, const int64_t *off, const int64_t *len,
                               int64_t *out_off, int64_t *out_len, hipStream_t s);
 
+// No-allocation run (sim_run_device_noalloc): a static device array of
+// kNoAllocScratchBytes per GPU holds every step buffer of the level schedule.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+// Look up `device`'s copy of the array (with that device current); once per
+// device, at context creation.
+hipError_t noalloc_scratch_setup(int device);
+// Its device address, or null before the set-up succeeded on that device.
+void *noalloc_scratch(int device);
+// Step descriptors of up to kDescBatch levels, written to dst[0, n) by one launch.
+constexpr int kDescBatch = 32;
+struct DescBatch {
+    JobDesc d[kDescBatch];
+    JobDesc *dst;
+    int32_t n;
+    int32_t pad;
+};
+hipError_t launch_write_descs(const DescBatch &b, hipStream_t s);
+// out[0..3] = n_out, overflow flag, check code, arena transitions used
+hipError_t launch_run_result(const DevState *st, int64_t *out, hipStream_t s);
+
 }  // namespace gsim

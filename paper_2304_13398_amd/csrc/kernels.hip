@@ -15,6 +15,8 @@
 // Transitions live in the arena packed as time << 2 | value (8 bytes).
 #include "eval_core.h"
 
+#include <mutex>
+
 namespace gsim {
 
 namespace {
@@ -602,7 +604,56 @@ __global__ __launch_bounds__(256) void gather_kernel(const int64_t *__restrict__
     }
 }
 
+// -------------------------------------------------------------------------
+// No-allocation run: the step descriptors of a batch of levels, written from
+// the kernel argument into the scratch table; the job's outcome copied to
+// the caller's result words.
+__global__ void write_descs_kernel(DescBatch b) {
+    const int i = threadIdx.x;
+    if (i < b.n) b.dst[i] = b.d[i];
+}
+
+__global__ void run_result_kernel(const DevState *__restrict__ st, int64_t *__restrict__ out) {
+    if (threadIdx.x == 0) {
+        out[0] = st->n_out;
+        out[1] = st->overflow;
+        out[2] = st->check_error;
+        out[3] = st->arena_top;
+    }
+}
+
 }  // namespace
+
+// -------------------------------------------------------------------------
+// Device scratch of the no-allocation entry point: one array per GPU, held
+// until the process ends, shared by every call on that GPU. The host-side
+// name `scratch` is not a device address and is never passed to a kernel:
+// set-up looks up each device's address once (noalloc_scratch_setup, with
+// that device current) and launches use that address.
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_at[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_at[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_at[device] = p;
+    return hipSuccess;
+}
+
+void *noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_at[device];
+}
 
 // -------------------------------------------------------------------------
 // Launchers.
@@ -719,6 +770,17 @@ hipError_t launch_gather(const int64_t *src_off, const int64_t *n_items, const i
     const int64_t nb = n_nets < 65536 ? n_nets : 65536;
     gather_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(src_off, n_items, dst_off, n_nets, K,
                                                           out_t, out_v);
+    return hipGetLastError();
+}
+
+hipError_t launch_write_descs(const DescBatch &b, hipStream_t s) {
+    if (b.n <= 0) return hipSuccess;
+    write_descs_kernel<<<dim3(1), dim3(kDescBatch), 0, s>>>(b);
+    return hipGetLastError();
+}
+
+hipError_t launch_run_result(const DevState *st, int64_t *out, hipStream_t s) {
+    run_result_kernel<<<dim3(1), dim3(64), 0, s>>>(st, out);
     return hipGetLastError();
 }
 

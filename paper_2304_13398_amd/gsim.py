@@ -31,7 +31,7 @@ EXPORTED = ("sim_create", "sim_destroy", "sim_last_error", "sim_set_option", "si
             "sim_unload_netlist", "sim_set_netlist_option", "sim_netlist_info", "sim_memory_info", "sim_submit", "sim_submit_device", "sim_run",
             "sim_run_device", "sim_run_batch", "sim_drive", "sim_job_done", "sim_wait",
             "sim_job_stats", "sim_fetch_waveforms", "sim_fetch_hashes", "sim_release_job", "sim_levelize",
-            "sim_validate_stimulus", "sim_version")
+            "sim_validate_stimulus", "sim_version", "sim_run_device_noalloc", "sim_netlist_net_order")
 
 
 class GsimError(RuntimeError):
@@ -104,6 +104,8 @@ def load_library(path: str = LIB_PATH):
         "sim_levelize": ([i64, i64, P, P, P, P, P, P, P], st),
         "sim_validate_stimulus": ([i64, P, P, P, i64], st),
         "sim_version": ([], ctypes.c_char_p),
+        "sim_run_device_noalloc": ([P, i64, P, P, P, i64, P, P, P, i64, P, P], st),
+        "sim_netlist_net_order": ([P, i64, P], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -239,6 +241,23 @@ class Sim:
                                          ctypes.byref(j)))
         self._job_nets[j.value] = self._nl_nets.get(h, 0)
         return j.value
+
+    def run_device_noalloc(self, h: int, d_src_off: int, d_t: int, d_v: int, n_in: int, d_off: int,
+                           d_len: int, d_arena: int, arena_cap: int, d_result: int,
+                           stream: int | None = None):
+        """The allocation-free run over caller-owned device buffers (raw device
+        pointers); asynchronous on `stream`."""
+        self._ck(self.lib.sim_run_device_noalloc(
+            self.ctx, h, ctypes.c_void_p(d_src_off), ctypes.c_void_p(d_t), ctypes.c_void_p(d_v), n_in,
+            ctypes.c_void_p(d_off), ctypes.c_void_p(d_len), ctypes.c_void_p(d_arena), arena_cap,
+            ctypes.c_void_p(d_result), ctypes.c_void_p(stream) if stream else None))
+
+    def net_order(self, h: int) -> np.ndarray:
+        """Index of every net (caller's ids) in the library's net order."""
+        n = self.netlist_info(h)
+        out = np.empty(n.S + n.G, dtype=np.int64)
+        self._ck(self.lib.sim_netlist_net_order(self.ctx, h, _p(out)))
+        return out
 
     def submit(self, h: int, st, stream: int | None = None) -> int:
         """Queue a job over host-resident stimuli (nothing runs until driven)."""
