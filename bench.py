@@ -81,8 +81,10 @@ def parse():
                     help="only the timed industrial steps (for profiler runs)")
     ap.add_argument("--mid-only", action="store_true",
                     help="only the timed mid-size steps (for profiler runs)")
-    ap.add_argument("--eval-form", choices=("segmented", "merged"), default="segmented",
+    ap.add_argument("--eval-form", choices=("segmented", "merged"), default="merged",
                     help="data-parallel form of the wavefront-per-gate kernel (same results)")
+    ap.add_argument("--schedule", choices=("levels", "dataflow"), default="levels",
+                    help="schedule of the --mid-only job")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mid", action="store_true", help="skip the 1M-gate mid-size sections")
     ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-configuration latency")
@@ -585,7 +587,8 @@ def bench_batched(G, sim, nl, h, n_sets, seed):
     transitions per PI log-uniform in [50, 5000] (the sets the full-size
     parity test checks); all sets through the executor (shared launches,
     admitted as HBM allows, largest sets first) vs one set per launch chain.
-    The lane threshold is autotuned on a sample set first."""
+    The schedule, evaluation form and lane threshold are autotuned on a
+    sample set first."""
     from paper_2304_13398_amd import autotune
     from paper_2304_13398_amd import workloads as W
     t = time.perf_counter()
@@ -594,9 +597,9 @@ def bench_batched(G, sim, nl, h, n_sets, seed):
     ns = np.array([a[1] for a in set_args])
     say(f"batched: {n_sets} sets generated in {time.perf_counter() - t:.1f}s "
         f"({sum(x.n for x in sets)} transitions)")
-    tuner = autotune.Autotuner(sim, candidates=(0, 64, 192, 512), reps=1)
+    tuner = autotune.Autotuner(sim, reps=1)
     median = sets[int(np.argsort(ns)[len(ns) // 2])]
-    thr, tms = tuner.tune(nl, h, median)
+    setting, tms = tuner.tune(nl, h, median)
 
     def one_per_launch():
         t0 = time.perf_counter()
@@ -643,7 +646,7 @@ def bench_batched(G, sim, nl, h, n_sets, seed):
         "batched_transitions_per_s": n2 / t2, "batched_s": t2,
         "one_per_launch_transitions_per_s": n1 / t1, "one_per_launch_s": t1,
         "speedup": t1 / t2,
-        "tuned_lane_threshold": thr, "tuning_ms": tms, "batched_diagnostics": diag,
+        "tuned_setting": autotune.setting_name(setting), "tuning_device_ms": tms, "batched_diagnostics": diag,
         "lookahead_steps": BATCH_LOOKAHEAD,
         "includes": "stimulus upload (pageable H2D), all levels, per-set completion wait",
     }
@@ -667,10 +670,14 @@ def bench_served(G, sim, rates, seed, seconds, full):
     pool = [stims[per * k:per * k + per] for k in range(len(nls))]
     hs = [sim.load_netlist(nl) for nl in nls]
     say(f"served: netlists and stimuli ready in {time.perf_counter() - t:.1f}s")
-    tuner = autotune.Autotuner(sim, candidates=(0, 64, 192, 512), reps=1)
+    # the request loop shares level steps across requests: the tuner chooses
+    # among level-schedule settings only
+    tuner = autotune.Autotuner(sim, reps=1, candidates=[c for c in autotune.CANDIDATES
+                                                        if c[0] == G.SCHEDULE_LEVELS])
     tuned = []
     for nl, h, p in zip(nls, hs, pool):
-        tuned.append(tuner.tune(nl, h, sorted(p, key=lambda x: x.n)[len(p) // 2])[0])
+        c, _ = tuner.tune(nl, h, sorted(p, key=lambda x: x.n)[len(p) // 2])
+        tuned.append(autotune.setting_name(c))
         big = max(p, key=lambda x: x.n)
         j = sim.run(h, big)          # learn the arena use of the largest request
         sim.wait(j)
@@ -679,7 +686,7 @@ def bench_served(G, sim, rates, seed, seconds, full):
                        "requests uniform over netlists, 20-2,000 transitions per PI (log-uniform), "
                        "Poisson arrivals; each request fetches its deepest level's waveforms and "
                        "every net's fingerprint",
-           "tuned_lane_thresholds": tuned, "rates": {}}
+           "tuned_settings": tuned, "rates": {}}
     for rate in rates:
         n_jobs = 1000 if full else int(min(1000, max(100, rate * seconds)))
         reqs = serve.served_workload(n_jobs, rate, nls, pool, seed=seed + int(rate))
@@ -729,6 +736,8 @@ def main():
     eq6 = {}
 
     if args.mid_only:
+        if args.schedule == "dataflow":
+            sim.set_option(G.OPT_SCHEDULE, 1)
         nl, st = W.config2(seed=args.seed)
         h, d, res, _ = timed_job(G, sim, nl, st, args.steps, args.warmup, "mid", "mid")
         print(json.dumps({"mid": res}), flush=True)

@@ -107,12 +107,12 @@ enum gsim_option {
      * workload WCV, Eq. 5) of at least 2.5; level by level otherwise.
      * Results are identical under every setting. */
     GSIM_OPT_SCHEDULE = 6,
-    /* Data-parallel form of the level schedule's wavefront-per-gate kernel
-     * (Algorithm 2 per gate either way; identical results): 0 = segmented,
-     * each lane runs the procedure over a time segment of the gate's inputs
-     * and the lanes' candidates are reconciled by Eq. 1 across lanes;
-     * 1 = merged positions, the inputs merged in time across the wavefront
-     * and every step a wavefront scan. */
+    /* Data-parallel form of the wavefront-per-gate kernels (Algorithm 2 per
+     * gate either way; identical results): 1 = merged positions (default),
+     * the inputs merged in time across the wavefront and every step of the
+     * procedure a wavefront scan; 0 = segmented, each lane runs the procedure
+     * over a time segment of the gate's inputs and the lanes' candidates are
+     * reconciled by Eq. 1 across lanes (measured 1.4x slower on MI355X). */
     GSIM_OPT_EVAL_FORM = 7
 };
 
@@ -179,8 +179,11 @@ gsim_status sim_load_netlist_ext(gsim_ctx ctx, int64_t S, int64_t G, const uint8
  * (plumbing). */
 gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl);
 
-/* Per-netlist setting of GSIM_OPT_LANE_THRESHOLD (-1 = follow the context's
- * option); other options are per context. Applies to jobs stepped afterwards.
+/* Per-netlist setting of GSIM_OPT_LANE_THRESHOLD, GSIM_OPT_SCHEDULE or
+ * GSIM_OPT_EVAL_FORM (-1 = follow the context's option); the other options
+ * are per context. The autotuner sets them per netlist. Applies to jobs
+ * submitted (schedule) or stepped (threshold, form) afterwards; a step shared
+ * by jobs of several netlists takes the form of its first job's netlist.
  * Passage: a task's cost grows with its input waveforms' length (Section 5,
  * the WCV discussion), which the threshold bins on. */
 gsim_status sim_set_netlist_option(gsim_ctx ctx, gsim_netlist nl, int option, int64_t value);

@@ -1,12 +1,20 @@
 """Autotuner for the evaluate path.
 
-The tunable is the dynamic-binning threshold (GSIM_OPT_LANE_THRESHOLD): gates
-whose inputs hold fewer transitions than the threshold run one per lane
-instead of one per wavefront. Which is faster depends on the netlist (fan-in
-mix, delays) and on how long the waveforms are, so the tuner times candidate
-thresholds on a sample job and keeps the fastest, per (netlist, stimulus
-length bucket). Results are cached in memory and, if a path is given, in a
-JSON file.
+Knobs, each with a measurable effect that depends on the netlist and on how
+long its waveforms are:
+
+* schedule (GSIM_OPT_SCHEDULE): level by level, with every admitted job's
+  level in shared launches, or dependency-driven, one persistent launch per
+  job with no level barrier (wins on small or unevenly active netlists);
+* evaluation form (GSIM_OPT_EVAL_FORM): merged positions or time segments per
+  lane;
+* dynamic-binning threshold (GSIM_OPT_LANE_THRESHOLD): gates whose inputs hold
+  fewer transitions than it run one per lane instead of one per wavefront.
+
+The tuner times each candidate setting on a sample job and keeps the
+fastest, per (netlist, stimulus length bucket), applying it to the netlist
+with sim_set_netlist_option. Results are cached in memory and, if a path is
+given, in a JSON file.
 """
 from __future__ import annotations
 
@@ -19,7 +27,21 @@ import numpy as np
 
 from . import gsim as G
 
-CANDIDATES = (0, 64, 192, 512, 2048)
+# (schedule, evaluation form, lane threshold)
+CANDIDATES = (
+    (G.SCHEDULE_LEVELS, G.FORM_MERGED, 0),
+    (G.SCHEDULE_LEVELS, G.FORM_MERGED, 64),
+    (G.SCHEDULE_LEVELS, G.FORM_MERGED, 512),
+    (G.SCHEDULE_LEVELS, G.FORM_SEGMENTED, 0),
+    (G.SCHEDULE_DEPENDENCY, G.FORM_MERGED, 0),
+    (G.SCHEDULE_DEPENDENCY, G.FORM_SEGMENTED, 0),
+)
+SCHEDULE_NAMES = {G.SCHEDULE_LEVELS: "levels", G.SCHEDULE_DEPENDENCY: "dataflow"}
+FORM_NAMES = {G.FORM_MERGED: "merged", G.FORM_SEGMENTED: "segmented"}
+
+
+def setting_name(c) -> str:
+    return f"{SCHEDULE_NAMES[c[0]]}/{FORM_NAMES[c[1]]}/lane{c[2]}"
 
 
 def netlist_key(nl) -> str:
@@ -39,15 +61,20 @@ class Autotuner:
     def __init__(self, sim: G.Sim, path: str | None = None, candidates=CANDIDATES, reps: int = 2):
         self.sim = sim
         self.path = path
-        self.candidates = tuple(candidates)
+        self.candidates = tuple(tuple(c) for c in candidates)
         self.reps = reps
         self.table = {}
         if path and os.path.exists(path):
             with open(path) as f:
                 self.table = json.load(f)
 
-    def _time(self, h, st, threshold):
-        self.sim.set_netlist_option(h, G.OPT_LANE_THRESHOLD, threshold)
+    def apply(self, h, c):
+        self.sim.set_netlist_option(h, G.OPT_SCHEDULE, c[0])
+        self.sim.set_netlist_option(h, G.OPT_EVAL_FORM, c[1])
+        self.sim.set_netlist_option(h, G.OPT_LANE_THRESHOLD, c[2])
+
+    def _time(self, h, st, c):
+        self.apply(h, c)
         best = float("inf")
         for _ in range(self.reps):
             j = self.sim.run(h, st)
@@ -57,19 +84,19 @@ class Autotuner:
         return best
 
     def tune(self, nl, h, st):
-        """Pick the lane threshold for netlist ``nl`` (loaded as ``h``) on
-        stimuli like ``st``; applies it to ``h`` and returns (threshold, ms by
-        candidate)."""
+        """Pick the setting for netlist ``nl`` (loaded as ``h``) on stimuli like
+        ``st``; applies it to ``h`` and returns (setting, device ms by
+        candidate name)."""
         key = f"{netlist_key(nl)}/b{length_bucket(st, nl.S)}"
         if key in self.table:
-            thr = int(self.table[key]["threshold"])
-            self.sim.set_netlist_option(h, G.OPT_LANE_THRESHOLD, thr)
-            return thr, self.table[key]["ms"]
-        ms = {str(c): self._time(h, st, c) for c in self.candidates}
-        thr = int(min(ms, key=ms.get))
-        self.sim.set_netlist_option(h, G.OPT_LANE_THRESHOLD, thr)
-        self.table[key] = {"threshold": thr, "ms": ms}
+            c = tuple(self.table[key]["setting"])
+            self.apply(h, c)
+            return c, self.table[key]["ms"]
+        ms = {setting_name(c): self._time(h, st, c) for c in self.candidates}
+        c = min(self.candidates, key=lambda x: ms[setting_name(x)])
+        self.apply(h, c)
+        self.table[key] = {"setting": list(c), "name": setting_name(c), "ms": ms}
         if self.path:
             with open(self.path, "w") as f:
                 json.dump(self.table, f, indent=1)
-        return thr, ms
+        return c, ms

@@ -867,7 +867,10 @@ __device__ __forceinline__ int seg_lower_bound(const uint32_t *t, int n, uint32_
     return idx;
 }
 
-template <int K, int W, bool EDGE, bool AGENT>
+// PREFETCH: the next round's tiles load into registers while the round runs
+// (the level kernel); otherwise after it (the dependency-driven kernel, whose
+// persistent loop leaves fewer registers).
+template <int K, int W, bool EDGE, bool PREFETCH, bool AGENT>
 __device__ __forceinline__ void eval_gate_seg(const JobDesc &J, int64_t ob, const GateRec &R,
                                               int64_t gate, SegLds<W> &L) {
     using Tl = SegTiling<K>;
@@ -896,6 +899,33 @@ __device__ __forceinline__ void eval_gate_seg(const JobDesc &J, int64_t ob, cons
 #pragma unroll
     for (int p = 0; p < K; p++) tile_fetch<TT, true>(Kar + pb[p], pl[p], tl[p]);
     delay_tables<K, EDGE>(J, R, gate, L.dtab, L.etab);
+    // one and two pins: the gate table (16 values of 2 bits) and the delay
+    // table (per new value, 10-bit fields for changed-pin sets 1, 2, 3) in
+    // scalar registers, so the step reads neither from LDS
+    uint32_t lut_reg = 0, dly_reg[3] = {0u, 0u, 0u};
+    if (K <= 2) {
+        __syncthreads();  // the caller's gate table copy
+        const uint32_t part = lane < 16 ? (uint32_t)(L.lut[lane] & 3u) << (2 * lane) : 0u;
+        lut_reg = (uint32_t)__builtin_amdgcn_readlane((int)wave_prefix_sum(part), 15);
+        if (!EDGE) {
+#pragma unroll
+            for (int ev = 0; ev < 3; ev++) {
+                uint32_t w = 0;
+#pragma unroll
+                for (int mset = 1; mset < 4; mset++) {
+                    int32_t d = INT32_MAX;
+#pragma unroll
+                    for (int q = 0; q < K; q++)
+                        if (mset & (1 << q)) {
+                            const int32_t dq = pin_delay(R.rise[q], R.fall[q], (uint32_t)ev);
+                            d = dq < d ? dq : d;
+                        }
+                    w |= (d == INT32_MAX ? 0u : (uint32_t)d) << (10 * (mset - 1));
+                }
+                dly_reg[ev] = (uint32_t)__builtin_amdgcn_readfirstlane((int)w);
+            }
+        }
+    }
 
     uint32_t last_val = kX;  // value of the last final survivor
     bool first_round = true;
@@ -958,26 +988,68 @@ __device__ __forceinline__ void eval_gate_seg(const JobDesc &J, int64_t ob, cons
         for (int p = 0; p < K; p++) all_in = all_in && m[p] == rem[p];
         const uint32_t hsplit = all_in ? kNoKey32 : (uint32_t)(H - base) << 2 | 3u;
         PinTile<TT> nx[K];
+        if constexpr (PREFETCH) {
 #pragma unroll
-        for (int p = 0; p < K; p++) tile_fetch<TT, true>(Kar + pb[p] + cur[p] + m[p], rem[p] - m[p], nx[p]);
+            for (int p = 0; p < K; p++) tile_fetch<TT, true>(Kar + pb[p] + cur[p] + m[p], rem[p] - m[p], nx[p]);
+        }
         __syncthreads();
 
-        // ---- this lane's segment: [s, next lane's s) in time
-        int q = 0, mq = m[0];
-#pragma unroll
-        for (int p = 1; p < K; p++)
-            if (m[p] > mq) {
-                q = p;
-                mq = m[p];
-            }
-        const int iq = (lane * mq) >> 6;
-        const uint32_t s = lane == 0 ? 0u : L.tile[Tl::OFF(0) + q * TT + iq] >> 4;
+        // ---- this lane's segment: [s, next lane's s) in time. With one pin, an
+        // equal share of its keys; otherwise equal shares of the merged keys of
+        // the two pins with the most (a merge-path search), moved back to the
+        // start of the time group they fall in, and the other pins' keys from
+        // that time on (binary searches).
         int ip[K], endi[K];
+        uint32_t s;
+        if constexpr (K == 1) {
+            ip[0] = (lane * m[0]) >> 6;
+            s = lane == 0 ? 0u : L.tile[ip[0]] >> 4;
+        } else {
+            int pa = 0, pb2 = 1;
+            if (m[1] > m[0]) {
+                pa = 1;
+                pb2 = 0;
+            }
+#pragma unroll
+            for (int p = 2; p < K; p++) {
+                if (m[p] > m[pa]) {
+                    pb2 = pa;
+                    pa = p;
+                } else if (m[p] > m[pb2]) {
+                    pb2 = p;
+                }
+            }
+            const uint32_t *A = L.tile + pa * TT;
+            const uint32_t *B = L.tile + pb2 * TT;
+            const int ma = m[pa], mb = m[pb2];
+            const int d = (lane * (ma + mb)) >> 6;
+            int lo = d - mb > 0 ? d - mb : 0, hi = d < ma ? d : ma;
+#pragma unroll
+            for (int it = 0; it < 10; it++) {
+                const int mid = (lo + hi) >> 1;
+                const int jb = d - 1 - mid;
+                const uint32_t ka = A[mid < TT ? mid : TT - 1];
+                const uint32_t kb = B[jb < 0 ? 0 : jb < TT ? jb : TT - 1];
+                const bool go = lo < hi;
+                const bool less = ka < kb;
+                lo = go && less ? mid + 1 : lo;
+                hi = go && !less ? mid : hi;
+            }
+            int ia = lo, ib = d - lo;
+            const uint32_t na = ia < ma ? A[ia] : kNoKey32;
+            const uint32_t nb = ib < mb ? B[ib] : kNoKey32;
+            s = lane == 0 ? 0u : umin32(na, nb) >> 4;
+            const uint32_t pa_t = A[ia > 0 ? ia - 1 : 0] >> 4, pb_t = B[ib > 0 ? ib - 1 : 0] >> 4;
+            ia -= ia > 0 && pa_t == s ? 1 : 0;
+            ib -= ib > 0 && pb_t == s ? 1 : 0;
+            if (lane == 0) ia = ib = 0;
+#pragma unroll
+            for (int p = 0; p < K; p++)
+                ip[p] = p == pa ? ia : p == pb2 ? ib : seg_lower_bound<TT>(L.tile + Tl::OFF(p), m[p], s);
+        }
         int sb = 0;  // merged index of the segment's first transition
 #pragma unroll
         for (int p = 0; p < K; p++) {
-            if (p == q) ip[p] = iq;
-            else ip[p] = seg_lower_bound<TT>(L.tile + Tl::OFF(p), m[p], s);
             endi[p] = (int)wave_shift_down((uint32_t)m[p], (uint32_t)ip[p]);
             sb += ip[p];
         }
@@ -999,13 +1071,18 @@ __device__ __forceinline__ void eval_gate_seg(const JobDesc &J, int64_t ob, cons
                 state_next = (state_next & ~(3u << (2 * p))) | (((k >> 2) & 3u) << (2 * p));
             }
 
-        // ---- Algorithm 2 over the segment; candidates on the lane's stack (Eq. 1)
-        uint32_t head[K];
+        // ---- Algorithm 2 over the segment; candidates on the lane's stack (Eq. 1).
+        // Branch-free per pin: the pin's head and the key after it are held in
+        // registers, so the LDS read of a pin's next key has a whole step to land.
+        uint32_t head[K], after[K];  // after: the key at idx + 1 as read (bounds checked at use)
         int idx[K];
 #pragma unroll
         for (int p = 0; p < K; p++) {
             idx[p] = ip[p];
-            head[p] = idx[p] < endi[p] ? L.tile[Tl::OFF(p) + idx[p]] : kNoKey32;
+            const int j = idx[p] + 1;
+            const uint32_t k0 = L.tile[Tl::OFF(p) + (idx[p] < TT ? idx[p] : TT - 1)];
+            head[p] = idx[p] < endi[p] ? k0 : kNoKey32;
+            after[p] = L.tile[Tl::OFF(p) + (j < TT ? j : TT - 1)];
         }
         int n = 0;         // the stack: L.stack[sb, sb + n)
         uint32_t top = 0;  // L.stack[sb + n - 1] when n > 0
@@ -1017,27 +1094,36 @@ __device__ __forceinline__ void eval_gate_seg(const JobDesc &J, int64_t ob, cons
             if (__ballot(act) == 0) break;
             if (act) {
                 const uint32_t t = mn >> 4;
+                const uint32_t t_end = (t + 1) << 4;  // keys of time t are below this
                 uint32_t mask = 0;
                 uint32_t r0 = kEdgeNone, r1 = kEdgeNone, rx = kEdgeNone;
 #pragma unroll
                 for (int p = 0; p < K; p++) {
-                    if ((head[p] >> 4) == t) {
-                        const uint32_t nv = (head[p] >> 2) & 3u;
-                        if (EDGE) {
-                            const uint32_t ent = L.etab[p * 3 + edge_class((st >> (2 * p)) & 3u, nv)];
-                            r0 = umin32(r0, ent & 1023u);
-                            r1 = umin32(r1, (ent >> 10) & 1023u);
-                            rx = umin32(rx, ent >> 20);
-                        }
-                        st = (st & ~(3u << (2 * p))) | (nv << (2 * p));
-                        mask |= 1u << p;
-                        idx[p]++;
-                        head[p] = idx[p] < endi[p] ? L.tile[Tl::OFF(p) + idx[p]] : kNoKey32;
+                    const bool c = head[p] < t_end;
+                    const uint32_t nv = (head[p] >> 2) & 3u;
+                    if (EDGE) {
+                        const uint32_t ent = L.etab[p * 3 + edge_class((st >> (2 * p)) & 3u, nv)];
+                        r0 = c ? umin32(r0, ent & 1023u) : r0;
+                        r1 = c ? umin32(r1, (ent >> 10) & 1023u) : r1;
+                        rx = c ? umin32(rx, ent >> 20) : rx;
                     }
+                    const uint32_t nst = (st & ~(3u << (2 * p))) | (nv << (2 * p));
+                    st = c ? nst : st;
+                    mask |= c ? 1u << p : 0u;
+                    idx[p] += c ? 1 : 0;
+                    const uint32_t hn = idx[p] < endi[p] ? after[p] : kNoKey32;
+                    head[p] = c ? hn : head[p];
+                    const int j = idx[p] + 1;
+                    after[p] = L.tile[Tl::OFF(p) + (j < TT ? j : TT - 1)];
                 }
-                const uint32_t e = __builtin_amdgcn_ubfe(L.lut[st], 0, 2);
+                const uint32_t e = K <= 2 ? __builtin_amdgcn_ubfe(lut_reg, 2 * st, 2)
+                                          : __builtin_amdgcn_ubfe(L.lut[st], 0, 2);
                 if (e != e_prev) {
-                    const uint32_t d = EDGE ? (e == 0u ? r0 : e == 1u ? r1 : rx) : L.dtab[e * 16 + mask];
+                    uint32_t d;
+                    if (EDGE) d = e == 0u ? r0 : e == 1u ? r1 : rx;
+                    else if (K <= 2) d = __builtin_amdgcn_ubfe(e == 0u ? dly_reg[0] : e == 1u ? dly_reg[1] : dly_reg[2],
+                                                               10 * (mask - 1), 10);
+                    else d = L.dtab[e * 16 + mask];
                     // (edge model: no related pin changed, the candidate never appears)
                     if (!EDGE || d != kEdgeNone) {
                         const uint32_t key = ((t + d) << 2) | e;
@@ -1185,8 +1271,9 @@ __device__ __forceinline__ void eval_gate_seg(const JobDesc &J, int64_t ob, cons
         state0 = state_next;
 #pragma unroll
         for (int p = 0; p < K; p++) {
+            if constexpr (PREFETCH) tl[p] = nx[p];
+            else tile_fetch<TT, true>(Kar + pb[p] + cur[p] + m[p], rem[p] - m[p], tl[p]);
             cur[p] += m[p];
-            tl[p] = nx[p];
         }
         __syncthreads();
     }

@@ -404,6 +404,8 @@ struct Netlist {
     int64_t active_jobs = 0;
     int64_t max_level_n = 0;        // gates of the largest level
     int32_t lane_threshold = -1;    // -1: the context's GSIM_OPT_LANE_THRESHOLD
+    int32_t schedule = -1;          // -1: the context's GSIM_OPT_SCHEDULE
+    int32_t form = -1;              // -1: the context's GSIM_OPT_EVAL_FORM
     double arena_per_input = 0.0;   // largest arena use per input transition seen so far
 };
 
@@ -501,7 +503,7 @@ struct gsim_ctx_s {
     int opt_kernel = 0;
     int opt_timing = 0;
     int opt_schedule = 0;
-    int opt_form = kFormSegmented;
+    int opt_form = kFormMerged;
     int64_t n_waves_resident = 0;  // persistent wavefronts of the dependency-driven schedule
     int32_t opt_lane_threshold = 0;
 };
@@ -927,8 +929,9 @@ Failure submit(gsim_ctx ctx, gsim_netlist nlh, const int64_t *src_off, const int
     j->ex = ex;
     j->n_in = n_in;
     j->capacity_request = ctx->opt_arena;
-    j->dataflow = ctx->opt_schedule == 1 ||
-                  (ctx->opt_schedule == 2 && prefer_dependency_driven(nl, device_arrays ? nullptr : src_off));
+    const int schedule = nl.schedule >= 0 ? nl.schedule : ctx->opt_schedule;
+    j->dataflow = schedule == 1 ||
+                  (schedule == 2 && prefer_dependency_driven(nl, device_arrays ? nullptr : src_off));
     if (!device_arrays) {
         const size_t S1 = (size_t)nl.S + 1;
         j->h_src_off = (int64_t *)ctx->pinned.get(sizeof(int64_t) * S1);
@@ -1021,7 +1024,7 @@ Failure enqueue_dataflow(gsim_ctx ctx, Job *j, hipStream_t s) {
         HIP_TRY(hipEventCreate(&tm->b));
         HIP_TRY(hipEventRecord(tm->a, s));
     }
-    HIP_TRY(launch_dataflow(a, n_waves, s));
+    HIP_TRY(launch_dataflow(a, n_waves, nl.form >= 0 ? nl.form : ctx->opt_form, s));
     if (tm) {
         HIP_TRY(hipEventRecord(tm->b, s));
         j->timing.push_back(tm);
@@ -1214,7 +1217,9 @@ Failure enqueue_step(gsim_ctx ctx, Executor *ex) {
         HIP_TRY(hipEventCreate(&tm->b));
         HIP_TRY(hipEventRecord(tm->a, s));
     }
-    for (int v = 0; v < kVariants; v++) HIP_TRY(launch_eval_wave(a, v, n_list + wave_list(v, 1), ctx->opt_form, s));
+    // the step's jobs share its launches: the first job's netlist sets the form
+    const int form = act[0]->nl->form >= 0 ? act[0]->nl->form : ctx->opt_form;
+    for (int v = 0; v < kVariants; v++) HIP_TRY(launch_eval_wave(a, v, n_list + wave_list(v, 1), form, s));
     HIP_TRY(launch_eval_lane(a, n_lane, s));
     if (tm) HIP_TRY(hipEventRecord(tm->b, s));
     ex->parity ^= 1;
@@ -1443,7 +1448,7 @@ Failure run_noalloc(gsim_ctx ctx, const Netlist &nl, const int64_t *d_src_off, c
         HIP_TRY(launch_size(a, s));
         HIP_TRY(launch_sort_lists(a, r.n_list, s));
         for (int v = 0; v < kVariants; v++)
-            HIP_TRY(launch_eval_wave(a, v, r.n_list + wave_list(v, 1), ctx->opt_form, s));
+            HIP_TRY(launch_eval_wave(a, v, r.n_list + wave_list(v, 1), nl.form >= 0 ? nl.form : ctx->opt_form, s));
         HIP_TRY(launch_eval_lane(a, n_lane, s));
     }
     HIP_TRY(launch_count_out(d_len, nl.S, nl.G, (int64_t *)(base + L.partial), L.n_partial, state, s));
@@ -1843,10 +1848,22 @@ gsim_status sim_set_netlist_option(gsim_ctx ctx, gsim_netlist nl, int option, in
     if (!ctx) return record(nullptr, fail(GSIM_E_HANDLE, "null context"));
     auto it = ctx->netlists.find(nl);
     if (it == ctx->netlists.end()) return record(ctx, fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nl));
-    if (option != GSIM_OPT_LANE_THRESHOLD) return record(ctx, fail(GSIM_E_ARG, "option %d is not per netlist", option));
-    if (value < -1 || value > INT32_MAX) return record(ctx, fail(GSIM_E_ARG, "lane threshold out of range"));
-    it->second->lane_threshold = (int32_t)value;
-    return GSIM_OK;
+    Netlist &n = *it->second;
+    switch (option) {
+    case GSIM_OPT_LANE_THRESHOLD:
+        if (value < -1 || value > INT32_MAX) return record(ctx, fail(GSIM_E_ARG, "lane threshold out of range"));
+        n.lane_threshold = (int32_t)value;
+        return GSIM_OK;
+    case GSIM_OPT_SCHEDULE:
+        if (value < -1 || value > 2) return record(ctx, fail(GSIM_E_ARG, "schedule must be -1, 0, 1 or 2"));
+        n.schedule = (int32_t)value;
+        return GSIM_OK;
+    case GSIM_OPT_EVAL_FORM:
+        if (value < -1 || value > 1) return record(ctx, fail(GSIM_E_ARG, "evaluation form must be -1, 0 or 1"));
+        n.form = (int32_t)value;
+        return GSIM_OK;
+    }
+    return record(ctx, fail(GSIM_E_ARG, "option %d is not per netlist", option));
 } catch (...) {
     return exception_status(ctx);
 }

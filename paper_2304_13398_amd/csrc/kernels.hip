@@ -15,6 +15,8 @@
 // Transitions live in the arena packed as time << 2 | value (8 bytes).
 #include "eval_core.h"
 
+#include <type_traits>
+
 #include <mutex>
 
 namespace gsim {
@@ -299,10 +301,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ev
         reinterpret_cast<const uint32_t *>(J.lut + (int)R.type * 256)[lane];
     const int64_t ob = A.blocksum[J.sblock_begin + (gate - J.lvl_begin) / kSizeBlock] + J.off[J.S + gate];
     switch (R.k) {
-    case 1: eval_gate_seg<1, W, EDGE, false>(J, ob, R, gate, L); break;
-    case 2: eval_gate_seg<2, W, EDGE, false>(J, ob, R, gate, L); break;
-    case 3: eval_gate_seg<3, W, EDGE, false>(J, ob, R, gate, L); break;
-    default: eval_gate_seg<4, W, EDGE, false>(J, ob, R, gate, L); break;
+    case 1: eval_gate_seg<1, W, EDGE, true, false>(J, ob, R, gate, L); break;
+    case 2: eval_gate_seg<2, W, EDGE, true, false>(J, ob, R, gate, L); break;
+    case 3: eval_gate_seg<3, W, EDGE, true, false>(J, ob, R, gate, L); break;
+    default: eval_gate_seg<4, W, EDGE, true, false>(J, ob, R, gate, L); break;
     }
 }
 
@@ -332,10 +334,9 @@ __global__ __launch_bounds__(64) void eval_lane_kernel(StepArgs A) {
 // gate enters the queue exactly once, so the G tickets are all filled and a
 // wavefront leaves when its ticket is past the end. Ordering across the
 // XCDs' L2 caches: outputs are published with an agent-scope release fence
-// before the decrements; the wavefront whose decrement makes a gate ready
-// acquires (so the other producers' outputs are ordered before it) and
-// queues the gate with a release store; the wavefront that takes the gate
-// reads its inputs after an agent-scope acquire fence.
+// before the decrements; the wavefront that takes a gate reads its pending
+// count (0) and then takes an agent-scope acquire fence, which orders every
+// producer's outputs before its reads (see df_acquire_inputs).
 // Safety exit: a wavefront that sees no new queue entry for kDfSpinLimit
 // polls (each after a sleep of about 2k cycles: tens of seconds in all) flags
 // the job (check_error = 3) and leaves, and so does every wavefront that sees
@@ -388,6 +389,30 @@ __device__ int32_t df_wait_slot(const DfArgs &A, uint32_t t, DevState *st) {
     }
 }
 
+// Before it reads the inputs of the gates it took from the queue, a
+// wavefront synchronises with every producer of those gates. Each producer
+// decrements a consumer's pending count after its agent-scope release fence;
+// the decrements form one release sequence on that count, so a relaxed read
+// of the count's final value 0 followed by an agent-scope acquire fence
+// synchronises with every producer's fence (fence-to-fence synchronisation
+// through the count). The queue slot only says which gate to take. The read
+// finds 0 at once in practice (the count reached 0 before the slot was
+// written); the loop waits for it rather than assume cross-location order.
+__device__ __forceinline__ void df_acquire_inputs(const DfArgs &A, int32_t g0, int32_t g1, int32_t g2,
+                                                  int32_t g3, int nb) {
+    const int lane = lane_id();
+    for (int b = 0; b < nb; b++) {
+        const int32_t g = b == 0 ? g0 : b == 1 ? g1 : b == 2 ? g2 : g3;
+        for (;;) {
+            uint32_t pend = 0;
+            if (lane == 0) pend = load_agent(reinterpret_cast<const uint32_t *>(A.pend + g));
+            if (__builtin_amdgcn_readfirstlane((int)pend) == 0) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
 // A wavefront takes A.tickets (1..kDfMaxTickets) consecutive tickets per
 // atomic and works through them in order. Queue slots are allocated in the
 // order gates become ready, so while a wavefront waits on its next slot no
@@ -398,9 +423,10 @@ constexpr uint32_t kDfMaxTickets = 4;
 // Arena space is reserved per wavefront in chunks of A.chunk transitions (or
 // one gate's bound if larger), so the arena top takes one atomic per chunk.
 
-template <bool EDGE>
+template <bool EDGE, int FORM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void dataflow_kernel(DfArgs A) {
-    __shared__ WaveLds<kWindowLarge> L;
+    using Lds = typename std::conditional<FORM == kFormSegmented, SegLds<kWindowLarge>, WaveLds<kWindowLarge>>::type;
+    __shared__ Lds L;
     const int lane = lane_id();
     const JobDesc &J = A.job;
     DevState *st = J.state;
@@ -438,7 +464,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
                 g3 = __builtin_amdgcn_readfirstlane((int)q[2]);
                 nb = g1 < 0 ? 1 : g2 < 0 ? 2 : g3 < 0 ? 3 : 4;
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            df_acquire_inputs(A, g0, g1, g2, g3, nb);
             for (int b = 0; b < nb; b++) {
                 const int32_t g = b == 0 ? g0 : b == 1 ? g1 : b == 2 ? g2 : g3;
                 const GateRec R = J.rec[g];
@@ -470,11 +496,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
                 } else {
                     reinterpret_cast<uint32_t *>(L.lut)[lane] =
                         reinterpret_cast<const uint32_t *>(J.lut + (int)R.type * 256)[lane];
-                    switch (R.k) {
-                    case 1: eval_gate<1, kWindowLarge, EDGE, false, false, true>(J, ob, R, g, L); break;
-                    case 2: eval_gate<2, kWindowLarge, EDGE, false, false, true>(J, ob, R, g, L); break;
-                    case 3: eval_gate<3, kWindowLarge, EDGE, false, false, true>(J, ob, R, g, L); break;
-                    default: eval_gate<4, kWindowLarge, EDGE, false, false, true>(J, ob, R, g, L); break;
+                    if constexpr (FORM == kFormSegmented) {
+                        switch (R.k) {
+                        case 1: eval_gate_seg<1, kWindowLarge, EDGE, false, true>(J, ob, R, g, L); break;
+                        case 2: eval_gate_seg<2, kWindowLarge, EDGE, false, true>(J, ob, R, g, L); break;
+                        case 3: eval_gate_seg<3, kWindowLarge, EDGE, false, true>(J, ob, R, g, L); break;
+                        default: eval_gate_seg<4, kWindowLarge, EDGE, false, true>(J, ob, R, g, L); break;
+                        }
+                    } else {
+                        switch (R.k) {
+                        case 1: eval_gate<1, kWindowLarge, EDGE, !EDGE, false, true>(J, ob, R, g, L); break;
+                        case 2: eval_gate<2, kWindowLarge, EDGE, !EDGE, false, true>(J, ob, R, g, L); break;
+                        case 3: eval_gate<3, kWindowLarge, EDGE, !EDGE, false, true>(J, ob, R, g, L); break;
+                        default: eval_gate<4, kWindowLarge, EDGE, !EDGE, false, true>(J, ob, R, g, L); break;
+                        }
                     }
                 }
             }
@@ -489,21 +524,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
                     const bool ready = c >= 0 && atomicSub(&A.pend[c], 1) == 1;
                     const uint64_t mask = __ballot(ready);
                     if (mask == 0) continue;
-                    // A count that reached zero here carries the decrements of
-                    // the consumer's other producers, each made after their
-                    // release fence. The acquire fence takes their outputs in,
-                    // and the release store of the queue slot hands them on with
-                    // this wavefront's own: whoever reads the slot and then
-                    // fences with acquire sees every input of the gate. Nothing
-                    // is left dirty since the fence above, so the release costs
-                    // little, and only batches that make a gate ready pay it.
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    // (the consumer synchronises with every producer through
+                    // the pending count itself: see df_acquire_inputs)
                     const int leader = __ffsll((unsigned long long)mask) - 1;
                     uint32_t base = 0;
                     if (lane == leader) base = atomicAdd(&A.ctl->tail, (uint32_t)__popcll(mask));
                     base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
                     if (ready)
-                        __hip_atomic_store(A.queue + base + lanes_below(mask), c, __ATOMIC_RELEASE,
+                        __hip_atomic_store(A.queue + base + lanes_below(mask), c, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
@@ -723,12 +751,16 @@ hipError_t launch_df_init(const DfArgs &a, const int32_t *pend0, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t launch_dataflow(const DfArgs &a, int64_t n_waves, hipStream_t s) {
+hipError_t launch_dataflow(const DfArgs &a, int64_t n_waves, int form, hipStream_t s) {
     if (a.G <= 0 || n_waves <= 0) return hipSuccess;
-    if (a.job.edly)
-        dataflow_kernel<true><<<dim3((unsigned)n_waves), dim3(64), 0, s>>>(a);
-    else
-        dataflow_kernel<false><<<dim3((unsigned)n_waves), dim3(64), 0, s>>>(a);
+    const dim3 grid((unsigned)n_waves), block(64);
+    if (form == kFormSegmented) {
+        if (a.job.edly) dataflow_kernel<true, kFormSegmented><<<grid, block, 0, s>>>(a);
+        else dataflow_kernel<false, kFormSegmented><<<grid, block, 0, s>>>(a);
+    } else {
+        if (a.job.edly) dataflow_kernel<true, kFormMerged><<<grid, block, 0, s>>>(a);
+        else dataflow_kernel<false, kFormMerged><<<grid, block, 0, s>>>(a);
+    }
     return hipGetLastError();
 }
 

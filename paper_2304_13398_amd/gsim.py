@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OK", -1: "GSIM_E_ARG", -2: "GSIM_E_CYCLE", -3: "GSIM_E_WAVEF
 OPT_ARENA_TRANSITIONS, OPT_KERNEL, OPT_KERNEL_TIMING, OPT_LANE_THRESHOLD, OPT_SCHEDULE = 1, 2, 4, 5, 6
 OPT_EVAL_FORM = 7
 # values of OPT_EVAL_FORM
-FORM_SEGMENTED, FORM_MERGED = 0, 1
+FORM_SEGMENTED, FORM_MERGED = 0, 1  # the library default is FORM_MERGED
 # values of OPT_SCHEDULE
 SCHEDULE_LEVELS, SCHEDULE_DEPENDENCY, SCHEDULE_AUTO = 0, 1, 2
 NO_RELATION = 2**31 - 1

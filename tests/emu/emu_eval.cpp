@@ -234,7 +234,7 @@ void seg_body(void *p) {
     Task &t = *(Task *)p;
     SegLds<W> &L = *(SegLds<W> *)t.L;
     reinterpret_cast<uint32_t *>(L.lut)[lane_id()] = reinterpret_cast<const uint32_t *>(t.lut)[lane_id()];
-    eval_gate_seg<K, W, EDGE, AGENT>(*t.J, t.ob, *t.R, t.gate, L);
+    eval_gate_seg<K, W, EDGE, !AGENT, AGENT>(*t.J, t.ob, *t.R, t.gate, L);
 }
 
 template <int W, bool EDGE, bool AGENT>
@@ -253,7 +253,7 @@ void (*variant(int mode, int window, int k))(void *) {
     case 4: return window == 64 ? pick_seg<64, EDGE, false>(k) : pick_seg<256, EDGE, false>(k);
     case 5: return pick_seg<256, EDGE, true>(k);
     case 0: return window == 64 ? pick<64, EDGE, true, true, false>(k) : pick<256, EDGE, true, true, false>(k);
-    case 1: return pick<256, EDGE, false, false, true>(k);
+    case 1: return pick<256, EDGE, !EDGE, false, true>(k);
     case 2: return pick<256, EDGE, false, true, true>(k);
     default: return window == 64 ? pick<64, EDGE, true, false, false>(k) : pick<256, EDGE, true, false, false>(k);
     }

@@ -92,10 +92,9 @@ def edge_mid():
 
 @pytest.mark.parametrize("mode", ["dataflow_lean", "seg", "dataflow", "levels"])
 def test_edge_model_mid_generator(edge_mid, mode):
-    """Every gate in the withdrawn form and in the segmented form; a third of
-    them in the two merged forms in use."""
+    """Every gate in the withdrawn form; a third of them in the forms in use."""
     nl, st, dly, want, lut = edge_mid
-    gates = np.arange(nl.G) if mode in ("dataflow_lean", "seg") else np.arange(0, nl.G, 3)
+    gates = np.arange(nl.G) if mode == "dataflow_lean" else np.arange(0, nl.G, 3)
     got, err, _ = E.run(mode, nl, st, want, lut, gates=gates, dly=dly, max_ops=MAX_OPS)
     compare(got, err, want, gates)
 

@@ -90,6 +90,36 @@ def test_dynamic_binning_thresholds(sim, threshold):
     assert same(got, O.o1_simulate(nl, st))
 
 
+def test_autotuner_settings_are_exact(sim):
+    """Every setting the autotuner may choose (schedule, evaluation form, lane
+    threshold) gives the oracle's waveforms when set on the netlist, also for
+    a batch of sets that share steps; the tuner applies the fastest one."""
+    from paper_2304_13398_amd import autotune
+    nl, st = W.config2(G=6000, S=40, L=30, n_per_src=200, seed=12)
+    want = O.o1_simulate(nl, st)
+    h = sim.load_netlist(nl)
+    try:
+        tuner = autotune.Autotuner(sim, reps=1)
+        for c in tuner.candidates:
+            tuner.apply(h, c)
+            j = sim.run(h, st)
+            sim.wait(j)
+            assert same(fetch_gates(sim, j, nl), want), autotune.setting_name(c)
+            assert sim.stats(j).schedule == c[0]
+            sim.release(j)
+        c, ms = tuner.tune(nl, h, st)
+        assert c in tuner.candidates and len(ms) == len(tuner.candidates)
+        sets = [W.make_stimulus(S=nl.S, n_per_src=n, window=1_000_000, seed=40 + n) for n in (30, 120, 400)]
+        for j, x in zip(sim.run_batch(h, sets), sets):
+            sim.wait(j)
+            assert same(fetch_gates(sim, j, nl), O.o1_simulate(nl, x)), autotune.setting_name(c)
+            sim.release(j)
+    finally:
+        for opt in (G.OPT_SCHEDULE, G.OPT_EVAL_FORM, G.OPT_LANE_THRESHOLD):
+            sim.set_netlist_option(h, opt, -1)
+        sim.unload_netlist(h)
+
+
 def test_admission_waves_under_a_small_budget():
     """A context whose HBM budget holds about two jobs: five sets are admitted
     as earlier ones are released, and every result is still exact."""

@@ -239,6 +239,7 @@ def test_batched_sets_full_size(batched, group):
         g_len, g_fp, _ = got[i]
         assert np.array_equal(g_len, ln), f"set {i} lengths: " + first_difference(g_len, ln)
         assert np.array_equal(g_fp, fp), f"set {i} fingerprints: " + first_difference(g_fp, fp)
+        say(f"  set {i}: {sets[i].n} given, {int(ln.sum())} output transitions, every gate equal")
     say(f"  sets {ids}: every gate equal ({time.perf_counter() - t0:.1f} s of oracle)")
 
 
