@@ -113,7 +113,14 @@ enum gsim_option {
      * procedure a wavefront scan; 0 = segmented, each lane runs the procedure
      * over a time segment of the gate's inputs and the lanes' candidates are
      * reconciled by Eq. 1 across lanes (measured 1.4x slower on MI355X). */
-    GSIM_OPT_EVAL_FORM = 7
+    GSIM_OPT_EVAL_FORM = 7,
+    /* Dependency-driven schedule: queue slots a wavefront claims per atomic,
+     * 1-16 (0 = automatic: 1 for netlists smaller than 16 gates per resident
+     * wavefront, else 4; on the 1M-gate mid job 2, 4, 8 and 16 measured
+     * 32.8, 25.4, 46.2 and 60.6 ms). The claimed gates that are already ready
+     * run between one pair of memory fences. Passage: Algorithm 1's threads
+     * take tasks from the shared queue (Section 3.3). */
+    GSIM_OPT_DF_TICKETS = 8
 };
 
 /* ---- context ------------------------------------------------------------ */

@@ -5,6 +5,12 @@
 
 #include "gsim_internal.h"
 
+// Qualifier of pointers into device global memory (the emulator of tests/emu
+// defines it empty).
+#ifndef gsim_global
+#define gsim_global __attribute__((address_space(1)))
+#endif
+
 namespace gsim {
 
 namespace {
@@ -276,7 +282,10 @@ __device__ __forceinline__ void tile_fetch(const uint64_t *src, int64_t r, PinTi
             const uint64_t a = (uint64_t)src;
             const uint32_t a_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
             const uint32_t a_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
-            const uint32_t *s32 = reinterpret_cast<const uint32_t *>(((uint64_t)a_hi << 32) | a_lo);
+            // a global-memory pointer, so that the loads take the scalar base and
+            // a 32-bit lane offset (a generic pointer costs a 64-bit address per lane)
+            const gsim_global uint32_t *s32 =
+                (const gsim_global uint32_t *)reinterpret_cast<const uint32_t *>(((uint64_t)a_hi << 32) | a_lo);
             const int last = t.n - 1;
 #pragma unroll
             for (int e = 0; e < T / 64; e++) {
@@ -573,7 +582,8 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         for (int k = 0; k < 8; k++) {
             const uint32_t sh = K == 1 ? 0u : (mk[k] & 3u) * 2u;
             const bool valid = mk[k] != kNoKey32;
-            if (valid) upd = (upd & ~(3u << sh)) | (((mk[k] >> 2) & 3u) << sh) | (0x300u << sh);
+            const uint32_t nu = (upd & ~(0x303u << sh)) | ((((mk[k] >> 2) & 3u) | 0x300u) << sh);
+            upd = valid ? nu : upd;
             if (!LEAN) trail_mask |= (mk[k] >> 4) == t_last ? 1u << (sh >> 1) : 0u;
         }
         if constexpr (LEAN) {

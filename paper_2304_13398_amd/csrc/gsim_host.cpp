@@ -504,6 +504,7 @@ struct gsim_ctx_s {
     int opt_timing = 0;
     int opt_schedule = 0;
     int opt_form = kFormMerged;
+    int opt_df_tickets = 0;
     int64_t n_waves_resident = 0;  // persistent wavefronts of the dependency-driven schedule
     int32_t opt_lane_threshold = 0;
 };
@@ -1014,8 +1015,10 @@ Failure enqueue_dataflow(gsim_ctx ctx, Job *j, hipStream_t s) {
     // reservation granule: at most 1/16 of the arena left idle over all wavefronts
     a.chunk = std::min<int64_t>(int64_t(1) << 15, (j->capacity - j->n_in) / (16 * std::max<int64_t>(n_waves, 1)));
     // small jobs are latency-bound: one ticket per claim keeps every ready gate
-    // on a wavefront of its own; large ones are bound by the claim counter
-    a.tickets = nl.G < 16 * ctx->n_waves_resident ? 1u : 2u;
+    // on a wavefront of its own; large ones are bound by the claim counter and
+    // by the fences, which a batch of ready gates shares
+    a.tickets = ctx->opt_df_tickets > 0 ? (uint32_t)ctx->opt_df_tickets
+                : nl.G < 16 * ctx->n_waves_resident ? 1u : 4u;
     HIP_TRY(launch_df_init(a, nl.d_pend0, s));
     std::shared_ptr<StepTiming> tm;
     if (ctx->opt_timing) {
@@ -1803,6 +1806,10 @@ gsim_status sim_set_option(gsim_ctx ctx, int option, int64_t value) try {
     case GSIM_OPT_EVAL_FORM:
         if (value < 0 || value > 1) return record(ctx, fail(GSIM_E_ARG, "evaluation form must be 0 or 1"));
         ctx->opt_form = (int)value;
+        return GSIM_OK;
+    case GSIM_OPT_DF_TICKETS:
+        if (value < 0 || value > 16) return record(ctx, fail(GSIM_E_ARG, "tickets per claim must be in [0, 16]"));
+        ctx->opt_df_tickets = (int)value;
         return GSIM_OK;
     }
     return record(ctx, fail(GSIM_E_ARG, "unknown option %d", option));

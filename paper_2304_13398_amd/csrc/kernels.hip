@@ -398,28 +398,26 @@ __device__ int32_t df_wait_slot(const DfArgs &A, uint32_t t, DevState *st) {
 // through the count). The queue slot only says which gate to take. The read
 // finds 0 at once in practice (the count reached 0 before the slot was
 // written); the loop waits for it rather than assume cross-location order.
-__device__ __forceinline__ void df_acquire_inputs(const DfArgs &A, int32_t g0, int32_t g1, int32_t g2,
-                                                  int32_t g3, int nb) {
+__device__ __forceinline__ void df_acquire_inputs(const DfArgs &A, int32_t g_lane, int nb) {
     const int lane = lane_id();
-    for (int b = 0; b < nb; b++) {
-        const int32_t g = b == 0 ? g0 : b == 1 ? g1 : b == 2 ? g2 : g3;
-        for (;;) {
-            uint32_t pend = 0;
-            if (lane == 0) pend = load_agent(reinterpret_cast<const uint32_t *>(A.pend + g));
-            if (__builtin_amdgcn_readfirstlane((int)pend) == 0) break;
-            __builtin_amdgcn_s_sleep(1);
-        }
+    for (;;) {
+        uint32_t pend = 0;
+        if (lane < nb) pend = load_agent(reinterpret_cast<const uint32_t *>(A.pend + g_lane));
+        if (__ballot(pend != 0) == 0) break;
+        __builtin_amdgcn_s_sleep(1);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 // A wavefront takes A.tickets (1..kDfMaxTickets) consecutive tickets per
-// atomic and works through them in order. Queue slots are allocated in the
+// atomic and works through them in order; the gates of those tickets whose
+// slots are already filled run as one batch between one acquire and one
+// release fence. Queue slots are allocated in the
 // order gates become ready, so while a wavefront waits on its next slot no
 // later slot holds a ready gate that only it could run (the deadlock-freedom
 // argument is unchanged). More tickets per atomic relieve the one contended
 // counter; fewer keep gates near the critical path on wavefronts of their own.
-constexpr uint32_t kDfMaxTickets = 4;
+constexpr uint32_t kDfMaxTickets = 16;
 // Arena space is reserved per wavefront in chunks of A.chunk transitions (or
 // one gate's bound if larger), so the arena top takes one atomic per chunk.
 
@@ -442,31 +440,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
         const uint32_t t1 = (uint32_t)min64((int64_t)t0 + n_t, A.G);
         uint32_t t = t0;
         while (t < t1) {
-            // the next gate, and the one after if its slot is already filled:
-            // both run between one acquire and one release fence
+            // the next gate, and the following tickets whose slots are already
+            // filled: all run between one acquire and one release fence
             const int32_t g0 = df_wait_slot(A, t, st);
             if (g0 < 0) {
                 stop = true;
                 break;
             }
-            // later tickets whose slots are already filled join the batch
-            int32_t g1 = -1, g2 = -1, g3 = -1;
-            int nb = 1;
-            if (t + 1 < t1) {
-                uint32_t q[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
-                if (lane == 0) {
-#pragma unroll
-                    for (int x = 0; x < 3; x++)
-                        if (t + 1 + x < t1) q[x] = load_agent(reinterpret_cast<const uint32_t *>(A.queue + t + 1 + x));
-                }
-                g1 = __builtin_amdgcn_readfirstlane((int)q[0]);
-                g2 = __builtin_amdgcn_readfirstlane((int)q[1]);
-                g3 = __builtin_amdgcn_readfirstlane((int)q[2]);
-                nb = g1 < 0 ? 1 : g2 < 0 ? 2 : g3 < 0 ? 3 : 4;
-            }
-            df_acquire_inputs(A, g0, g1, g2, g3, nb);
+            // lane b holds the gate of ticket t + b (b < nb)
+            int32_t g_lane = lane == 0 ? g0 : -1;
+            if (lane > 0 && t + (uint32_t)lane < t1)
+                g_lane = (int32_t)load_agent(reinterpret_cast<const uint32_t *>(A.queue + t + lane));
+            const uint64_t filled = __ballot(g_lane >= 0);
+            const int nb = (~filled) == 0 ? 64 : __builtin_ctzll(~filled);  // leading filled slots
+            df_acquire_inputs(A, g_lane, nb);
             for (int b = 0; b < nb; b++) {
-                const int32_t g = b == 0 ? g0 : b == 1 ? g1 : b == 2 ? g2 : g3;
+                const int32_t g = __builtin_amdgcn_readlane(g_lane, b);
                 const GateRec R = J.rec[g];
                 int64_t w = 0;
 #pragma unroll
@@ -516,7 +505,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             // consumers whose last pending pin this was: queued with one atomic per batch
             for (int b = 0; b < nb; b++) {
-                const int32_t g = b == 0 ? g0 : b == 1 ? g1 : b == 2 ? g2 : g3;
+                const int32_t g = __builtin_amdgcn_readlane(g_lane, b);
                 const int64_t f1 = A.fo_off[g + 1];
                 for (int64_t i0 = A.fo_off[g]; i0 < f1; i0 += 64) {
                     const int64_t i = i0 + lane;

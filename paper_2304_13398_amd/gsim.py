@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "OK", -1: "GSIM_E_ARG", -2: "GSIM_E_CYCLE", -3: "GSIM_E_WAVEF
                 -4: "GSIM_E_OOM", -5: "GSIM_E_DEVICE", -6: "GSIM_E_HANDLE", -7: "GSIM_E_OVERFLOW"}
 OPT_ARENA_TRANSITIONS, OPT_KERNEL, OPT_KERNEL_TIMING, OPT_LANE_THRESHOLD, OPT_SCHEDULE = 1, 2, 4, 5, 6
 OPT_EVAL_FORM = 7
+OPT_DF_TICKETS = 8
 # values of OPT_EVAL_FORM
 FORM_SEGMENTED, FORM_MERGED = 0, 1  # the library default is FORM_MERGED
 # values of OPT_SCHEDULE

@@ -186,6 +186,7 @@ typedef int hipError_t;
 typedef void *hipStream_t;
 constexpr hipError_t hipSuccess = 0;
 
+#define gsim_global
 #define __host__
 #define __device__
 #define __global__
