@@ -81,6 +81,7 @@ def parse():
                     help="only the timed industrial steps (for profiler runs)")
     ap.add_argument("--served-only", action="store_true", help="only the served section")
     ap.add_argument("--batched-only", action="store_true", help="only the batched section")
+    ap.add_argument("--skewed-only", action="store_true", help="only the skewed-activity section")
     ap.add_argument("--mid-only", action="store_true",
                     help="only the timed mid-size steps (for profiler runs)")
     ap.add_argument("--eval-form", choices=("segmented", "merged"), default="merged",
@@ -743,6 +744,13 @@ def main():
         rates = [float(x) for x in args.served_rates.split(",") if x]
         print(json.dumps({"served": bench_served(G, sim, rates, args.seed, args.served_seconds,
                                                  args.served_full)}), flush=True)
+        sim.close()
+        return 0
+    if args.skewed_only:
+        sim.set_option(G.OPT_DF_TICKETS, args.df_tickets)
+        nl = W.config2_netlist(seed=args.seed)
+        h = sim.load_netlist(nl)
+        print(json.dumps({"skewed": bench_skewed(G, sim, nl, h, args.seed)}), flush=True)
         sim.close()
         return 0
     if args.batched_only:

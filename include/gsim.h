@@ -107,8 +107,10 @@ enum gsim_option {
      * workload WCV, Eq. 5) of at least 2.5; level by level otherwise.
      * Results are identical under every setting. */
     GSIM_OPT_SCHEDULE = 6,
-    /* Data-parallel form of the wavefront-per-gate kernels (Algorithm 2 per
-     * gate either way; identical results): 1 = merged positions (default),
+    /* Data-parallel form of the level schedule's wavefront-per-gate kernel
+     * (Algorithm 2 per gate either way; identical results; the
+     * dependency-driven kernel always uses the merged form): 1 = merged
+     * positions (default),
      * the inputs merged in time across the wavefront and every step of the
      * procedure a wavefront scan; 0 = segmented, each lane runs the procedure
      * over a time segment of the gate's inputs and the lanes' candidates are
@@ -116,10 +118,13 @@ enum gsim_option {
     GSIM_OPT_EVAL_FORM = 7,
     /* Dependency-driven schedule: queue slots a wavefront claims per atomic,
      * 1-16 (0 = automatic: 1 for netlists smaller than 16 gates per resident
-     * wavefront, else 4; on the 1M-gate mid job 2, 4, 8 and 16 measured
-     * 32.8, 25.4, 46.2 and 60.6 ms). The claimed gates that are already ready
-     * run between one pair of memory fences. Passage: Algorithm 1's threads
-     * take tasks from the shared queue (Section 3.3). */
+     * wavefront, else 2). The claimed gates that are already ready run
+     * between one pair of memory fences. More tickets cut the contended
+     * atomics (uniform 1M-gate mid job: 2, 4, 8, 16 tickets 32.4, 25.0,
+     * 46.2, 60.6 ms) but make light gates wait behind a heavy one claimed by
+     * the same wavefront (sources with WCV 20: 85 ms with 2, 124 ms with 4);
+     * the autotuner sets it per netlist. Passage: Algorithm 1's threads take
+     * tasks from the shared queue (Section 3.3). */
     GSIM_OPT_DF_TICKETS = 8
 };
 
@@ -186,8 +191,9 @@ gsim_status sim_load_netlist_ext(gsim_ctx ctx, int64_t S, int64_t G, const uint8
  * (plumbing). */
 gsim_status sim_unload_netlist(gsim_ctx ctx, gsim_netlist nl);
 
-/* Per-netlist setting of GSIM_OPT_LANE_THRESHOLD, GSIM_OPT_SCHEDULE or
- * GSIM_OPT_EVAL_FORM (-1 = follow the context's option); the other options
+/* Per-netlist setting of GSIM_OPT_LANE_THRESHOLD, GSIM_OPT_SCHEDULE,
+ * GSIM_OPT_EVAL_FORM or GSIM_OPT_DF_TICKETS (-1 = follow the context's
+ * option); the other options
  * are per context. The autotuner sets them per netlist. Applies to jobs
  * submitted (schedule) or stepped (threshold, form) afterwards; a step shared
  * by jobs of several netlists takes the form of its first job's netlist.

@@ -6,10 +6,13 @@ long its waveforms are:
 * schedule (GSIM_OPT_SCHEDULE): level by level, with every admitted job's
   level in shared launches, or dependency-driven, one persistent launch per
   job with no level barrier (wins on small or unevenly active netlists);
-* evaluation form (GSIM_OPT_EVAL_FORM): merged positions or time segments per
-  lane;
+* evaluation form of the level schedule (GSIM_OPT_EVAL_FORM): merged
+  positions or time segments per lane;
 * dynamic-binning threshold (GSIM_OPT_LANE_THRESHOLD): gates whose inputs hold
-  fewer transitions than it run one per lane instead of one per wavefront.
+  fewer transitions than it run one per lane instead of one per wavefront;
+* tickets per claim of the dependency-driven schedule (GSIM_OPT_DF_TICKETS):
+  more cut the contended atomics, fewer keep light gates from waiting behind
+  heavy ones.
 
 The tuner times each candidate setting on a sample job and keeps the
 fastest, per (netlist, stimulus length bucket), applying it to the netlist
@@ -27,21 +30,23 @@ import numpy as np
 
 from . import gsim as G
 
-# (schedule, evaluation form, lane threshold)
+# (schedule, evaluation form, lane threshold, dependency-driven tickets per claim; 0 = automatic)
 CANDIDATES = (
-    (G.SCHEDULE_LEVELS, G.FORM_MERGED, 0),
-    (G.SCHEDULE_LEVELS, G.FORM_MERGED, 64),
-    (G.SCHEDULE_LEVELS, G.FORM_MERGED, 512),
-    (G.SCHEDULE_LEVELS, G.FORM_SEGMENTED, 0),
-    (G.SCHEDULE_DEPENDENCY, G.FORM_MERGED, 0),
-    (G.SCHEDULE_DEPENDENCY, G.FORM_SEGMENTED, 0),
+    (G.SCHEDULE_LEVELS, G.FORM_MERGED, 0, 0),
+    (G.SCHEDULE_LEVELS, G.FORM_MERGED, 64, 0),
+    (G.SCHEDULE_LEVELS, G.FORM_MERGED, 512, 0),
+    (G.SCHEDULE_LEVELS, G.FORM_SEGMENTED, 0, 0),
+    (G.SCHEDULE_DEPENDENCY, G.FORM_MERGED, 0, 0),
+    (G.SCHEDULE_DEPENDENCY, G.FORM_MERGED, 0, 4),
 )
 SCHEDULE_NAMES = {G.SCHEDULE_LEVELS: "levels", G.SCHEDULE_DEPENDENCY: "dataflow"}
 FORM_NAMES = {G.FORM_MERGED: "merged", G.FORM_SEGMENTED: "segmented"}
 
 
 def setting_name(c) -> str:
-    return f"{SCHEDULE_NAMES[c[0]]}/{FORM_NAMES[c[1]]}/lane{c[2]}"
+    if c[0] == G.SCHEDULE_DEPENDENCY:
+        return f"dataflow/tickets{c[3] if c[3] else 'auto'}"
+    return f"levels/{FORM_NAMES[c[1]]}/lane{c[2]}"
 
 
 def netlist_key(nl) -> str:
@@ -72,6 +77,7 @@ class Autotuner:
         self.sim.set_netlist_option(h, G.OPT_SCHEDULE, c[0])
         self.sim.set_netlist_option(h, G.OPT_EVAL_FORM, c[1])
         self.sim.set_netlist_option(h, G.OPT_LANE_THRESHOLD, c[2])
+        self.sim.set_netlist_option(h, G.OPT_DF_TICKETS, c[3] if c[3] else -1)
 
     def _time(self, h, st, c):
         self.apply(h, c)

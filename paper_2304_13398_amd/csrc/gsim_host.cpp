@@ -406,6 +406,7 @@ struct Netlist {
     int32_t lane_threshold = -1;    // -1: the context's GSIM_OPT_LANE_THRESHOLD
     int32_t schedule = -1;          // -1: the context's GSIM_OPT_SCHEDULE
     int32_t form = -1;              // -1: the context's GSIM_OPT_EVAL_FORM
+    int32_t df_tickets = -1;        // -1: the context's GSIM_OPT_DF_TICKETS
     double arena_per_input = 0.0;   // largest arena use per input transition seen so far
 };
 
@@ -1017,8 +1018,9 @@ Failure enqueue_dataflow(gsim_ctx ctx, Job *j, hipStream_t s) {
     // small jobs are latency-bound: one ticket per claim keeps every ready gate
     // on a wavefront of its own; large ones are bound by the claim counter and
     // by the fences, which a batch of ready gates shares
-    a.tickets = ctx->opt_df_tickets > 0 ? (uint32_t)ctx->opt_df_tickets
-                : nl.G < 16 * ctx->n_waves_resident ? 1u : 4u;
+    a.tickets = nl.df_tickets > 0 ? (uint32_t)nl.df_tickets
+                : ctx->opt_df_tickets > 0 ? (uint32_t)ctx->opt_df_tickets
+                : nl.G < 16 * ctx->n_waves_resident ? 1u : 2u;
     HIP_TRY(launch_df_init(a, nl.d_pend0, s));
     std::shared_ptr<StepTiming> tm;
     if (ctx->opt_timing) {
@@ -1027,7 +1029,7 @@ Failure enqueue_dataflow(gsim_ctx ctx, Job *j, hipStream_t s) {
         HIP_TRY(hipEventCreate(&tm->b));
         HIP_TRY(hipEventRecord(tm->a, s));
     }
-    HIP_TRY(launch_dataflow(a, n_waves, nl.form >= 0 ? nl.form : ctx->opt_form, s));
+    HIP_TRY(launch_dataflow(a, n_waves, s));
     if (tm) {
         HIP_TRY(hipEventRecord(tm->b, s));
         j->timing.push_back(tm);
@@ -1868,6 +1870,10 @@ gsim_status sim_set_netlist_option(gsim_ctx ctx, gsim_netlist nl, int option, in
     case GSIM_OPT_EVAL_FORM:
         if (value < -1 || value > 1) return record(ctx, fail(GSIM_E_ARG, "evaluation form must be -1, 0 or 1"));
         n.form = (int32_t)value;
+        return GSIM_OK;
+    case GSIM_OPT_DF_TICKETS:
+        if (value < -1 || value > 16) return record(ctx, fail(GSIM_E_ARG, "tickets per claim must be in [-1, 16]"));
+        n.df_tickets = (int32_t)value <= 0 ? -1 : (int32_t)value;
         return GSIM_OK;
     }
     return record(ctx, fail(GSIM_E_ARG, "option %d is not per netlist", option));

@@ -165,7 +165,7 @@ hipError_t launch_eval_lane(const StepArgs &a, int64_t max_items, hipStream_t s)
 // Dependency-driven schedule: reset the counters and queue, then run every
 // gate of the job with n_waves persistent wavefronts.
 hipError_t launch_df_init(const DfArgs &a, const int32_t *pend0, hipStream_t s);
-hipError_t launch_dataflow(const DfArgs &a, int64_t n_waves, int form, hipStream_t s);
+hipError_t launch_dataflow(const DfArgs &a, int64_t n_waves, hipStream_t s);
 hipError_t launch_count_out(const int64_t *len, int64_t S, int64_t G, int64_t *partial,
                             int64_t n_partial, DevState *state, hipStream_t s);
 hipError_t launch_gather(const int64_t *src_off, const int64_t *n_items, const int64_t *dst_off,

@@ -15,8 +15,6 @@
 // Transitions live in the arena packed as time << 2 | value (8 bytes).
 #include "eval_core.h"
 
-#include <type_traits>
-
 #include <mutex>
 
 namespace gsim {
@@ -409,6 +407,20 @@ __device__ __forceinline__ void df_acquire_inputs(const DfArgs &A, int32_t g_lan
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
+// Queue the n gates listed at list[0, n) (LDS) with one atomic on the tail.
+constexpr int kDfReadyList = 512;
+static_assert(kDfReadyList <= kWindowLarge + kRoundSlots + 32, "the ready list fits the survivor area");
+__device__ __forceinline__ void df_push(const DfArgs &A, const uint32_t *list, int n) {
+    const int lane = lane_id();
+    __syncthreads();  // the list's entries, written by every lane
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&A.ctl->tail, (uint32_t)n);
+    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+    for (int i = lane; i < n; i += 64)
+        __hip_atomic_store(A.queue + base + i, (int32_t)list[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();  // before the list is written again
+}
+
 // A wavefront takes A.tickets (1..kDfMaxTickets) consecutive tickets per
 // atomic and works through them in order; the gates of those tickets whose
 // slots are already filled run as one batch between one acquire and one
@@ -421,10 +433,9 @@ constexpr uint32_t kDfMaxTickets = 16;
 // Arena space is reserved per wavefront in chunks of A.chunk transitions (or
 // one gate's bound if larger), so the arena top takes one atomic per chunk.
 
-template <bool EDGE, int FORM>
+template <bool EDGE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void dataflow_kernel(DfArgs A) {
-    using Lds = typename std::conditional<FORM == kFormSegmented, SegLds<kWindowLarge>, WaveLds<kWindowLarge>>::type;
-    __shared__ Lds L;
+    __shared__ WaveLds<kWindowLarge> L;
     const int lane = lane_id();
     const JobDesc &J = A.job;
     DevState *st = J.state;
@@ -485,25 +496,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
                 } else {
                     reinterpret_cast<uint32_t *>(L.lut)[lane] =
                         reinterpret_cast<const uint32_t *>(J.lut + (int)R.type * 256)[lane];
-                    if constexpr (FORM == kFormSegmented) {
-                        switch (R.k) {
-                        case 1: eval_gate_seg<1, kWindowLarge, EDGE, false, true>(J, ob, R, g, L); break;
-                        case 2: eval_gate_seg<2, kWindowLarge, EDGE, false, true>(J, ob, R, g, L); break;
-                        case 3: eval_gate_seg<3, kWindowLarge, EDGE, false, true>(J, ob, R, g, L); break;
-                        default: eval_gate_seg<4, kWindowLarge, EDGE, false, true>(J, ob, R, g, L); break;
-                        }
-                    } else {
-                        switch (R.k) {
-                        case 1: eval_gate<1, kWindowLarge, EDGE, !EDGE, false, true>(J, ob, R, g, L); break;
-                        case 2: eval_gate<2, kWindowLarge, EDGE, !EDGE, false, true>(J, ob, R, g, L); break;
-                        case 3: eval_gate<3, kWindowLarge, EDGE, !EDGE, false, true>(J, ob, R, g, L); break;
-                        default: eval_gate<4, kWindowLarge, EDGE, !EDGE, false, true>(J, ob, R, g, L); break;
-                        }
+                    switch (R.k) {
+                    case 1: eval_gate<1, kWindowLarge, EDGE, !EDGE, false, true>(J, ob, R, g, L); break;
+                    case 2: eval_gate<2, kWindowLarge, EDGE, !EDGE, false, true>(J, ob, R, g, L); break;
+                    case 3: eval_gate<3, kWindowLarge, EDGE, !EDGE, false, true>(J, ob, R, g, L); break;
+                    default: eval_gate<4, kWindowLarge, EDGE, !EDGE, false, true>(J, ob, R, g, L); break;
                     }
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            // consumers whose last pending pin this was: queued with one atomic per batch
+            // consumers whose last pending pin this was: listed in LDS (the
+            // evaluation's survivor area, free between gates) and queued with
+            // one tail atomic for the whole batch. (A consumer synchronises
+            // with every producer through its pending count: df_acquire_inputs.)
+            int n_ready = 0;
             for (int b = 0; b < nb; b++) {
                 const int32_t g = __builtin_amdgcn_readlane(g_lane, b);
                 const int64_t f1 = A.fo_off[g + 1];
@@ -513,17 +519,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
                     const bool ready = c >= 0 && atomicSub(&A.pend[c], 1) == 1;
                     const uint64_t mask = __ballot(ready);
                     if (mask == 0) continue;
-                    // (the consumer synchronises with every producer through
-                    // the pending count itself: see df_acquire_inputs)
-                    const int leader = __ffsll((unsigned long long)mask) - 1;
-                    uint32_t base = 0;
-                    if (lane == leader) base = atomicAdd(&A.ctl->tail, (uint32_t)__popcll(mask));
-                    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
-                    if (ready)
-                        __hip_atomic_store(A.queue + base + lanes_below(mask), c, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+                    if (ready) L.seq[n_ready + lanes_below(mask)] = (uint32_t)c;
+                    n_ready += __popcll(mask);
+                    if (n_ready > kDfReadyList - 64) {
+                        df_push(A, L.seq, n_ready);
+                        n_ready = 0;
+                    }
                 }
             }
+            if (n_ready > 0) df_push(A, L.seq, n_ready);
             t += nb;
         }
     }
@@ -740,16 +744,11 @@ hipError_t launch_df_init(const DfArgs &a, const int32_t *pend0, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t launch_dataflow(const DfArgs &a, int64_t n_waves, int form, hipStream_t s) {
+hipError_t launch_dataflow(const DfArgs &a, int64_t n_waves, hipStream_t s) {
     if (a.G <= 0 || n_waves <= 0) return hipSuccess;
     const dim3 grid((unsigned)n_waves), block(64);
-    if (form == kFormSegmented) {
-        if (a.job.edly) dataflow_kernel<true, kFormSegmented><<<grid, block, 0, s>>>(a);
-        else dataflow_kernel<false, kFormSegmented><<<grid, block, 0, s>>>(a);
-    } else {
-        if (a.job.edly) dataflow_kernel<true, kFormMerged><<<grid, block, 0, s>>>(a);
-        else dataflow_kernel<false, kFormMerged><<<grid, block, 0, s>>>(a);
-    }
+    if (a.job.edly) dataflow_kernel<true><<<grid, block, 0, s>>>(a);
+    else dataflow_kernel<false><<<grid, block, 0, s>>>(a);
     return hipGetLastError();
 }
 

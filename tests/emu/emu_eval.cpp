@@ -20,7 +20,7 @@
 // dependency-driven form with the level kernel's shorter tile and
 // trailing-group code; 3 the level kernel's form without that shorter code;
 // 4 the segmented form (eval_gate_seg) as the level kernel runs it; 5 the
-// segmented form as the dependency-driven kernel runs it.
+// segmented form with agent-scope stores and no prefetch.
 #include <sys/mman.h>
 
 #include <cstdarg>

@@ -10,8 +10,9 @@ Each gate gets the oracle's waveforms of its input nets, so the comparison is
 of the per-gate procedure alone (Algorithm 2 with Eq. 1 and the Fig. 3 drop),
 independent of the schedule that feeds it.
 
-Forms: "seg" and "seg_dataflow" (the segmented form, eval_gate_seg, as the
-level and the dependency-driven kernels run it), "levels" (the merged form
+Forms: "seg" (the segmented form, eval_gate_seg, as the level kernel runs
+it), "seg_dataflow" (the same with agent-scope stores and no prefetch),
+"levels" (the merged form
 of the level kernel: tiles prefetched, shorter tile and trailing-group code),
 "levels_long" (that form without the shorter code), "dataflow" (the merged
 form of the dependency-driven kernel), and

@@ -115,7 +115,7 @@ def test_autotuner_settings_are_exact(sim):
             assert same(fetch_gates(sim, j, nl), O.o1_simulate(nl, x)), autotune.setting_name(c)
             sim.release(j)
     finally:
-        for opt in (G.OPT_SCHEDULE, G.OPT_EVAL_FORM, G.OPT_LANE_THRESHOLD):
+        for opt in (G.OPT_SCHEDULE, G.OPT_EVAL_FORM, G.OPT_LANE_THRESHOLD, G.OPT_DF_TICKETS):
             sim.set_netlist_option(h, opt, -1)
         sim.unload_netlist(h)
 
