@@ -263,10 +263,12 @@ def timed_job(G, sim, nl, st, steps, warmup, name, profile_key):
     avg_launch_s = eval_ms / launches / 1000.0
     achieved = b_min / launches / avg_launch_s / 1e9
     traffic_file, sq_file = PROFILE_FILES[profile_key]
-    traffic_per_launch = profile_value(traffic_file, "traffic_bytes_per_launch")
-    valu = profile_value(sq_file, "SQ_INSTS_VALU")
+    # per level: both delay windows' evaluate kernels, as the live timing brackets them
+    traffic_per_launch = profile_value(traffic_file, "level_traffic_bytes")
+    valu = profile_value(sq_file, "level_valu")
     roof = {
-        "kernel": "eval_wave_kernel (one wavefront per gate; the level's launches bracketed together)",
+        "kernel": "eval_wave_kernel (one wavefront per gate; per level, the 64 ps and 256 ps window launches "
+                  "bracketed together by HIP events on the job's stream)",
         "bound": "hbm",
         "achieved": achieved,
         "peak": HBM_PEAK_GBPS,
