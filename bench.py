@@ -697,8 +697,10 @@ def bench_served(G, sim, rates, seed, seconds, full):
     for rate in rates:
         n_jobs = 1000 if full else int(min(1000, max(100, rate * seconds)))
         reqs = serve.served_workload(n_jobs, rate, nls, pool, seed=seed + int(rate))
-        rc, mc = serve.serve_continuous(sim, hs, reqs, max_ahead=SERVE_LOOKAHEAD)
-        rs, ms = serve.serve_sequential(sim, hs, reqs)
+        rc, mc = serve.serve_continuous(sim, hs, reqs, max_ahead=SERVE_LOOKAHEAD,
+                                        progress=lambda m: say(f"served rate {rate} continuous: {m}"))
+        rs, ms = serve.serve_sequential(sim, hs, reqs,
+                                        progress=lambda m: say(f"served rate {rate} sequential: {m}"))
         c, s = serve.summarize(rc, mc), serve.summarize(rs, ms)
         out["rates"][str(rate)] = {"jobs": n_jobs, "continuous": c, "sequential": s}
         say(f"served rate {rate} ({n_jobs} jobs): continuous p50/p99 {c['p50_ms']:.1f}/{c['p99_ms']:.1f} ms, "

@@ -67,7 +67,12 @@ def _finish(sim, j, req, t0):
     return Result(lat, int(n_out), int(off[-1]), fp, req)
 
 
-def serve_continuous(sim: G.Sim, handles, requests, max_ahead: int = 8):
+def _progress(progress, results, total):
+    if progress and len(results) % 100 == 0:
+        progress(f"{len(results)}/{total} requests done")
+
+
+def serve_continuous(sim: G.Sim, handles, requests, max_ahead: int = 8, progress=None):
     reqs = sorted(requests, key=lambda r: r.arrival)
     results = []
     running = {}
@@ -83,12 +88,13 @@ def serve_continuous(sim: G.Sim, handles, requests, max_ahead: int = 8):
             sim.drive(max_ahead=max_ahead)
             for j in [j for j in running if sim.done(j)]:
                 results.append(_finish(sim, j, running.pop(j), t0))
+                _progress(progress, results, len(reqs))
         elif i < len(reqs):
             time.sleep(max(0.0, min(0.001, reqs[i].arrival - now)))
     return results, time.perf_counter() - t0
 
 
-def serve_sequential(sim: G.Sim, handles, requests):
+def serve_sequential(sim: G.Sim, handles, requests, progress=None):
     reqs = sorted(requests, key=lambda r: r.arrival)
     results = []
     t0 = time.perf_counter()
@@ -99,6 +105,7 @@ def serve_sequential(sim: G.Sim, handles, requests):
         j = sim.run(handles[r.netlist], r.stim)
         sim.wait(j)
         results.append(_finish(sim, j, r, t0))
+        _progress(progress, results, len(reqs))
     return results, time.perf_counter() - t0
 
 
