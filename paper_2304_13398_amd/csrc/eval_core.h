@@ -68,6 +68,13 @@ __device__ __forceinline__ uint32_t dpp_u32(uint32_t identity, uint32_t x) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)x, CTRL, ROW_MASK, 0xf, false);
 }
 
+// The same move with every row and bank enabled and out-of-range source lanes
+// reading 0: every lane is written, so no register is set up for `old`.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32_zero(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, true);
+}
+
 __device__ __forceinline__ uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
 
 
@@ -217,10 +224,11 @@ __device__ __forceinline__ uint32_t compose_upd(uint32_t e, uint32_t l) {
 }
 
 __device__ __forceinline__ uint32_t wave_prefix_compose(uint32_t x) {
-    x = compose_upd(dpp_u32<kDppRowShr1>(0u, x), x);
-    x = compose_upd(dpp_u32<kDppRowShr2>(0u, x), x);
-    x = compose_upd(dpp_u32<kDppRowShr4>(0u, x), x);
-    x = compose_upd(dpp_u32<kDppRowShr8>(0u, x), x);
+    // (0 is the identity update)
+    x = compose_upd(dpp_u32_zero<kDppRowShr1>(x), x);
+    x = compose_upd(dpp_u32_zero<kDppRowShr2>(x), x);
+    x = compose_upd(dpp_u32_zero<kDppRowShr4>(x), x);
+    x = compose_upd(dpp_u32_zero<kDppRowShr8>(x), x);
     x = compose_upd(dpp_u32<kDppRowBcast15, 0xa>(0u, x), x);
     x = compose_upd(dpp_u32<kDppRowBcast31, 0xc>(0u, x), x);
     return x;
@@ -516,12 +524,29 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
             merge8<9, AGENT>(AB, ab, L.tile + Tl::OFF(2) + 1, m[2], 8 * lane, mk);
             if (m[0] + m[1] + m[2] > 512) cut = (uint32_t)__builtin_amdgcn_readlane((int)mk[7], 63) >> 4;
         } else {
-            // the first 256 of pins 0 and 1 (lanes 0-31) and of pins 2 and 3 (lanes 32-63)
+            // the first 256 of one pair of pins (lanes 0-31) and of the other
+            // (lanes 32-63). A pair ends the round at its 257th key, so the
+            // pins are paired to make the larger pair's in-round count as
+            // small as possible (the keys carry their pin; any pairing gives
+            // the same merged order)
+            int q1 = 1, q2 = 2, q3 = 3;  // pairs (0, q1) and (q2, q3)
+            {
+                const int a01 = m[0] + m[1], a23 = m[2] + m[K - 1], a02 = m[0] + m[2],
+                          a13 = m[1] + m[K - 1], a03 = m[0] + m[K - 1], a12 = m[1] + m[2];
+                const int s01 = a01 > a23 ? a01 : a23, s02 = a02 > a13 ? a02 : a13,
+                          s03 = a03 > a12 ? a03 : a12;
+                if (s02 < s01 && s02 <= s03) { q1 = 2; q2 = 1; }
+                else if (s03 < s01 && s03 < s02) { q1 = 3; q2 = 1; q3 = 2; }
+            }
+            const int m_q1 = q1 == 1 ? m[1] : q1 == 2 ? m[2] : m[K - 1];
+            const int m_q2 = q2 == 1 ? m[1] : m[2];
+            const int m_q3 = q3 == 2 ? m[2] : m[K - 1];
+            const int n_ab = m[0] + m_q1, n_cd = m_q2 + m_q3;
             const bool hi_half = lane >= 32;
-            const uint32_t *A = L.tile + (hi_half ? Tl::OFF(2) : Tl::OFF(0)) + 1;
-            const uint32_t *B = L.tile + (hi_half ? Tl::OFF(3) : Tl::OFF(1)) + 1;
-            const int a = hi_half ? m[2] : m[0];
-            const int b = hi_half ? m[K - 1] : m[1];
+            const uint32_t *A = L.tile + (hi_half ? q2 * (TT + 1 + kMergePad) : Tl::OFF(0)) + 1;
+            const uint32_t *B = L.tile + (hi_half ? q3 : q1) * (TT + 1 + kMergePad) + 1;
+            const int a = hi_half ? m_q2 : m[0];
+            const int b = hi_half ? m_q3 : m_q1;
             uint32_t h[8];
             merge8<8, AGENT>(A, a, B, b, 8 * (lane & 31), h);
             uint32_t *dst = (hi_half ? CD : AB) + 8 * (lane & 31);
@@ -531,11 +556,10 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
             if (!AGENT && lane == 2 * kMergePad) CD[-1] = 0u;  // the second list's guard (after AB's pads)
             const uint32_t c_ab = (uint32_t)__builtin_amdgcn_readlane((int)h[7], 31) >> 4;
             const uint32_t c_cd = (uint32_t)__builtin_amdgcn_readlane((int)h[7], 63) >> 4;
-            if (m[0] + m[1] > 256) cut = c_ab;
-            if (m[2] + m[K - 1] > 256) cut = umin32(cut, c_cd);
+            if (n_ab > 256) cut = c_ab;
+            if (n_cd > 256) cut = umin32(cut, c_cd);
             __syncthreads();
-            merge8<9, AGENT>(AB, m[0] + m[1] < 256 ? m[0] + m[1] : 256, CD,
-                      m[2] + m[K - 1] < 256 ? m[2] + m[K - 1] : 256, 8 * lane, mk);
+            merge8<9, AGENT>(AB, n_ab < 256 ? n_ab : 256, CD, n_cd < 256 ? n_cd : 256, 8 * lane, mk);
         }
         if (cut != kNoTime28 && (int64_t)cut - 1 < H - base) {
             // the round ends before the cut key's time: fewer keys of each pin are in
@@ -544,23 +568,18 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
             const uint32_t hk32 = hoff << 4 | 15u;
 #pragma unroll
             for (int k = 0; k < 8; k++) mk[k] = mk[k] <= hk32 ? mk[k] : kNoKey32;
-            // in-round keys per pin: 8-bit counts per lane, summed over each
-            // row of 16 lanes (at most 128 per field), then over the rows
-            uint32_t cnt = 0;
-#pragma unroll
-            for (int k = 0; k < 8; k++) cnt += mk[k] != kNoKey32 ? 1u << (8 * (mk[k] & 3u)) : 0u;
-            cnt += dpp_u32<kDppRowShr1>(0u, cnt);
-            cnt += dpp_u32<kDppRowShr2>(0u, cnt);
-            cnt += dpp_u32<kDppRowShr4>(0u, cnt);
-            cnt += dpp_u32<kDppRowShr8>(0u, cnt);
-            uint32_t rows[4];
-#pragma unroll
-            for (int r = 0; r < 4; r++) rows[r] = (uint32_t)__builtin_amdgcn_readlane((int)cnt, 16 * r + 15);
+            // in-round keys per pin: a prefix of its sorted LDS tile (the rest
+            // of the tile and its pads hold kNoKey32). Lane j tests the last
+            // key of block [8j, 8j + 8); the full blocks counted, lanes 0-7
+            // test the keys of the next block.
 #pragma unroll
             for (int p = 0; p < K; p++) {
-                m[p] = 0;
-#pragma unroll
-                for (int r = 0; r < 4; r++) m[p] += (int)((rows[r] >> (8 * p)) & 0xFFu);
+                const uint32_t *tp = L.tile + Tl::OFF(p) + 1;
+                constexpr int kBlocks = TT / 8;
+                const uint32_t k1 = tp[lane < kBlocks ? 8 * lane + 7 : TT - 1];
+                const int c1 = __popcll(__ballot(lane < kBlocks && k1 <= hk32));
+                const uint32_t k2 = tp[8 * c1 + (lane & 7)];  // < TT + 8: inside the tile and its pads
+                m[p] = 8 * c1 + __popcll(__ballot(lane < 8 && k2 <= hk32));
             }
         }
         bool all_in = true;
@@ -569,11 +588,6 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         // split horizon: with every remaining input in this round, all survivors are final
         const uint32_t hsplit = all_in ? kNoKey32 : (uint32_t)(H - base) << 2 | 3u;
         constexpr bool kPrefetch = PREFETCH;
-        PinTile<TT> nx[K];
-        if constexpr (kPrefetch) {
-#pragma unroll
-            for (int p = 0; p < K; p++) tile_fetch<TT, LEAN>(Kar + pb[p] + cur[p] + m[p], rem[p] - m[p], nx[p]);
-        }
 
         // ---- pin states: this lane's composed update, scanned over the wave
         uint32_t upd = 0, trail_mask = 0;
@@ -594,80 +608,111 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
             }
         }
         const uint32_t upd_incl = wave_prefix_compose(upd);
-        const uint32_t upd_excl = wave_shift_up(0u, upd_incl);
+        const uint32_t upd_excl = dpp_u32_zero<kDppWaveShr1>(upd_incl);
         const uint32_t upd_all = (uint32_t)__builtin_amdgcn_readlane((int)upd_incl, 63);
         const uint32_t next_first = wave_shift_down(kNoTime28, mk[0] >> 4);
         const uint32_t prev_trail = wave_shift_up(kNoKey32, t_last << 4 | trail_mask);
 
-        // ---- gate value after each transition; time-group ends; edge classes
+        // ---- gate value after each transition, time-group ends and candidates
         uint32_t st = (state0 & ~(upd_excl >> 8) & 0xFFu) | (upd_excl & 0xFFu);
-        uint32_t evs = 0;    // gate value after each transition, 2 bits each
-        uint32_t edges = 0;  // edge model: edge class of each transition, 2 bits each
-        uint32_t ge = 0, e_lastge = 0;
-#pragma unroll
-        for (int k = 0; k < 8; k++) {
-            const uint32_t sh = K == 1 ? 0u : (mk[k] & 3u) * 2u;
-            const uint32_t nv = (mk[k] >> 2) & 3u;
-            if (EDGE) edges |= edge_class((st >> sh) & 3u, nv) << (2 * k);
-            st = (st & ~(3u << sh)) | (nv << sh);
-            // table entries are 0, 1 or X (2); the 2-bit extract replaces the
-            // byte mask the compiler adds after each byte load
-            const uint32_t ek = __builtin_amdgcn_ubfe(L.lut[st], 0, 2);
-            evs |= ek << (2 * k);
-            const uint32_t tn = k < 7 ? mk[k + 1] >> 4 : next_first;
-            const bool end = mk[k] != kNoKey32 && (mk[k] >> 4) != tn;
-            ge |= end ? 1u << k : 0u;
-            e_lastge = end ? ek : e_lastge;
-        }
-        const uint32_t e0 = first_round ? kX : L.lut[state0];
-        const uint32_t e_from_prev = wave_shift_up(e0, e_lastge);
-        // edge model: this lane's trailing time group, delays to 0/1/X (10-bit fields)
-        uint32_t prev_trail_d = 0;
-        if (EDGE) {
-            uint32_t d0 = kEdgeNone, d1 = kEdgeNone, dx = kEdgeNone;
-#pragma unroll
-            for (int k = LEAN ? 8 - K : 0; k < 8; k++) {
-                if ((mk[k] >> 4) != t_last || mk[k] == kNoKey32) continue;
-                const uint32_t ent = L.etab[(mk[k] & 3u) * 3 + ((edges >> (2 * k)) & 3u)];
-                d0 = umin32(d0, ent & 1023u);
-                d1 = umin32(d1, (ent >> 10) & 1023u);
-                dx = umin32(dx, ent >> 20);
-            }
-            prev_trail_d = wave_shift_up(kEdgeNone | kEdgeNone << 10 | kEdgeNone << 20,
-                                         d0 | d1 << 10 | dx << 20);
-        }
-
-        // ---- candidates at group ends
         uint32_t sk[8];
-        {
+        if constexpr (!EDGE) {
+            // One pass. A group's candidate is kept if its value differs from
+            // the value after the previous group. For the lane's first group
+            // that is the gate value at the lane's start, unless the group
+            // began in the previous lane (a straddling group): then its
+            // candidate is kept here and decided after the pass, against the
+            // previous lane's value.
+            const uint32_t e_start = lane == 0 && first_round ? kX : __builtin_amdgcn_ubfe(L.lut[st], 0, 2);
             uint32_t run_t = prev_trail >> 4, run_m = prev_trail & 15u;
+            const bool straddle = mk[0] != kNoKey32 && (mk[0] >> 4) == run_t;
+            bool open = straddle;  // the straddling group has not ended yet
+            uint32_t e_prev = e_start;
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const uint32_t sh = K == 1 ? 0u : (mk[k] & 3u) * 2u;
+                st = (st & ~(3u << sh)) | (((mk[k] >> 2) & 3u) << sh);
+                // table entries are 0, 1 or X (2); the 2-bit extract replaces the
+                // byte mask the compiler adds after each byte load
+                const uint32_t ek = __builtin_amdgcn_ubfe(L.lut[st], 0, 2);
+                const uint32_t tk = mk[k] >> 4;
+                const uint32_t tn = k < 7 ? mk[k + 1] >> 4 : next_first;
+                const bool end = mk[k] != kNoKey32 && tk != tn;
+                const uint32_t pbit = K == 1 ? 1u : 1u << (mk[k] & 3u);
+                run_m = tk == run_t ? run_m | pbit : pbit;
+                run_t = tk;
+                sk[k] = end && (open || ek != e_prev) ? ((tk + L.dtab[ek * 16 + run_m]) << 2) | ek : kNoKey32;
+                e_prev = end ? ek : e_prev;
+                open = open && !end;
+            }
+            // the value after the previous lane's last group
+            const uint32_t e0 = first_round ? kX : L.lut[state0];
+            const uint32_t e_from_prev = wave_shift_up(e0, e_prev);
+            if (straddle) {
+                // its first candidate (the first key present) is dropped if
+                // the gate value did not change
+                bool seen = false;
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    const bool here = !seen && sk[k] != kNoKey32;
+                    if (here && (sk[k] & 3u) == e_from_prev) sk[k] = kNoKey32;
+                    seen = seen || here;
+                }
+            }
+        } else {
+            uint32_t evs = 0;    // gate value after each transition, 2 bits each
+            uint32_t edges = 0;  // edge class of each transition, 2 bits each
+            uint32_t ge = 0, e_lastge = 0;
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const uint32_t sh = K == 1 ? 0u : (mk[k] & 3u) * 2u;
+                const uint32_t nv = (mk[k] >> 2) & 3u;
+                edges |= edge_class((st >> sh) & 3u, nv) << (2 * k);
+                st = (st & ~(3u << sh)) | (nv << sh);
+                const uint32_t ek = __builtin_amdgcn_ubfe(L.lut[st], 0, 2);
+                evs |= ek << (2 * k);
+                const uint32_t tn = k < 7 ? mk[k + 1] >> 4 : next_first;
+                const bool end = mk[k] != kNoKey32 && (mk[k] >> 4) != tn;
+                ge |= end ? 1u << k : 0u;
+                e_lastge = end ? ek : e_lastge;
+            }
+            const uint32_t e0 = first_round ? kX : L.lut[state0];
+            const uint32_t e_from_prev = wave_shift_up(e0, e_lastge);
+            // this lane's trailing time group, delays to 0/1/X (10-bit fields)
+            uint32_t prev_trail_d;
+            {
+                uint32_t d0 = kEdgeNone, d1 = kEdgeNone, dx = kEdgeNone;
+#pragma unroll
+                for (int k = LEAN ? 8 - K : 0; k < 8; k++) {
+                    if ((mk[k] >> 4) != t_last || mk[k] == kNoKey32) continue;
+                    const uint32_t ent = L.etab[(mk[k] & 3u) * 3 + ((edges >> (2 * k)) & 3u)];
+                    d0 = umin32(d0, ent & 1023u);
+                    d1 = umin32(d1, (ent >> 10) & 1023u);
+                    dx = umin32(dx, ent >> 20);
+                }
+                prev_trail_d = wave_shift_up(kEdgeNone | kEdgeNone << 10 | kEdgeNone << 20,
+                                             d0 | d1 << 10 | dx << 20);
+            }
+            // candidates at group ends
+            uint32_t run_t = prev_trail >> 4;
             uint32_t r0 = prev_trail_d & 1023u, r1 = (prev_trail_d >> 10) & 1023u, rx = prev_trail_d >> 20;
             uint32_t e_prev = e_from_prev;
 #pragma unroll
             for (int k = 0; k < 8; k++) {
                 const uint32_t tk = mk[k] >> 4;
                 const bool cont = tk == run_t;
-                if (EDGE) {
-                    const uint32_t ent = L.etab[(mk[k] & 3u) * 3 + ((edges >> (2 * k)) & 3u)];
-                    r0 = cont ? umin32(r0, ent & 1023u) : ent & 1023u;
-                    r1 = cont ? umin32(r1, (ent >> 10) & 1023u) : (ent >> 10) & 1023u;
-                    rx = cont ? umin32(rx, ent >> 20) : ent >> 20;
-                } else {
-                    const uint32_t pbit = K == 1 ? 1u : 1u << (mk[k] & 3u);
-                    run_m = cont ? run_m | pbit : pbit;
-                }
+                const uint32_t ent = L.etab[(mk[k] & 3u) * 3 + ((edges >> (2 * k)) & 3u)];
+                r0 = cont ? umin32(r0, ent & 1023u) : ent & 1023u;
+                r1 = cont ? umin32(r1, (ent >> 10) & 1023u) : (ent >> 10) & 1023u;
+                rx = cont ? umin32(rx, ent >> 20) : ent >> 20;
                 run_t = tk;
                 sk[k] = kNoKey32;
                 if ((ge >> k) & 1u) {
                     const uint32_t ek = (evs >> (2 * k)) & 3u;
                     if (ek != e_prev) {
-                        if (EDGE) {
-                            const uint32_t d = ek == 0u ? r0 : ek == 1u ? r1 : rx;
-                            // no related pin changed: the candidate never appears
-                            if (d != kEdgeNone) sk[k] = ((tk + d) << 2) | ek;
-                        } else {
-                            sk[k] = ((tk + L.dtab[ek * 16 + run_m]) << 2) | ek;
-                        }
+                        const uint32_t d = ek == 0u ? r0 : ek == 1u ? r1 : rx;
+                        // no related pin changed: the candidate never appears
+                        if (d != kEdgeNone) sk[k] = ((tk + d) << 2) | ek;
                     }
                     e_prev = ek;
                 }
@@ -675,6 +720,13 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         }
         first_round = false;
         state0 = (state0 & ~(upd_all >> 8) & 0xFFu) | (upd_all & 0xFFu);
+
+        // the next round's tiles load while the survivors are found
+        PinTile<TT> nx[K];
+        if constexpr (kPrefetch) {
+#pragma unroll
+            for (int p = 0; p < K; p++) tile_fetch<TT, LEAN>(Kar + pb[p] + cur[p] + m[p], rem[p] - m[p], nx[p]);
+        }
 
         // ---- survivors among this round's candidates
         uint32_t lmin = kNoKey32;
@@ -686,7 +738,9 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         uint32_t keepmask = 0;
 #pragma unroll
         for (int k = 7; k >= 0; k--) {
-            const bool keep = sk[k] != kNoKey32 && (sk[k] >> 2) < (later >> 2);
+            // appears before every later candidate (a missing one, kNoKey32,
+            // is never below a key with its value bits cleared)
+            const bool keep = sk[k] < (later & ~3u);
             later = umin32(later, sk[k]);
             keepmask |= keep ? (1u << k) : 0u;
         }

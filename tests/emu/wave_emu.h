@@ -137,6 +137,15 @@ inline int update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, b
     return (int)(uint32_t)wave().slot[r][s];
 }
 
+// DPP move without an `old` operand: defined only when every lane is written
+// (all rows and banks enabled, out-of-range sources reading 0).
+inline int mov_dpp(int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
+    if (row_mask != 0xf || bank_mask != 0xf || !bound_ctrl)
+        fail("mov_dpp leaves lanes unwritten (row mask 0x%x, bank mask 0x%x, bound_ctrl %d)",
+             row_mask, bank_mask, (int)bound_ctrl);
+    return update_dpp(0, src, ctrl, row_mask, bank_mask, bound_ctrl);
+}
+
 inline int shfl_up(int x, int d, int width) {
     const int r = exchange(kOpShflUp, (uint32_t)x);
     const int i = lane();
@@ -207,6 +216,7 @@ constexpr hipError_t hipSuccess = 0;
 #define __builtin_amdgcn_readlane(x, l) ::emu::readlane((x), (l))
 #define __builtin_amdgcn_readfirstlane(x) ::emu::readfirstlane((x))
 #define __builtin_amdgcn_update_dpp(o, s, c, rm, bm, bc) ::emu::update_dpp((o), (s), (c), (rm), (bm), (bc))
+#define __builtin_amdgcn_mov_dpp(s, c, rm, bm, bc) ::emu::mov_dpp((s), (c), (rm), (bm), (bc))
 #define __builtin_amdgcn_mbcnt_lo(m, a) ::emu::mbcnt_lo((m), (a))
 #define __builtin_amdgcn_mbcnt_hi(m, a) ::emu::mbcnt_hi((m), (a))
 #define __builtin_amdgcn_ubfe(x, o, w) ::emu::ubfe((x), (o), (w))

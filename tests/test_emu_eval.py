@@ -112,3 +112,25 @@ def test_wide_delays_xz_sources():
     for mode in ("seg", "seg_dataflow", "levels", "dataflow"):
         got, err, _ = E.run(mode, nl, st, want, lut, dly=dly, max_ops=MAX_OPS)
         compare(got, err, want, np.arange(nl.G))
+
+
+def test_long_waveforms_every_pin_count():
+    """Industrial-shaped netlist (all cell types, power-law fanout, 1-200 ps
+    delays) with 600 transitions per source: gates of every pin count whose
+    inputs span several rounds, so that rounds end at the 512-slot cut, the
+    four-pin merge pairs its pins both ways, and time groups straddle two
+    lanes of a round."""
+    nl = W.make_netlist(G=20_000, S=200, L=40, types=W.TYPES_ALL, dmax=200, powerlaw=True,
+                        fanout_cap=5000, seed=3, name="long")
+    st = W.make_stimulus(S=200, n_per_src=600, window=1_000_000, probs=(0.49, 0.49, 0.01, 0.01), seed=3)
+    want = O.o1_simulate(nl, st, threads=4)
+    lut = E.builtin_lut(O.gate_eval)
+    k = np.diff(nl.pin_off)
+    n_in = np.concatenate([np.diff(st.off), np.diff(want[0])])[nl.pin_net]
+    wg = np.add.reduceat(n_in, nl.pin_off[:-1])
+    gates = np.unique(np.concatenate([np.nonzero((k == kk) & (wg > 1500))[0][:80] for kk in (1, 2, 3, 4)] +
+                                     [np.arange(0, nl.G, 211)]))
+    assert all(np.count_nonzero(k[gates] == kk) >= 40 for kk in (1, 2, 3, 4))
+    for mode in ("levels", "dataflow"):
+        got, err, _ = E.run(mode, nl, st, want, lut, gates=gates, max_ops=MAX_OPS)
+        compare(got, err, want, gates)
