@@ -132,12 +132,16 @@ __device__ __forceinline__ uint32_t wave_shift_down(uint32_t identity, uint32_t 
 // 256 of each pair through LDS, then one more merge). Tiles are held as the
 // low 32 bits of the packed transitions; a tile keeps only transitions whose
 // high word equals its first one's (the rest wait for a later round), so
-// one uniform word completes every key of the tile. Pin values after each
-// merged transition come from a wave scan of "set pin p to v" updates; a
-// transition ends a time group when the next one has another time; the
-// group's candidate takes its delay from a per-gate table indexed by new
-// value and the set of pins in the group. Candidates appear at 32-bit
-// offsets (offset << 2 | value). Survivors come from a suffix minimum over
+// one uniform word completes every key of the tile. Each lane applies its
+// transitions to the pin values before its first position: with one pin the
+// previous lane's last key gives them, with two the key before the
+// merge-path split in each pin's tile, with three or four a wave scan of "set
+// pin p to v" updates. A transition ends a time group when the next one has
+// another time; the group's candidate takes its delay from a per-gate table
+// indexed by new value and the set of pins in the group, and is kept if the
+// gate value differs from the one after the previous group (decided after
+// the pass for a group that began in the previous lane). Candidates appear
+// at 32-bit offsets (offset << 2 | value). Survivors come from a suffix minimum over
 // the round (DPP scans). A survivor with r <= H is final (later candidates
 // appear after H); the others stay tentative in LDS and are re-tested
 // against the next rounds -- at most W of them exist for gates whose largest
@@ -158,7 +162,8 @@ struct WaveLds {
     uint32_t seq[W + kRoundSlots + 32];  // tentative survivors [0, nq), then this round's;
                                          // the pairwise-merge buffers alias seq[W, W + kMergeBuf)
     uint32_t tile[kTileWords];           // K x [guard, T keys, 8 INF]
-    uint32_t dtab[48];                   // min delay by (new value, set of changed pins)
+    uint32_t dtab[48];                   // by (new value e, set of changed pins): the smallest
+                                         // delay d over those pins, as d << 2 | e
     uint32_t etab[12];                   // edge model: per (pin, edge class) the delays to
                                          // 0, 1 and X in 10-bit fields (kEdgeNone = unrelated)
     uint8_t lut[256];
@@ -196,8 +201,8 @@ __device__ __forceinline__ void cswap(uint32_t &a, uint32_t &b) {
 // need no check that the range is still open; CHECKED keeps that check (the
 // dependency-driven kernel: without it, its register allocation spills).
 template <int NIT, bool CHECKED>
-__device__ __forceinline__ void merge8(const uint32_t *A, int a, const uint32_t *B, int b, int d,
-                                       uint32_t (&c)[8]) {
+__device__ __forceinline__ int merge8(const uint32_t *A, int a, const uint32_t *B, int b, int d,
+                                      uint32_t (&c)[8]) {
     d = d < a + b ? d : a + b;
     int lo = d - b > 0 ? d - b : 0;
     int hi = d < a ? d : a;
@@ -215,6 +220,7 @@ __device__ __forceinline__ void merge8(const uint32_t *A, int a, const uint32_t 
     cswap(c[0], c[4]); cswap(c[1], c[5]); cswap(c[2], c[6]); cswap(c[3], c[7]);
     cswap(c[0], c[2]); cswap(c[1], c[3]); cswap(c[4], c[6]); cswap(c[5], c[7]);
     cswap(c[0], c[1]); cswap(c[2], c[3]); cswap(c[4], c[5]); cswap(c[6], c[7]);
+    return lo;  // keys of A among the first min(d, a + b) merged
 }
 
 // Pin-state updates: bits [2p, 2p+2) hold pin p's new value, bits [8+2p,
@@ -302,9 +308,11 @@ __device__ __forceinline__ void tile_fetch(const uint64_t *src, int64_t r, PinTi
             }
             t.aux = s32[lane == 0 ? 1 : lane == 1 ? 2 * last + 1 : 2 * last];
         } else {
+            // nothing is loaded; the tile's words are never read (its count is 0)
+            const uint32_t z = 0u;
 #pragma unroll
-            for (int e = 0; e < T / 64; e++) t.lo[e] = 0u;
-            t.aux = 0u;
+            for (int e = 0; e < T / 64; e++) t.lo[e] = __builtin_nondeterministic_value(z);
+            t.aux = __builtin_nondeterministic_value(z);
         }
     } else {
         const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src);  // low word first
@@ -424,7 +432,7 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
                 const int32_t dq = pin_delay(R.rise[q], R.fall[q], ev);
                 d = dq < d ? dq : d;
             }
-        L.dtab[lane] = (uint32_t)d;
+        L.dtab[lane] = (uint32_t)d << 2 | ev;  // (the empty set, d = INT32_MAX, is never read)
     }
 
     uint32_t last_val = kX;  // value of the last final survivor
@@ -504,11 +512,13 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         // of a merged key past the round's 512 (pairs: 256) slots
         uint32_t mk[8];
         uint32_t cut = kNoTime28;
+        int split = 0, merged = 0;  // two pins: keys of pin 0 before this lane's first position; keys merged
         if constexpr (K == 1) {
 #pragma unroll
             for (int k = 0; k < 8; k++) mk[k] = L.tile[1 + 8 * lane + k];
         } else if constexpr (K == 2) {
-            merge8<9, AGENT>(L.tile + Tl::OFF(0) + 1, m[0], L.tile + Tl::OFF(1) + 1, m[1], 8 * lane, mk);
+            split = merge8<9, AGENT>(L.tile + Tl::OFF(0) + 1, m[0], L.tile + Tl::OFF(1) + 1, m[1], 8 * lane, mk);
+            merged = m[0] + m[1];
             if (m[0] + m[1] > 512) cut = (uint32_t)__builtin_amdgcn_readlane((int)mk[7], 63) >> 4;
         } else if constexpr (K == 3) {
             // the first 512 of pins 0 and 1 into AB, then AB with pin 2's tile
@@ -589,32 +599,66 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
         const uint32_t hsplit = all_in ? kNoKey32 : (uint32_t)(H - base) << 2 | 3u;
         constexpr bool kPrefetch = PREFETCH;
 
-        // ---- pin states: this lane's composed update, scanned over the wave
-        uint32_t upd = 0, trail_mask = 0;
+        // ---- pin values before this lane's first position (st) and after
+        // the round (st_round); the pins of this lane's trailing time group
+        uint32_t st, st_round, trail_mask = 0;
         const uint32_t t_last = mk[7] >> 4;
+        if constexpr (K <= 2) {
+            // each pin's value is that of its last key before the lane's first
+            // position: with one pin the previous lane's last key; with two
+            // the key before the merge-path split in each pin's tile (the
+            // split is exact for every lane that still holds a key of the
+            // round after a cut)
+            if constexpr (K == 1) {
+                const uint32_t prev = dpp_u32_zero<kDppWaveShr1>(mk[7]);
+                st = lane == 0 ? state0 : (prev >> 2) & 3u;
+            } else {
+                const int d = 8 * lane < merged ? 8 * lane : merged;
+                const int na = split, nb = d - split;
+                const uint32_t ka = L.tile[Tl::OFF(0) + na];  // key na - 1 of pin 0 (the guard if na = 0)
+                const uint32_t kb = L.tile[Tl::OFF(1) + nb];
+                st = (na > 0 ? (ka >> 2) & 3u : state0 & 3u) | (nb > 0 ? (kb >> 2) & 3u : (state0 >> 2) & 3u) << 2;
+            }
+            st_round = state0;
 #pragma unroll
-        for (int k = 0; k < 8; k++) {
-            const uint32_t sh = K == 1 ? 0u : (mk[k] & 3u) * 2u;
-            const bool valid = mk[k] != kNoKey32;
-            const uint32_t nu = (upd & ~(0x303u << sh)) | ((((mk[k] >> 2) & 3u) | 0x300u) << sh);
-            upd = valid ? nu : upd;
-            if (!LEAN) trail_mask |= (mk[k] >> 4) == t_last ? 1u << (sh >> 1) : 0u;
-        }
-        if constexpr (LEAN) {
+            for (int p = 0; p < K; p++)
+                if (m[p] > 0) {
+                    const uint32_t kl = (uint32_t)__builtin_amdgcn_readfirstlane((int)L.tile[Tl::OFF(p) + m[p]]);
+                    st_round = (st_round & ~(3u << (2 * p))) | (((kl >> 2) & 3u) << (2 * p));
+                }
 #pragma unroll
-            for (int k = 8 - K; k < 8; k++) {
+            for (int k = LEAN ? 8 - K : 0; k < 8; k++) {
                 const uint32_t sh = K == 1 ? 0u : (mk[k] & 3u) * 2u;
                 trail_mask |= (mk[k] >> 4) == t_last ? 1u << (sh >> 1) : 0u;
             }
+        } else {
+            // this lane's composed update, scanned over the wave
+            uint32_t upd = 0;
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const uint32_t sh = (mk[k] & 3u) * 2u;
+                const bool valid = mk[k] != kNoKey32;
+                const uint32_t nu = (upd & ~(0x303u << sh)) | ((((mk[k] >> 2) & 3u) | 0x300u) << sh);
+                upd = valid ? nu : upd;
+                if (!LEAN) trail_mask |= (mk[k] >> 4) == t_last ? 1u << (sh >> 1) : 0u;
+            }
+            if constexpr (LEAN) {
+#pragma unroll
+                for (int k = 8 - K; k < 8; k++) {
+                    const uint32_t sh = (mk[k] & 3u) * 2u;
+                    trail_mask |= (mk[k] >> 4) == t_last ? 1u << (sh >> 1) : 0u;
+                }
+            }
+            const uint32_t upd_incl = wave_prefix_compose(upd);
+            const uint32_t upd_excl = dpp_u32_zero<kDppWaveShr1>(upd_incl);
+            const uint32_t upd_all = (uint32_t)__builtin_amdgcn_readlane((int)upd_incl, 63);
+            st = (state0 & ~(upd_excl >> 8) & 0xFFu) | (upd_excl & 0xFFu);
+            st_round = (state0 & ~(upd_all >> 8) & 0xFFu) | (upd_all & 0xFFu);
         }
-        const uint32_t upd_incl = wave_prefix_compose(upd);
-        const uint32_t upd_excl = dpp_u32_zero<kDppWaveShr1>(upd_incl);
-        const uint32_t upd_all = (uint32_t)__builtin_amdgcn_readlane((int)upd_incl, 63);
         const uint32_t next_first = wave_shift_down(kNoTime28, mk[0] >> 4);
         const uint32_t prev_trail = wave_shift_up(kNoKey32, t_last << 4 | trail_mask);
 
         // ---- gate value after each transition, time-group ends and candidates
-        uint32_t st = (state0 & ~(upd_excl >> 8) & 0xFFu) | (upd_excl & 0xFFu);
         uint32_t sk[8];
         if constexpr (!EDGE) {
             // One pass. A group's candidate is kept if its value differs from
@@ -641,7 +685,7 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
                 const uint32_t pbit = K == 1 ? 1u : 1u << (mk[k] & 3u);
                 run_m = tk == run_t ? run_m | pbit : pbit;
                 run_t = tk;
-                sk[k] = end && (open || ek != e_prev) ? ((tk + L.dtab[ek * 16 + run_m]) << 2) | ek : kNoKey32;
+                sk[k] = end && (open || ek != e_prev) ? (tk << 2) + L.dtab[ek * 16 + run_m] : kNoKey32;
                 e_prev = end ? ek : e_prev;
                 open = open && !end;
             }
@@ -719,7 +763,7 @@ __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const Ga
             }
         }
         first_round = false;
-        state0 = (state0 & ~(upd_all >> 8) & 0xFFu) | (upd_all & 0xFFu);
+        state0 = st_round;
 
         // the next round's tiles load while the survivors are found
         PinTile<TT> nx[K];

@@ -32,7 +32,7 @@ namespace emu {
 constexpr int kLanes = 64;
 constexpr size_t kStackBytes = size_t(1) << 18;
 
-enum Op : int { kOpBarrier = 1, kOpBallot, kOpReadlane, kOpReadfirst, kOpDpp, kOpShflUp, kOpShflDown };
+enum Op : int { kOpBarrier = 1, kOpBallot, kOpReadlane, kOpReadfirst, kOpDpp, kOpShflUp, kOpShflDown, kOpBpermute };
 
 struct Dim3 {
     unsigned x, y, z;
@@ -153,6 +153,12 @@ inline int shfl_up(int x, int d, int width) {
     return i >= d ? (int)(uint32_t)wave().slot[r][i - d] : x;
 }
 
+// ds_bpermute: every lane reads `src` of lane (addr / 4) mod 64.
+inline int bpermute(int addr, int src) {
+    const int r = exchange(kOpBpermute, (uint32_t)src);
+    return (int)(uint32_t)wave().slot[r][((unsigned)addr >> 2) & 63];
+}
+
 inline int shfl_down(int x, int d, int width) {
     const int r = exchange(kOpShflDown, (uint32_t)x);
     const int i = lane();
@@ -213,6 +219,8 @@ constexpr hipError_t hipSuccess = 0;
 #define __clzll(x) __builtin_clzll((unsigned long long)(x))
 #define __shfl_up(x, d, w) ::emu::shfl_up((x), (d), (w))
 #define __shfl_down(x, d, w) ::emu::shfl_down((x), (d), (w))
+#define __builtin_amdgcn_ds_bpermute(a, s) ::emu::bpermute((a), (s))
+#define __builtin_nondeterministic_value(x) (x)
 #define __builtin_amdgcn_readlane(x, l) ::emu::readlane((x), (l))
 #define __builtin_amdgcn_readfirstlane(x) ::emu::readfirstlane((x))
 #define __builtin_amdgcn_update_dpp(o, s, c, rm, bm, bc) ::emu::update_dpp((o), (s), (c), (rm), (bm), (bc))
