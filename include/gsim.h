@@ -322,7 +322,9 @@ gsim_status sim_netlist_net_order(gsim_ctx ctx, gsim_netlist nl, int64_t *net_in
  * memory (wait, fetch and release in submission order when the sets do not all
  * fit). Sets are admitted first fit in the order given: a caller that releases
  * jobs as they finish can pass the largest sets first, so they do not run
- * alone at the end. Errors as sim_submit; on error no job is created. */
+ * alone at the end. Every set is checked and copied before any job is made
+ * (on up to 16 host threads); the caller's arrays may be freed on return.
+ * Errors as sim_submit; on error no job is created. */
 gsim_status sim_run_batch(gsim_ctx ctx, gsim_netlist nl, int32_t n_sets,
                           const int64_t *const *src_off, const int64_t *const *t,
                           const uint8_t *const *v, void *hip_stream, gsim_job *out);

@@ -6,6 +6,7 @@
 #include "gsim_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <exception>
 #include <new>
 #include <cmath>
@@ -891,6 +892,92 @@ bool prefer_dependency_driven(const Netlist &nl, const int64_t *src_off) {
     return std::sqrt(var > 0.0 ? var : 0.0) / mean >= 2.5;
 }
 
+// Host stimuli of one job copied into pinned staging.
+struct HostStim {
+    int64_t *src_off = nullptr, *t = nullptr;
+    uint8_t *v = nullptr;
+    int64_t n_in = 0;
+};
+
+void stage_free(gsim_ctx ctx, HostStim *hs) {
+    ctx->pinned.put(hs->src_off);
+    ctx->pinned.put(hs->t);
+    ctx->pinned.put(hs->v);
+    *hs = HostStim{};
+}
+
+// Pinned staging for S sources and n_in transitions (the pinned cache is not
+// shared across threads: call from the caller's thread).
+Failure stage_alloc(gsim_ctx ctx, int64_t S, int64_t n_in, HostStim *hs) {
+    hs->n_in = n_in;
+    hs->src_off = (int64_t *)ctx->pinned.get(sizeof(int64_t) * ((size_t)S + 1));
+    hs->t = (int64_t *)ctx->pinned.get(sizeof(int64_t) * (size_t)std::max<int64_t>(n_in, 1));
+    hs->v = (uint8_t *)ctx->pinned.get((size_t)std::max<int64_t>(n_in, 1));
+    if (!hs->src_off || !hs->t || !hs->v) {
+        stage_free(ctx, hs);
+        return fail(GSIM_E_OOM, "no pinned host memory to hold the stimuli");
+    }
+    return kOk;
+}
+
+void stage_copy(int64_t S, const int64_t *src_off, const int64_t *t, const uint8_t *v, HostStim *hs) {
+    std::memcpy(hs->src_off, src_off, sizeof(int64_t) * ((size_t)S + 1));
+    if (hs->n_in > 0) {
+        std::memcpy(hs->t, t, sizeof(int64_t) * (size_t)hs->n_in);
+        std::memcpy(hs->v, v, (size_t)hs->n_in);
+    }
+}
+
+// fn(i) for i in [0, n) on up to 16 host threads (fewer if none can start).
+template <typename Fn>
+void parallel_for(int64_t n, Fn fn) {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int64_t nt = std::min<int64_t>({16, (int64_t)hw, n});
+    std::atomic<int64_t> next{0};
+    auto work = [&] {
+        for (int64_t i = next++; i < n; i = next++) fn(i);
+    };
+    std::vector<std::thread> pool;
+    try {
+        for (int64_t k = 1; k < nt; k++) pool.emplace_back(work);
+    } catch (...) {  // no more threads: fewer helpers
+    }
+    work();
+    for (auto &th : pool) th.join();
+}
+
+// A job over staged host stimuli (hs, taken over by the job) or over device
+// arrays, queued on the executor.
+Failure queue_job(gsim_ctx ctx, gsim_netlist nlh, Netlist &nl, Executor *ex, HostStim *hs,
+                  const int64_t *dev_src_off, const int64_t *dev_t, const uint8_t *dev_v, int64_t n_in,
+                  Job **out) {
+    auto j = std::make_unique<Job>();
+    j->nl_id = nlh;
+    j->nl = &nl;
+    j->ex = ex;
+    j->n_in = n_in;
+    j->capacity_request = ctx->opt_arena;
+    const int schedule = nl.schedule >= 0 ? nl.schedule : ctx->opt_schedule;
+    j->dataflow = schedule == 1 || (schedule == 2 && prefer_dependency_driven(nl, hs ? hs->src_off : nullptr));
+    if (hs) {
+        j->h_src_off = hs->src_off;
+        j->h_t = hs->t;
+        j->h_v = hs->v;
+        *hs = HostStim{};
+    } else {
+        j->dev_src_off = dev_src_off;
+        j->dev_t = dev_t;
+        j->dev_v = dev_v;
+    }
+    j->id = ctx->next_id++;
+    nl.active_jobs++;
+    Job *raw = j.get();
+    ctx->jobs[j->id] = std::move(j);
+    ex->queue.push_back(raw);
+    *out = raw;
+    return kOk;
+}
+
 Failure submit(gsim_ctx ctx, gsim_netlist nlh, const int64_t *src_off, const int64_t *t, const uint8_t *v,
                bool device_arrays, int64_t n_in_device, int validate, hipStream_t stream, Job **out) {
     if (!src_off) return fail(GSIM_E_ARG, "null src_off");
@@ -925,43 +1012,12 @@ Failure submit(gsim_ctx ctx, gsim_netlist nlh, const int64_t *src_off, const int
             if (f.st != GSIM_OK) return f;
         }
     }
-    auto j = std::make_unique<Job>();
-    j->nl_id = nlh;
-    j->nl = &nl;
-    j->ex = ex;
-    j->n_in = n_in;
-    j->capacity_request = ctx->opt_arena;
-    const int schedule = nl.schedule >= 0 ? nl.schedule : ctx->opt_schedule;
-    j->dataflow = schedule == 1 ||
-                  (schedule == 2 && prefer_dependency_driven(nl, device_arrays ? nullptr : src_off));
-    if (!device_arrays) {
-        const size_t S1 = (size_t)nl.S + 1;
-        j->h_src_off = (int64_t *)ctx->pinned.get(sizeof(int64_t) * S1);
-        j->h_t = (int64_t *)ctx->pinned.get(sizeof(int64_t) * (size_t)std::max<int64_t>(n_in, 1));
-        j->h_v = (uint8_t *)ctx->pinned.get((size_t)std::max<int64_t>(n_in, 1));
-        if (!j->h_src_off || !j->h_t || !j->h_v) {
-            ctx->pinned.put(j->h_src_off);
-            ctx->pinned.put(j->h_t);
-            ctx->pinned.put(j->h_v);
-            return fail(GSIM_E_OOM, "no pinned host memory to hold the stimuli");
-        }
-        std::memcpy(j->h_src_off, src_off, sizeof(int64_t) * S1);
-        if (n_in > 0) {
-            std::memcpy(j->h_t, t, sizeof(int64_t) * (size_t)n_in);
-            std::memcpy(j->h_v, v, (size_t)n_in);
-        }
-    } else {
-        j->dev_src_off = src_off;
-        j->dev_t = t;
-        j->dev_v = v;
-    }
-    j->id = ctx->next_id++;
-    nl.active_jobs++;
-    Job *raw = j.get();
-    ctx->jobs[j->id] = std::move(j);
-    ex->queue.push_back(raw);
-    *out = raw;
-    return kOk;
+    if (device_arrays) return queue_job(ctx, nlh, nl, ex, nullptr, src_off, t, v, n_in, out);
+    HostStim hs;
+    f = stage_alloc(ctx, nl.S, n_in, &hs);
+    if (f.st != GSIM_OK) return f;
+    stage_copy(nl.S, src_off, t, v, &hs);
+    return queue_job(ctx, nlh, nl, ex, &hs, nullptr, nullptr, nullptr, n_in, out);
 }
 
 // Emit the work that closes a job after its last level.
@@ -2005,18 +2061,37 @@ gsim_status sim_run_batch(gsim_ctx ctx, gsim_netlist nl, int32_t n_sets, const i
     if (n_sets < 0 || (n_sets > 0 && (!src_off || !t || !v || !out)))
         return record(ctx, fail(GSIM_E_ARG, "bad batch arguments"));
     std::vector<Job *> made;
-    for (int32_t i = 0; i < n_sets; i++) {
-        Job *j = nullptr;
-        Failure f = submit(ctx, nl, src_off[i], t[i], v[i], false, 0, 0, (hipStream_t)hip_stream, &j);
+    if (n_sets > 0) {
+        // every set is checked and copied into pinned staging on host threads
+        // (submit's work, in parallel), then queued in order
+        auto it = ctx->netlists.find(nl);
+        if (it == ctx->netlists.end()) return record(ctx, fail(GSIM_E_HANDLE, "unknown netlist handle %lld", (long long)nl));
+        Netlist &net = *it->second;
+        Failure f = set_device(ctx);
+        Executor *ex = nullptr;
+        if (f.st == GSIM_OK) f = get_executor(ctx, (hipStream_t)hip_stream, &ex);
+        if (f.st != GSIM_OK) return record(ctx, f);
+        for (int32_t i = 0; i < n_sets; i++)
+            if (!src_off[i]) return record(ctx, fail(GSIM_E_ARG, "set %d: null src_off", i));
+        std::vector<Failure> checked((size_t)n_sets, kOk);
+        parallel_for(n_sets, [&](int64_t i) {
+            checked[i] = validate_stimulus(net.S, src_off[i], t[i], v[i], net.max_path_delay);
+        });
+        for (int32_t i = 0; i < n_sets; i++)
+            if (checked[i].st != GSIM_OK) return record(ctx, checked[i]);
+        std::vector<HostStim> staged((size_t)n_sets);
+        for (int32_t i = 0; i < n_sets && f.st == GSIM_OK; i++) f = stage_alloc(ctx, net.S, src_off[i][net.S], &staged[i]);
         if (f.st != GSIM_OK) {
-            for (Job *m : made) {
-                destroy_job(ctx, m);
-                ctx->jobs.erase(m->id);
-            }
+            for (HostStim &hs : staged) stage_free(ctx, &hs);
             return record(ctx, f);
         }
-        made.push_back(j);
-        out[i] = j->id;
+        parallel_for(n_sets, [&](int64_t i) { stage_copy(net.S, src_off[i], t[i], v[i], &staged[i]); });
+        for (int32_t i = 0; i < n_sets; i++) {
+            Job *j = nullptr;
+            (void)queue_job(ctx, nl, net, ex, &staged[i], nullptr, nullptr, nullptr, staged[i].n_in, &j);
+            made.push_back(j);
+            out[i] = j->id;
+        }
     }
     // drive while jobs can be admitted or have levels left; jobs that do not
     // fit yet are admitted by later calls as released jobs free memory

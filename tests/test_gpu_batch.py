@@ -49,6 +49,31 @@ def test_batch_of_uneven_sets(sim):
     sim.unload_netlist(h)
 
 
+def test_batch_with_a_bad_set_leaves_nothing(sim):
+    """Sets are checked (on host threads) before any job is made: a batch
+    with one unordered set fails as a whole, and the netlist can be unloaded
+    at once (no job of it is left); the same batch without that set runs
+    exactly."""
+    nl = W.config2_netlist(G=3000, S=40, L=20, seed=8)
+    sets = [W.make_stimulus(S=nl.S, n_per_src=200 + 50 * i, window=1_000_000, seed=200 + i) for i in range(12)]
+    bad = W.Stimulus(off=sets[5].off.copy(), t=sets[5].t.copy(), v=sets[5].v.copy())
+    a = int(bad.off[3])
+    bad.t[a], bad.t[a + 1] = bad.t[a + 1], bad.t[a]  # times out of order in source 3
+    say(f"bad batch: G={nl.G} sets={len(sets)}")
+    h = sim.load_netlist(nl)
+    with pytest.raises(G.GsimError) as e:
+        sim.run_batch(h, sets[:5] + [bad] + sets[6:])
+    assert e.value.status == G.E_WAVEFORM
+    sim.unload_netlist(h)
+    h = sim.load_netlist(nl)
+    good = sets[:5] + sets[6:]
+    for j, st in zip(sim.run_batch(h, good), good):
+        sim.wait(j)
+        assert same(fetch_gates(sim, j, nl), O.o1_simulate(nl, st))
+        sim.release(j)
+    sim.unload_netlist(h)
+
+
 def test_continuous_batching_mixed_netlists(sim):
     """Jobs of three netlists (different sizes and depths) join a running
     executor at different steps; each result equals the job run alone."""
