@@ -436,6 +436,9 @@ constexpr uint32_t kDfMaxTickets = 16;
 template <bool EDGE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void dataflow_kernel(DfArgs A) {
     __shared__ WaveLds<kWindowLarge> L;
+    // the batch, one gate per entry: record, read bound w_g, fanout range
+    __shared__ GateRec brec[kDfMaxTickets];
+    __shared__ int64_t bw[kDfMaxTickets], bfo[kDfMaxTickets], bpre[kDfMaxTickets], bfst[kDfMaxTickets];
     const int lane = lane_id();
     const JobDesc &J = A.job;
     DevState *st = J.state;
@@ -465,13 +468,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
             const uint64_t filled = __ballot(g_lane >= 0);
             const int nb = (~filled) == 0 ? 64 : __builtin_ctzll(~filled);  // leading filled slots
             df_acquire_inputs(A, g_lane, nb);
-            for (int b = 0; b < nb; b++) {
-                const int32_t g = __builtin_amdgcn_readlane(g_lane, b);
-                const GateRec R = J.rec[g];
+            // the batch's gate records, read bounds and fanout sizes, loaded
+            // together (lane b: ticket t + b) and kept in LDS
+            if (lane < nb) {
+                const GateRec Rl = J.rec[g_lane];
                 int64_t w = 0;
 #pragma unroll
                 for (int p = 0; p < kMaxPins; p++)
-                    if (p < R.k) w += J.len[R.net[p]];
+                    if (p < Rl.k) w += J.len[Rl.net[p]];
+                brec[lane] = Rl;
+                bw[lane] = w;
+                bfst[lane] = A.fo_off[g_lane];
+                bfo[lane] = A.fo_off[g_lane + 1] - bfst[lane];
+            }
+            const bool halted = load_agent(reinterpret_cast<const uint32_t *>(&st->overflow)) != 0;
+            __syncthreads();
+            for (int b = 0; b < nb; b++) {
+                const int32_t g = __builtin_amdgcn_readlane(g_lane, b);
+                GateRec R;
+                {
+                    const int32_t *src = reinterpret_cast<const int32_t *>(&brec[b]);
+                    int32_t *dst = reinterpret_cast<int32_t *>(&R);
+#pragma unroll
+                    for (int d = 0; d < 16; d++) dst[d] = __builtin_amdgcn_readfirstlane(src[d]);
+                }
+                const int64_t w = uniform64(bw[b]);
                 reads += w;
                 if (chunk_end - chunk_at < w) {
                     const int64_t want = w > A.chunk ? w : A.chunk;
@@ -485,7 +506,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
                 const int64_t ob = chunk_at;
                 chunk_at += w;
                 const bool full = ob + w > st->capacity;
-                if (full || load_agent(reinterpret_cast<const uint32_t *>(&st->overflow))) {
+                if (full || halted) {
                     if (lane == 0) {
                         if (full) atomicOr(&st->overflow, 1);
                         put<true>(J.len + J.S + g, (int64_t)0);
@@ -507,15 +528,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             // consumers whose last pending pin this was: listed in LDS (the
             // evaluation's survivor area, free between gates) and queued with
-            // one tail atomic for the whole batch. (A consumer synchronises
-            // with every producer through its pending count: df_acquire_inputs.)
+            // one tail atomic for the whole batch. The batch's fanout entries
+            // (one per reading pin) are decremented 64 at a time across its
+            // gates. (A consumer synchronises with every producer through its
+            // pending count: df_acquire_inputs.)
             int n_ready = 0;
-            for (int b = 0; b < nb; b++) {
-                const int32_t g = __builtin_amdgcn_readlane(g_lane, b);
-                const int64_t f1 = A.fo_off[g + 1];
-                for (int64_t i0 = A.fo_off[g]; i0 < f1; i0 += 64) {
+            {
+                int64_t total = 0;
+                for (int b = 0; b < nb; b++) {
+                    if (lane == 0) bpre[b] = total;
+                    total += uniform64(bfo[b]);
+                }
+                __syncthreads();
+                for (int64_t i0 = 0; i0 < total; i0 += 64) {
                     const int64_t i = i0 + lane;
-                    const int32_t c = i < f1 ? A.fo[i] : -1;
+                    int32_t c = -1;
+                    if (i < total) {
+                        int b = nb - 1;
+                        while (b > 0 && i < bpre[b]) b--;
+                        c = A.fo[bfst[b] + (i - bpre[b])];
+                    }
                     const bool ready = c >= 0 && atomicSub(&A.pend[c], 1) == 1;
                     const uint64_t mask = __ballot(ready);
                     if (mask == 0) continue;
