@@ -211,12 +211,11 @@ Failure levelize(int64_t S, int64_t G, const uint8_t *type, const int64_t *pin_o
     return kOk;
 }
 
-Failure validate_stimulus(int64_t S, const int64_t *src_off, const int64_t *t, const uint8_t *v,
-                          int64_t max_path_delay) {
-    if (!src_off) return fail(GSIM_E_ARG, "null src_off");
-    if (src_off[0] != 0) return fail(GSIM_E_WAVEFORM, "src_off[0] must be 0");
+// Sources [s0, s1) of a host stimulus (see validate_stimulus).
+Failure validate_sources(int64_t s0, int64_t s1, const int64_t *src_off, const int64_t *t, const uint8_t *v,
+                         int64_t max_path_delay) {
     const int64_t limit = kTimeLimit - max_path_delay;
-    for (int64_t s = 0; s < S; s++) {
+    for (int64_t s = s0; s < s1; s++) {
         const int64_t a = src_off[s], b = src_off[s + 1];
         if (b < a) return fail(GSIM_E_WAVEFORM, "source %lld: negative length", (long long)s);
         if (b > a && (!t || !v)) return fail(GSIM_E_ARG, "null t or v");
@@ -236,6 +235,13 @@ Failure validate_stimulus(int64_t S, const int64_t *src_off, const int64_t *t, c
         }
     }
     return kOk;
+}
+
+Failure validate_stimulus(int64_t S, const int64_t *src_off, const int64_t *t, const uint8_t *v,
+                          int64_t max_path_delay) {
+    if (!src_off) return fail(GSIM_E_ARG, "null src_off");
+    if (src_off[0] != 0) return fail(GSIM_E_WAVEFORM, "src_off[0] must be 0");
+    return validate_sources(0, S, src_off, t, v, max_path_delay);
 }
 
 // ---------------------------------------------------------------------------
@@ -920,11 +926,16 @@ Failure stage_alloc(gsim_ctx ctx, int64_t S, int64_t n_in, HostStim *hs) {
     return kOk;
 }
 
-void stage_copy(int64_t S, const int64_t *src_off, const int64_t *t, const uint8_t *v, HostStim *hs) {
+void parallel_copy(void *dst, const void *src, size_t bytes);
+
+// threads: whether the copies may use host threads of their own
+void stage_copy(int64_t S, const int64_t *src_off, const int64_t *t, const uint8_t *v, HostStim *hs,
+                bool threads) {
     std::memcpy(hs->src_off, src_off, sizeof(int64_t) * ((size_t)S + 1));
     if (hs->n_in > 0) {
-        std::memcpy(hs->t, t, sizeof(int64_t) * (size_t)hs->n_in);
-        std::memcpy(hs->v, v, (size_t)hs->n_in);
+        auto copy = threads ? parallel_copy : [](void *d, const void *s, size_t n) { std::memcpy(d, s, n); };
+        copy(hs->t, t, sizeof(int64_t) * (size_t)hs->n_in);
+        copy(hs->v, v, (size_t)hs->n_in);
     }
 }
 
@@ -944,6 +955,26 @@ void parallel_for(int64_t n, Fn fn) {
     }
     work();
     for (auto &th : pool) th.join();
+}
+
+// validate_stimulus over ranges of sources on host threads, for large
+// stimuli; the first failing source is reported, as by the serial check
+// (which also handles offsets that are not increasing).
+Failure validate_stimulus_mt(int64_t S, const int64_t *src_off, const int64_t *t, const uint8_t *v,
+                             int64_t max_path_delay) {
+    constexpr int64_t kMinParallel = int64_t(1) << 20;  // transitions
+    if (!src_off || src_off[0] != 0 || S < 64 || src_off[S] < kMinParallel)
+        return validate_stimulus(S, src_off, t, v, max_path_delay);
+    for (int64_t s = 0; s < S; s++)
+        if (src_off[s + 1] < src_off[s]) return validate_stimulus(S, src_off, t, v, max_path_delay);
+    constexpr int64_t kParts = 64;
+    std::vector<Failure> part((size_t)kParts, kOk);
+    parallel_for(kParts, [&](int64_t c) {
+        part[c] = validate_sources(S * c / kParts, S * (c + 1) / kParts, src_off, t, v, max_path_delay);
+    });
+    for (const Failure &f : part)
+        if (f.st != GSIM_OK) return f;
+    return kOk;
 }
 
 // A job over staged host stimuli (hs, taken over by the job) or over device
@@ -991,7 +1022,7 @@ Failure submit(gsim_ctx ctx, gsim_netlist nlh, const int64_t *src_off, const int
     if (f.st != GSIM_OK) return f;
     int64_t n_in = 0;
     if (!device_arrays) {
-        f = validate_stimulus(nl.S, src_off, t, v, nl.max_path_delay);
+        f = validate_stimulus_mt(nl.S, src_off, t, v, nl.max_path_delay);
         if (f.st != GSIM_OK) return f;
         n_in = src_off[nl.S];
     } else {
@@ -1016,7 +1047,7 @@ Failure submit(gsim_ctx ctx, gsim_netlist nlh, const int64_t *src_off, const int
     HostStim hs;
     f = stage_alloc(ctx, nl.S, n_in, &hs);
     if (f.st != GSIM_OK) return f;
-    stage_copy(nl.S, src_off, t, v, &hs);
+    stage_copy(nl.S, src_off, t, v, &hs, true);
     return queue_job(ctx, nlh, nl, ex, &hs, nullptr, nullptr, nullptr, n_in, out);
 }
 
@@ -2085,7 +2116,7 @@ gsim_status sim_run_batch(gsim_ctx ctx, gsim_netlist nl, int32_t n_sets, const i
             for (HostStim &hs : staged) stage_free(ctx, &hs);
             return record(ctx, f);
         }
-        parallel_for(n_sets, [&](int64_t i) { stage_copy(net.S, src_off[i], t[i], v[i], &staged[i]); });
+        parallel_for(n_sets, [&](int64_t i) { stage_copy(net.S, src_off[i], t[i], v[i], &staged[i], false); });
         for (int32_t i = 0; i < n_sets; i++) {
             Job *j = nullptr;
             (void)queue_job(ctx, nl, net, ex, &staged[i], nullptr, nullptr, nullptr, staged[i].n_in, &j);

@@ -265,6 +265,30 @@ def test_invalid_stimulus_rejected(sim):
     sim.unload_netlist(h)
 
 
+def test_invalid_large_stimulus_names_the_first_bad_source(sim):
+    """A stimulus above a million transitions is checked over ranges of
+    sources on host threads; the error names the first bad source, as the
+    serial check does, and a good copy of it runs exactly."""
+    nl = W.config2_netlist(G=2000, S=512, L=10, seed=9)
+    st = W.make_stimulus(S=nl.S, n_per_src=2500, window=1_000_000, seed=9)
+    assert st.n > (1 << 20)
+    h = sim.load_netlist(nl)
+    for bad_sources in ((400,), (77, 400), (3, 77, 400)):
+        t = st.t.copy()
+        for s in bad_sources:
+            a = int(st.off[s]) + 10
+            t[a], t[a + 1] = t[a + 1], t[a]
+        with pytest.raises(G.GsimError) as e:
+            sim.run(h, W.Stimulus(st.off, t, st.v))
+        assert e.value.status == G.E_WAVEFORM
+        assert f"source {bad_sources[0]}:" in str(e.value)
+    j = sim.run(h, st)
+    sim.wait(j)
+    assert_same(sim.fetch(j, np.arange(nl.S, nl.S + nl.G)), O.o1_simulate(nl, st), nl)
+    sim.release(j)
+    sim.unload_netlist(h)
+
+
 def test_run_device_from_torch(sim):
     import torch
     nl, st = W.config1(seed=2)
