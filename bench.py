@@ -382,7 +382,7 @@ def oracle_threads():
     return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
-def bench_end_to_end(G, sim, nl, h, st, reps=2):
+def bench_end_to_end(G, sim, nl, h, st, reps=3):
     """The headline job from host stimuli to every net's waveform in host
     memory: stimulus upload, validation and the run (sim_run + sim_wait), then
     sim_fetch_waveforms of all S+G nets into host buffers allocated and
