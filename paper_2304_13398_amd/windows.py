@@ -63,25 +63,37 @@ def window_stimulus(st, S, t_lo, t_hi) -> W.Stimulus:
     """Source transitions in [t_lo, t_hi), each source first set to the value
     it holds at t_lo (a transition at t_lo, unless that value is X or the
     source already changes at t_lo; a change to X exactly at t_lo is dropped,
-    since every window starts at X)."""
-    offs, ts, vs = [0], [], []
-    for s in range(S):
-        a, b = int(st.off[s]), int(st.off[s + 1])
-        t, v = st.t[a:b], st.v[a:b]
-        i0 = int(np.searchsorted(t, t_lo, side="left"))
-        i1 = int(np.searchsorted(t, t_hi, side="left"))
-        tt, vv = t[i0:i1], v[i0:i1]
-        if i0 > 0 and v[i0 - 1] != 2 and (len(tt) == 0 or tt[0] != t_lo):
-            tt = np.concatenate([[t_lo], tt])
-            vv = np.concatenate([[v[i0 - 1]], vv])
-        elif len(tt) and vv[0] == 2:  # a change to X exactly at t_lo: the window starts at X
-            tt, vv = tt[1:], vv[1:]
-        ts.append(tt)
-        vs.append(vv)
-        offs.append(offs[-1] + len(tt))
-    t = np.concatenate(ts).astype(np.int64) if ts else np.zeros(0, np.int64)
-    v = np.concatenate(vs).astype(np.uint8) if vs else np.zeros(0, np.uint8)
-    return W.Stimulus(np.asarray(offs, dtype=np.int64), t, v)
+    since every window starts at X). Vectorised over all sources."""
+    off = np.asarray(st.off, dtype=np.int64)
+    t = np.asarray(st.t, dtype=np.int64)
+    v = np.asarray(st.v, dtype=np.uint8)
+    a, b = off[:S], off[1:S + 1]
+    before = np.concatenate([[0], np.cumsum(t < t_lo)])     # per source: transitions before t_lo
+    below = np.concatenate([[0], np.cumsum(t < t_hi)])      # ... and before t_hi
+    i0 = a + (before[b] - before[a])
+    i1 = a + (below[b] - below[a])
+    has = i1 > i0
+    first_t = np.where(has, t[np.minimum(i0, max(len(t) - 1, 0))] if len(t) else 0, -1)
+    first_v = np.where(has, v[np.minimum(i0, max(len(v) - 1, 0))] if len(v) else 0, 0)
+    prev_v = np.where(i0 > a, v[np.maximum(i0 - 1, 0)] if len(v) else 2, 2)
+    add = (i0 > a) & (prev_v != 2) & ~(has & (first_t == t_lo))   # the held value, at t_lo
+    drop = ~add & has & (first_v == 2)                             # a change to X at t_lo
+    start = i0 + drop                                              # first kept transition
+    n_keep = i1 - start
+    counts = n_keep + add
+    out_off = np.zeros(S + 1, dtype=np.int64)
+    np.cumsum(counts, out=out_off[1:])
+    out_t = np.empty(int(out_off[-1]), dtype=np.int64)
+    out_v = np.empty(int(out_off[-1]), dtype=np.uint8)
+    ia = np.nonzero(add)[0]
+    out_t[out_off[ia]] = t_lo
+    out_v[out_off[ia]] = prev_v[ia]
+    # kept transitions: source s's [start_s, i1_s) to [out_off_s + add_s, ...)
+    src = np.repeat(np.arange(S, dtype=np.int64), n_keep)
+    k = np.arange(int(n_keep.sum()), dtype=np.int64) - np.repeat(np.cumsum(n_keep) - n_keep, n_keep)
+    out_t[out_off[src] + add[src] + k] = t[start[src] + k]
+    out_v[out_off[src] + add[src] + k] = v[start[src] + k]
+    return W.Stimulus(out_off, out_t, out_v)
 
 
 def window_bounds(st, n_windows: int) -> list[int]:
@@ -120,23 +132,37 @@ def simulate_windowed(nl, st, run, n_windows: int, halo: int | None = None, run_
     (so the windows can run together)."""
     wins = window_stimuli(nl, st, n_windows, halo)
     results = run_many([w[2] for w in wins]) if run_many is not None else [run(w[2]) for w in wins]
-    gid_parts, t_parts, v_parts = [], [], []
-    for (lo, hi, _), (off, t, v) in zip(wins, results):
-        gid = np.repeat(np.arange(nl.G, dtype=np.int64), np.diff(off))
-        keep = np.ones(len(t), dtype=bool)
-        if lo is not None:
-            keep &= t >= lo
-        if hi is not None:
-            keep &= t < hi
-        gid_parts.append(gid[keep])
-        t_parts.append(t[keep])
-        v_parts.append(v[keep])
-    gid = np.concatenate(gid_parts) if gid_parts else np.zeros(0, np.int64)
-    order = np.argsort(gid, kind="stable")  # windows are in time order: stable keeps it
-    out_off = np.zeros(nl.G + 1, dtype=np.int64)
-    np.cumsum(np.bincount(gid, minlength=nl.G)[:nl.G], out=out_off[1:])
-    out_t = np.concatenate(t_parts)[order].astype(np.int64)
-    out_v = np.concatenate(v_parts)[order].astype(np.uint8)
+    # each window keeps its gates' transitions in [lo, hi); gate g's pieces
+    # follow each other in window (time) order: a scatter, no sort
+    G = nl.G
+    kept = []
+    counts = np.zeros((len(wins), G), dtype=np.int64)
+    for k, ((lo, hi, _), (off, t, v)) in enumerate(zip(wins, results)):
+        off = np.asarray(off, dtype=np.int64)
+        t = np.asarray(t, dtype=np.int64)
+        # the kept part of each gate's sorted list is [off_g + below(lo), off_g + below(hi))
+        def below(x):
+            if x is None:
+                return None
+            c = np.concatenate([[0], np.cumsum(t < x)])
+            return c[off[1:]] - c[off[:-1]]
+        n = np.diff(off)
+        lo_n = np.zeros(G, dtype=np.int64) if lo is None else below(lo)
+        hi_n = n if hi is None else below(hi)
+        counts[k] = hi_n - lo_n
+        kept.append((off[:-1] + lo_n, t, np.asarray(v, dtype=np.uint8)))
+    out_off = np.zeros(G + 1, dtype=np.int64)
+    np.cumsum(counts.sum(axis=0), out=out_off[1:])
+    out_t = np.empty(int(out_off[-1]), dtype=np.int64)
+    out_v = np.empty(int(out_off[-1]), dtype=np.uint8)
+    dest0 = out_off[:-1].copy()
+    for k, (src0, t, v) in enumerate(kept):
+        c = counts[k]
+        gid = np.repeat(np.arange(G, dtype=np.int64), c)
+        r = np.arange(int(c.sum()), dtype=np.int64) - np.repeat(np.cumsum(c) - c, c)
+        out_t[dest0[gid] + r] = t[src0[gid] + r]
+        out_v[dest0[gid] + r] = v[src0[gid] + r]
+        dest0 += c
     return out_off, out_t, out_v
 
 

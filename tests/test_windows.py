@@ -76,3 +76,41 @@ def test_mid_generator_windows_are_valid_stimuli():
                                  np.iinfo(np.int64).max if hi is None else hi)
         G.validate_stimulus(nl.S, sub.off, sub.t, sub.v)
     assert same(WN.simulate_windowed(nl, st, oracle_engine(nl), 6), O.o1_simulate(nl, st))
+
+
+def _window_stimulus_by_source(st, S, t_lo, t_hi):
+    """The window's stimulus source by source, as its definition reads."""
+    offs, ts, vs = [0], [], []
+    for s in range(S):
+        t, v = st.t[st.off[s]:st.off[s + 1]], st.v[st.off[s]:st.off[s + 1]]
+        inside = (t >= t_lo) & (t < t_hi)
+        tt, vv = list(t[inside]), list(v[inside])
+        before = v[t < t_lo]
+        held = int(before[-1]) if len(before) else 2
+        if held != 2 and not (tt and tt[0] == t_lo):
+            tt, vv = [t_lo] + tt, [held] + vv
+        elif tt and vv[0] == 2:
+            tt, vv = tt[1:], vv[1:]
+        ts += tt
+        vs += vv
+        offs.append(len(ts))
+    return np.array(offs, np.int64), np.array(ts, np.int64), np.array(vs, np.uint8)
+
+
+def test_window_stimulus_equals_its_definition():
+    """Random cuts, cuts on transition times, X/Z values and empty sources."""
+    rng = np.random.default_rng(11)
+    st = W.make_stimulus(S=60, n_per_src=40, window=10_000, probs=(0.3, 0.3, 0.2, 0.2), seed=11)
+    # a few empty sources
+    keep = np.ones(st.n, dtype=bool)
+    for s in (0, 17, 59):
+        keep[st.off[s]:st.off[s + 1]] = False
+    lens = np.diff(st.off) * np.isin(np.arange(60), (0, 17, 59), invert=True)
+    st = W.Stimulus(np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), st.t[keep], st.v[keep])
+    cuts = list(rng.integers(0, 12_000, size=40)) + list(st.t[rng.integers(0, st.n, size=40)])
+    for lo in cuts:
+        for hi in (lo + 1, lo + int(rng.integers(1, 5000)), np.iinfo(np.int64).max):
+            got = WN.window_stimulus(st, 60, int(lo), int(hi))
+            want = _window_stimulus_by_source(st, 60, int(lo), int(hi))
+            assert np.array_equal(got.off, want[0]) and np.array_equal(got.t, want[1]) \
+                and np.array_equal(got.v, want[2]), (lo, hi)
