@@ -372,8 +372,11 @@ __device__ __forceinline__ void tile_settle(const uint64_t *src, int64_t r, cons
 // last loaded transition comes from an extra lane of the tile's auxiliary
 // register, and the lane's trailing time group is looked for among its last
 // K positions only (at most one transition per pin shares a time). The
-// dependency-driven kernel keeps the longer form of both: one of its runs
-// with the shorter form did not finish, and the cause is not known.
+// dependency-driven kernel keeps the longer form of both. One of its runs
+// with the shorter form once did not finish; the cause found since was in
+// that kernel's publication order (fixed), and the shorter form gives the
+// oracle's result on every gate under the CPU wave emulator, but it has not
+// run in that kernel on the device since.
 template <int K, int W, bool EDGE, bool PREFETCH, bool LEAN, bool AGENT>
 __device__ __forceinline__ void eval_gate(const JobDesc &J, int64_t ob, const GateRec &R,
                                           int64_t gate, WaveLds<W> &L) {
