@@ -382,7 +382,8 @@ class PinnedCache {
 // ---------------------------------------------------------------------------
 
 // Gates of one level in consecutive groups, one per work list: by largest
-// pin delay (<= kWindowSmall, <= kWindowLarge) and pin count for the
+// pin delay (<= kWindowSmall, <= kWindowLarge; the small window only when
+// its gates are not fewer than the large window's) and pin count for the
 // wavefront kernels, then the gates whose delays need the lane kernel. The
 // group sizes bound the wavefront work lists of a step (the lane list may
 // take any gate).
@@ -602,13 +603,23 @@ Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, co
         return d;
     };
     const int edge_model = dly ? 1 : 0;
+    std::vector<int32_t> dmax_of(G);
+    int64_t n_small = 0, n_large = 0;
+    for (int64_t g = 0; g < G; g++) {
+        dmax_of[g] = gate_dmax(g);
+        n_small += dmax_of[g] <= kWindowSmall;
+        n_large += dmax_of[g] > kWindowSmall && dmax_of[g] <= kWindowLarge;
+    }
+    // The small window's kernel runs more wavefronts per SIMD, but a launch of
+    // its own per level only pays while it has a real share of the gates:
+    // when they are fewer than the large window's, they join those (the
+    // large window is exact for them too).
+    const bool small_window = n_small >= n_large;
+    auto window_of = [&](int64_t g) { return small_window && dmax_of[g] <= kWindowSmall ? 0 : 1; };
     auto group_of = [&](int64_t g) {
         if (ctx->opt_kernel == 1) return kListLane;  // every gate on the lane kernel
-        const int32_t d = gate_dmax(g);
         const int k = (int)(pin_off[g + 1] - pin_off[g]);
-        return d <= kWindowSmall   ? wave_list(wave_variant(0, edge_model), k)
-               : d <= kWindowLarge ? wave_list(wave_variant(1, edge_model), k)
-                                   : kListLane;
+        return dmax_of[g] <= kWindowLarge ? wave_list(wave_variant(window_of(g), edge_model), k) : kListLane;
     };
     const int32_t L = lv.n_levels;
     constexpr size_t NL = kNumLists;
@@ -651,7 +662,8 @@ Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, co
             r.fall[i] = fall[p];
         }
         // the lane-kernel option routes every gate to the lane kernel
-        r.dmax = ctx->opt_kernel == 1 ? INT32_MAX : gate_dmax(g);
+        r.dmax = ctx->opt_kernel == 1 ? INT32_MAX : dmax_of[g];
+        r.window = (uint8_t)window_of(g);
         r.user_gate = (int32_t)g;
         recs[nl->internal_of_user[g]] = r;
     }

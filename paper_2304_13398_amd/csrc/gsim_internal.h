@@ -68,7 +68,8 @@ struct alignas(64) GateRec {
     int32_t fall[kMaxPins];
     uint8_t type;
     uint8_t k;               // pin count
-    uint8_t pad0[2];
+    uint8_t window;          // wavefront kernels: 0 the small delay window, 1 the large one
+    uint8_t pad0;
     int32_t dmax;            // largest rise/fall delay over the pins
     int32_t user_gate;       // the caller's gate index
     int32_t pad1;

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kSizeBlock) void size_kernel(StepArgs A) {
             if (p < k) w += J.len[r.net[p]];
         cls = (r.dmax > kWindowLarge || w < J.lane_threshold)
                   ? kListLane
-                  : wave_list(wave_variant(r.dmax > kWindowSmall ? 1 : 0, J.edly ? 1 : 0), k);
+                  : wave_list(wave_variant(r.window, J.edly ? 1 : 0), k);
         if (cls != kListLane) seg_key = (uint32_t)(cls / 4) * kSegments + cost_segment(w, k);
     }
     const int lane = lane_id(), wv = t >> 6;
