@@ -472,9 +472,11 @@ def bench_skewed(G, sim, nl, h, seed, wcvs=(5.0, 20.0), steps=3):
     2,048,000 given transitions with per-source counts of coefficient of
     variation WCV (the paper's Eq. 5), under both schedules."""
     import torch
+    from paper_2304_13398_amd import autotune
     from paper_2304_13398_amd import workloads as W
     out = {"workload": "1M-gate mid netlist, 2,048,000 given transitions, per-source counts "
                        "log-normal with the stated WCV", "runs": {}}
+    tuner = autotune.Autotuner(sim, reps=1)
     for wcv in wcvs:
         st = W.make_stimulus_skewed(S=nl.S, mean_per_src=1000, wcv=wcv, window=1_000_000, seed=seed)
         dev = torch.device("cuda:0")
@@ -497,11 +499,16 @@ def bench_skewed(G, sim, nl, h, seed, wcvs=(5.0, 20.0), steps=3):
             ms = statistics.median(times) * 1000.0
             row[name] = {"ms_per_job": ms, "transitions_per_s": n_out / (ms / 1000.0), "n_out": int(n_out)}
         sim.set_option(G.OPT_SCHEDULE, 0)
+        # the tuner's choice for this stimulus (its key includes the skew)
+        c, tms = tuner.tune(nl, h, st)
+        row["tuned_setting"], row["tuning_device_ms"] = autotune.setting_name(c), tms
+        tuner.clear(h)
         n = np.diff(st.off)
         row["wcv_given"] = float(n.std() / n.mean())
         out["runs"][str(wcv)] = row
         print(f"[bench] skewed wcv {wcv}: levels {row['levels']['ms_per_job']:.1f} ms, "
-              f"dataflow {row['dataflow']['ms_per_job']:.1f} ms", file=sys.stderr, flush=True)
+              f"dataflow {row['dataflow']['ms_per_job']:.1f} ms, tuner chose {row['tuned_setting']}",
+              file=sys.stderr, flush=True)
     return out
 
 

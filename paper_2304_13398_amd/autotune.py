@@ -15,7 +15,7 @@ long its waveforms are:
   heavy ones.
 
 The tuner times each candidate setting on a sample job and keeps the
-fastest, per (netlist, stimulus length bucket), applying it to the netlist
+fastest, per (netlist, stimulus length bucket, source skew bucket), applying it to the netlist
 with sim_set_netlist_option. Results are cached in memory and, if a path is
 given, in a JSON file.
 """
@@ -62,6 +62,17 @@ def length_bucket(st, S: int) -> int:
     return int(round(math.log2(max(mean, 1.0))))
 
 
+def skew_bucket(st, S: int) -> int:
+    """Unevenness of the sources' activity (the coefficient of variation of
+    their transition counts, the paper's WCV): 0 below 1, then one bucket per
+    doubling (1 + floor(log2 WCV)). The two schedules cross near WCV 2.4 on
+    the mid-size netlist, and the level schedule's loss grows with WCV."""
+    n = np.diff(np.asarray(st.off[:S + 1], dtype=np.int64))
+    m = n.mean() if len(n) else 0.0
+    wcv = float(n.std() / m) if m > 0 else 0.0
+    return 0 if wcv < 1.0 else 1 + int(math.floor(math.log2(wcv)))
+
+
 class Autotuner:
     def __init__(self, sim: G.Sim, path: str | None = None, candidates=CANDIDATES, reps: int = 2):
         self.sim = sim
@@ -79,6 +90,11 @@ class Autotuner:
         self.sim.set_netlist_option(h, G.OPT_LANE_THRESHOLD, c[2])
         self.sim.set_netlist_option(h, G.OPT_DF_TICKETS, c[3] if c[3] else -1)
 
+    def clear(self, h):
+        """Back to the context's settings on ``h``."""
+        for opt in (G.OPT_SCHEDULE, G.OPT_EVAL_FORM, G.OPT_LANE_THRESHOLD, G.OPT_DF_TICKETS):
+            self.sim.set_netlist_option(h, opt, -1)
+
     def _time(self, h, st, c):
         self.apply(h, c)
         best = float("inf")
@@ -93,7 +109,7 @@ class Autotuner:
         """Pick the setting for netlist ``nl`` (loaded as ``h``) on stimuli like
         ``st``; applies it to ``h`` and returns (setting, device ms by
         candidate name)."""
-        key = f"{netlist_key(nl)}/b{length_bucket(st, nl.S)}"
+        key = f"{netlist_key(nl)}/b{length_bucket(st, nl.S)}/s{skew_bucket(st, nl.S)}"
         if key in self.table:
             c = tuple(self.table[key]["setting"])
             self.apply(h, c)
