@@ -86,7 +86,7 @@ def parse():
                     help="only the timed mid-size steps (for profiler runs)")
     ap.add_argument("--eval-form", choices=("segmented", "merged"), default="merged",
                     help="data-parallel form of the wavefront-per-gate kernel (same results)")
-    ap.add_argument("--schedule", choices=("levels", "dataflow"), default="levels",
+    ap.add_argument("--schedule", choices=("levels", "dataflow", "levelsync"), default="levels",
                     help="schedule of the --mid-only job")
     ap.add_argument("--df-tickets", type=int, default=0,
                     help="dependency-driven schedule: queue slots claimed per atomic (0 = automatic)")
@@ -100,7 +100,7 @@ def parse():
     ap.add_argument("--no-skewed", action="store_true",
                     help="skip the uneven-source-activity (WCV) runs")
     ap.add_argument("--no-dataflow", action="store_true",
-                    help="skip the dependency-driven schedule measurement")
+                    help="skip the one-launch schedules (dependency-driven, level barriers)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched section (64 stimulus sets over the 1M-gate netlist)")
     ap.add_argument("--batched-sets", type=int, default=64)
@@ -470,7 +470,7 @@ def bench_tiny_latency(G, sim, seed, reps=200):
 def bench_skewed(G, sim, nl, h, seed, wcvs=(5.0, 20.0), steps=3):
     """Uneven source activity on the resident 1M-gate netlist: the same
     2,048,000 given transitions with per-source counts of coefficient of
-    variation WCV (the paper's Eq. 5), under both schedules."""
+    variation WCV (the paper's Eq. 5), under each schedule."""
     import torch
     from paper_2304_13398_amd import autotune
     from paper_2304_13398_amd import workloads as W
@@ -483,7 +483,7 @@ def bench_skewed(G, sim, nl, h, seed, wcvs=(5.0, 20.0), steps=3):
         d = [torch.from_numpy(a).to(dev) for a in (st.off, st.t, st.v)]
         stream = torch.cuda.current_stream()
         row = {}
-        for name, sched in (("levels", 0), ("dataflow", 1)):
+        for name, sched in (("levels", 0), ("dataflow", 1), ("levelsync", 3)):
             sim.set_option(G.OPT_SCHEDULE, sched)
             times, n_out = [], 0
             for i in range(steps + 1):
@@ -774,6 +774,8 @@ def main():
         if args.schedule == "dataflow":
             sim.set_option(G.OPT_SCHEDULE, 1)
             sim.set_option(G.OPT_DF_TICKETS, args.df_tickets)
+        elif args.schedule == "levelsync":
+            sim.set_option(G.OPT_SCHEDULE, 3)
         nl, st = W.config2(seed=args.seed)
         h, d, res, _ = timed_job(G, sim, nl, st, args.steps, args.warmup, "mid", "mid")
         print(json.dumps({"mid": res}), flush=True)
@@ -866,9 +868,14 @@ def main():
             return sim.run_device(h, d[0].data_ptr(), d[1].data_ptr(), d[2].data_ptr(), st.n,
                                   stream=stream.cuda_stream)
 
-        if not args.no_dataflow:
-            # the same jobs under the dependency-driven schedule (one persistent launch per job)
-            sim.set_option(G.OPT_SCHEDULE, 1)
+        # the same jobs under the one-launch schedules
+        for key, sched, desc in (
+                ("dataflow", 1, "dependency-driven: one persistent launch per job, no level barrier"),
+                ("levelsync", 3, "level barriers: one persistent launch per job, a device-wide "
+                                 "barrier after each level")):
+            if args.no_dataflow:
+                break
+            sim.set_option(G.OPT_SCHEDULE, sched)
             sim.set_option(G.OPT_KERNEL_TIMING, 1)
             j = launch()
             sim.wait(j)
@@ -885,17 +892,16 @@ def main():
             dwall = time.perf_counter() - t0
             sim.set_option(G.OPT_SCHEDULE, 0)
             sim.set_option(G.OPT_KERNEL_TIMING, 0)
-            assert all(x.n_out == mid["n_out"] for x in dstats), "dependency-driven runs disagree"
+            assert all(x.n_out == mid["n_out"] for x in dstats), f"{key} runs disagree"
             d_ms = dwall / steps * 1000.0
             d_eval = statistics.median(x.eval_ms for x in dstats)
-            out["dataflow"] = {
-                "workload": "the mid-size job",
-                "schedule": "dependency-driven: one persistent launch per job, no level barrier",
+            out[key] = {
+                "workload": "the mid-size job", "schedule": desc,
                 "ms_per_step": d_ms, "value": mid["n_out"] / (d_ms / 1000.0), "kernel_ms": d_eval,
                 "b_min_gbps": mid["roofline"]["b_min_bytes_per_job"] / (d_eval / 1000.0) / 1e9,
                 "vs_levels": mid["ms_per_step"] / d_ms,
             }
-            say(f"dependency-driven: {d_ms:.2f} ms per mid job (levels {mid['ms_per_step']:.2f})")
+            say(f"{key}: {d_ms:.2f} ms per mid job (levels {mid['ms_per_step']:.2f})")
         if not args.no_cpu_baseline:
             from oracle import oracle as O
             n_o, par_s, _ = oracle_whole_job(O, nl, st, n_threads, single=False)
@@ -925,14 +931,16 @@ def main():
     if not args.no_tiny:
         out["tiny_latency"] = bench_tiny_latency(G, sim, args.seed)
         if not args.no_dataflow:
-            sim.set_option(G.OPT_SCHEDULE, 1)
-            out["tiny_latency_dataflow"] = bench_tiny_latency(G, sim, args.seed)
+            for key, sched in (("tiny_latency_dataflow", 1), ("tiny_latency_levelsync", 3)):
+                sim.set_option(G.OPT_SCHEDULE, sched)
+                out[key] = bench_tiny_latency(G, sim, args.seed)
             sim.set_option(G.OPT_SCHEDULE, 0)
         if not args.no_cpu_baseline:
             from oracle import oracle as O
             nl1, st1 = W.config1(seed=args.seed)
             n_o, par_s, single_s = oracle_whole_job(O, nl1, st1, n_threads)
-            key = "tiny_latency_dataflow" if "tiny_latency_dataflow" in out else "tiny_latency"
+            key = min((k for k in ("tiny_latency", "tiny_latency_dataflow", "tiny_latency_levelsync") if k in out),
+                      key=lambda k: out[k]["resident_p50_us"])
             gpu_s = out[key]["resident_p50_us"] / 1e6
             eq6["tiny"] = {"gpu_transitions_per_s": n_o / gpu_s, "oracle_parallel_per_s": n_o / par_s,
                            "oracle_single_per_s": n_o / single_s, "gpu_schedule": key}

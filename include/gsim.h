@@ -104,8 +104,15 @@ enum gsim_option {
      * 800 gates per level on average (launch overhead dominates the level
      * chain) or, for stimuli given in host memory, when the per-source
      * transition counts vary with a coefficient of variation (the paper's
-     * workload WCV, Eq. 5) of at least 2.5; level by level otherwise.
-     * Results are identical under every setting. */
+     * workload WCV, Eq. 5) of at least 2.5; level by level otherwise;
+     * 3 = level barriers in one launch: the level order of setting 0 for one
+     * job, run by persistent wavefronts (a cooperative launch, every one
+     * resident) that meet at a device-wide barrier after each level, so a
+     * job costs one launch instead of a chain per level. The barrier's wait
+     * is bounded: a wait that does not end (another program holding the
+     * device's wavefront slots, for instance) fails the job with
+     * GSIM_E_DEVICE instead of hanging. Results are identical under every
+     * setting. */
     GSIM_OPT_SCHEDULE = 6,
     /* Data-parallel form of the level schedule's wavefront-per-gate kernel
      * (Algorithm 2 per gate either way; identical results; the
@@ -365,7 +372,7 @@ typedef struct {
                                 evaluate launches, else 0 */
     int64_t eval_launches;   /* levels timed for eval_ms */
     int64_t retries;         /* automatic re-runs after an output-storage overflow */
-    int64_t schedule;        /* the job's schedule: 0 level by level, 1 dependency-driven */
+    int64_t schedule;        /* the job's schedule: 0 level by level, 1 dependency-driven, 3 level barriers in one launch */
 } gsim_job_stats;
 /* Statistics of a finished job (waits for it). Passage: `pin_reads` is the
  * per-gate Eq. 2 bound summed over the job; n_out the output lengths. */

@@ -5,7 +5,9 @@ long its waveforms are:
 
 * schedule (GSIM_OPT_SCHEDULE): level by level, with every admitted job's
   level in shared launches, or dependency-driven, one persistent launch per
-  job with no level barrier (wins on small or unevenly active netlists);
+  job with no level barrier (wins on small or unevenly active netlists), or
+  the level order in one persistent launch with a device-wide barrier per
+  level (no launch chain);
 * evaluation form of the level schedule (GSIM_OPT_EVAL_FORM): merged
   positions or time segments per lane;
 * dynamic-binning threshold (GSIM_OPT_LANE_THRESHOLD): gates whose inputs hold
@@ -38,14 +40,18 @@ CANDIDATES = (
     (G.SCHEDULE_LEVELS, G.FORM_SEGMENTED, 0, 0),
     (G.SCHEDULE_DEPENDENCY, G.FORM_MERGED, 0, 0),
     (G.SCHEDULE_DEPENDENCY, G.FORM_MERGED, 0, 4),
+    (G.SCHEDULE_LEVEL_BARRIERS, G.FORM_MERGED, 0, 0),
 )
-SCHEDULE_NAMES = {G.SCHEDULE_LEVELS: "levels", G.SCHEDULE_DEPENDENCY: "dataflow"}
+SCHEDULE_NAMES = {G.SCHEDULE_LEVELS: "levels", G.SCHEDULE_DEPENDENCY: "dataflow",
+                  G.SCHEDULE_LEVEL_BARRIERS: "levelsync"}
 FORM_NAMES = {G.FORM_MERGED: "merged", G.FORM_SEGMENTED: "segmented"}
 
 
 def setting_name(c) -> str:
     if c[0] == G.SCHEDULE_DEPENDENCY:
         return f"dataflow/tickets{c[3] if c[3] else 'auto'}"
+    if c[0] == G.SCHEDULE_LEVEL_BARRIERS:
+        return "levelsync"
     return f"levels/{FORM_NAMES[c[1]]}/lane{c[2]}"
 
 

@@ -409,6 +409,8 @@ struct Netlist {
     int32_t *d_fo = nullptr;
     int32_t *d_pend0 = nullptr;
     int64_t n_first = 0;
+    // level-barrier schedule: first gate of each level, then G ([n_levels + 1])
+    int64_t *d_level_off = nullptr;
     int64_t active_jobs = 0;
     int64_t max_level_n = 0;        // gates of the largest level
     int32_t lane_threshold = -1;    // -1: the context's GSIM_OPT_LANE_THRESHOLD
@@ -454,12 +456,14 @@ struct Job {
     std::vector<std::shared_ptr<StepTiming>> timing;
     int64_t n_partial = 0;
     bool dataflow = false;        // dependency-driven schedule (one launch for every gate)
+    bool levelsync = false;       // level-barrier schedule (one launch, a device-wide barrier per level)
     // the job's step descriptor of every level, for steps it has alone
     // (uploaded once at admission instead of once per step)
     JobDesc *h_desc = nullptr;    // pinned
     JobDesc *d_desc = nullptr;
     int32_t *d_pend = nullptr, *d_queue = nullptr;
     DfCtl *d_ctl = nullptr;
+    uint32_t *d_sync = nullptr;   // level-barrier schedule: barrier counters and flags
     int32_t retries = 0;          // automatic re-runs after an arena overflow
     bool waited = false, failed = false;
 };
@@ -515,6 +519,7 @@ struct gsim_ctx_s {
     int opt_form = kFormMerged;
     int opt_df_tickets = 0;
     int64_t n_waves_resident = 0;  // persistent wavefronts of the dependency-driven schedule
+    int64_t n_waves_levelsync = 0; // level-barrier kernel's wavefronts that fit the device at once
     int32_t opt_lane_threshold = 0;
 };
 
@@ -551,12 +556,14 @@ void put_netlist(gsim_ctx ctx, Netlist *nl) {
     ctx->pool->put(nl->d_pend0);
     ctx->pool->put(nl->d_lut);
     ctx->pool->put(nl->d_edly);
+    ctx->pool->put(nl->d_level_off);
     nl->d_rec = nullptr;
     nl->d_fo_off = nullptr;
     nl->d_fo = nullptr;
     nl->d_pend0 = nullptr;
     nl->d_lut = nullptr;
     nl->d_edly = nullptr;
+    nl->d_level_off = nullptr;
 }
 
 // dly (optional): per pin [2 edges][2 outputs] delays of the extended model;
@@ -743,6 +750,18 @@ Failure load_netlist(gsim_ctx ctx, int64_t S, int64_t G, const uint8_t *type, co
             return fail(GSIM_E_OOM, "no device memory for the edge delay table");
         }
     }
+    if (nl->n_levels > 0) {
+        std::vector<int64_t> lo((size_t)nl->n_levels + 1);
+        for (int32_t l = 0; l < nl->n_levels; l++) lo[l] = nl->levels[l].begin;
+        lo[nl->n_levels] = G;
+        nl->d_level_off = pool_get<int64_t>(*ctx->pool, nl->n_levels + 1);
+        if (!nl->d_level_off ||
+            hipMemcpy(nl->d_level_off, lo.data(), sizeof(int64_t) * lo.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            put_netlist(ctx, nl.get());
+            return fail(GSIM_E_OOM, "no device memory for the level table");
+        }
+    }
     const int64_t id = ctx->next_id++;
     ctx->netlists[id] = std::move(nl);
     *out = id;
@@ -837,6 +856,7 @@ void free_job_buffers(gsim_ctx ctx, Job *j) {
     pool.put(j->d_pend);
     pool.put(j->d_queue);
     pool.put(j->d_ctl);
+    pool.put(j->d_sync);
     pool.put(j->d_desc);
     j->d_desc = nullptr;
     j->d_off = j->d_len = j->d_partial = j->d_src_off = nullptr;
@@ -844,6 +864,7 @@ void free_job_buffers(gsim_ctx ctx, Job *j) {
     j->d_state = nullptr;
     j->d_pend = j->d_queue = nullptr;
     j->d_ctl = nullptr;
+    j->d_sync = nullptr;
 }
 
 void destroy_job(gsim_ctx ctx, Job *j) {
@@ -1002,6 +1023,7 @@ Failure queue_job(gsim_ctx ctx, gsim_netlist nlh, Netlist &nl, Executor *ex, Hos
     j->capacity_request = ctx->opt_arena;
     const int schedule = nl.schedule >= 0 ? nl.schedule : ctx->opt_schedule;
     j->dataflow = schedule == 1 || (schedule == 2 && prefer_dependency_driven(nl, hs ? hs->src_off : nullptr));
+    j->levelsync = schedule == 3;
     if (hs) {
         j->h_src_off = hs->src_off;
         j->h_t = hs->t;
@@ -1137,6 +1159,43 @@ Failure enqueue_dataflow(gsim_ctx ctx, Job *j, hipStream_t s) {
     return finish_job(j, s);
 }
 
+// Every level of an admitted job in one launch with a device-wide barrier
+// between levels. The grid is no larger than what is resident at once nor
+// than the widest level.
+Failure enqueue_levelsync(gsim_ctx ctx, Job *j, hipStream_t s) {
+    Netlist &nl = *j->nl;
+    LsArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.job.rec = nl.d_rec;
+    a.job.S = nl.S;
+    a.job.off = j->d_off;
+    a.job.len = j->d_len;
+    a.job.K = j->d_K;
+    a.job.state = j->d_state;
+    a.job.lut = nl.d_lut ? nl.d_lut : ctx->d_lut;
+    a.job.edly = nl.d_edly;
+    a.level_off = nl.d_level_off;
+    a.sync = j->d_sync;
+    a.n_levels = nl.n_levels;
+    const int64_t n_waves =
+        std::max<int64_t>(1, std::min({ctx->n_waves_levelsync, nl.max_level_n, kLsMaxWaves}));
+    a.chunk = std::min<int64_t>(int64_t(1) << 15, (j->capacity - j->n_in) / (16 * n_waves));
+    std::shared_ptr<StepTiming> tm;
+    if (ctx->opt_timing) {
+        tm = std::make_shared<StepTiming>();
+        HIP_TRY(hipEventCreate(&tm->a));
+        HIP_TRY(hipEventCreate(&tm->b));
+        HIP_TRY(hipEventRecord(tm->a, s));
+    }
+    HIP_TRY(launch_levelsync(a, n_waves, s));
+    if (tm) {
+        HIP_TRY(hipEventRecord(tm->b, s));
+        j->timing.push_back(tm);
+    }
+    j->next_level = nl.n_levels;
+    return finish_job(j, s);
+}
+
 // Allocate a queued job's device storage and pack its sources into the arena.
 // Returns GSIM_E_OOM (and leaves the job queued) if the budget has no room.
 Failure admit(gsim_ctx ctx, Executor *ex, Job *j) {
@@ -1184,16 +1243,18 @@ Failure admit(gsim_ctx ctx, Executor *ex, Job *j) {
     if (j->dataflow) {
         j->d_pend = pool_get<int32_t>(pool, std::max<int64_t>(nl.G, 1));
         j->d_queue = pool_get<int32_t>(pool, std::max<int64_t>(nl.G, 1));
-        j->d_ctl = pool_get<DfCtl>(pool, 1);
     }
+    if (j->dataflow) j->d_ctl = pool_get<DfCtl>(pool, 1);
+    if (j->levelsync) j->d_sync = pool_get<uint32_t>(pool, kLsSyncWords);
     if (!j->d_off || !j->d_len || !j->d_partial || !j->d_state || !j->d_K || (j->h_t && !j->d_src_off) ||
-        (j->dataflow && (!j->d_pend || !j->d_queue || !j->d_ctl))) {
+        (j->dataflow && (!j->d_pend || !j->d_queue || !j->d_ctl)) || (j->levelsync && !j->d_sync)) {
         pool.put(j->d_off); pool.put(j->d_len); pool.put(j->d_partial); pool.put(j->d_state); pool.put(j->d_K);
         pool.put(j->d_src_off);
-        pool.put(j->d_pend); pool.put(j->d_queue); pool.put(j->d_ctl);
+        pool.put(j->d_pend); pool.put(j->d_queue); pool.put(j->d_ctl); pool.put(j->d_sync);
         j->d_off = j->d_len = j->d_partial = j->d_src_off = nullptr;
         j->d_pend = j->d_queue = nullptr;
         j->d_ctl = nullptr;
+        j->d_sync = nullptr;
         j->d_state = nullptr;
         j->d_K = nullptr;
         return fail(GSIM_E_OOM, "no device memory for a job of %lld transitions of output storage", (long long)cap);
@@ -1229,6 +1290,7 @@ Failure admit(gsim_ctx ctx, Executor *ex, Job *j) {
     j->next_level = 0;
     if (nl.n_levels == 0) return finish_job(j, s);
     if (j->dataflow) return enqueue_dataflow(ctx, j, s);
+    if (j->levelsync) return enqueue_levelsync(ctx, j, s);
     // descriptors for the steps this job has alone (optional: skipped if no memory)
     const size_t desc_bytes = sizeof(JobDesc) * (size_t)nl.n_levels;
     if (!j->h_desc) j->h_desc = (JobDesc *)ctx->pinned.get(desc_bytes);
@@ -1438,7 +1500,8 @@ Failure wait_job(gsim_ctx ctx, Job *j) {
                     "(after %d automatic retries); set GSIM_OPT_ARENA_TRANSITIONS larger",
                     (long long)j->capacity, (int)j->retries);
     if (j->h_state->check_error == 3)
-        return fail(GSIM_E_DEVICE, "the dependency-driven schedule made no progress and stopped");
+        return fail(GSIM_E_DEVICE, j->levelsync ? "the level-barrier schedule's barrier wait timed out"
+                                                : "the dependency-driven schedule made no progress and stopped");
     if (j->h_state->check_error == 4)
         return fail(GSIM_E_DEVICE, "a gate's evaluation made no progress (an input waveform out of order)");
     if (j->h_state->check_error)
@@ -1831,6 +1894,8 @@ gsim_status sim_create(int device, uint64_t hbm_budget_bytes, gsim_ctx *out) try
         if (hipGetDeviceProperties(&prop, device) != hipSuccess)
             return record(nullptr, fail(GSIM_E_DEVICE, "hipGetDeviceProperties failed"));
         ctx->n_waves_resident = (int64_t)prop.multiProcessorCount * 16;
+        if (levelsync_max_waves(prop.multiProcessorCount, &ctx->n_waves_levelsync) != hipSuccess)
+            return record(nullptr, fail(GSIM_E_DEVICE, "occupancy query failed"));
     }
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess)
         return record(nullptr, fail(GSIM_E_DEVICE, "stream creation failed"));
@@ -1901,7 +1966,7 @@ gsim_status sim_set_option(gsim_ctx ctx, int option, int64_t value) try {
         ctx->opt_lane_threshold = (int32_t)value;
         return GSIM_OK;
     case GSIM_OPT_SCHEDULE:
-        if (value < 0 || value > 2) return record(ctx, fail(GSIM_E_ARG, "schedule option must be 0, 1 or 2"));
+        if (value < 0 || value > 3) return record(ctx, fail(GSIM_E_ARG, "schedule option must be 0, 1, 2 or 3"));
         ctx->opt_schedule = (int)value;
         return GSIM_OK;
     case GSIM_OPT_EVAL_FORM:
@@ -1963,7 +2028,7 @@ gsim_status sim_set_netlist_option(gsim_ctx ctx, gsim_netlist nl, int option, in
         n.lane_threshold = (int32_t)value;
         return GSIM_OK;
     case GSIM_OPT_SCHEDULE:
-        if (value < -1 || value > 2) return record(ctx, fail(GSIM_E_ARG, "schedule must be -1, 0, 1 or 2"));
+        if (value < -1 || value > 3) return record(ctx, fail(GSIM_E_ARG, "schedule must be -1, 0, 1, 2 or 3"));
         n.schedule = (int32_t)value;
         return GSIM_OK;
     case GSIM_OPT_EVAL_FORM:
@@ -2220,7 +2285,7 @@ gsim_status sim_job_stats(gsim_ctx ctx, gsim_job job, gsim_job_stats *out) try {
     out->eval_ms = 0.0;
     out->eval_launches = 0;
     out->retries = j->retries;
-    out->schedule = j->dataflow ? 1 : 0;
+    out->schedule = j->dataflow ? 1 : j->levelsync ? 3 : 0;
     for (const auto &tm : j->timing) {
         float e = 0.f;
         if (hipEventElapsedTime(&e, tm->a, tm->b) != hipSuccess)

@@ -144,6 +144,25 @@ struct DfArgs {
     uint32_t tickets;       // queue slots a wavefront claims per atomic (1..4)
 };
 
+// Level-barrier schedule: one persistent launch per job; its wavefronts take
+// the gates of each level in turn and meet at a device-wide barrier before
+// the next level. Barrier storage: 128-byte lines of 32 words, the top
+// arrival counter, one arrival counter per group of kLsGroup wavefronts, then
+// one release flag per group (zeroed per launch).
+constexpr uint32_t kLsGroup = 64;
+constexpr int64_t kLsMaxWaves = 64 * 64;
+constexpr int kLsLineWords = 32;
+constexpr int kLsLineTop = 0, kLsLineGroups = 1, kLsLineFlags = 1 + 64;
+constexpr int64_t kLsSyncWords = (int64_t)kLsLineWords * (1 + 2 * 64);
+struct LsArgs {
+    JobDesc job;               // netlist and storage of the job (level fields unused)
+    const int64_t *level_off;  // [n_levels + 1] first gate of each level (internal order)
+    uint32_t *sync;            // [kLsSyncWords] barrier counters and flags
+    int64_t chunk;             // arena reservation granule per wavefront, in transitions
+    int32_t n_levels;
+    int32_t pad;
+};
+
 // Kernel launchers (kernels.hip). All are asynchronous on `s`.
 hipError_t launch_init_sources(const int64_t *d_src_off, const int64_t *d_t, const uint8_t *d_v,
                                int64_t S, int64_t n_in, int64_t *off, int64_t *len, uint64_t *K,
@@ -167,6 +186,12 @@ hipError_t launch_eval_lane(const StepArgs &a, int64_t max_items, hipStream_t s)
 // gate of the job with n_waves persistent wavefronts.
 hipError_t launch_df_init(const DfArgs &a, const int32_t *pend0, hipStream_t s);
 hipError_t launch_dataflow(const DfArgs &a, int64_t n_waves, hipStream_t s);
+// Level-barrier schedule: clear the barrier counter, then run every level of
+// the job with n_waves persistent wavefronts in a cooperative launch (every
+// one resident; at most levelsync_max_waves and kLsMaxWaves).
+hipError_t launch_levelsync(const LsArgs &a, int64_t n_waves, hipStream_t s);
+// Wavefronts of the level-barrier kernel that fit the device at once.
+hipError_t levelsync_max_waves(int n_cu, int64_t *out);
 hipError_t launch_count_out(const int64_t *len, int64_t S, int64_t G, int64_t *partial,
                             int64_t n_partial, DevState *state, hipStream_t s);
 hipError_t launch_gather(const int64_t *src_off, const int64_t *n_items, const int64_t *dst_off,

@@ -568,6 +568,128 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void da
 }
 
 // -------------------------------------------------------------------------
+// Level-barrier schedule: the level chain of one job in a single launch. The
+// persistent wavefronts take the gates of each level in strides of the grid,
+// reserve each gate's region from a per-wave arena chunk, evaluate it as the
+// level kernel does, and meet at a device-wide barrier before the next level.
+//
+// The barrier is a combining tree with one release flag per group of 64
+// wavefronts, each counter and flag on a cache line of its own, so that no
+// address is polled by more than 64 wavefronts: a wavefront's agent-scope
+// release fence (its level's plain stores become visible), one relaxed
+// increment of its group's arrival counter; the group's last arrival
+// (acquire-release fence) increments the top counter; the last of those
+// (acquire-release fence) sets every group's flag to the barrier's
+// generation; a waiting wavefront polls its group's flag, then takes an
+// agent-scope acquire fence (fence-to-fence synchronisation at each step).
+// Counters only grow: generation g has completed when a group counter reaches
+// g times the group's size. Every wavefront of the grid is resident (a
+// cooperative launch), so the wait ends; as a safety exit, a wait longer than
+// kLsSpinLimit polls flags the job (check_error = 3), and a flagged job stops
+// every wavefront at its next barrier.
+constexpr uint32_t kLsSpinLimit = 1u << 22;
+
+__device__ __forceinline__ uint32_t *ls_line(const LsArgs &A, int i) { return A.sync + (size_t)i * kLsLineWords; }
+
+__device__ bool ls_barrier(const LsArgs &A, uint32_t gen, DevState *st) {
+    const int lane = lane_id();
+    const uint32_t nw = gridDim.x, m = blockIdx.x / kLsGroup, M = (nw + kLsGroup - 1) / kLsGroup;
+    const uint32_t gs = m + 1 < M ? kLsGroup : nw - kLsGroup * m;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    uint32_t old = 0;
+    if (lane == 0)
+        old = __hip_atomic_fetch_add(ls_line(A, kLsLineGroups + m), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    old = (uint32_t)__builtin_amdgcn_readfirstlane((int)old);
+    if (old + 1 == gs * gen) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        uint32_t top = 0;
+        if (lane == 0)
+            top = __hip_atomic_fetch_add(ls_line(A, kLsLineTop), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        top = (uint32_t)__builtin_amdgcn_readfirstlane((int)top);
+        if (top + 1 == M * gen) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            if ((uint32_t)lane < M)
+                __hip_atomic_store(ls_line(A, kLsLineFlags + lane), gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    const uint32_t *flag = ls_line(A, kLsLineFlags + m);
+    for (uint32_t spins = 0;; spins++) {
+        uint32_t seen = 0;
+        if (lane == 0) seen = load_agent(flag);
+        seen = (uint32_t)__builtin_amdgcn_readfirstlane((int)seen);
+        if (seen >= gen) break;
+        if ((spins & 255u) == 255u) {
+            uint32_t err = 0;
+            if (lane == 0) err = load_agent(reinterpret_cast<const uint32_t *>(&st->check_error));
+            if (__builtin_amdgcn_readfirstlane((int)err)) return false;
+            if (spins > kLsSpinLimit) {
+                if (lane == 0) atomicMax(&st->check_error, 3);
+                return false;
+            }
+        }
+        __builtin_amdgcn_s_sleep(4);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+}
+
+template <bool EDGE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void levelsync_kernel(LsArgs A) {
+    __shared__ WaveLds<kWindowLarge> L;
+    const int lane = lane_id();
+    const JobDesc &J = A.job;
+    DevState *st = J.state;
+    const int64_t nw = gridDim.x, capacity = st->capacity;
+    int64_t chunk_at = 0, chunk_end = 0;  // this wavefront's unused arena space
+    int64_t reads = 0;                    // sum of w_g over this wavefront's gates
+    for (int32_t l = 0; l < A.n_levels; l++) {
+        const int64_t g1 = A.level_off[l + 1];
+        const bool halted = load_agent(reinterpret_cast<const uint32_t *>(&st->overflow)) != 0;
+        for (int64_t g = A.level_off[l] + blockIdx.x; g < g1; g += nw) {
+            const GateRec R = J.rec[g];
+            int64_t w = 0;
+#pragma unroll
+            for (int p = 0; p < kMaxPins; p++)
+                if (p < R.k) w += J.len[R.net[p]];
+            reads += w;
+            if (chunk_end - chunk_at < w) {
+                const int64_t want = w > A.chunk ? w : A.chunk;
+                int64_t at = 0;
+                if (lane == 0)
+                    at = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&st->arena_top),
+                                            (unsigned long long)want);
+                chunk_at = (int64_t)readlane_u64((uint64_t)at, 0);
+                chunk_end = chunk_at + want;
+            }
+            const int64_t ob = chunk_at;
+            chunk_at += w;
+            const bool full = ob + w > capacity;
+            if (full || halted) {
+                if (lane == 0) {
+                    if (full) atomicOr(&st->overflow, 1);
+                    J.len[J.S + g] = 0;
+                    J.off[J.S + g] = 0;
+                }
+            } else if (R.dmax > kWindowLarge) {
+                if (lane == 0) eval_seq<false>(J, R, g, ob, J.lut + (int)R.type * 256);
+            } else {
+                reinterpret_cast<uint32_t *>(L.lut)[lane] =
+                    reinterpret_cast<const uint32_t *>(J.lut + (int)R.type * 256)[lane];
+                switch (R.k) {
+                case 1: eval_gate<1, kWindowLarge, EDGE, true, true, false>(J, ob, R, g, L); break;
+                case 2: eval_gate<2, kWindowLarge, EDGE, true, true, false>(J, ob, R, g, L); break;
+                case 3: eval_gate<3, kWindowLarge, EDGE, true, true, false>(J, ob, R, g, L); break;
+                default: eval_gate<4, kWindowLarge, EDGE, true, true, false>(J, ob, R, g, L); break;
+                }
+            }
+        }
+        if (l + 1 < A.n_levels && !ls_barrier(A, (uint32_t)(l + 1), st)) break;
+    }
+    if (lane == 0 && reads > 0)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&st->pin_reads), (unsigned long long)reads);
+}
+
+// -------------------------------------------------------------------------
 // Per-net fingerprint: mix(n) + sum over transitions i of mix(key_i ^ mix(i))
 // (mod 2^64), key_i = time << 2 | value, mix = the SplitMix64 finaliser. The
 // index inside mix binds each transition to its position, so reordering is
@@ -782,6 +904,29 @@ hipError_t launch_dataflow(const DfArgs &a, int64_t n_waves, hipStream_t s) {
     if (a.job.edly) dataflow_kernel<true><<<grid, block, 0, s>>>(a);
     else dataflow_kernel<false><<<grid, block, 0, s>>>(a);
     return hipGetLastError();
+}
+
+hipError_t levelsync_max_waves(int n_cu, int64_t *out) {
+    int a = 0, b = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, levelsync_kernel<false>, 64, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, levelsync_kernel<true>, 64, 0);
+    if (e != hipSuccess) return e;
+    *out = (int64_t)n_cu * (a < b ? a : b);
+    return hipSuccess;
+}
+
+// A cooperative launch: the runtime starts it only with every wavefront
+// resident at once, which the barrier needs.
+hipError_t launch_levelsync(const LsArgs &a, int64_t n_waves, hipStream_t s) {
+    if (a.n_levels <= 0 || n_waves <= 0) return hipSuccess;
+    if (n_waves > kLsMaxWaves) return hipErrorInvalidValue;
+    hipError_t e = launch_clear_u32(a.sync, kLsSyncWords, s);
+    if (e != hipSuccess) return e;
+    LsArgs arg = a;
+    void *params[] = {&arg};
+    const dim3 grid((unsigned)n_waves), block(64);
+    if (a.job.edly) return hipLaunchCooperativeKernel(levelsync_kernel<true>, grid, block, params, 0, s);
+    return hipLaunchCooperativeKernel(levelsync_kernel<false>, grid, block, params, 0, s);
 }
 
 hipError_t launch_hash(const int64_t *nets_off, const int64_t *nets_len, int64_t n_nets,

@@ -24,7 +24,7 @@ OPT_DF_TICKETS = 8
 # values of OPT_EVAL_FORM
 FORM_SEGMENTED, FORM_MERGED = 0, 1  # the library default is FORM_MERGED
 # values of OPT_SCHEDULE
-SCHEDULE_LEVELS, SCHEDULE_DEPENDENCY, SCHEDULE_AUTO = 0, 1, 2
+SCHEDULE_LEVELS, SCHEDULE_DEPENDENCY, SCHEDULE_AUTO, SCHEDULE_LEVEL_BARRIERS = 0, 1, 2, 3
 NO_RELATION = 2**31 - 1
 
 EXPORTED = ("sim_create", "sim_destroy", "sim_last_error", "sim_set_option", "sim_load_netlist",

@@ -32,11 +32,12 @@ def build(asan: bool = False) -> str:
     if os.path.exists(exe) and os.path.getmtime(exe) >= max(os.path.getmtime(s) for s in srcs):
         return exe
     cmd = ["g++", "-O2", "-g", "-std=c++17", "-I", os.path.join(HERE, "shim"), "-I", CSRC,
-           os.path.join(HERE, "emu_eval.cpp"), "-o", exe + ".tmp"]
+           os.path.join(HERE, "emu_eval.cpp"), "-o", f"{exe}.{os.getpid()}.tmp"]
     if asan:
         cmd[1:1] = ["-fsanitize=address", "-fno-omit-frame-pointer"]
     subprocess.check_call(cmd)
-    os.replace(exe + ".tmp", exe)
+    # a name of its own per process: parallel test workers may build at once
+    os.replace(f"{exe}.{os.getpid()}.tmp", exe)
     return exe
 
 

@@ -163,15 +163,16 @@ def mid():
     return nl, st, OracleRun(nl, st, sample_gates(nl.G))
 
 
-@pytest.mark.parametrize("schedule", [0, 1], ids=["levels", "dataflow"])
+@pytest.mark.parametrize("schedule", [0, 1, 3], ids=["levels", "dataflow", "levelsync"])
 def test_mid_full_size(sim, mid, schedule):
     nl, st, want = mid
     sim.set_option(G.OPT_SCHEDULE, schedule)
     try:
         h, j, keep = run_resident(sim, nl, st)
         s = sim.stats(j)
-        say(f"  gpu ({'dependency-driven' if schedule else 'levels'}): {s.n_out} output transitions, "
-            f"{s.device_ms:.1f} ms device")
+        assert s.schedule == schedule
+        say(f"  gpu ({['levels', 'dependency-driven', '', 'level barriers'][schedule]}): {s.n_out} output "
+            f"transitions, {s.device_ms:.1f} ms device")
         compare_job(sim, j, nl, want)
         if schedule == 0:
             check_properties(sim, j, nl, st)

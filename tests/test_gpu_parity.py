@@ -21,10 +21,10 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module", params=[0, 1], ids=["levels", "dataflow"])
+@pytest.fixture(scope="module", params=[0, 1, 3], ids=["levels", "dataflow", "levelsync"])
 def sim(request):
-    """Every case runs under both schedules: level by level, and
-    dependency-driven (one persistent launch per job)."""
+    """Every case runs under every schedule: level by level, dependency-driven
+    (one persistent launch per job), and level barriers in one launch."""
     s = G.Sim(0)
     s.set_option(G.OPT_SCHEDULE, request.param)
     say(f"schedule {request.param}")
