@@ -1,5 +1,6 @@
 """HIP path vs the CPU oracle O1, element by element, through the C ABI,
-under both schedules (level by level; dependency-driven).
+under every schedule (level by level; dependency-driven; level barriers in
+one launch).
 
 Every comparison is exact (integer times and 2-bit values: tolerance 0).
 """
@@ -182,6 +183,36 @@ def test_no_gates(sim):
     assert off.tolist() == [0, 1, 1] and t.tolist() == [0] and v.tolist() == [1]
     sim.release(j)
     sim.unload_netlist(h)
+
+
+def layered(widths, S, seed):
+    """Gates in strict levels of the given widths; each gate reads 1-4 nets of
+    the previous level (sources for the first), delays 1-60 ps."""
+    rng = np.random.default_rng(seed)
+    arity = {O.BUF: 1, O.NOT: 1, O.AND2: 2, O.XOR2: 2, O.NOR2: 2, O.AND3: 3, O.MUX2: 3, O.OR4: 4}
+    types = list(arity)
+    gates, prev, first = [], np.arange(S), S
+    for w in widths:
+        for _ in range(w):
+            ty = types[rng.integers(len(types))]
+            gates.append((ty, [int(x) for x in rng.choice(prev, size=arity[ty])]))
+        prev = np.arange(first, first + w)
+        first += w
+    P_ = sum(len(g[1]) for g in gates)
+    return P.netlist_of(S, gates, rng.integers(1, 61, P_), rng.integers(1, 61, P_))
+
+
+def test_level_shapes(sim):
+    """Shapes that set the level-barrier grid: a 300-level chain (one
+    wavefront, 299 barriers), one level of 9,000 gates (the full grid, no
+    barrier), and 1,000-gate levels (a grid of 1,000: a partial last group of
+    40 wavefronts)."""
+    for name, widths, S in (("chain", [1] * 300, 3), ("one wide level", [9000], 64),
+                            ("1,000 per level", [1000] * 4, 64)):
+        nl = layered(widths, S, seed=len(widths))
+        nl.name = name
+        st = W.make_stimulus(S=S, n_per_src=60, window=50_000, seed=3)
+        check(sim, nl, st)
 
 
 def test_shuffled_gate_order(sim):
