@@ -28,7 +28,7 @@ from paper_2304_13398_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-# host threads for the oracle (a GPU machine grants 16 cores to a job)
+# host threads for the oracle (16: the host cores a GPU job is given)
 THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
 SAMPLE_FRACTION = 0.01
 
