@@ -108,9 +108,10 @@ enum gsim_option {
      * 3 = level barriers in one launch: the level order of setting 0 for one
      * job, run by persistent wavefronts (a cooperative launch, every one
      * resident) that meet at a device-wide barrier after each level, so a
-     * job costs one launch instead of a chain per level. The barrier's wait
-     * is bounded: a wait that does not end (another program holding the
-     * device's wavefront slots, for instance) fails the job with
+     * job costs one launch instead of a chain per level; each such launch
+     * waits for the context's previous one, on any stream. The barrier's
+     * wait is bounded: a wait that does not end (another program holding
+     * the device's wavefront slots, for instance) fails the job with
      * GSIM_E_DEVICE instead of hanging. Results are identical under every
      * setting. */
     GSIM_OPT_SCHEDULE = 6,

@@ -520,6 +520,10 @@ struct gsim_ctx_s {
     int opt_df_tickets = 0;
     int64_t n_waves_resident = 0;  // persistent wavefronts of the dependency-driven schedule
     int64_t n_waves_levelsync = 0; // level-barrier kernel's wavefronts that fit the device at once
+    // the last level-barrier launch of this context: the next one, from any
+    // executor's stream, waits for it, so that two such grids never share the
+    // device (each needs every wavefront resident)
+    hipEvent_t ls_event = nullptr;
     int32_t opt_lane_threshold = 0;
 };
 
@@ -1161,7 +1165,8 @@ Failure enqueue_dataflow(gsim_ctx ctx, Job *j, hipStream_t s) {
 
 // Every level of an admitted job in one launch with a device-wide barrier
 // between levels. The grid is no larger than what is resident at once nor
-// than the widest level.
+// than the widest level, and the launch waits for the context's previous one
+// (on whatever stream it ran).
 Failure enqueue_levelsync(gsim_ctx ctx, Job *j, hipStream_t s) {
     Netlist &nl = *j->nl;
     LsArgs a;
@@ -1180,6 +1185,8 @@ Failure enqueue_levelsync(gsim_ctx ctx, Job *j, hipStream_t s) {
     const int64_t n_waves =
         std::max<int64_t>(1, std::min({ctx->n_waves_levelsync, nl.max_level_n, kLsMaxWaves}));
     a.chunk = std::min<int64_t>(int64_t(1) << 15, (j->capacity - j->n_in) / (16 * n_waves));
+    if (!ctx->ls_event) HIP_TRY(hipEventCreateWithFlags(&ctx->ls_event, hipEventDisableTiming));
+    else HIP_TRY(hipStreamWaitEvent(s, ctx->ls_event, 0));
     std::shared_ptr<StepTiming> tm;
     if (ctx->opt_timing) {
         tm = std::make_shared<StepTiming>();
@@ -1188,6 +1195,7 @@ Failure enqueue_levelsync(gsim_ctx ctx, Job *j, hipStream_t s) {
         HIP_TRY(hipEventRecord(tm->a, s));
     }
     HIP_TRY(launch_levelsync(a, n_waves, s));
+    HIP_TRY(hipEventRecord(ctx->ls_event, s));
     if (tm) {
         HIP_TRY(hipEventRecord(tm->b, s));
         j->timing.push_back(tm);
@@ -1939,6 +1947,7 @@ gsim_status sim_destroy(gsim_ctx ctx) try {
     ctx->pool->put(ctx->d_stage_v);
     ctx->pool->put(ctx->d_stage_meta);
     ctx->pool.reset();
+    if (ctx->ls_event) (void)hipEventDestroy(ctx->ls_event);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return GSIM_OK;

@@ -260,6 +260,35 @@ def test_dependency_driven_batch_and_mix(sim):
         sim.set_option(G.OPT_SCHEDULE, 0)
 
 
+def test_level_barrier_batch_and_two_streams(sim):
+    """Jobs under the level-barrier schedule: a batch of uneven sets, then two
+    jobs started on two streams before either is waited for (each launch
+    waits for the context's previous one, so two grids never share the
+    device); each equals the oracle."""
+    import torch
+    sim.set_option(G.OPT_SCHEDULE, 3)
+    try:
+        nl = W.config2_netlist(G=30000, S=64, L=30, seed=13)
+        h = sim.load_netlist(nl)
+        rng = np.random.default_rng(13)
+        sets = [W.make_stimulus(S=nl.S, n_per_src=int(n), window=1_000_000, seed=500 + i)
+                for i, n in enumerate(W.loguniform_int(rng, 20, 800, size=4))]
+        for j, st in zip(sim.run_batch(h, sets), sets):
+            sim.wait(j)
+            assert sim.stats(j).schedule == 3
+            assert same(fetch_gates(sim, j, nl), O.o1_simulate(nl, st))
+            sim.release(j)
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        jobs = [sim.run(h, st, stream=s.cuda_stream) for s, st in zip(streams, sets[:2])]
+        for j, st in zip(jobs, sets[:2]):
+            sim.wait(j)
+            assert same(fetch_gates(sim, j, nl), O.o1_simulate(nl, st))
+            sim.release(j)
+        sim.unload_netlist(h)
+    finally:
+        sim.set_option(G.OPT_SCHEDULE, 0)
+
+
 @pytest.mark.parametrize("n_windows", [3, 8])
 def test_time_windows_on_the_gpu_equal_the_oracle(sim, n_windows):
     """A job cut into exact time windows (halo from the netlist's delays), each
