@@ -136,6 +136,14 @@ enum gsim_option {
     GSIM_OPT_DF_TICKETS = 8
 };
 
+/* Values of GSIM_OPT_SCHEDULE (see there). */
+enum gsim_schedule {
+    GSIM_SCHEDULE_LEVELS = 0,
+    GSIM_SCHEDULE_DEPENDENCY = 1,
+    GSIM_SCHEDULE_AUTO = 2,
+    GSIM_SCHEDULE_LEVEL_BARRIERS = 3
+};
+
 /* ---- context ------------------------------------------------------------ */
 
 /* Open a context on HIP device `device`. `hbm_budget_bytes` caps the device

@@ -131,3 +131,26 @@ def test_binding_structs_match_the_header(c_name, py_cls):
     want = [(n, ctype_of[t]) for n, t in header_struct(c_name)]
     got = list(getattr(G, py_cls)._fields_)
     assert got == want
+
+
+def header_enum(name):
+    """{member: value} of `enum name { ... };` in gsim.h (comments removed)."""
+    src = open(os.path.join(ROOT, "include", "gsim.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"enum " + name + r"\s*\{([^}]*)\}", src).group(1)
+    return {m.group(1): int(m.group(2)) for m in re.finditer(r"(\w+)\s*=\s*(-?\d+)", body)}
+
+
+def test_binding_constants_match_the_header():
+    """The binding's option, schedule and gate-type numbers are the header's."""
+    opts = header_enum("gsim_option")
+    for name, value in opts.items():
+        assert getattr(G, name[len("GSIM_"):]) == value, name
+    for name, value in header_enum("gsim_schedule").items():
+        assert getattr(G, name[len("GSIM_"):]) == value, name
+    gates = header_enum("gsim_gate_type")
+    n = gates.pop("GSIM_NUM_TYPES")
+    assert sorted(gates.values()) == list(range(n))
+    from oracle import oracle as O
+    for name, value in gates.items():
+        assert getattr(O, name[len("GSIM_"):]) == value, name
